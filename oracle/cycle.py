@@ -1,0 +1,241 @@
+"""Hierarchy, smoother, k-cycle and flexible CG -- oracle (test infrastructure only).
+
+Section 3 defines the two-level method (coarse correction with A_H^+ followed by
+smoothing with R) and its symmetrized form B = R_bar + (I-RA) P A_H^+ P^T (I-AR)
+with R_bar = 2R - RAR.  Section 4 builds the multilevel solver: a nonlinear AMLI
+cycle (k-cycle) in which nonlinear PCG (flexible CG) is applied recursively to
+the coarse-level equations, the outer flexible CG restarted every five
+iterations, W(1,1) cycles (two coarse corrections, one pre- and one
+post-smoothing step) with the degree-m polynomial smoother, and coarsening until
+the coarsest level is small.
+
+Readings taken where the paper is silent:
+
+* Smoother application y = q_m(A) v uses the Chebyshev three-term recurrence in
+  the shifted variable t = (x - theta)/eta: w_0 = v, w_1 = (A w_0 - theta w_0)/eta,
+  w_{k+1} = 2 (A w_k - theta w_k)/eta - w_{k-1}; y = (1/eta) sum_k c_k w_k.
+  Exactly m matrix-vector products.
+* Kcycle(l, r): x = S r; s = r - A x; b = P^T s; e = inner solve of A_{l+1} e = b;
+  x += P e; s = r - A x; x += S s.  The inner solve is exactly nu = 2 flexible
+  CG steps from zero, each preconditioned by Kcycle(l+1), with no early exit;
+  when l+1 is the coarsest level it is the exact Cholesky solve instead (two
+  FCG steps against an exact solve would break down on the second step).
+* Flexible CG: p = z - sum_i ((z, q_i)/rho_i) p_i over the stored directions
+  (classical Gram-Schmidt against z), q = A p, rho = (p, q), alpha = (p, r)/rho.
+  "Restart every five iterations" is read as clearing the stored directions once
+  five are held.  A coefficient whose denominator rho is not positive is taken
+  as zero (this only happens for a zero right-hand side); the outer iteration
+  instead reports a breakdown.
+* Stopping test: relative residual ||r_k||_2 <= tol ||r_0||_2 on the recursively
+  updated residual (the paper stops on the relative A-norm error, which needs
+  the exact solution); the iteration count is the number of outer
+  preconditioner applications.
+* Coarsening stops when n <= coarse_max, or when a level shrinks by less than
+  10 % (then that level is the coarsest, which must have at most
+  max_coarsest rows).
+* Coarsest solve: dense Cholesky factorization of A_L (SPD because some d_i > 0
+  on a connected graph) and two triangular solves.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from .aggregation import aggregate_level
+from .level import Level, apply_A, assemble
+from .poly import SmootherPoly, best_poly, error_Em, lambda_max_bound
+
+
+@dataclass
+class Params:
+    degree: int = 4
+    agg_size: int = 4
+    coarse_max: int = 64
+    lambda0_ratio: float = 10.0
+    inner_steps: int = 2
+    restart: int = 5
+    tol: float = 1e-8
+    max_iter: int = 200
+    match_key: str = "normalized"
+    max_coarsest: int = 2048
+    stagnation: float = 0.9
+
+    @property
+    def passes(self) -> int:
+        return max(1, int(round(math.log2(self.agg_size))))
+
+
+@dataclass
+class Hierarchy:
+    levels: list  # list[Level], finest first
+    aggs: list  # aggs[l][i] = aggregate of fine vertex i of level l (in level l+1)
+    polys: list  # SmootherPoly per non-coarsest level
+    chol: np.ndarray  # lower Cholesky factor of the coarsest matrix
+    params: Params
+
+    @property
+    def L(self) -> int:
+        """Index of the coarsest level."""
+        return len(self.levels) - 1
+
+    def grid_complexity(self) -> float:
+        return sum(l.n for l in self.levels) / self.levels[0].n
+
+    def operator_complexity(self) -> float:
+        nnzA = [l.nnz + l.n for l in self.levels]
+        return sum(nnzA) / nnzA[0]
+
+
+class CoarsenError(RuntimeError):
+    pass
+
+
+def build_hierarchy(n, row_ptr, col, w, d, params: Params | None = None) -> Hierarchy:
+    p = params or Params()
+    if error_Em(p.degree, p.lambda0_ratio) >= 1.0:
+        raise ValueError("smoother degree too low: E_m >= 1")
+    levels = [assemble(n, row_ptr, col, w, d)]
+    aggs = []
+    while levels[-1].n > p.coarse_max:
+        cur = levels[-1]
+        agg, coarse = aggregate_level(cur, p.passes, p.match_key)
+        if coarse.n > p.stagnation * cur.n:
+            break
+        aggs.append(agg)
+        levels.append(coarse)
+    if levels[-1].n > p.max_coarsest:
+        raise CoarsenError(f"coarsest level has {levels[-1].n} rows")
+    polys = [best_poly(lambda_max_bound(l), p.degree, p.lambda0_ratio) for l in levels[:-1]]
+    chol = np.linalg.cholesky(levels[-1].dense())
+    return Hierarchy(levels, aggs, polys, chol, p)
+
+
+# ---- single steps ---------------------------------------------------------------
+
+
+def smooth(lvl: Level, poly: SmootherPoly, v: np.ndarray) -> np.ndarray:
+    """y = q_m(A) v by the three-term recurrence (m matrix-vector products)."""
+    c = poly.c
+    y = c[0] * v
+    if poly.m == 0:
+        return y / poly.eta
+    w_prev = v
+    w = (apply_A(lvl, v) - poly.theta * v) / poly.eta
+    y = y + c[1] * w
+    for k in range(1, poly.m):
+        w_next = 2.0 * (apply_A(lvl, w) - poly.theta * w) / poly.eta - w_prev
+        y = y + c[k + 1] * w_next
+        w_prev, w = w, w_next
+    return y / poly.eta
+
+
+def residual(lvl: Level, f: np.ndarray, x: np.ndarray) -> np.ndarray:
+    return f - apply_A(lvl, x)
+
+
+def restrict(agg: np.ndarray, nc: int, s: np.ndarray) -> np.ndarray:
+    """b = P^T s: b_I = sum of s_i over i in aggregate I."""
+    return np.bincount(agg, weights=s, minlength=nc)
+
+
+def prolong(agg: np.ndarray, e: np.ndarray) -> np.ndarray:
+    """P e: the coarse value of each vertex's aggregate."""
+    return e[agg]
+
+
+def coarse_solve(chol: np.ndarray, b: np.ndarray) -> np.ndarray:
+    y = sla.solve_triangular(chol, b, lower=True)
+    return sla.solve_triangular(chol.T, y, lower=False)
+
+
+def _dot(a, b) -> float:
+    return float(np.dot(a, b))
+
+
+# ---- k-cycle and flexible CG ----------------------------------------------------
+
+
+def kcycle(h: Hierarchy, l: int, r: np.ndarray) -> np.ndarray:
+    """Nonlinear AMLI (k-cycle) preconditioner applied to r on level l."""
+    if l == h.L:
+        return coarse_solve(h.chol, r)
+    lvl, poly, agg = h.levels[l], h.polys[l], h.aggs[l]
+    nc = h.levels[l + 1].n
+    x = smooth(lvl, poly, r)
+    s = residual(lvl, r, x)
+    b = restrict(agg, nc, s)
+    if l + 1 == h.L:
+        e = coarse_solve(h.chol, b)
+    else:
+        e = fcg_fixed(h, l + 1, b, h.params.inner_steps)
+    x = x + prolong(agg, e)
+    s = residual(lvl, r, x)
+    return x + smooth(lvl, poly, s)
+
+
+def fcg_fixed(h: Hierarchy, l: int, b: np.ndarray, steps: int) -> np.ndarray:
+    """Exactly ``steps`` flexible CG iterations on level l from x = 0."""
+    lvl = h.levels[l]
+    x = np.zeros_like(b)
+    r = b.copy()
+    window = []
+    for k in range(steps):
+        z = kcycle(h, l, r)
+        p = z.copy()
+        for pi, qi, rhoi in window:
+            beta = _dot(z, qi) / rhoi if rhoi > 0.0 else 0.0
+            p = p - beta * pi
+        q = apply_A(lvl, p)
+        rho = _dot(p, q)
+        alpha = _dot(p, r) / rho if rho > 0.0 else 0.0
+        x = x + alpha * p
+        if k + 1 < steps:
+            r = r - alpha * q
+        window.append((p, q, rho))
+    return x
+
+
+@dataclass
+class FCGResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    breakdown: bool
+    res_history: list = field(default_factory=list)
+
+
+def fcg(h: Hierarchy, f: np.ndarray, u0: np.ndarray | None = None, precond=None) -> FCGResult:
+    """Outer flexible CG preconditioned by Kcycle(0) (or by ``precond``)."""
+    p_ = h.params
+    lvl = h.levels[0]
+    B = precond if precond is not None else (lambda r: kcycle(h, 0, r))
+    x = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
+    r = f - apply_A(lvl, x)
+    rho0 = math.sqrt(_dot(r, r))
+    hist = [rho0]
+    if rho0 == 0.0:
+        return FCGResult(x, 0, True, False, hist)
+    window = []
+    for it in range(1, p_.max_iter + 1):
+        z = B(r)
+        p = z.copy()
+        for pi, qi, rhoi in window:
+            p = p - (_dot(z, qi) / rhoi) * pi
+        q = apply_A(lvl, p)
+        rho = _dot(p, q)
+        if not (rho > 0.0) or not math.isfinite(rho):
+            return FCGResult(x, it, False, True, hist)
+        alpha = _dot(p, r) / rho
+        x = x + alpha * p
+        r = r - alpha * q
+        window.append((p, q, rho))
+        if len(window) == p_.restart:
+            window = []
+        rn = math.sqrt(_dot(r, r))
+        hist.append(rn)
+        if rn <= p_.tol * rho0:
+            return FCGResult(x, it, True, False, hist)
+    return FCGResult(x, p_.max_iter, False, False, hist)

@@ -1,0 +1,182 @@
+"""Pins for the oracle's smoother application, coarsest solve, two-level
+structure (Section 3), k-cycle and flexible CG (Section 4)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import inputs
+import oracle
+from oracle import spectral
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _level(g):
+    return oracle.assemble(g.n, g.row_ptr, g.col, g.w, g.d)
+
+
+@pytest.mark.parametrize("m", [0, 1, 3, 4, 5, 7])
+def test_smoother_equals_spectral_definition(m):
+    """q_m(A) v by the recurrence equals V q_m(Lambda) V^T v (eigh + chebval)."""
+    g = inputs.random_graph(40, 0.1, seed=m, weighted=True)
+    lvl = _level(g)
+    poly = oracle.best_poly(oracle.lambda_max_bound(lvl), m, 10.0)
+    v = np.random.default_rng(m).standard_normal(g.n)
+    R = spectral.smoother_matrix(lvl.dense(), poly)
+    np.testing.assert_allclose(oracle.smooth(lvl, poly, v), R @ v, rtol=1e-12, atol=1e-12)
+
+
+def test_lambda1_bounds_spectrum():
+    for g in (inputs.grid2d(10), inputs.tet3d(4), inputs.random_graph(30, 0.2, 1, True)):
+        lvl = _level(g)
+        lam = np.linalg.eigvalsh(lvl.dense())
+        assert lam.max() <= oracle.lambda_max_bound(lvl) + 1e-12
+    g = inputs.grid2d(10)
+    assert oracle.lambda_max_bound(_level(g)) == 12.0  # interior: D = 6, six unit weights
+
+
+def test_coarse_solve_matches_dense_solve():
+    g = inputs.random_graph(50, 0.1, seed=5, weighted=True)
+    lvl = _level(g)
+    A = lvl.dense()
+    L = np.linalg.cholesky(A)
+    b = np.random.default_rng(1).standard_normal(g.n)
+    np.testing.assert_allclose(oracle.coarse_solve(L, b), np.linalg.solve(A, b), rtol=1e-11)
+
+
+def _two_level_hierarchy(g, m, agg_size):
+    p = oracle.Params(degree=m, agg_size=agg_size, coarse_max=g.n - 1, max_coarsest=g.n)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    assert h.L == 1
+    return h
+
+
+@pytest.mark.parametrize("m", [3, 4, 5])
+def test_two_level_kcycle_is_symmetrized_B(m):
+    """With an exact coarsest solve, Kcycle(0) applies
+    B = R_bar + (I-RA) P A_H^-1 P^T (I-AR), R_bar = 2R - RAR (Section 3)."""
+    g = inputs.grid2d(6)
+    h = _two_level_hierarchy(g, m, 4)
+    A = h.levels[0].dense()
+    P = spectral.prolongator(h.aggs[0], h.levels[1].n)
+    R = spectral.smoother_matrix(A, h.polys[0])
+    E, B = spectral.two_level(A, P, R)
+    r = np.random.default_rng(m).standard_normal(g.n)
+    np.testing.assert_allclose(oracle.kcycle(h, 0, r), B @ r, rtol=1e-11, atol=1e-12)
+    # spectrum of BA in (0, 1] and ||E_TL||_A^2 = rho(I - BA)
+    ev = np.linalg.eigvals(B @ A).real
+    assert ev.min() > 0 and ev.max() <= 1 + 1e-10
+    Ah = np.linalg.cholesky(A)
+    En = np.linalg.norm(Ah.T @ E @ np.linalg.inv(Ah.T), 2) ** 2
+    assert En == pytest.approx(1 - ev.min(), rel=1e-8)
+
+
+def test_two_level_condition_trends():
+    """kappa(BA) falls as the degree grows and rises with the aggregate size."""
+    g = inputs.grid2d(8)
+
+    def kappa(m, a):
+        h = _two_level_hierarchy(g, m, a)
+        A = h.levels[0].dense()
+        P = spectral.prolongator(h.aggs[0], h.levels[1].n)
+        _, B = spectral.two_level(A, P, spectral.smoother_matrix(A, h.polys[0]))
+        ev = np.linalg.eigvals(B @ A).real
+        return ev.max() / ev.min()
+
+    k3, k4, k5 = kappa(3, 4), kappa(4, 4), kappa(5, 4)
+    assert k3 > k4 > k5
+    assert kappa(3, 16) > k3
+
+
+def test_weak_approximation_property():
+    """||v - Qv||^2 <= c_p (Av, v) for all v (eq. (wap)), c_p from local
+    eigenproblems; checked on random v and through the generalized eigenvalue."""
+    g = inputs.grid2d(8)
+    lvl = _level(g)
+    agg, coarse = oracle.aggregate_level(lvl, 2)
+    cp = spectral.local_cp(lvl, agg)
+    Q = spectral.l2_projection(agg, coarse.n)
+    A = lvl.dense()
+    IQ = np.eye(g.n) - Q
+    M = IQ.T @ IQ
+    # largest generalized eigenvalue of (I-Q)^T(I-Q) v = mu A v
+    Linv = np.linalg.inv(np.linalg.cholesky(A))
+    mu = np.linalg.eigvalsh(Linv @ M @ Linv.T).max()
+    assert mu <= cp * (1 + 1e-12)
+    for s in range(5):
+        v = np.random.default_rng(s).standard_normal(g.n)
+        lhs = np.sum((v - Q @ v) ** 2)
+        assert lhs <= cp * float(v @ A @ v)
+
+
+def test_fcg_with_fixed_preconditioner_is_pcg():
+    """With a fixed SPD preconditioner and no restart, flexible CG takes the
+    same steps as preconditioned CG (scipy's cg)."""
+    g = inputs.grid2d(20)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d,
+                               oracle.Params(degree=3, agg_size=4, restart=10 ** 6, max_iter=500))
+    A = h.levels[0].dense()
+    Dinv = 1.0 / np.diag(A)
+    f = inputs.rhs(g.n, 3)
+    res = oracle.fcg(h, f, precond=lambda r: Dinv * r)
+    count = [0]
+
+    def cb(xk):
+        count[0] += 1
+
+    x, info = spla.cg(A, f, rtol=1e-8, atol=0.0, M=spla.LinearOperator(A.shape, matvec=lambda r: Dinv * r),
+                      callback=cb, maxiter=500)
+    assert info == 0 and res.converged
+    assert abs(res.iters - count[0]) <= 1
+    np.testing.assert_allclose(res.x, x, rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("N,m,agg", [(32, 3, 4), (40, 4, 8), (24, 5, 16)])
+def test_solve_matches_dense_solution(N, m, agg):
+    g = inputs.grid2d(N)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(degree=m, agg_size=agg))
+    f = inputs.rhs(g.n, 9)
+    res = oracle.fcg(h, f)
+    assert res.converged and not res.breakdown
+    A = h.levels[0].dense()
+    u = np.linalg.solve(A, f)
+    r = f - A @ res.x
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(f) * (1 + 1e-6)
+    errA = np.sqrt((res.x - u) @ A @ (res.x - u)) / np.sqrt(u @ A @ u)
+    # ||e||_A <= ||r||_2 / sqrt(lambda_min): the A-norm error the residual allows
+    lmin = np.linalg.eigvalsh(A).min()
+    assert errA <= np.linalg.norm(r) / np.sqrt(lmin) / np.sqrt(u @ A @ u) * (1 + 1e-6)
+
+
+def test_single_level_hierarchy_converges_in_one_step():
+    g = inputs.grid2d(7)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(degree=3))
+    assert h.L == 0
+    res = oracle.fcg(h, inputs.rhs(g.n, 1))
+    assert res.iters == 1 and res.converged
+
+
+def test_zero_rhs():
+    g = inputs.grid2d(16)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(degree=3))
+    res = oracle.fcg(h, np.zeros(g.n))
+    assert res.iters == 0 and np.all(res.x == 0)
+
+
+def test_iteration_counts_near_constant_in_n():
+    """Table 1's trend: outer iterations grow only slowly with the mesh size
+    (exact counts are parity unpinned: different aggregation and boundary)."""
+    with open(os.path.join(GOLDEN, "table1_iterations.json")) as fh:
+        t1 = json.load(fh)
+    paper = [v[1] for v in t1["2d_structured"].values()]
+    assert max(paper) - min(paper) <= 2
+    its = []
+    for N in (32, 64, 128):
+        g = inputs.grid2d(N)
+        h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(degree=3, agg_size=4))
+        its.append(oracle.fcg(h, inputs.rhs(g.n, 1)).iters)
+    assert max(its) - min(its) <= 5
+    assert max(its) <= 25
