@@ -1,0 +1,210 @@
+/*
+ * amg.h -- C ABI of the MI355X (gfx950) solver for graph-Laplacian systems
+ *
+ *     (Au, v) = sum_{e=(i,j) in E} w_e (u_i - u_j)(v_i - v_j) + sum_{i in S_b} d_i u_i v_i = (f, v)
+ *
+ * (eq. (prob), Section 1 of Brannick, "Aggregation-based aggressive coarsening
+ * with polynomial smoothing"), solved by flexible CG preconditioned by a
+ * nonlinear AMLI cycle (k-cycle) over unsmoothed-aggregation coarse levels with
+ * the polynomial smoother of best uniform approximation to 1/x (Sections 3-4).
+ *
+ * Conventions shared by every call:
+ *   - All integers are int32 unless stated; all floating point is IEEE binary64
+ *     at the boundary.
+ *   - "host pointer": ordinary CPU memory, read during the call only; the
+ *     library copies what it keeps.  "device pointer": memory on the current
+ *     HIP device (e.g. a torch tensor's data_ptr()), never freed by the library.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *     ordered on that stream; calls that return results to the host synchronize
+ *     it.
+ *   - Every call returns AMG_OK (0) or a negative amg_status.  Argument and graph
+ *     validation happens on the host before any device call, so invalid input is
+ *     reported identically with or without a GPU.
+ *   - A hierarchy handle owns all device memory it allocated until amg_free.
+ *     Calls on one handle must not overlap in time (they share its workspace).
+ */
+#ifndef AMG_H
+#define AMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMG_OK = 0,
+  AMG_ERR_ARG = -1,          /* null pointer, bad size or bad parameter value      */
+  AMG_ERR_GRAPH = -2,        /* malformed CSR: range, order, self loop, asymmetry,
+                                w <= 0 or non-finite, d < 0 or non-finite          */
+  AMG_ERR_DISCONNECTED = -3, /* the graph is not connected                         */
+  AMG_ERR_SINGULAR = -4,     /* all d_i = 0 (A singular) or a non-positive pivot
+                                in the coarsest Cholesky factorization             */
+  AMG_ERR_DEGREE = -5,       /* smoother error E_m >= 1 for the requested degree   */
+  AMG_ERR_COARSEN = -6,      /* coarsening stagnated above max_coarsest rows       */
+  AMG_ERR_NOMEM = -7,        /* device allocation failed                           */
+  AMG_ERR_DEVICE = -8,       /* no usable HIP device, or a HIP runtime error       */
+  AMG_ERR_BREAKDOWN = -9,    /* outer FCG: (p, Ap) <= 0 or non-finite              */
+  AMG_ERR_MAXIT = -10,       /* max_iter reached before tol (u is still written)   */
+  AMG_ERR_BUDGET = -11       /* request does not fit the HBM budget                */
+} amg_status;
+
+enum { AMG_FP64 = 0, AMG_MIXED = 1 };
+enum { AMG_KEY_NORMALIZED = 0, AMG_KEY_RAW = 1 };
+
+#define AMG_MAX_LEVELS 32
+
+/*
+ * Solver parameters (plain struct, passed by pointer, copied by amg_setup).
+ *   degree        m of the smoother q_m (Section 3; Section 4 uses 4).  Must give
+ *                 E_m = delta^m (kappa-1)/2 < 1, else AMG_ERR_DEGREE.
+ *   agg_size      target aggregate size; log2(agg_size) rounded = number of
+ *                 matching passes per level (4 -> 2 passes, 16 -> 4).
+ *   coarse_max    stop coarsening once a level has at most this many rows.
+ *   lambda0_ratio lambda1 / lambda0 of the smoothing interval (Section 4: 10).
+ *   inner_steps   flexible-CG steps per coarse level in the k-cycle (W-cycle: 2).
+ *   restart       outer FCG keeps at most this many directions (Section 4: 5).
+ *   tol           stop when ||r_k||_2 <= tol * ||r_0||_2.
+ *   max_iter      outer iteration cap.
+ *   precision     AMG_FP64, or AMG_MIXED: cycle, smoother and coarse-level
+ *                 vectors and matrices in FP32 with FP32 accumulation; outer FCG,
+ *                 every inner product, the coarsest factor and solve in FP64.
+ *   match_key     AMG_KEY_NORMALIZED: edge strength W_ij^2/(D_i D_j);
+ *                 AMG_KEY_RAW: W_ij.  Ties broken by the vertex indices (i, j).
+ *   max_coarsest  largest coarsest level accepted when coarsening stagnates.
+ *   stagnation    a level that keeps more than this fraction of its rows stops
+ *                 the coarsening.
+ *   use_graph     1: replay the cycle and the outer iteration as HIP graphs.
+ *   tail_rows     levels with at most this many rows run their whole k-cycle in
+ *                 one workgroup-resident kernel (0 disables).
+ */
+typedef struct {
+  int32_t degree;
+  int32_t agg_size;
+  int32_t coarse_max;
+  double lambda0_ratio;
+  int32_t inner_steps;
+  int32_t restart;
+  double tol;
+  int32_t max_iter;
+  int32_t precision;
+  int32_t match_key;
+  int32_t max_coarsest;
+  double stagnation;
+  int32_t use_graph;
+  int32_t tail_rows;
+} amg_params;
+
+typedef struct amg_hier amg_hier;
+
+/* Per-solve report.  rel_res is the recursively updated residual norm ratio the
+ * stopping test uses; rel_res_true = ||f - A u||_2 / ||f - A u0||_2 recomputed in
+ * FP64 at the end. */
+typedef struct {
+  int32_t status;
+  int32_t iters;
+  double rel_res;
+  double rel_res_true;
+  double solve_ms;
+} amg_info;
+
+/* Hierarchy description (sizes, complexities and setup timings). */
+typedef struct {
+  int32_t levels;                     /* number of levels, finest = 0           */
+  int32_t n[AMG_MAX_LEVELS];          /* rows per level                         */
+  int64_t nnz[AMG_MAX_LEVELS];        /* stored off-diagonal entries per level  */
+  double lambda1[AMG_MAX_LEVELS];     /* ||A_l||_inf per level                  */
+  double grid_complexity;             /* sum n_l / n_0 (Section 4)              */
+  double operator_complexity;         /* sum (nnz_l + n_l) / (nnz_0 + n_0)      */
+  double setup_ms;                    /* whole amg_setup, device time           */
+  double aggregation_ms;              /* matching passes + coarse numbering     */
+  double galerkin_ms;                 /* coarse operators (sort and reduce)     */
+  int32_t match_rounds;               /* handshake rounds summed over passes    */
+  int32_t precision;
+} amg_hier_desc;
+
+/* Fill *p with the defaults: degree 4, agg_size 4, coarse_max 64,
+ * lambda0_ratio 10, inner_steps 2, restart 5, tol 1e-8, max_iter 200, FP64,
+ * normalized key, max_coarsest 2048, stagnation 0.9, use_graph 1,
+ * tail_rows 2048. */
+void amg_params_default(amg_params* p);
+
+/* Human-readable name of a status code (static string). */
+const char* amg_strerror(int32_t status);
+
+/* Detail message of the last failing call on this thread (static storage,
+ * valid until the next failing call). */
+const char* amg_last_error(void);
+
+/*
+ * Build the hierarchy for the graph of eq. (prob) (Sections 2-4): matching
+ * aggregation passes, Galerkin coarse operators (the quotient graph of
+ * Section 2 with summed weights), smoother intervals and coefficients, and the
+ * Cholesky factor of the coarsest matrix, all computed on the device.
+ *   n        number of vertices (>= 1)
+ *   row_ptr  host, n+1 entries, row_ptr[0] = 0, non-decreasing
+ *   col      host, row_ptr[n] entries: neighbours of each vertex, both
+ *            directions stored, strictly increasing within a row, no self loop
+ *   w        host, edge weights aligned with col; w_ij == w_ji > 0 exactly
+ *   d        host, n lower-order terms d_i >= 0 (zero off S_b), not all zero
+ *   params   host, NULL = defaults
+ *   out      receives the handle (set to NULL on failure)
+ * Errors: ARG, GRAPH, DISCONNECTED, SINGULAR, DEGREE (host validation, before
+ * any device call); DEVICE, NOMEM, COARSEN, SINGULAR (device phase).
+ */
+int32_t amg_setup(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
+                  const double* d, const amg_params* params, void* stream, amg_hier** out);
+
+/* Release every device allocation of the handle (NULL is accepted). */
+void amg_free(amg_hier* h);
+
+/* Describe the hierarchy (host struct). */
+int32_t amg_describe(const amg_hier* h, amg_hier_desc* out);
+
+/*
+ * Solve A u = f by flexible CG preconditioned by the k-cycle (Section 4).
+ *   f     device, n doubles
+ *   u     device, n doubles: initial guess on entry, solution on exit
+ *   info  host, may be NULL
+ * Returns OK, MAXIT (u holds the last iterate), BREAKDOWN or DEVICE.  One
+ * host synchronization per outer iteration (the stopping test).
+ */
+int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info);
+
+/* ---- Level inspection and single steps (tests and diagnostics) ------------
+ * The single steps below (all but amg_apply_cycle) need an AMG_FP64
+ * hierarchy (AMG_ERR_ARG otherwise); each synchronizes `stream` before it
+ * returns. */
+
+/* Export level l (host pointers, sized from amg_describe): off-diagonal CSR
+ * (row_ptr n+1, col nnz, W nnz), d and D (n each), and for l < levels-1 the
+ * aggregate map agg (n entries, values in [0, n_{l+1})).  Any pointer may be
+ * NULL to skip that array. */
+int32_t amg_level_export(const amg_hier* h, int32_t level, int32_t* row_ptr, int32_t* col,
+                         double* W, double* d, double* D, int32_t* agg);
+
+/* y = q_m(A_l) r (Section 3 smoother, m matrix-vector products); device
+ * pointers of n_l doubles; level < levels-1. */
+int32_t amg_apply_smoother(amg_hier* h, int32_t level, const double* r, double* y, void* stream);
+
+/* s = f - A_l x; device pointers of n_l doubles. */
+int32_t amg_apply_residual(amg_hier* h, int32_t level, const double* f, const double* x,
+                           double* s, void* stream);
+
+/* b = P^T s (sum over each aggregate): s has n_l, b has n_{l+1} doubles. */
+int32_t amg_apply_restrict(amg_hier* h, int32_t level, const double* s, double* b, void* stream);
+
+/* x += P e (each vertex adds its aggregate's value): e has n_{l+1}, x n_l. */
+int32_t amg_apply_prolong(amg_hier* h, int32_t level, const double* e, double* x, void* stream);
+
+/* x = A_L^{-1} b on the coarsest level by the Cholesky factor. */
+int32_t amg_apply_coarse(amg_hier* h, const double* b, double* x, void* stream);
+
+/* z = Kcycle(0, r): one application of the preconditioner on the finest level. */
+int32_t amg_apply_cycle(amg_hier* h, const double* r, double* z, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMG_H */

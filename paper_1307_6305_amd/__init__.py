@@ -1,0 +1,301 @@
+"""Python binding of the MI355X graph-Laplacian solver (C ABI in include/amg.h).
+
+The binding only marshals arguments: every step of setup and solve runs in the
+HIP library ``libamg.so`` built from ``csrc/``.  Device vectors are torch
+tensors on the current HIP device (float64, contiguous); graphs are host numpy
+arrays.  The functions keep the names of the C entry points.
+
+There is no fallback: if the library is missing or cannot be loaded, importing
+the binding's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+try:  # torch first: the library must bind to the HIP runtime torch already loaded
+    import torch
+except ImportError:  # pragma: no cover - torch is part of the image
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamg.so")
+
+AMG_OK = 0
+AMG_ERR_ARG = -1
+AMG_ERR_GRAPH = -2
+AMG_ERR_DISCONNECTED = -3
+AMG_ERR_SINGULAR = -4
+AMG_ERR_DEGREE = -5
+AMG_ERR_COARSEN = -6
+AMG_ERR_NOMEM = -7
+AMG_ERR_DEVICE = -8
+AMG_ERR_BREAKDOWN = -9
+AMG_ERR_MAXIT = -10
+AMG_ERR_BUDGET = -11
+AMG_FP64 = 0
+AMG_MIXED = 1
+AMG_KEY_NORMALIZED = 0
+AMG_KEY_RAW = 1
+AMG_MAX_LEVELS = 32
+
+
+class amg_params(ctypes.Structure):
+    _fields_ = [
+        ("degree", ctypes.c_int32),
+        ("agg_size", ctypes.c_int32),
+        ("coarse_max", ctypes.c_int32),
+        ("lambda0_ratio", ctypes.c_double),
+        ("inner_steps", ctypes.c_int32),
+        ("restart", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("match_key", ctypes.c_int32),
+        ("max_coarsest", ctypes.c_int32),
+        ("stagnation", ctypes.c_double),
+        ("use_graph", ctypes.c_int32),
+        ("tail_rows", ctypes.c_int32),
+    ]
+
+
+class amg_info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("rel_res", ctypes.c_double),
+        ("rel_res_true", ctypes.c_double),
+        ("solve_ms", ctypes.c_double),
+    ]
+
+
+class amg_hier_desc(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32),
+        ("n", ctypes.c_int32 * AMG_MAX_LEVELS),
+        ("nnz", ctypes.c_int64 * AMG_MAX_LEVELS),
+        ("lambda1", ctypes.c_double * AMG_MAX_LEVELS),
+        ("grid_complexity", ctypes.c_double),
+        ("operator_complexity", ctypes.c_double),
+        ("setup_ms", ctypes.c_double),
+        ("aggregation_ms", ctypes.c_double),
+        ("galerkin_ms", ctypes.c_double),
+        ("match_rounds", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class AmgError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        self.code = code
+        super().__init__(f"{where}: {amg_strerror(code)} ({code}): {detail}")
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+
+# C signatures: name -> (restype, argtypes)
+SIGNATURES = {
+    "amg_params_default": (None, [ctypes.POINTER(amg_params)]),
+    "amg_strerror": (ctypes.c_char_p, [_I32]),
+    "amg_last_error": (ctypes.c_char_p, []),
+    "amg_setup": (_I32, [_I32, _P, _P, _P, _P, ctypes.POINTER(amg_params), _P, ctypes.POINTER(_P)]),
+    "amg_free": (None, [_P]),
+    "amg_describe": (_I32, [_P, ctypes.POINTER(amg_hier_desc)]),
+    "amg_solve": (_I32, [_P, _P, _P, _P, ctypes.POINTER(amg_info)]),
+    "amg_level_export": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P]),
+    "amg_apply_smoother": (_I32, [_P, _I32, _P, _P, _P]),
+    "amg_apply_residual": (_I32, [_P, _I32, _P, _P, _P, _P]),
+    "amg_apply_restrict": (_I32, [_P, _I32, _P, _P, _P]),
+    "amg_apply_prolong": (_I32, [_P, _I32, _P, _P, _P]),
+    "amg_apply_coarse": (_I32, [_P, _P, _P, _P]),
+    "amg_apply_cycle": (_I32, [_P, _P, _P, _P]),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libamg.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int, where: str):
+    if code != AMG_OK:
+        raise AmgError(code, where, load_library().amg_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev(t, n: int | None = None, name: str = "vector"):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 tensor on the GPU")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def amg_strerror(code: int) -> str:
+    return load_library().amg_strerror(int(code)).decode()
+
+
+def amg_last_error() -> str:
+    return load_library().amg_last_error().decode()
+
+
+def amg_params_default(**overrides) -> amg_params:
+    p = amg_params()
+    load_library().amg_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": AMG_FP64, "mixed": AMG_MIXED}[v]
+        if k == "match_key" and isinstance(v, str):
+            v = {"normalized": AMG_KEY_NORMALIZED, "raw": AMG_KEY_RAW}[v]
+        setattr(p, k, v)
+    return p
+
+
+class Hierarchy:
+    """Owns an amg_hier handle; amg_free runs when it is collected or closed."""
+
+    def __init__(self, handle: int, n: int, params: amg_params):
+        self.handle = ctypes.c_void_p(handle)
+        self.n = n
+        self.params = params
+
+    def close(self):
+        if self.handle and self.handle.value:
+            load_library().amg_free(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def amg_setup(n, row_ptr, col, w, d, params: amg_params | None = None, stream=None) -> Hierarchy:
+    """Build the hierarchy from host CSR arrays (copied by the library)."""
+    lib = load_library()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    wv = np.ascontiguousarray(w, dtype=np.float64)
+    dv = np.ascontiguousarray(d, dtype=np.float64)
+    p = params if params is not None else amg_params_default()
+    out = ctypes.c_void_p()
+    st = _stream(stream) if torch is not None and torch.cuda.is_available() else ctypes.c_void_p(None)
+    code = lib.amg_setup(int(n), rp.ctypes.data_as(_P), cl.ctypes.data_as(_P), wv.ctypes.data_as(_P),
+                         dv.ctypes.data_as(_P), ctypes.byref(p), st, ctypes.byref(out))
+    _check(code, "amg_setup")
+    return Hierarchy(out.value, int(n), p)
+
+
+def amg_free(h: Hierarchy):
+    h.close()
+
+
+def amg_describe(h: Hierarchy) -> dict:
+    ds = amg_hier_desc()
+    _check(load_library().amg_describe(h.handle, ctypes.byref(ds)), "amg_describe")
+    L = ds.levels
+    return {
+        "levels": L,
+        "n": list(ds.n[:L]),
+        "nnz": list(ds.nnz[:L]),
+        "lambda1": list(ds.lambda1[:L]),
+        "grid_complexity": ds.grid_complexity,
+        "operator_complexity": ds.operator_complexity,
+        "setup_ms": ds.setup_ms,
+        "aggregation_ms": ds.aggregation_ms,
+        "galerkin_ms": ds.galerkin_ms,
+        "match_rounds": ds.match_rounds,
+        "precision": ds.precision,
+    }
+
+
+def amg_solve(h: Hierarchy, f, u, stream=None, check: bool = False) -> dict:
+    """Solve A u = f (u: initial guess in, solution out).  Returns the info
+    record; raises only for argument/device errors unless ``check``."""
+    info = amg_info()
+    code = load_library().amg_solve(h.handle, _dev(f, h.n, "f"), _dev(u, h.n, "u"), _stream(stream),
+                                    ctypes.byref(info))
+    if code in (AMG_ERR_ARG, AMG_ERR_DEVICE, AMG_ERR_NOMEM) or (check and code != AMG_OK):
+        _check(code, "amg_solve")
+    return {"status": info.status, "iters": info.iters, "rel_res": info.rel_res,
+            "rel_res_true": info.rel_res_true, "solve_ms": info.solve_ms}
+
+
+def amg_level_export(h: Hierarchy, level: int) -> dict:
+    """Level ``level`` as host numpy arrays (CSR, d, D and the aggregate map)."""
+    desc = amg_describe(h)
+    n, nnz = desc["n"][level], desc["nnz"][level]
+    rp = np.zeros(n + 1, np.int32)
+    col = np.zeros(max(nnz, 1), np.int32)
+    W = np.zeros(max(nnz, 1), np.float64)
+    d = np.zeros(n, np.float64)
+    D = np.zeros(n, np.float64)
+    coarsest = level == desc["levels"] - 1
+    agg = None if coarsest else np.zeros(n, np.int32)
+    code = load_library().amg_level_export(
+        h.handle, int(level), rp.ctypes.data_as(_P), col.ctypes.data_as(_P), W.ctypes.data_as(_P),
+        d.ctypes.data_as(_P), D.ctypes.data_as(_P), None if agg is None else agg.ctypes.data_as(_P))
+    _check(code, "amg_level_export")
+    return {"n": n, "row_ptr": rp, "col": col[:nnz], "W": W[:nnz], "d": d, "D": D, "agg": agg}
+
+
+def _sizes(h: Hierarchy):
+    return amg_describe(h)["n"]
+
+
+def amg_apply_smoother(h: Hierarchy, level: int, r, y, stream=None):
+    n = _sizes(h)[level]
+    _check(load_library().amg_apply_smoother(h.handle, int(level), _dev(r, n, "r"), _dev(y, n, "y"),
+                                             _stream(stream)), "amg_apply_smoother")
+
+
+def amg_apply_residual(h: Hierarchy, level: int, f, x, s, stream=None):
+    n = _sizes(h)[level]
+    _check(load_library().amg_apply_residual(h.handle, int(level), _dev(f, n, "f"), _dev(x, n, "x"),
+                                             _dev(s, n, "s"), _stream(stream)), "amg_apply_residual")
+
+
+def amg_apply_restrict(h: Hierarchy, level: int, s, b, stream=None):
+    ns = _sizes(h)
+    _check(load_library().amg_apply_restrict(h.handle, int(level), _dev(s, ns[level], "s"),
+                                             _dev(b, ns[level + 1], "b"), _stream(stream)), "amg_apply_restrict")
+
+
+def amg_apply_prolong(h: Hierarchy, level: int, e, x, stream=None):
+    ns = _sizes(h)
+    _check(load_library().amg_apply_prolong(h.handle, int(level), _dev(e, ns[level + 1], "e"),
+                                            _dev(x, ns[level], "x"), _stream(stream)), "amg_apply_prolong")
+
+
+def amg_apply_coarse(h: Hierarchy, b, x, stream=None):
+    n = _sizes(h)[-1]
+    _check(load_library().amg_apply_coarse(h.handle, _dev(b, n, "b"), _dev(x, n, "x"), _stream(stream)),
+           "amg_apply_coarse")
+
+
+def amg_apply_cycle(h: Hierarchy, r, z, stream=None):
+    _check(load_library().amg_apply_cycle(h.handle, _dev(r, h.n, "r"), _dev(z, h.n, "z"), _stream(stream)),
+           "amg_apply_cycle")

@@ -1,0 +1,225 @@
+// C ABI (include/amg.h): argument checking, handle lifetime, dispatch to the
+// setup and solve translation units.
+#include <cstring>
+#include <string>
+
+#include "hier.h"
+
+namespace amg {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& m) { g_last_error = m; }
+
+int32_t dalloc(amg_hier* h, void** p, size_t bytes) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    set_last_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+    *p = nullptr;
+    return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
+  }
+  h->allocs.push_back(q);
+  *p = q;
+  return AMG_OK;
+}
+
+}  // namespace amg
+
+namespace {
+
+int32_t check_device() {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) {
+    amg::set_last_error(e != hipSuccess ? std::string("hipGetDeviceCount: ") + hipGetErrorString(e)
+                                        : std::string("no HIP device"));
+    return AMG_ERR_DEVICE;
+  }
+  return AMG_OK;
+}
+
+int32_t check_level(const amg_hier* h, int32_t level, bool allow_coarsest) {
+  if (!h) { amg::set_last_error("null handle"); return AMG_ERR_ARG; }
+  const int top = allow_coarsest ? h->L : h->L - 1;
+  if (level < 0 || level > top) { amg::set_last_error("level out of range"); return AMG_ERR_ARG; }
+  return AMG_OK;
+}
+
+int32_t check_fp64_steps(const amg_hier* h) {
+  if (h->mixed) {
+    amg::set_last_error("single-step entry points need an FP64 hierarchy");
+    return AMG_ERR_ARG;
+  }
+  return AMG_OK;
+}
+
+int32_t sync_status(hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    amg::set_last_error(std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    return AMG_ERR_DEVICE;
+  }
+  return AMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void amg_params_default(amg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->degree = 4;
+  p->agg_size = 4;
+  p->coarse_max = 64;
+  p->lambda0_ratio = 10.0;
+  p->inner_steps = 2;
+  p->restart = 5;
+  p->tol = 1e-8;
+  p->max_iter = 200;
+  p->precision = AMG_FP64;
+  p->match_key = AMG_KEY_NORMALIZED;
+  p->max_coarsest = 2048;
+  p->stagnation = 0.9;
+  p->use_graph = 1;
+  p->tail_rows = 2048;
+}
+
+const char* amg_strerror(int32_t s) {
+  switch (s) {
+    case AMG_OK: return "ok";
+    case AMG_ERR_ARG: return "invalid argument";
+    case AMG_ERR_GRAPH: return "malformed graph";
+    case AMG_ERR_DISCONNECTED: return "graph not connected";
+    case AMG_ERR_SINGULAR: return "singular operator";
+    case AMG_ERR_DEGREE: return "smoother degree too low";
+    case AMG_ERR_COARSEN: return "coarsening stagnated";
+    case AMG_ERR_NOMEM: return "out of device memory";
+    case AMG_ERR_DEVICE: return "device error";
+    case AMG_ERR_BREAKDOWN: return "flexible CG breakdown";
+    case AMG_ERR_MAXIT: return "iteration limit reached";
+    case AMG_ERR_BUDGET: return "over memory budget";
+    default: return "unknown status";
+  }
+}
+
+const char* amg_last_error(void) { return amg::g_last_error.c_str(); }
+
+int32_t amg_setup(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* w, const double* d,
+                  const amg_params* params, void* stream, amg_hier** out) {
+  if (!out) { amg::set_last_error("null output handle"); return AMG_ERR_ARG; }
+  *out = nullptr;
+  amg_params p;
+  if (params) p = *params; else amg_params_default(&p);
+  std::string msg;
+  int32_t st = amg::validate_params(p, msg);
+  if (st != AMG_OK) { amg::set_last_error(msg); return st; }
+  st = amg::validate_graph(n, row_ptr, col, w, d, msg);
+  if (st != AMG_OK) { amg::set_last_error(msg); return st; }
+  AMG_TRY(check_device());
+  amg_hier* h = new amg_hier();
+  h->p = p;
+  h->mixed = p.precision == AMG_MIXED;
+  (void)hipGetDevice(&h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = amg::build_hierarchy(h, n, row_ptr, col, w, d, s);
+  if (st == AMG_OK) st = amg::prepare_solve(h, s);
+  if (st != AMG_OK) {
+    amg_free(h);
+    return st;
+  }
+  *out = h;
+  return AMG_OK;
+}
+
+void amg_free(amg_hier* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  amg::destroy_graphs(h);
+  if (h->graph_stream) (void)hipStreamDestroy(h->graph_stream);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->host_scal) (void)hipHostFree(h->host_scal);
+  delete h;
+}
+
+int32_t amg_describe(const amg_hier* h, amg_hier_desc* out) {
+  if (!h || !out) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
+  *out = h->desc;
+  return AMG_OK;
+}
+
+int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info) {
+  if (!h || !f || !u) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
+  return amg::solve(h, f, u, static_cast<hipStream_t>(stream), info);
+}
+
+int32_t amg_level_export(const amg_hier* h, int32_t level, int32_t* row_ptr, int32_t* col, double* W, double* d,
+                         double* D, int32_t* agg) {
+  AMG_TRY(check_level(h, level, true));
+  const amg::Level& lv = h->lv[level];
+  AMG_HIP(hipDeviceSynchronize());
+  if (row_ptr) AMG_HIP(hipMemcpy(row_ptr, lv.row_ptr, sizeof(int32_t) * (lv.n + 1), hipMemcpyDeviceToHost));
+  if (col && lv.nnz) AMG_HIP(hipMemcpy(col, lv.col, sizeof(int32_t) * lv.nnz, hipMemcpyDeviceToHost));
+  if (W && lv.nnz) AMG_HIP(hipMemcpy(W, lv.W, sizeof(double) * lv.nnz, hipMemcpyDeviceToHost));
+  if (d) AMG_HIP(hipMemcpy(d, lv.d, sizeof(double) * lv.n, hipMemcpyDeviceToHost));
+  if (D) AMG_HIP(hipMemcpy(D, lv.D, sizeof(double) * lv.n, hipMemcpyDeviceToHost));
+  if (agg && level < h->L) AMG_HIP(hipMemcpy(agg, lv.agg, sizeof(int32_t) * lv.n, hipMemcpyDeviceToHost));
+  return AMG_OK;
+}
+
+int32_t amg_apply_smoother(amg_hier* h, int32_t level, const double* r, double* y, void* stream) {
+  AMG_TRY(check_level(h, level, false));
+  AMG_TRY(check_fp64_steps(h));
+  if (!r || !y) return AMG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  AMG_TRY(amg::step_smoother(h, level, r, y, s));
+  return sync_status(s);
+}
+
+int32_t amg_apply_residual(amg_hier* h, int32_t level, const double* f, const double* x, double* s_out,
+                           void* stream) {
+  AMG_TRY(check_level(h, level, false));
+  AMG_TRY(check_fp64_steps(h));
+  if (!f || !x || !s_out) return AMG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  AMG_TRY(amg::step_residual(h, level, f, x, s_out, s));
+  return sync_status(s);
+}
+
+int32_t amg_apply_restrict(amg_hier* h, int32_t level, const double* sv, double* b, void* stream) {
+  AMG_TRY(check_level(h, level, false));
+  AMG_TRY(check_fp64_steps(h));
+  if (!sv || !b) return AMG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  AMG_TRY(amg::step_restrict(h, level, sv, b, s));
+  return sync_status(s);
+}
+
+int32_t amg_apply_prolong(amg_hier* h, int32_t level, const double* e, double* x, void* stream) {
+  AMG_TRY(check_level(h, level, false));
+  AMG_TRY(check_fp64_steps(h));
+  if (!e || !x) return AMG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  AMG_TRY(amg::step_prolong(h, level, e, x, s));
+  return sync_status(s);
+}
+
+int32_t amg_apply_coarse(amg_hier* h, const double* b, double* x, void* stream) {
+  if (!h || !b || !x) return AMG_ERR_ARG;
+  AMG_TRY(check_fp64_steps(h));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  AMG_TRY(amg::step_coarse(h, b, x, s));
+  return sync_status(s);
+}
+
+int32_t amg_apply_cycle(amg_hier* h, const double* r, double* z, void* stream) {
+  if (!h || !r || !z) return AMG_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  AMG_TRY(amg::step_cycle(h, r, z, s));
+  return sync_status(s);
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Device helpers: wavefront (64-lane) reductions and scans, deterministic
+// block reductions, and the XCD-aware block remap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace amg {
+
+// Sum over the 64 lanes of a wavefront; the result is valid in every lane.
+// The shuffle tree is fixed, so the result is deterministic.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    T o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// Block-wide sum of K values per thread (blockDim.x a multiple of 64, at most
+// 1024).  Returns the totals in thread 0; `red` is LDS scratch of 16*K doubles.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[wid * K + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = red[k];
+      for (int w = 1; w < nw; ++w) s += red[w * K + k];
+      v[k] = s;
+    }
+  }
+}
+
+// Up to 8 destination slots of a reduction in the hierarchy's scalar area.
+struct Slots {
+  int s[8];
+};
+
+// Deterministic grid reduction of K doubles: every block deposits its partial
+// sums; the last block to arrive adds the partials of all blocks in a fixed
+// order, writes scal[slots.s[k]] (k < K) and rearms the counter.  `partials`
+// holds gridDim.x * K doubles; `counter` must be zero before the launch.  The
+// result does not depend on which block arrives last.
+template <int K>
+__device__ __forceinline__ void grid_sum_finish(double (&v)[K], double* partials, unsigned* counter,
+                                                double* scal, Slots slots) {
+  __shared__ double red[16 * 8];
+  __shared__ bool last;
+  block_sum<K>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) partials[blockIdx.x * K + k] = v[k];
+    __threadfence();
+    unsigned t = atomicAdd(counter, 1u);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += partials[b * K + k];
+  }
+  __syncthreads();
+  block_sum<K>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) scal[slots.s[k]] = acc[k];
+    *counter = 0u;
+  }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X.  This
+// maps the hardware block id to a logical tile id such that every XCD works
+// on one contiguous range of tiles (better reuse of its private L2).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int x = bid & 7, k = bid >> 3;
+  const int start = x * q + (x < r ? x : r);
+  return start + k;
+}
+
+}  // namespace amg

@@ -1,0 +1,87 @@
+// The hierarchy object behind the opaque amg_hier handle, and the interfaces
+// between the setup, solve and API translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+struct amg_hier {
+  amg_params p{};
+  int device = 0;
+  bool mixed = false;
+  std::vector<amg::Level> lv;  // finest first; lv.back() is the coarsest
+  int L = 0;                   // index of the coarsest level
+  // coarsest level: dense Cholesky factor (row-major, lower triangle used)
+  double* chol = nullptr;
+  int32_t nL = 0;
+
+  // Solve workspace.  `vt` buffers hold the cycle's vector type (double, or
+  // float in mixed precision); per level: A, B (smoother recurrence), S
+  // (residual); rhs/sol of the level's inner solve; Z[k], Q[k] directions.
+  struct Work {
+    void* A = nullptr;
+    void* B = nullptr;
+    void* S = nullptr;
+    void* rhs = nullptr;
+    void* sol = nullptr;
+    void* Z[8] = {};
+    void* Q[8] = {};
+  };
+  std::vector<Work> ws;
+  // outer flexible CG (always FP64, finest level)
+  double* r = nullptr;
+  void* z = nullptr;  // cycle output (cycle vector type)
+  double* P[8] = {};
+  double* Qo[8] = {};
+  double* tmp = nullptr;
+
+  double* scal = nullptr;       // device scalar area (see solve.hip for the slots)
+  double* partials = nullptr;   // grid-reduction partial sums
+  unsigned* counter = nullptr;  // grid-reduction arrival counter
+  double* host_scal = nullptr;  // pinned host mirror of a few scalars
+  int max_blocks = 0;
+
+  // replayable outer iterations (one per position in the restart window)
+  bool graphs_ready = false;
+  hipGraphExec_t iter_exec[8] = {};
+  hipStream_t graph_stream = nullptr;  // stream the graphs were captured on
+  const void* graph_u = nullptr;       // solution pointer baked into the graphs
+
+  amg_hier_desc desc{};
+  std::vector<void*> allocs;
+  std::vector<void*> tail_allocs;
+};
+
+namespace amg {
+
+int32_t validate_params(const amg_params& p, std::string& msg);
+int32_t validate_graph(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
+                       const double* d, std::string& msg);
+
+// Device allocation owned by the hierarchy (freed by amg_free).
+int32_t dalloc(amg_hier* h, void** p, size_t bytes);
+template <typename T>
+int32_t dalloc(amg_hier* h, T** p, size_t count) {
+  return dalloc(h, reinterpret_cast<void**>(p), count * sizeof(T) + 16);
+}
+
+int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const int32_t* col,
+                        const double* w, const double* d, hipStream_t s);
+int32_t prepare_solve(amg_hier* h, hipStream_t s);
+void destroy_graphs(amg_hier* h);
+
+// single steps (FP64 device vectors at the boundary)
+int32_t step_smoother(amg_hier* h, int l, const double* r, double* y, hipStream_t s);
+int32_t step_residual(amg_hier* h, int l, const double* f, const double* x, double* out, hipStream_t s);
+int32_t step_restrict(amg_hier* h, int l, const double* sv, double* b, hipStream_t s);
+int32_t step_prolong(amg_hier* h, int l, const double* e, double* x, hipStream_t s);
+int32_t step_coarse(amg_hier* h, const double* b, double* x, hipStream_t s);
+int32_t step_cycle(amg_hier* h, const double* r, double* z, hipStream_t s);
+
+int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info);
+
+}  // namespace amg

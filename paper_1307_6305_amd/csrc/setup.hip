@@ -1,0 +1,812 @@
+// Hierarchy construction on the device.
+//
+// Per level (Sections 2-4 of the paper): P matching passes, each on the
+// quotient graph of the previous pass; the Galerkin operator of every pass as a
+// per-coarse-row sort and reduce of the (agg_i, agg_j) pairs of the fine
+// entries; the composite aggregate map and its member lists (restriction =
+// segmented sum, prolongation = gather, P never stored); lambda1 = ||A||_inf;
+// and finally the dense Cholesky factor of the coarsest matrix.
+//
+// Bit-exactness contract (matching and coarse operators): every quantity that
+// decides the matching -- D_i, the edge strengths, the coarse weights -- is
+// computed with correctly rounded binary64 operations in a fixed order (row
+// sums left to right from d_i; strength (w*w)/(D_i*D_j) taken from the entry
+// of row min(i, j); coarse sums in increasing fine row, then entry order).
+// This file is compiled with -ffp-contract=off so that no multiply-add is
+// fused.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "device_util.h"
+#include "hier.h"
+
+namespace amg {
+namespace {
+
+constexpr int TPB = 256;
+inline int nblk(int64_t n, int tpb = TPB) { return (int)std::max<int64_t>(1, (n + tpb - 1) / tpb); }
+
+// ------------------------------------------------------------------ temporaries
+struct Temps {
+  std::vector<void*> ptrs;
+  ~Temps() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  int32_t get(T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T) + 16);
+    if (e != hipSuccess) {
+      set_last_error(std::string("hipMalloc (setup temporary): ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
+    }
+    ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return AMG_OK;
+  }
+};
+
+// ------------------------------------------------------------------ generic kernels
+__global__ void k_iota(int n, int* a) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = i;
+}
+
+template <typename T>
+__global__ void k_fill(size_t n, T* a, T v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// out_i = start_i + W[rp_i] + W[rp_i + 1] + ...  (left to right)
+__global__ void k_row_sums(int n, const int* __restrict__ rp, const double* __restrict__ W,
+                           const double* __restrict__ start, double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = start[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) acc += W[k];
+  out[i] = acc;
+}
+
+// lambda1 = max_i (D_i + sum_j W_ij); the bits of positive doubles order like
+// unsigned integers, so the maximum is an integer atomic max.
+__global__ void k_rowabs_max(int n, const int* __restrict__ rp, const double* __restrict__ W,
+                             const double* __restrict__ D, unsigned long long* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    v = D[i];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) v += W[k];
+  }
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+
+// Exclusive scan of tiles of 2048 values: in[i] for i < n_in, 0 beyond;
+// writes out[i] for i < n_out and each tile's total.
+__global__ void k_scan_tile(const int* __restrict__ in, int n_in, int* __restrict__ out, int n_out,
+                            int* __restrict__ tile_sums) {
+  __shared__ int wsum[TPB / 64];
+  const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int t = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    v[q] = (base + q < n_in) ? in[base + q] : 0;
+    t += v[q];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int incl = wave_incl_scan(t);
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int woff = 0;
+  for (int w = 0; w < wid; ++w) woff += wsum[w];
+  int run = woff + incl - t;
+#pragma unroll
+  for (int q = 0; q < SCAN_ITEMS; ++q) {
+    if (base + q < n_out) out[base + q] = run;
+    run += v[q];
+  }
+  if (threadIdx.x == TPB - 1) tile_sums[blockIdx.x] = woff + incl;
+}
+
+__global__ void k_scan_add(int* out, int n, const int* __restrict__ tile_off) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += tile_off[i / SCAN_TILE];
+}
+
+// out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.
+int32_t scan_excl(Temps& T, const int* in, int n, int* out, hipStream_t s) {
+  const int n_out = n + 1;
+  const int tiles = (n_out + SCAN_TILE - 1) / SCAN_TILE;
+  int* sums = nullptr;
+  AMG_TRY(T.get(&sums, tiles + 1));
+  hipLaunchKernelGGL(k_scan_tile, dim3(tiles), dim3(TPB), 0, s, in, n, out, n_out, sums);
+  AMG_HIP(hipGetLastError());
+  if (tiles > 1) {
+    int* off = nullptr;
+    AMG_TRY(T.get(&off, tiles + 1));
+    AMG_TRY(scan_excl(T, sums, tiles, off, s));
+    hipLaunchKernelGGL(k_scan_add, dim3(nblk(n_out)), dim3(TPB), 0, s, out, n_out, off);
+    AMG_HIP(hipGetLastError());
+  }
+  return AMG_OK;
+}
+
+int32_t read_int(const int* dptr, int* host, hipStream_t s) {
+  AMG_HIP(hipMemcpyAsync(host, dptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  return AMG_OK;
+}
+
+// ------------------------------------------------------------------ matching
+// Strength of every stored entry, taken from the entry of row min(i, j) and
+// mirrored to its partner so both endpoints see the same key.
+__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                           const double* __restrict__ W, const double* __restrict__ D, int raw,
+                           double* __restrict__ S) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double Di = D[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = col[k];
+    if (j < i) continue;
+    const double w = W[k];
+    double s;
+    if (raw) {
+      s = w;
+    } else {
+      const double ww = w * w;
+      const double dd = Di * D[j];
+      s = ww / dd;
+    }
+    S[k] = s;
+    int lo = rp[j], hi = rp[j + 1];
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (col[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    S[lo] = s;
+  }
+}
+
+// Edge order: (-s, min endpoint, max endpoint) ascending.  True if edge 1
+// comes first.
+__device__ __forceinline__ bool edge_first(double s1, int a1, int b1, double s2, int a2, int b2) {
+  if (s1 != s2) return s1 > s2;
+  if (a1 != a2) return a1 < a2;
+  return b1 < b2;
+}
+
+// mate[v]: -1 free, -2 finished single, >= 0 partner.
+__device__ __forceinline__ int best_free_neighbour(int v, const int* __restrict__ rp, const int* __restrict__ col,
+                                                   const double* __restrict__ S, const int* mate) {
+  int best = -1, ba = 0, bb = 0;
+  double bs = 0.0;
+  for (int k = rp[v]; k < rp[v + 1]; ++k) {
+    const int u = col[k];
+    if (mate[u] != -1) continue;
+    const double s = S[k];
+    const int a = u < v ? u : v, b = u < v ? v : u;
+    if (best < 0 || edge_first(s, a, b, bs, ba, bb)) {
+      best = u; bs = s; ba = a; bb = b;
+    }
+  }
+  return best;
+}
+
+__global__ void k_match_propose(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                                const double* __restrict__ S, const int* __restrict__ mate,
+                                int* __restrict__ cand, int* cnt, int slot) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int proposed = 0;
+  if (v < n && mate[v] == -1) {
+    const int b = best_free_neighbour(v, rp, col, S, mate);
+    cand[v] = b >= 0 ? b : -2;
+    proposed = b >= 0;
+  }
+  proposed = wave_sum(proposed);
+  if ((threadIdx.x & 63) == 0 && proposed) atomicAdd(&cnt[slot], proposed);
+}
+
+__global__ void k_match_accept(int n, int* __restrict__ mate, const int* __restrict__ cand, int* cnt,
+                               int clear_slot) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) cnt[clear_slot] = 0;
+  if (v >= n || mate[v] != -1) return;
+  const int u = cand[v];
+  if (u == -2) mate[v] = -2;
+  else if (cand[u] == v) mate[v] = u;
+}
+
+// Whole matching in one workgroup (small graphs): rounds separated by
+// workgroup barriers; stops after a round without proposals.
+__global__ void __launch_bounds__(1024) k_match_small(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ col,
+                                                      const double* __restrict__ S, int* mate,
+                                                      int* cand, int* rounds_out) {
+  __shared__ int act[2];
+  if (threadIdx.x == 0) { act[0] = 0; act[1] = 0; }
+  __syncthreads();
+  int round = 0;
+  for (;; ++round) {
+    const int slot = round & 1;
+    int c = 0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      if (mate[v] != -1) continue;
+      const int b = best_free_neighbour(v, rp, col, S, mate);
+      cand[v] = b >= 0 ? b : -2;
+      c += b >= 0;
+    }
+    c = wave_sum(c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&act[slot], c);
+    __syncthreads();
+    const int a = act[slot];
+    if (threadIdx.x == 0) act[slot ^ 1] = 0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) {
+      if (mate[v] != -1) continue;
+      const int u = cand[v];
+      if (u == -2) mate[v] = -2;
+      else if (cand[u] == v) mate[v] = u;
+    }
+    __syncthreads();
+    if (a == 0) break;
+  }
+  if (threadIdx.x == 0) *rounds_out = round + 1;
+}
+
+// ------------------------------------------------------------------ coarse numbering
+__global__ void k_rep_flags(int n, const int* __restrict__ mate, int* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = mate[i];
+  flag[i] = (m < 0 || i < m) ? 1 : 0;
+}
+
+__global__ void k_pair_ids(int n, const int* __restrict__ mate, const int* __restrict__ pos,
+                           int* __restrict__ ids, int* __restrict__ rep) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = mate[i];
+  const int r = (m >= 0 && m < i) ? m : i;
+  ids[i] = pos[r];
+  if (r == i) rep[pos[i]] = i;
+}
+
+// ------------------------------------------------------------------ Galerkin (pairs)
+__device__ __forceinline__ int partner(const int* mate, int a) {
+  const int b = mate[a];
+  return b >= 0 ? b : -1;
+}
+
+__global__ void k_gal_len(int nc, const int* __restrict__ rep, const int* __restrict__ mate,
+                          const int* __restrict__ rp, int* __restrict__ len) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int a = rep[I], b = partner(mate, a);
+  len[I] = (rp[a + 1] - rp[a]) + (b >= 0 ? rp[b + 1] - rp[b] : 0);
+}
+
+// For coarse row I = {a, b} (a < b): the pairs (J = agg(j), w) of rows a then b
+// with J != I, stably sorted by J (insertion sort: equal keys keep the fine
+// order), and the number of distinct J.
+__global__ void k_gal_sort(int nc, const int* __restrict__ rep, const int* __restrict__ mate,
+                           const int* __restrict__ rp, const int* __restrict__ col,
+                           const double* __restrict__ W, const int* __restrict__ ids,
+                           const int* __restrict__ toff, int* __restrict__ tJ, double* __restrict__ tW,
+                           int* __restrict__ tcnt, int* __restrict__ ucnt) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int a = rep[I], b = partner(mate, a);
+  const int o = toff[I];
+  int cnt = 0;
+  for (int t = 0; t < 2; ++t) {
+    const int row = t == 0 ? a : b;
+    if (row < 0) break;
+    for (int k = rp[row]; k < rp[row + 1]; ++k) {
+      const int J = ids[col[k]];
+      if (J == I) continue;
+      const double w = W[k];
+      int p = cnt;
+      while (p > 0 && tJ[o + p - 1] > J) {
+        tJ[o + p] = tJ[o + p - 1];
+        tW[o + p] = tW[o + p - 1];
+        --p;
+      }
+      tJ[o + p] = J;
+      tW[o + p] = w;
+      ++cnt;
+    }
+  }
+  int u = 0;
+  for (int q = 0; q < cnt; ++q) u += (q == 0 || tJ[o + q] != tJ[o + q - 1]);
+  tcnt[I] = cnt;
+  ucnt[I] = u;
+}
+
+// Sum every run of equal J left to right; coarse d_H = d_a (+ d_b).
+__global__ void k_gal_reduce(int nc, const int* __restrict__ toff, const int* __restrict__ tcnt,
+                             const int* __restrict__ tJ, const double* __restrict__ tW,
+                             const int* __restrict__ rpH, int* __restrict__ colH, double* __restrict__ WH,
+                             const int* __restrict__ rep, const int* __restrict__ mate,
+                             const double* __restrict__ d, double* __restrict__ dH) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int o = toff[I], cnt = tcnt[I];
+  int out = rpH[I] - 1;
+  int lastJ = -1;
+  double acc = 0.0;
+  for (int q = 0; q < cnt; ++q) {
+    const int J = tJ[o + q];
+    if (J != lastJ) {
+      if (out >= rpH[I]) WH[out] = acc;
+      ++out;
+      colH[out] = J;
+      acc = tW[o + q];
+      lastJ = J;
+    } else {
+      acc += tW[o + q];
+    }
+  }
+  if (cnt > 0) WH[out] = acc;
+  const int a = rep[I], b = partner(mate, a);
+  double dd = d[a];
+  if (b >= 0) dd += d[b];
+  dH[I] = dd;
+}
+
+__global__ void k_compose(int n, int* __restrict__ agg, const int* __restrict__ ids) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) agg[i] = ids[agg[i]];
+}
+
+// ------------------------------------------------------------------ member lists
+__global__ void k_count(int n, const int* __restrict__ agg, int* cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[agg[i]], 1);
+}
+
+__global__ void k_scatter_members(int n, const int* __restrict__ agg, const int* __restrict__ off,
+                                  int* cursor, int* __restrict__ members) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = agg[i];
+  members[off[a] + atomicAdd(&cursor[a], 1)] = i;
+}
+
+// Members of each aggregate in increasing vertex order (deterministic).
+__global__ void k_sort_members(int nc, const int* __restrict__ off, int* __restrict__ members) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int o = off[I], e = off[I + 1];
+  for (int k = o + 1; k < e; ++k) {
+    const int v = members[k];
+    int p = k;
+    while (p > o && members[p - 1] > v) {
+      members[p] = members[p - 1];
+      --p;
+    }
+    members[p] = v;
+  }
+}
+
+// ------------------------------------------------------------------ sliced ELL
+__global__ void k_sell_width(int nrows_pad, int n, const int* __restrict__ rp, int* __restrict__ w) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  int deg = (r < n) ? rp[r + 1] - rp[r] : 0;
+  deg = wave_max(deg);
+  if (r < nrows_pad && (threadIdx.x & 63) == 0) w[r >> 6] = deg;
+}
+
+__global__ void k_sell_len(int ns, const int* __restrict__ w, int* __restrict__ len) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < ns) len[s] = w[s] * kWave;
+}
+
+__global__ void k_sell_fill(int nrows_pad, int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const double* __restrict__ W, const int* __restrict__ off,
+                            const int* __restrict__ width, int* __restrict__ scol, double* __restrict__ sval,
+                            float* __restrict__ svalf) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows_pad) return;
+  const int s = r >> 6, lane = r & 63;
+  const int base = off[s] + lane, wd = width[s];
+  const int b = r < n ? rp[r] : 0;
+  const int deg = r < n ? rp[r + 1] - b : 0;
+  const int self = r < n ? r : 0;
+  for (int k = 0; k < wd; ++k) {
+    const int idx = base + k * kWave;
+    int c = self;
+    double v = 0.0;
+    if (k < deg) { c = col[b + k]; v = W[b + k]; }
+    scol[idx] = c;
+    sval[idx] = v;
+    if (svalf) svalf[idx] = (float)v;
+  }
+}
+
+__global__ void k_to_float(int n, const double* __restrict__ a, float* __restrict__ b) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// ------------------------------------------------------------------ coarsest level
+__global__ void k_dense(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                        const double* __restrict__ W, const double* __restrict__ D, double* __restrict__ A) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  A[(size_t)i * n + i] = D[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) A[(size_t)i * n + col[k]] = -W[k];
+}
+
+// Right-looking Cholesky A = L L^T in one workgroup (row-major, lower part);
+// the strict upper triangle is zeroed.  status = 1 on a non-positive pivot.
+__global__ void __launch_bounds__(1024) k_chol(int n, double* A, int* status) {
+  __shared__ double piv;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double akk = A[(size_t)k * n + k];
+      if (!(akk > 0.0) || !isfinite(akk)) bad = 1;
+      piv = sqrt(akk);
+      A[(size_t)k * n + k] = piv;
+    }
+    __syncthreads();
+    if (bad) break;
+    const double p = piv;
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[(size_t)i * n + k] /= p;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+      const int i = k + 1 + t / m, j = k + 1 + t % m;
+      if (j <= i) A[(size_t)i * n + j] -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t % n;
+    if (j > i) A[t] = 0.0;
+  }
+  if (threadIdx.x == 0) *status = bad;
+}
+
+// ------------------------------------------------------------------ host helpers
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+struct Graph {  // a pass graph on the device (not owned)
+  int n = 0;
+  int nnz = 0;
+  int* rp = nullptr;
+  int* col = nullptr;
+  double* W = nullptr;
+  double* d = nullptr;
+  double* D = nullptr;
+};
+
+// One matching pass on g: mate[] (device) and the number of rounds.
+int32_t match_pass(Temps& T, const Graph& g, int raw, int* mate, int* rounds, hipStream_t s) {
+  double* S = nullptr;
+  int* cand = nullptr;
+  AMG_TRY(T.get(&S, std::max(g.nnz, 1)));
+  AMG_TRY(T.get(&cand, g.n));
+  hipLaunchKernelGGL(k_strength, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, g.rp, g.col, g.W, g.D, raw, S);
+  hipLaunchKernelGGL(k_fill<int>, dim3(nblk(g.n)), dim3(TPB), 0, s, (size_t)g.n, mate, -1);
+  AMG_HIP(hipGetLastError());
+  constexpr int kSmall = 8192;
+  if (g.n <= kSmall) {
+    int* r = nullptr;
+    AMG_TRY(T.get(&r, 1));
+    hipLaunchKernelGGL(k_match_small, dim3(1), dim3(1024), 0, s, g.n, g.rp, g.col, S, mate, cand, r);
+    AMG_HIP(hipGetLastError());
+    AMG_TRY(read_int(r, rounds, s));
+    return AMG_OK;
+  }
+  constexpr int kRing = 64, kBatch = 16;
+  int* cnt = nullptr;
+  AMG_TRY(T.get(&cnt, kRing));
+  hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(kRing), 0, s, (size_t)kRing, cnt, 0);
+  int round = 0;
+  for (;;) {
+    for (int b = 0; b < kBatch; ++b, ++round) {
+      hipLaunchKernelGGL(k_match_propose, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, g.rp, g.col, S, mate,
+                         cand, cnt, round % kRing);
+      hipLaunchKernelGGL(k_match_accept, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, mate, cand, cnt,
+                         (round + 1) % kRing);
+    }
+    AMG_HIP(hipGetLastError());
+    int last = 0;
+    AMG_TRY(read_int(cnt + (round - 1) % kRing, &last, s));
+    if (last == 0) break;
+    if (round > 4 * g.n + 64) {
+      set_last_error("matching did not terminate");
+      return AMG_ERR_DEVICE;
+    }
+  }
+  *rounds = round;
+  return AMG_OK;
+}
+
+// Coarse numbering and Galerkin operator of one pass.  Allocates the coarse
+// graph from `alloc_owned` (hierarchy-owned) or from T.
+int32_t galerkin_pass(amg_hier* h, Temps& T, const Graph& g, const int* mate, bool owned, Graph* out,
+                      int** ids_out, double* t_agg_ms, double* t_gal_ms, hipStream_t s) {
+  auto t0 = clk::now();
+  int *flag, *pos, *ids, *rep;
+  AMG_TRY(T.get(&flag, g.n));
+  AMG_TRY(T.get(&pos, g.n + 1));
+  AMG_TRY(T.get(&ids, g.n));
+  hipLaunchKernelGGL(k_rep_flags, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, mate, flag);
+  AMG_TRY(scan_excl(T, flag, g.n, pos, s));
+  int nc = 0;
+  AMG_TRY(read_int(pos + g.n, &nc, s));
+  AMG_TRY(T.get(&rep, nc));
+  hipLaunchKernelGGL(k_pair_ids, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, mate, pos, ids, rep);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+  *t_agg_ms += ms_since(t0);
+
+  auto t1 = clk::now();
+  int *len, *toff, *tJ, *tcnt, *ucnt;
+  double* tW;
+  AMG_TRY(T.get(&len, nc));
+  AMG_TRY(T.get(&toff, nc + 1));
+  AMG_TRY(T.get(&tJ, std::max(g.nnz, 1)));
+  AMG_TRY(T.get(&tW, std::max(g.nnz, 1)));
+  AMG_TRY(T.get(&tcnt, nc));
+  AMG_TRY(T.get(&ucnt, nc));
+  hipLaunchKernelGGL(k_gal_len, dim3(nblk(nc)), dim3(TPB), 0, s, nc, rep, mate, g.rp, len);
+  AMG_TRY(scan_excl(T, len, nc, toff, s));
+  hipLaunchKernelGGL(k_gal_sort, dim3(nblk(nc)), dim3(TPB), 0, s, nc, rep, mate, g.rp, g.col, g.W, ids,
+                     toff, tJ, tW, tcnt, ucnt);
+  Graph c;
+  c.n = nc;
+  if (owned) {
+    AMG_TRY(dalloc(h, &c.rp, nc + 1));
+  } else {
+    AMG_TRY(T.get(&c.rp, nc + 1));
+  }
+  AMG_TRY(scan_excl(T, ucnt, nc, c.rp, s));
+  AMG_TRY(read_int(c.rp + nc, &c.nnz, s));
+  if (owned) {
+    AMG_TRY(dalloc(h, &c.col, std::max(c.nnz, 1)));
+    AMG_TRY(dalloc(h, &c.W, std::max(c.nnz, 1)));
+    AMG_TRY(dalloc(h, &c.d, nc));
+    AMG_TRY(dalloc(h, &c.D, nc));
+  } else {
+    AMG_TRY(T.get(&c.col, std::max(c.nnz, 1)));
+    AMG_TRY(T.get(&c.W, std::max(c.nnz, 1)));
+    AMG_TRY(T.get(&c.d, nc));
+    AMG_TRY(T.get(&c.D, nc));
+  }
+  hipLaunchKernelGGL(k_gal_reduce, dim3(nblk(nc)), dim3(TPB), 0, s, nc, toff, tcnt, tJ, tW, c.rp, c.col, c.W,
+                     rep, mate, g.d, c.d);
+  hipLaunchKernelGGL(k_row_sums, dim3(nblk(nc)), dim3(TPB), 0, s, nc, c.rp, c.W, c.d, c.D);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+  *t_gal_ms += ms_since(t1);
+  *out = c;
+  *ids_out = ids;
+  return AMG_OK;
+}
+
+int32_t build_members(amg_hier* h, Temps& T, Level& lv, int nc, hipStream_t s) {
+  int *cnt, *cursor;
+  AMG_TRY(T.get(&cnt, nc));
+  AMG_TRY(T.get(&cursor, nc));
+  AMG_TRY(dalloc(h, &lv.members, lv.n));
+  AMG_TRY(dalloc(h, &lv.member_off, nc + 1));
+  hipLaunchKernelGGL(k_fill<int>, dim3(nblk(nc)), dim3(TPB), 0, s, (size_t)nc, cnt, 0);
+  hipLaunchKernelGGL(k_fill<int>, dim3(nblk(nc)), dim3(TPB), 0, s, (size_t)nc, cursor, 0);
+  hipLaunchKernelGGL(k_count, dim3(nblk(lv.n)), dim3(TPB), 0, s, lv.n, lv.agg, cnt);
+  AMG_TRY(scan_excl(T, cnt, nc, lv.member_off, s));
+  hipLaunchKernelGGL(k_scatter_members, dim3(nblk(lv.n)), dim3(TPB), 0, s, lv.n, lv.agg, lv.member_off, cursor,
+                     lv.members);
+  hipLaunchKernelGGL(k_sort_members, dim3(nblk(nc)), dim3(TPB), 0, s, nc, lv.member_off, lv.members);
+  AMG_HIP(hipGetLastError());
+  return AMG_OK;
+}
+
+int32_t build_sell(amg_hier* h, Temps& T, Level& lv, bool mixed, hipStream_t s) {
+  lv.nslices = (lv.n + kWave - 1) / kWave;
+  const int rows_pad = lv.nslices * kWave;
+  int* len = nullptr;
+  AMG_TRY(dalloc(h, &lv.sell_w, lv.nslices));
+  AMG_TRY(dalloc(h, &lv.sell_off, lv.nslices + 1));
+  AMG_TRY(T.get(&len, lv.nslices));
+  hipLaunchKernelGGL(k_sell_width, dim3(nblk(rows_pad)), dim3(TPB), 0, s, rows_pad, lv.n, lv.row_ptr, lv.sell_w);
+  hipLaunchKernelGGL(k_sell_len, dim3(nblk(lv.nslices)), dim3(TPB), 0, s, lv.nslices, lv.sell_w, len);
+  AMG_HIP(hipGetLastError());
+  // total entries in int64 to guard against overflow of the int32 offsets
+  std::vector<int> wh(lv.nslices);
+  AMG_HIP(hipMemcpyAsync(wh.data(), lv.sell_w, sizeof(int) * lv.nslices, hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  int64_t total = 0;
+  for (int x : wh) total += (int64_t)x * kWave;
+  if (total >= (int64_t)1 << 31) {
+    set_last_error("level too large for 32-bit sliced-ELL offsets");
+    return AMG_ERR_ARG;
+  }
+  lv.sell_entries = total;
+  AMG_TRY(scan_excl(T, len, lv.nslices, lv.sell_off, s));
+  AMG_TRY(dalloc(h, &lv.sell_col, std::max<int64_t>(total, 1)));
+  AMG_TRY(dalloc(h, &lv.sell_val, std::max<int64_t>(total, 1)));
+  if (mixed) {
+    AMG_TRY(dalloc(h, &lv.sell_valf, std::max<int64_t>(total, 1)));
+    AMG_TRY(dalloc(h, &lv.Df, lv.n));
+    hipLaunchKernelGGL(k_to_float, dim3(nblk(lv.n)), dim3(TPB), 0, s, lv.n, lv.D, lv.Df);
+  }
+  hipLaunchKernelGGL(k_sell_fill, dim3(nblk(rows_pad)), dim3(TPB), 0, s, rows_pad, lv.n, lv.row_ptr, lv.col,
+                     lv.W, lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_val, lv.sell_valf);
+  AMG_HIP(hipGetLastError());
+  return AMG_OK;
+}
+
+// Chebyshev coefficients of eta * q_m in t = (x - theta)/eta (best uniform
+// approximation to 1/x on [lambda1/ratio, lambda1]); stored divided by eta.
+void smoother_coefficients(Level& lv, int m, double ratio) {
+  const double l1 = lv.lambda1, l0 = l1 / ratio;
+  lv.theta = 0.5 * (l1 + l0);
+  lv.eta = 0.5 * (l1 - l0);
+  const double kappa = l1 / l0;
+  const double sk = std::sqrt(kappa);
+  const double dl = (sk - 1.0) / (sk + 1.0);
+  const double om = 1.0 - dl * dl;
+  std::vector<double> c(m + 1, 0.0);
+  if (m == 0) {
+    c[0] = 2.0 * dl * (1.0 + dl * dl) / (om * om);
+  } else {
+    c[0] = 2.0 * dl / om;
+    double pw = 1.0;
+    for (int k = 1; k <= m; ++k) {
+      pw *= -dl;
+      c[k] = (k < m) ? 4.0 * dl * pw / om : 4.0 * dl * pw / (om * om);
+    }
+  }
+  lv.coef.resize(m + 1);
+  for (int k = 0; k <= m; ++k) lv.coef[k] = c[k] / lv.eta;
+}
+
+}  // namespace
+
+int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
+                        const double* d, hipStream_t s) {
+  const amg_params& p = h->p;
+  auto t_setup = clk::now();
+  double t_agg = 0.0, t_gal = 0.0;
+  int total_rounds = 0;
+  Temps T;
+
+  Level l0;
+  l0.n = n;
+  l0.nnz = row_ptr[n];
+  AMG_TRY(dalloc(h, &l0.row_ptr, n + 1));
+  AMG_TRY(dalloc(h, &l0.col, std::max<int64_t>(l0.nnz, 1)));
+  AMG_TRY(dalloc(h, &l0.W, std::max<int64_t>(l0.nnz, 1)));
+  AMG_TRY(dalloc(h, &l0.d, n));
+  AMG_TRY(dalloc(h, &l0.D, n));
+  AMG_HIP(hipMemcpyAsync(l0.row_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+  if (l0.nnz > 0) {
+    AMG_HIP(hipMemcpyAsync(l0.col, col, sizeof(int32_t) * l0.nnz, hipMemcpyHostToDevice, s));
+    AMG_HIP(hipMemcpyAsync(l0.W, w, sizeof(double) * l0.nnz, hipMemcpyHostToDevice, s));
+  }
+  AMG_HIP(hipMemcpyAsync(l0.d, d, sizeof(double) * n, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_row_sums, dim3(nblk(n)), dim3(TPB), 0, s, n, l0.row_ptr, l0.W, l0.d, l0.D);
+  AMG_HIP(hipGetLastError());
+  h->lv.clear();
+  h->lv.push_back(l0);
+
+  const int passes = std::max(1, (int)std::lround(std::log2((double)p.agg_size)));
+  const int raw = p.match_key == AMG_KEY_RAW;
+  while (h->lv.back().n > p.coarse_max && (int)h->lv.size() < AMG_MAX_LEVELS) {
+    Level& cur = h->lv.back();
+    Graph g{cur.n, (int)cur.nnz, cur.row_ptr, cur.col, cur.W, cur.d, cur.D};
+    int* agg = nullptr;
+    AMG_TRY(dalloc(h, &agg, cur.n));
+    hipLaunchKernelGGL(k_iota, dim3(nblk(cur.n)), dim3(TPB), 0, s, cur.n, agg);
+    Temps TL;  // intermediate pass graphs of this level
+    for (int ps = 0; ps < passes; ++ps) {
+      auto ta = clk::now();
+      int* mate = nullptr;
+      AMG_TRY(TL.get(&mate, g.n));
+      int rounds = 0;
+      AMG_TRY(match_pass(TL, g, raw, mate, &rounds, s));
+      total_rounds += rounds;
+      t_agg += ms_since(ta);
+      Graph c;
+      int* ids = nullptr;
+      AMG_TRY(galerkin_pass(h, TL, g, mate, ps == passes - 1, &c, &ids, &t_agg, &t_gal, s));
+      hipLaunchKernelGGL(k_compose, dim3(nblk(cur.n)), dim3(TPB), 0, s, cur.n, agg, ids);
+      AMG_HIP(hipGetLastError());
+      g = c;
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+    if (g.n > p.stagnation * cur.n) break;  // stagnation: cur becomes the coarsest level
+    cur.agg = agg;
+    Level nl;
+    nl.n = g.n;
+    nl.nnz = g.nnz;
+    nl.row_ptr = g.rp;
+    nl.col = g.col;
+    nl.W = g.W;
+    nl.d = g.d;
+    nl.D = g.D;
+    AMG_TRY(build_members(h, T, cur, g.n, s));
+    h->lv.push_back(nl);
+  }
+  h->L = (int)h->lv.size() - 1;
+  Level& co = h->lv.back();
+  if (co.n > p.max_coarsest) {
+    set_last_error("coarsening stagnated at " + std::to_string(co.n) + " rows");
+    return AMG_ERR_COARSEN;
+  }
+  // lambda1 and the smoother of every level but the coarsest
+  unsigned long long* lmax = nullptr;
+  AMG_TRY(T.get(&lmax, AMG_MAX_LEVELS));
+  hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, (size_t)AMG_MAX_LEVELS, lmax, 0ull);
+  for (int l = 0; l <= h->L; ++l) {
+    Level& lv = h->lv[l];
+    hipLaunchKernelGGL(k_rowabs_max, dim3(nblk(lv.n)), dim3(TPB), 0, s, lv.n, lv.row_ptr, lv.W, lv.D, lmax + l);
+  }
+  AMG_HIP(hipGetLastError());
+  std::vector<unsigned long long> lh(AMG_MAX_LEVELS);
+  AMG_HIP(hipMemcpyAsync(lh.data(), lmax, sizeof(unsigned long long) * AMG_MAX_LEVELS, hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  for (int l = 0; l <= h->L; ++l) {
+    double v;
+    std::memcpy(&v, &lh[l], sizeof(double));
+    h->lv[l].lambda1 = v;
+    if (l < h->L) smoother_coefficients(h->lv[l], p.degree, p.lambda0_ratio);
+  }
+  // coarsest: dense matrix and its Cholesky factor
+  h->nL = co.n;
+  AMG_TRY(dalloc(h, &h->chol, (size_t)co.n * co.n));
+  hipLaunchKernelGGL(k_fill<double>, dim3(nblk((int64_t)co.n * co.n)), dim3(TPB), 0, s, (size_t)co.n * co.n,
+                     h->chol, 0.0);
+  hipLaunchKernelGGL(k_dense, dim3(nblk(co.n)), dim3(TPB), 0, s, co.n, co.row_ptr, co.col, co.W, co.D, h->chol);
+  int* st = nullptr;
+  AMG_TRY(T.get(&st, 1));
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, s, co.n, h->chol, st);
+  AMG_HIP(hipGetLastError());
+  int bad = 0;
+  AMG_TRY(read_int(st, &bad, s));
+  if (bad) {
+    set_last_error("coarsest matrix is not positive definite");
+    return AMG_ERR_SINGULAR;
+  }
+  // solve-phase layouts
+  for (int l = 0; l < h->L; ++l) AMG_TRY(build_sell(h, T, h->lv[l], h->mixed, s));
+  AMG_HIP(hipStreamSynchronize(s));
+
+  amg_hier_desc& ds = h->desc;
+  std::memset(&ds, 0, sizeof(ds));
+  ds.levels = (int)h->lv.size();
+  double gsum = 0.0, osum = 0.0;
+  for (int l = 0; l <= h->L; ++l) {
+    ds.n[l] = h->lv[l].n;
+    ds.nnz[l] = h->lv[l].nnz;
+    ds.lambda1[l] = h->lv[l].lambda1;
+    gsum += h->lv[l].n;
+    osum += (double)h->lv[l].nnz + h->lv[l].n;
+  }
+  ds.grid_complexity = gsum / h->lv[0].n;
+  ds.operator_complexity = osum / ((double)h->lv[0].nnz + h->lv[0].n);
+  ds.aggregation_ms = t_agg;
+  ds.galerkin_ms = t_gal;
+  ds.match_rounds = total_rounds;
+  ds.precision = p.precision;
+  ds.setup_ms = ms_since(t_setup);
+  return AMG_OK;
+}
+
+}  // namespace amg

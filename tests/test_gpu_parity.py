@@ -1,0 +1,227 @@
+"""GPU path (through the C ABI) against the CPU FP64 oracle.
+
+Bars: aggregates, coarse sparsity patterns and coarse values bit-exact; single
+kernels within 1e-12 relative; one k-cycle application within 1e-10 relative;
+outer FCG iteration counts within one and the true FP64 relative residual at
+most the tolerance."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def amg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1307_6305_amd as amg
+
+    amg.load_library()
+    return amg
+
+
+def _oracle_params(p):
+    return oracle.Params(degree=p.degree, agg_size=p.agg_size, coarse_max=p.coarse_max,
+                         lambda0_ratio=p.lambda0_ratio, inner_steps=p.inner_steps, restart=p.restart,
+                         tol=p.tol, max_iter=p.max_iter,
+                         match_key="raw" if p.match_key == 1 else "normalized",
+                         max_coarsest=p.max_coarsest, stagnation=p.stagnation)
+
+
+CASES = {
+    "grid64_agg4_m3": (lambda: inputs.grid2d(64), dict(degree=3, agg_size=4)),
+    "grid100x37_agg16_m5": (lambda: inputs.grid2d(100, 37), dict(degree=5, agg_size=16)),
+    "grid64_raw_agg4": (lambda: inputs.grid2d(64), dict(degree=3, agg_size=4, match_key=1)),
+    "tet3d_12_agg8_m4": (lambda: inputs.tet3d(12), dict(degree=4, agg_size=8)),
+    "rgg_6000_agg8_m4": (lambda: inputs.rgg(6000, seed=inputs.seed_for(4, 1)), dict(degree=4, agg_size=8)),
+    "random_weighted_agg4": (lambda: inputs.random_graph(700, 0.006, seed=5, weighted=True),
+                             dict(degree=4, agg_size=4, coarse_max=40)),
+    "grid130_agg4_m7_inner3": (lambda: inputs.grid2d(130), dict(degree=7, agg_size=4, inner_steps=3, restart=3)),
+}
+
+_cache = {}
+
+
+def _case(amg, name):
+    if name not in _cache:
+        make, kw = CASES[name]
+        g = make()
+        p = amg.amg_params_default(**kw)
+        h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+        ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(p))
+        _cache[name] = (g, p, h, ho)
+    return _cache[name]
+
+
+def _t(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
+
+
+def _rel(a, b):
+    a = a.cpu().numpy() if hasattr(a, "cpu") else a
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_bit_exact(amg, name):
+    g, p, h, ho = _case(amg, name)
+    desc = amg.amg_describe(h)
+    assert desc["n"] == [l.n for l in ho.levels]
+    for l, lo in enumerate(ho.levels):
+        ex = amg.amg_level_export(h, l)
+        assert np.array_equal(ex["row_ptr"], lo.row_ptr), l
+        assert np.array_equal(ex["col"], lo.col), l
+        assert np.array_equal(ex["W"], lo.W), l
+        assert np.array_equal(ex["d"], lo.d), l
+        assert np.array_equal(ex["D"], lo.D), l
+        if l < ho.L:
+            assert np.array_equal(ex["agg"], ho.aggs[l]), l
+        assert desc["lambda1"][l] == oracle.lambda_max_bound(lo)
+    assert desc["grid_complexity"] == pytest.approx(ho.grid_complexity(), rel=1e-14)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_single_steps(amg, name):
+    g, p, h, ho = _case(amg, name)
+    rng = np.random.default_rng(7)
+    for l in range(ho.L):
+        lo = ho.levels[l]
+        v = rng.standard_normal(lo.n)
+        x = rng.standard_normal(lo.n)
+        y = torch.zeros(lo.n, dtype=torch.float64, device="cuda")
+        amg.amg_apply_smoother(h, l, _t(v), y)
+        assert _rel(y, oracle.smooth(lo, ho.polys[l], v)) <= 1e-12, ("smoother", l)
+        s = torch.zeros_like(y)
+        amg.amg_apply_residual(h, l, _t(v), _t(x), s)
+        assert _rel(s, oracle.residual(lo, v, x)) <= 1e-13, ("residual", l)
+        nc = ho.levels[l + 1].n
+        b = torch.zeros(nc, dtype=torch.float64, device="cuda")
+        amg.amg_apply_restrict(h, l, _t(v), b)
+        assert _rel(b, oracle.restrict(ho.aggs[l], nc, v)) <= 1e-14, ("restrict", l)
+        e = rng.standard_normal(nc)
+        xx = _t(x)
+        amg.amg_apply_prolong(h, l, _t(e), xx)
+        assert _rel(xx, x + oracle.prolong(ho.aggs[l], e)) <= 1e-15, ("prolong", l)
+    nL = ho.levels[-1].n
+    bL = rng.standard_normal(nL)
+    xL = torch.zeros(nL, dtype=torch.float64, device="cuda")
+    amg.amg_apply_coarse(h, _t(bL), xL)
+    assert _rel(xL, oracle.coarse_solve(ho.chol, bL)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cycle_application(amg, name):
+    g, p, h, ho = _case(amg, name)
+    for seed in (1, 2):
+        r = inputs.rhs(g.n, seed)
+        z = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        amg.amg_apply_cycle(h, _t(r), z)
+        assert _rel(z, oracle.kcycle(ho, 0, r)) <= 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_matches_oracle(amg, name):
+    g, p, h, ho = _case(amg, name)
+    f = inputs.rhs(g.n, inputs.seed_for(1))
+    u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, _t(f), u)
+    res = oracle.fcg(ho, f)
+    assert info["status"] == 0 and res.converged
+    assert abs(info["iters"] - res.iters) <= 1, (info, res.iters)
+    assert info["rel_res_true"] <= p.tol * 1.05
+    uo = res.x
+    lo = ho.levels[0]
+    e = u.cpu().numpy() - uo
+    errA = np.sqrt(e @ oracle.apply_A(lo, e)) / np.sqrt(uo @ oracle.apply_A(lo, uo))
+    assert errA <= 1e-6
+
+
+def test_graph_replay_equals_eager(amg):
+    g = inputs.grid2d(96, 71)
+    f = _t(inputs.rhs(g.n, 3))
+    out = []
+    for use_graph in (0, 1, 1):
+        p = amg.amg_params_default(degree=4, agg_size=8, use_graph=use_graph)
+        h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+        u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        info = amg.amg_solve(h, f, u)
+        # a second solve on the same handle replays the recorded graphs
+        u2 = torch.zeros_like(u)
+        info2 = amg.amg_solve(h, f, u2)
+        assert info["iters"] == info2["iters"]
+        assert torch.equal(u, u2)
+        out.append((info["iters"], u.cpu().numpy()))
+        h.close()
+    assert out[0][0] == out[1][0] == out[2][0]
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[1][1], out[2][1])
+
+
+def test_nonzero_initial_guess_and_zero_rhs(amg):
+    g = inputs.grid2d(50)
+    p = amg.amg_params_default(degree=3, agg_size=4)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(p))
+    f = inputs.rhs(g.n, 11)
+    u0 = inputs.rhs(g.n, 12)
+    u = _t(u0)
+    info = amg.amg_solve(h, _t(f), u)
+    res = oracle.fcg(ho, f, u0)
+    assert abs(info["iters"] - res.iters) <= 1 and info["rel_res_true"] <= 1.05e-8
+    z = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, torch.zeros_like(z), z)
+    assert info["iters"] == 0 and info["status"] == 0 and float(z.abs().max()) == 0.0
+
+
+def test_single_level_hierarchy(amg):
+    g = inputs.grid2d(7, 9)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, amg.amg_params_default(degree=3))
+    assert amg.amg_describe(h)["levels"] == 1
+    f = inputs.rhs(g.n, 1)
+    u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, _t(f), u)
+    assert info["iters"] == 1 and info["rel_res_true"] <= 1e-12
+
+
+def test_stagnating_coarsening_uses_block_cholesky(amg):
+    """A star graph coarsens by one pair per pass: stagnation stops the
+    hierarchy and the coarsest level (> 64 rows) is solved by the workgroup
+    Cholesky path."""
+    n = 300
+    hub = np.zeros(n - 1, dtype=np.int64)
+    leaves = np.arange(1, n)
+    rp, col, w = inputs.csr_from_edges(n, hub, leaves)
+    d = np.zeros(n)
+    d[5] = 1.0
+    p = amg.amg_params_default(degree=3, agg_size=4, coarse_max=16)
+    h = amg.amg_setup(n, rp, col, w, d, p)
+    desc = amg.amg_describe(h)
+    ho = oracle.build_hierarchy(n, rp, col, w, d, _oracle_params(p))
+    assert desc["n"] == [l.n for l in ho.levels] and desc["n"][-1] > 64
+    b = np.random.default_rng(0).standard_normal(desc["n"][-1])
+    x = torch.zeros(desc["n"][-1], dtype=torch.float64, device="cuda")
+    amg.amg_apply_coarse(h, _t(b), x)
+    assert _rel(x, oracle.coarse_solve(ho.chol, b)) <= 1e-11
+    f = inputs.rhs(n, 2)
+    u = torch.zeros(n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, _t(f), u)
+    assert info["status"] == 0 and abs(info["iters"] - oracle.fcg(ho, f).iters) <= 1
+
+
+def test_determinism(amg):
+    g = inputs.tet3d(10)
+    p = amg.amg_params_default(degree=4, agg_size=8)
+    f = _t(inputs.rhs(g.n, 4, "normal"))
+    sols = []
+    for _ in range(2):
+        h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+        u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        amg.amg_solve(h, f, u)
+        sols.append(u.cpu().numpy())
+        h.close()
+    assert np.array_equal(sols[0], sols[1])
