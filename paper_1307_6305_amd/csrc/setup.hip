@@ -784,8 +784,9 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
     set_last_error("coarsest matrix is not positive definite");
     return AMG_ERR_SINGULAR;
   }
-  // solve-phase layouts
-  for (int l = 0; l < h->L; ++l) AMG_TRY(build_sell(h, T, h->lv[l], h->mixed, s));
+  // solve-phase layouts: every level that is smoothed, and always the finest
+  // level (outer-iteration products and residuals), even when it is the coarsest
+  for (int l = 0; l < std::max(h->L, 1); ++l) AMG_TRY(build_sell(h, T, h->lv[l], h->mixed, s));
   AMG_HIP(hipStreamSynchronize(s));
 
   amg_hier_desc& ds = h->desc;

@@ -571,6 +571,13 @@ void destroy_graphs(amg_hier* h) {
 }
 
 int32_t prepare_solve(amg_hier* h, hipStream_t s) {
+  for (int l = 0; l < std::max(h->L, 1); ++l) {
+    const Level& lv = h->lv[l];
+    if (!lv.sell_off || !lv.sell_w || !lv.sell_col || !lv.sell_val || !lv.D || (h->mixed && (!lv.sell_valf || !lv.Df))) {
+      set_last_error("level " + std::to_string(l) + " has no sliced-ELL form");
+      return AMG_ERR_DEVICE;
+    }
+  }
   const size_t vt = h->mixed ? sizeof(float) : sizeof(double);
   h->ws.assign(h->lv.size(), amg_hier::Work{});
   for (int l = 0; l <= h->L; ++l) {
