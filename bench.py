@@ -1,0 +1,241 @@
+"""Benchmark: solve throughput (DOF/s to a 1e-8 relative residual) of the
+MI355X solver on one GPU, with the roofline figure of its dominant kernel and
+the CPU oracle timed beside it.
+
+A step is one complete solve A u = f from u = 0 to the tolerance on a resident
+hierarchy (setup runs once before the warm-up and is reported separately).
+Default workload: 1024 x 1024 triangulated grid (1,048,576 unknowns), unit
+weights, d = 1 on the boundary, f uniform in [-1, 1], FP64, aggregates of 16
+(four matching passes), smoother degree 3, W(1,1) k-cycle, flexible CG.
+
+Output: one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import os
+
+# the CPU oracle leg is timed single-threaded
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import argparse
+import hashlib
+import json
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import inputs  # noqa: E402
+
+METRIC = "solve DOF/s to 1e-8 rel. residual + HBM GB/s; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (graph builder, rhs kind, seed config, params)
+    "grid2d-1024": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=3, agg_size=16)),
+    "grid2d-1024-m5": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=5, agg_size=16)),
+    "grid2d-1024-m7": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=7, agg_size=16)),
+    "grid2d-1024-agg4": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=3, agg_size=4)),
+    "grid2d-64": (lambda: inputs.grid2d(64), "uniform", 1, dict(degree=3, agg_size=4)),
+    "tet3d-128": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16)),
+    "tet3d-128-mixed": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16, precision=1)),
+}
+
+
+def kernel_source_hash() -> str:
+    """Hash of the solve kernels' source: stored traffic counters are only
+    reported while the kernel they were taken on is unchanged."""
+    h = hashlib.sha256()
+    for fn in ("solve.hip", "device_util.h"):
+        with open(os.path.join(ROOT, "paper_1307_6305_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str):
+    """FETCH_SIZE + WRITE_SIZE bytes per launch of the dominant kernel from the
+    committed counter summary, or None if absent or taken on other code."""
+    path = os.path.join(ROOT, "profiles", f"traffic_cheb_step_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+def cheb_step_bytes(n: int, nnz: int, mixed: bool) -> int:
+    """Algorithmic bytes of one interior Chebyshev step on a level: the matrix
+    once (column index + weight per stored entry) and each vector once per
+    touch: D, w_k, w_{k-1} read, y read and written, w_{k+1} written."""
+    if mixed:
+        return 8 * nnz + 4 * n + 4 * n + 4 * n + 8 * n + 4 * n
+    return 12 * nnz + 8 * n + 8 * n + 8 * n + 16 * n + 8 * n
+
+
+def run_cpu_baseline(g, f, params: dict, sample: str):
+    import oracle
+
+    op = oracle.Params(degree=params["degree"], agg_size=params["agg_size"])
+    t0 = time.perf_counter()
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, op)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = oracle.fcg(h, f)
+    t_solve = time.perf_counter() - t0
+    return {
+        "value": g.n / t_solve,
+        "unit": "DOF/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": sample,
+        "setup_s": round(t_setup, 3),
+        "solve_s": round(t_solve, 3),
+        "iters": res.iters,
+        "host_cpus": os.cpu_count(),
+    }, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grid2d-1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tail-rows", type=int, default=None,
+                    help="levels with at most this many rows run in the one-workgroup tail program")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1307_6305_amd as amg
+
+    amg.load_library()
+    dev = torch.device("cuda:0")
+    make, rhs_kind, cfg, pkw = WORKLOADS[args.workload]
+    g = make()
+    f_np = inputs.rhs(g.n, inputs.seed_for(cfg), rhs_kind)
+    pkw = dict(pkw)
+    if args.no_graph:
+        pkw["use_graph"] = 0
+    if args.tail_rows is not None:
+        pkw["tail_rows"] = args.tail_rows
+    params = amg.amg_params_default(**pkw)
+    mixed = params.precision == amg.AMG_MIXED
+    print(f"[bench] workload {args.workload}: n={g.n} nnz={g.nnz}", file=sys.stderr, flush=True)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, params)
+    desc = amg.amg_describe(h)
+    print(f"[bench] setup {desc['setup_ms']:.1f} ms, levels {desc['n']}", file=sys.stderr, flush=True)
+    f = torch.tensor(f_np, dtype=torch.float64, device=dev)
+    u = torch.zeros_like(f)
+    for _ in range(args.warmup):
+        u.zero_()
+        info = amg.amg_solve(h, f, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u.zero_()
+        info = amg.amg_solve(h, f, u)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] {args.steps} solves in {elapsed:.3f} s, iters {info['iters']}, "
+          f"true rel res {info['rel_res_true']:.2e}", file=sys.stderr, flush=True)
+    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
+    value = g.n * args.steps / elapsed
+    u_gpu = u.cpu().numpy()
+
+    # dominant kernel: interior Chebyshev step on the finest level, timed with
+    # HIP events around each launch on the solve stream (eager profiled solve)
+    u2 = torch.zeros_like(f)
+    pinfo, kt = amg.amg_profile_solve(h, f, u2)
+    bytes_launch = cheb_step_bytes(kt["rows"], kt["nnz"], mixed)
+    achieved = bytes_launch / (kt["avg_ms"] * 1e-3) / 1e9 if kt["avg_ms"] > 0 else 0.0
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": stored_traffic(args.workload),
+        "kernel": "k_cheb_next (finest level, stores w_k+1)",
+        "bytes_per_launch": bytes_launch,
+        "avg_us": round(kt["avg_ms"] * 1e3, 2),
+        "launches_timed": kt["launches"],
+    }
+    print(f"[bench] cheb step: {kt['launches']} launches, avg {kt['avg_ms'] * 1e3:.2f} us -> {achieved:.0f} GB/s",
+          file=sys.stderr, flush=True)
+
+    if args.copy_probe:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)  # 256 MiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    err_vs_oracle = None
+    if not args.no_cpu_baseline:
+        cpu, res = run_cpu_baseline(
+            g, f_np, pkw, sample=f"the oracle's full setup and FP64 solve of the same workload "
+                                 f"(n={g.n}), single thread; value = n / solve seconds")
+        e = u_gpu - res.x
+        import oracle as _o
+
+        lvl0 = _o.assemble(g.n, g.row_ptr, g.col, g.w, g.d)
+        err_vs_oracle = float(np.sqrt(e @ _o.apply_A(lvl0, e)) / np.sqrt(res.x @ _o.apply_A(lvl0, res.x)))
+        print(f"[bench] oracle solve {cpu['solve_s']:.2f} s, iters {cpu['iters']}, A-norm err vs oracle "
+              f"{err_vs_oracle:.2e}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {g.name}, n={g.n}, stored off-diagonals={g.nnz}, "
+                        f"{'mixed FP32 cycle / FP64 FCG' if mixed else 'FP64'}, agg {params.agg_size}, "
+                        f"degree {params.degree}, W(1,1) k-cycle, FCG restart {params.restart}, tol {params.tol}",
+            "levels": desc["n"],
+            "iters": info["iters"],
+            "rel_res_true": info["rel_res_true"],
+            "err_A_vs_oracle": err_vs_oracle,
+            "setup_ms": round(desc["setup_ms"], 2),
+            "aggregation_ms": round(desc["aggregation_ms"], 2),
+            "galerkin_ms": round(desc["galerkin_ms"], 2),
+            "grid_complexity": round(desc["grid_complexity"], 4),
+            "operator_complexity": round(desc["operator_complexity"], 4),
+            "hip_graphs": not args.no_graph,
+            "tail_rows": params.tail_rows,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -126,7 +126,7 @@ typedef struct {
 /* Fill *p with the defaults: degree 4, agg_size 4, coarse_max 64,
  * lambda0_ratio 10, inner_steps 2, restart 5, tol 1e-8, max_iter 200, FP64,
  * normalized key, max_coarsest 2048, stagnation 0.9, use_graph 1,
- * tail_rows 2048. */
+ * tail_rows 512. */
 void amg_params_default(amg_params* p);
 
 /* Human-readable name of a status code (static string). */
@@ -170,6 +170,27 @@ int32_t amg_describe(const amg_hier* h, amg_hier_desc* out);
  * host synchronization per outer iteration (the stopping test).
  */
 int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info);
+
+/* Duration of the finest level's interior Chebyshev step kernel (one fused
+ * pass: w_{k+1} = 2 (A w_k - theta w_k)/eta - w_{k-1}, y += c_{k+1} w_{k+1};
+ * Section 3 smoother) as measured by HIP events around each launch during a
+ * profiled solve. */
+typedef struct {
+  int32_t launches;   /* timed launches                          */
+  double avg_ms;      /* mean event-to-event duration per launch */
+  double min_ms;
+  double max_ms;
+  int32_t rows;       /* rows of the finest level                */
+  int64_t nnz;        /* stored off-diagonal entries             */
+  int32_t grid;       /* workgroups per launch (256 rows each)   */
+} amg_kernel_timing;
+
+/* Same as amg_solve, but launched eagerly (no graph replay) with HIP events
+ * recorded on `stream` around every interior Chebyshev step of the finest
+ * level; fills *timing.  Needs at least two levels and degree >= 3.  For
+ * measurement only: the extra events make it slower than amg_solve. */
+int32_t amg_profile_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info,
+                          amg_kernel_timing* timing);
 
 /* ---- Level inspection and single steps (tests and diagnostics) ------------
  * The single steps below (all but amg_apply_cycle) need an AMG_FP64

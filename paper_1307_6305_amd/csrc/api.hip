@@ -85,7 +85,7 @@ void amg_params_default(amg_params* p) {
   p->max_coarsest = 2048;
   p->stagnation = 0.9;
   p->use_graph = 1;
-  p->tail_rows = 2048;
+  p->tail_rows = 512;
 }
 
 const char* amg_strerror(int32_t s) {
@@ -142,6 +142,7 @@ void amg_free(amg_hier* h) {
   if (h->graph_stream) (void)hipStreamDestroy(h->graph_stream);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->host_scal) (void)hipHostFree(h->host_scal);
+  for (hipEvent_t e : h->probe_ev) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -154,6 +155,16 @@ int32_t amg_describe(const amg_hier* h, amg_hier_desc* out) {
 int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info) {
   if (!h || !f || !u) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
   return amg::solve(h, f, u, static_cast<hipStream_t>(stream), info);
+}
+
+int32_t amg_profile_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info,
+                          amg_kernel_timing* timing) {
+  if (!h || !f || !u || !timing) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
+  if (h->L < 1 || h->p.degree < 3) {
+    amg::set_last_error("profiling needs at least two levels and degree >= 3");
+    return AMG_ERR_ARG;
+  }
+  return amg::profile_solve(h, f, u, static_cast<hipStream_t>(stream), info, timing);
 }
 
 int32_t amg_level_export(const amg_hier* h, int32_t level, int32_t* row_ptr, int32_t* col, double* W, double* d,

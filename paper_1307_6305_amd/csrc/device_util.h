@@ -65,40 +65,64 @@ struct Slots {
   int s[8];
 };
 
-// Deterministic grid reduction of K doubles: every block deposits its partial
-// sums; the last block to arrive adds the partials of all blocks in a fixed
-// order, writes scal[slots.s[k]] (k < K) and rearms the counter.  `partials`
-// holds gridDim.x * K doubles; `counter` must be zero before the launch.  The
-// result does not depend on which block arrives last.
+// Where a grid reduction deposits its result.  Every block writes its partial
+// sums to partials[block * K + k].  With `last_block` set, the last block to
+// arrive (release/acquire ordering through `counter`) adds all partials and
+// writes scal[slots.s[k]]; otherwise a separate one-block kernel
+// (k_finish_sum) does it.  Large grids use the separate kernel: a fence per
+// block costs an L2 write-back per block on this GPU.  Both paths add the
+// partials in the same fixed order, so the result does not depend on which
+// block arrives last nor on the path taken.
+struct Red {
+  double* partials;
+  unsigned* counter;
+  double* scal;
+  Slots slots;
+  int last_block;
+};
+
+constexpr int kFinishThreads = 256;
+
+// Sum of partials[b*K + k] over b < nparts in a fixed order, by one block of
+// kFinishThreads threads: thread t adds b = t, t + 256, ...; then the block tree.
 template <int K>
-__device__ __forceinline__ void grid_sum_finish(double (&v)[K], double* partials, unsigned* counter,
-                                                double* scal, Slots slots) {
+__device__ __forceinline__ void sum_partials(const double* partials, int nparts, double (&acc)[K], double* red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  if (threadIdx.x < kFinishThreads) {
+    for (int b = threadIdx.x; b < nparts; b += kFinishThreads) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc[k] += partials[b * K + k];
+    }
+  }
+  block_sum<K>(acc, red);
+}
+
+template <int K>
+__device__ __forceinline__ void grid_sum_finish(double (&v)[K], const Red& r) {
   __shared__ double red[16 * 8];
   __shared__ bool last;
   block_sum<K>(v, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) partials[blockIdx.x * K + k] = v[k];
-    __threadfence();
-    unsigned t = atomicAdd(counter, 1u);
+    for (int k = 0; k < K; ++k) r.partials[blockIdx.x * K + k] = v[k];
+  }
+  if (!r.last_block) return;
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned t = atomicAdd(r.counter, 1u);
     last = (t == gridDim.x - 1);
   }
   __syncthreads();
   if (!last) return;
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   double acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += partials[b * K + k];
-  }
   __syncthreads();
-  block_sum<K>(acc, red);
+  sum_partials<K>(r.partials, gridDim.x, acc, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) scal[slots.s[k]] = acc[k];
-    *counter = 0u;
+    for (int k = 0; k < K; ++k) r.scal[r.slots.s[k]] = acc[k];
+    *r.counter = 0u;
   }
 }
 

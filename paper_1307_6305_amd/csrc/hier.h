@@ -17,7 +17,17 @@ struct amg_hier {
   int L = 0;                   // index of the coarsest level
   // coarsest level: dense Cholesky factor (row-major, lower triangle used)
   double* chol = nullptr;
+  double* chol_inv = nullptr;   // L^-1 (row-major), when nL <= 1024
+  double* chol_invT = nullptr;  // (L^-1)^T
   int32_t nL = 0;
+
+  // tail program: the inner solve of level tail_level (and all below) run by
+  // one workgroup (0 = no tail)
+  int tail_level = 0;
+  int tail_nops = 0;
+  void* tail_ops = nullptr;
+  void* tail_mats = nullptr;
+  void* tail_trs = nullptr;
 
   // Solve workspace.  `vt` buffers hold the cycle's vector type (double, or
   // float in mixed precision); per level: A, B (smoother recurrence), S
@@ -51,9 +61,14 @@ struct amg_hier {
   hipStream_t graph_stream = nullptr;  // stream the graphs were captured on
   const void* graph_u = nullptr;       // solution pointer baked into the graphs
 
+  // timing probe of the finest level's Chebyshev step (eager solves only):
+  // events bracket every launch that stores w_{k+1}
+  bool probe = false;
+  std::vector<hipEvent_t> probe_ev;
+  int probe_used = 0;
+
   amg_hier_desc desc{};
   std::vector<void*> allocs;
-  std::vector<void*> tail_allocs;
 };
 
 namespace amg {
@@ -83,5 +98,7 @@ int32_t step_coarse(amg_hier* h, const double* b, double* x, hipStream_t s);
 int32_t step_cycle(amg_hier* h, const double* r, double* z, hipStream_t s);
 
 int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info);
+int32_t profile_solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info,
+                      amg_kernel_timing* t);
 
 }  // namespace amg

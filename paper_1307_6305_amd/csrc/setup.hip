@@ -478,6 +478,24 @@ __global__ void __launch_bounds__(1024) k_chol(int n, double* A, int* status) {
   if (threadIdx.x == 0) *status = bad;
 }
 
+// Inverse of the lower Cholesky factor: thread j computes column j of L^-1 by
+// forward substitution (n <= 1024, one workgroup); also writes the transpose.
+__global__ void __launch_bounds__(1024) k_tri_inv(int n, const double* __restrict__ L, double* __restrict__ X,
+                                                  double* __restrict__ XT) {
+  const int j = threadIdx.x;
+  if (j >= n) return;
+  for (int i = 0; i < n; ++i) {
+    double v = 0.0;
+    if (i >= j) {
+      double acc = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) acc -= L[(size_t)i * n + k] * X[(size_t)k * n + j];
+      v = acc / L[(size_t)i * n + i];
+    }
+    X[(size_t)i * n + j] = v;
+    XT[(size_t)j * n + i] = v;
+  }
+}
+
 // ------------------------------------------------------------------ host helpers
 using clk = std::chrono::steady_clock;
 double ms_since(clk::time_point t0) {
@@ -783,6 +801,12 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
   if (bad) {
     set_last_error("coarsest matrix is not positive definite");
     return AMG_ERR_SINGULAR;
+  }
+  if (co.n <= 1024) {
+    AMG_TRY(dalloc(h, &h->chol_inv, (size_t)co.n * co.n));
+    AMG_TRY(dalloc(h, &h->chol_invT, (size_t)co.n * co.n));
+    hipLaunchKernelGGL(k_tri_inv, dim3(1), dim3(1024), 0, s, co.n, h->chol, h->chol_inv, h->chol_invT);
+    AMG_HIP(hipGetLastError());
   }
   // solve-phase layouts: every level that is smoothed, and always the finest
   // level (outer-iteration products and residuals), even when it is the coarsest

@@ -2,25 +2,31 @@
 // cycle (k-cycle) with the best-uniform-approximation polynomial smoother
 // (Sections 3 and 4 of the paper).
 //
-// Kernels (one row per lane over sliced ELL, slice height 64 = one wavefront):
-//   k_cheb_first / k_cheb_next  one Chebyshev three-term step of q_m(A): SpMV,
-//                               recurrence and the accumulation y += c_k w_k
-//                               fused in one pass over the matrix
-//   k_residual                  s = r - A x
-//   k_restrict                  b = P^T s as a segmented sum over the member
-//                               list of each aggregate (P is never stored)
-//   k_prolong                   x += P e as a gather of the aggregate value
-//   k_chol_solve_*              coarsest solve with the dense Cholesky factor
-//   k_multidot, k_fcg_p,        flexible-CG steps; inner products are
-//   k_spmv_dots, k_fcg_xr       deterministic fused grid reductions in FP64
+// Per-row device functions (one row per lane over sliced ELL, slice height 64
+// = one wavefront) implement each step once; two executors use them:
+//   * device-wide kernels, one launch per step, for the large levels;
+//   * k_tail, a one-workgroup interpreter that runs a recorded op program --
+//     the whole inner solve of a small level and everything below it -- with
+//     workgroup barriers between the steps, so that the W-cycle's many visits
+//     of the small levels cost no kernel launches.
+// Steps:
+//   cheb_first / cheb_next  one Chebyshev three-term step of q_m(A): SpMV,
+//                           recurrence and y += c_k w_k in one pass
+//   residual                s = r - A x
+//   restrict                b = P^T s, a segmented sum over each aggregate's
+//                           member list (P is never stored)
+//   prolong                 x += P e, a gather of the aggregate value
+//   coarse                  coarsest solve with the inverted Cholesky factor
+//   multidot, fcg_p,        flexible-CG steps; inner products are
+//   spmv_dots, fcg_xr       deterministic reductions in FP64
 //
-// Scalars (inner products and the coefficients derived from them) never leave
-// the device inside an iteration; the host reads two numbers per outer
-// iteration for the stopping test.
+// Scalars never leave the device inside an iteration; the host reads two
+// numbers per outer iteration for the stopping test.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "device_util.h"
 #include "hier.h"
@@ -29,16 +35,16 @@ namespace amg {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int RED_BLOCKS = 1024;  // grid of the vector kernels with reductions
+constexpr int TAIL_THREADS = 1024;
+constexpr int LAST_BLOCK_MAX = 16;  // grids up to this size finish their reduction in-kernel
 
-// Scalar area.  Outer iteration: rr, (p,q), (p,r), window dots, window rho.
+// Scalar area.  Outer iteration: rr, (p,r), window dots, window rho.
 // Inner solve on level l: base(l) + [0,8) rho_k, [8,16) gamma_k, [16,24) dots.
-constexpr int S_RR = 0, S_RHO = 1, S_GAM = 2, S_RR0 = 3, S_RRT = 4, S_DUMMY = 7, S_DOTS = 8, S_RHOW = 16;
+constexpr int S_RR = 0, S_GAM = 2, S_RR0 = 3, S_RRT = 4, S_DUMMY = 7, S_DOTS = 8, S_RHOW = 16;
 inline int lbase(int l) { return 64 + 32 * l; }
 constexpr int SCAL_SIZE = 64 + 32 * (AMG_MAX_LEVELS + 1);
 
 inline int nblk(int64_t n, int tpb = TPB) { return (int)std::max<int64_t>(1, (n + tpb - 1) / tpb); }
-inline int rblk(int64_t n) { return std::min(RED_BLOCKS, nblk(n)); }
 
 struct VecPtrs {
   const void* p[8];
@@ -48,11 +54,24 @@ template <typename MT>
 struct Mat {
   int n;
   int nb;  // blocks of TPB rows
-  const int* __restrict__ off;
-  const int* __restrict__ width;
-  const int* __restrict__ col;
-  const MT* __restrict__ val;
-  const MT* __restrict__ D;
+  const int* off;
+  const int* width;
+  const int* col;
+  const MT* val;
+  const MT* D;
+};
+
+struct Transfer {
+  int n, nc;
+  const int* agg;
+  const int* members;
+  const int* member_off;
+};
+
+struct CoarseView {
+  int n;
+  const double* Linv;   // inverse of the Cholesky factor, row-major (lower)
+  const double* LinvT;  // its transpose
 };
 
 template <typename MT>
@@ -66,14 +85,12 @@ Mat<float> mat_of<float>(const Level& lv) {
   return Mat<float>{lv.n, nblk(lv.n), lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_valf, lv.Df};
 }
 
-// Row handled by this thread (XCD-aware tile order), or -1.
-template <typename MT>
-__device__ __forceinline__ int row_of(const Mat<MT>& A) {
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int r = tile * TPB + threadIdx.x;
-  return r < A.n ? r : -1;
+Transfer transfer_of(const amg_hier* h, int l) {
+  const Level& lv = h->lv[l];
+  return Transfer{lv.n, h->lv[l + 1].n, lv.agg, lv.members, lv.member_off};
 }
 
+// ------------------------------------------------------------------ per-row steps
 // sum_j W_rj x_j over the stored off-diagonal entries of row r.
 template <typename AT, typename MT, typename XT>
 __device__ __forceinline__ AT offdiag(const Mat<MT>& A, int r, const XT* __restrict__ x) {
@@ -87,15 +104,12 @@ __device__ __forceinline__ AT offdiag(const Mat<MT>& A, int r, const XT* __restr
   return acc;
 }
 
-// ------------------------------------------------------------------ smoother
-// w1 = (A w0 - theta w0) / eta;  y = [y +] c0 w0 + c1 w1   (c already / eta)
+// w1 = (A w0 - theta w0) / eta;  y = [y +] c0 w0 + c1 w1   (c already divided by eta)
 template <typename VT, typename MT, typename RT>
-__global__ void __launch_bounds__(TPB) k_cheb_first(Mat<MT> A, const RT* __restrict__ w0, VT* __restrict__ w1,
-                                                    VT* __restrict__ y, double theta, double inv_eta, double c0,
-                                                    double c1, int accum, int store) {
+__device__ __forceinline__ void row_cheb_first(const Mat<MT>& A, int r, const RT* __restrict__ w0, VT* w1, VT* y,
+                                               double theta, double inv_eta, double c0, double c1, int accum,
+                                               int store) {
   using AT = VT;
-  const int r = row_of(A);
-  if (r < 0) return;
   const AT x0 = (AT)w0[r];
   const AT ax = (AT)A.D[r] * x0 - offdiag<AT>(A, r, w0);
   const AT t = (ax - (AT)theta * x0) * (AT)inv_eta;
@@ -108,12 +122,10 @@ __global__ void __launch_bounds__(TPB) k_cheb_first(Mat<MT> A, const RT* __restr
 // w_{k+1} = 2 (A w_k - theta w_k) / eta - w_{k-1};  y += c_{k+1} w_{k+1}.
 // wnext may alias wprev (each element is read before it is overwritten).
 template <typename VT, typename MT, typename PT>
-__global__ void __launch_bounds__(TPB) k_cheb_next(Mat<MT> A, const VT* __restrict__ wk, const PT* wprev, VT* wnext,
-                                                   VT* __restrict__ y, double theta, double two_inv_eta, double ck,
-                                                   int store) {
+__device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int r, const VT* __restrict__ wk, const PT* wprev,
+                                              VT* wnext, VT* y, double theta, double two_inv_eta, double ck,
+                                              int store) {
   using AT = VT;
-  const int r = row_of(A);
-  if (r < 0) return;
   const AT xk = (AT)wk[r];
   const AT ax = (AT)A.D[r] * xk - offdiag<AT>(A, r, wk);
   const AT t = (ax - (AT)theta * xk) * (AT)two_inv_eta - (AT)wprev[r];
@@ -121,9 +133,74 @@ __global__ void __launch_bounds__(TPB) k_cheb_next(Mat<MT> A, const VT* __restri
   y[r] = (VT)((AT)y[r] + (AT)ck * t);
 }
 
+template <typename VT, typename MT, typename RT>
+__device__ __forceinline__ void row_residual(const Mat<MT>& A, int r, const RT* __restrict__ f,
+                                             const VT* __restrict__ x, VT* s) {
+  using AT = VT;
+  const AT ax = (AT)A.D[r] * (AT)x[r] - offdiag<AT>(A, r, x);
+  s[r] = (VT)((AT)f[r] - ax);
+}
+
+template <typename VT>
+__device__ __forceinline__ void row_restrict(const Transfer& T, int I, const VT* __restrict__ s, VT* b) {
+  VT acc = 0;
+  for (int k = T.member_off[I]; k < T.member_off[I + 1]; ++k) acc += s[T.members[k]];
+  b[I] = acc;
+}
+
+template <typename VT>
+__device__ __forceinline__ void row_prolong(const Transfer& T, int i, const VT* __restrict__ e, VT* x) {
+  x[i] += e[T.agg[i]];
+}
+
+// q_r = (A p)_r; accumulates p_r q_r and p_r rv_r in FP64
+template <typename VT, typename MT, typename RT>
+__device__ __forceinline__ void row_spmv_dots(const Mat<MT>& A, int r, const VT* __restrict__ p, VT* q,
+                                              const RT* __restrict__ rv, double (&v)[2]) {
+  using AT = VT;
+  const AT pr = (AT)p[r];
+  const AT ap = (AT)A.D[r] * pr - offdiag<AT>(A, r, p);
+  q[r] = (VT)ap;
+  v[0] += (double)pr * (double)ap;
+  v[1] += (double)pr * (double)rv[r];
+}
+
+__device__ __forceinline__ double fcg_alpha(const double* scal, int s_rho, int s_gam) {
+  const double rho = scal[s_rho];
+  return (rho > 0.0 && isfinite(rho)) ? scal[s_gam] / rho : 0.0;
+}
+
+__device__ __forceinline__ double fcg_beta(const double* scal, int s_dot, int s_rho) {
+  const double rho = scal[s_rho];
+  return rho > 0.0 ? scal[s_dot] / rho : 0.0;
+}
+
+// ------------------------------------------------------------------ device-wide kernels
+template <typename MT>
+__device__ __forceinline__ int row_of(const Mat<MT>& A) {
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int r = tile * TPB + threadIdx.x;
+  return r < A.n ? r : -1;
+}
+
+template <typename VT, typename MT, typename RT>
+__global__ void __launch_bounds__(TPB) k_cheb_first(Mat<MT> A, const RT* __restrict__ w0, VT* w1, VT* y,
+                                                    double theta, double inv_eta, double c0, double c1, int accum,
+                                                    int store) {
+  const int r = row_of(A);
+  if (r >= 0) row_cheb_first<VT, MT, RT>(A, r, w0, w1, y, theta, inv_eta, c0, c1, accum, store);
+}
+
+template <typename VT, typename MT, typename PT>
+__global__ void __launch_bounds__(TPB) k_cheb_next(Mat<MT> A, const VT* __restrict__ wk, const PT* wprev, VT* wnext,
+                                                   VT* y, double theta, double two_inv_eta, double ck, int store) {
+  const int r = row_of(A);
+  if (r >= 0) row_cheb_next<VT, MT, PT>(A, r, wk, wprev, wnext, y, theta, two_inv_eta, ck, store);
+}
+
 // degree 0: y = [y +] c0 w0
 template <typename VT, typename RT>
-__global__ void k_scale_add(int n, const RT* __restrict__ w0, VT* __restrict__ y, double c0, int accum) {
+__global__ void k_scale_add(int n, const RT* __restrict__ w0, VT* y, double c0, int accum) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   VT v = (VT)c0 * (VT)w0[i];
@@ -131,74 +208,68 @@ __global__ void k_scale_add(int n, const RT* __restrict__ w0, VT* __restrict__ y
   y[i] = v;
 }
 
-// ------------------------------------------------------------------ residual, transfer
 template <typename VT, typename MT, typename RT>
 __global__ void __launch_bounds__(TPB) k_residual(Mat<MT> A, const RT* __restrict__ f, const VT* __restrict__ x,
-                                                  VT* __restrict__ s) {
-  using AT = VT;
+                                                  VT* s) {
   const int r = row_of(A);
-  if (r < 0) return;
-  const AT ax = (AT)A.D[r] * (AT)x[r] - offdiag<AT>(A, r, x);
-  s[r] = (VT)((AT)f[r] - ax);
+  if (r >= 0) row_residual<VT, MT, RT>(A, r, f, x, s);
 }
 
-// FP64 residual with its squared norm: s = f - A x, scal[slot] = (s, s).
+// FP64 residual with its squared norm: s = f - A x, (s, s).
 __global__ void __launch_bounds__(TPB) k_residual_dot(Mat<double> A, const double* __restrict__ f,
-                                                      const double* __restrict__ x, double* __restrict__ s,
-                                                      double* partials, unsigned* counter, double* scal, Slots out) {
+                                                      const double* __restrict__ x, double* s, Red red) {
   const int r = row_of(A);
   double v[1] = {0.0};
   if (r >= 0) {
-    const double res = f[r] - (A.D[r] * x[r] - offdiag<double>(A, r, x));
-    s[r] = res;
-    v[0] = res * res;
+    row_residual<double, double, double>(A, r, f, x, s);
+    v[0] = s[r] * s[r];
   }
-  grid_sum_finish<1>(v, partials, counter, scal, out);
+  grid_sum_finish<1>(v, red);
 }
 
 template <typename VT>
-__global__ void k_restrict(int nc, const int* __restrict__ members, const int* __restrict__ off,
-                           const VT* __restrict__ s, VT* __restrict__ b) {
+__global__ void k_restrict(Transfer T, const VT* __restrict__ s, VT* b) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  VT acc = 0;
-  for (int k = off[I]; k < off[I + 1]; ++k) acc += s[members[k]];
-  b[I] = acc;
+  if (I < T.nc) row_restrict<VT>(T, I, s, b);
 }
 
 template <typename VT>
-__global__ void k_prolong(int n, const int* __restrict__ agg, const VT* __restrict__ e, VT* __restrict__ x) {
+__global__ void k_prolong(Transfer T, const VT* __restrict__ e, VT* x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] += e[agg[i]];
+  if (i < T.n) row_prolong<VT>(T, i, e, x);
 }
 
-// ------------------------------------------------------------------ coarsest solve
-// L y = b, L^T x = y with the dense factor; one wavefront, lane i owns row i.
+// Coarsest solve x = L^-T (L^-1 b) with the inverted factor: two triangular
+// products, thread i owning rows i, i + blockDim, ... (n <= 1024).
 template <typename VT, typename RT>
-__global__ void __launch_bounds__(64) k_chol_solve_wave(int n, const double* __restrict__ Lg, const RT* __restrict__ b,
-                                                        VT* __restrict__ x) {
-  __shared__ double Ls[64 * 65];
-  const int lane = threadIdx.x;
-  for (int t = lane; t < n * n; t += 64) Ls[(t / n) * 65 + (t % n)] = Lg[t];
+__device__ __forceinline__ void coarse_apply(const CoarseView& C, const RT* __restrict__ b, VT* x, double* sb,
+                                             double* sy) {
+  const int n = C.n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[i];
   __syncthreads();
-  double bi = lane < n ? (double)b[lane] : 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double yk = __shfl(bi, k, 64) / Ls[k * 65 + k];
-    if (lane == k) bi = yk;
-    else if (lane > k && lane < n) bi -= Ls[lane * 65 + k] * yk;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j <= i; ++j) acc += C.LinvT[(size_t)j * n + i] * sb[j];
+    sy[i] = acc;
   }
-  for (int k = n - 1; k >= 0; --k) {
-    const double xk = __shfl(bi, k, 64) / Ls[k * 65 + k];
-    if (lane == k) bi = xk;
-    else if (lane < k) bi -= Ls[k * 65 + lane] * xk;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double acc = 0.0;
+    for (int j = i; j < n; ++j) acc += C.Linv[(size_t)j * n + i] * sy[j];
+    x[i] = (VT)acc;
   }
-  if (lane < n) x[lane] = (VT)bi;
 }
 
-// Same for larger coarsest levels: one workgroup, the vector in LDS.
 template <typename VT, typename RT>
-__global__ void __launch_bounds__(TPB) k_chol_solve_block(int n, const double* __restrict__ Lg,
-                                                          const RT* __restrict__ b, VT* __restrict__ x) {
+__global__ void __launch_bounds__(TPB) k_coarse_inv(CoarseView C, const RT* __restrict__ b, VT* x) {
+  __shared__ double sb[1024], sy[1024];
+  coarse_apply<VT, RT>(C, b, x, sb, sy);
+}
+
+// Substitution with the factor itself for coarsest levels above 1024 rows.
+template <typename VT, typename RT>
+__global__ void __launch_bounds__(TPB) k_coarse_subst(int n, const double* __restrict__ Lg, const RT* __restrict__ b,
+                                                      VT* x) {
   extern __shared__ double y[];
   for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = (double)b[i];
   __syncthreads();
@@ -219,85 +290,78 @@ __global__ void __launch_bounds__(TPB) k_chol_solve_block(int n, const double* _
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = (VT)y[i];
 }
 
-// ------------------------------------------------------------------ flexible CG
-// scal[dots.s[i]] = (z, q_i) for i < k.
+// (z, q_i) for i < k.
 template <typename ZT, typename QT>
-__global__ void __launch_bounds__(TPB) k_multidot(int n, const ZT* __restrict__ z, VecPtrs qs, int k,
-                                                  double* partials, unsigned* counter, double* scal, Slots dots) {
+__global__ void __launch_bounds__(TPB) k_multidot(int n, const ZT* __restrict__ z, VecPtrs qs, int k, Red red) {
   double v[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) v[i] = 0.0;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
     const double zj = (double)z[j];
 #pragma unroll
     for (int i = 0; i < 8; ++i)
       if (i < k) v[i] += zj * (double)static_cast<const QT*>(qs.p[i])[j];
   }
-  grid_sum_finish<8>(v, partials, counter, scal, dots);
+  grid_sum_finish<8>(v, red);
 }
 
 // p = z - sum_i (dots_i / rho_i) p_i  (term dropped when rho_i <= 0); FP64 arithmetic.
 template <typename PT, typename ZT>
 __global__ void __launch_bounds__(TPB) k_fcg_p(int n, PT* p, const ZT* z, VecPtrs ps, int k, const double* scal,
                                                Slots dots, Slots rhos) {
-  __shared__ double beta[8];
-  if (threadIdx.x < 8) {
-    const int i = threadIdx.x;
-    double b = 0.0;
-    if (i < k) {
-      const double rho = scal[rhos.s[i]];
-      b = rho > 0.0 ? scal[dots.s[i]] / rho : 0.0;
-    }
-    beta[i] = b;
-  }
-  __syncthreads();
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    double v = (double)z[j];
+  double beta[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (i < k) v -= beta[i] * (double)static_cast<const PT*>(ps.p[i])[j];
-    p[j] = (PT)v;
-  }
+  for (int i = 0; i < 8; ++i) beta[i] = i < k ? fcg_beta(scal, dots.s[i], rhos.s[i]) : 0.0;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double v = (double)z[j];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (i < k) v -= beta[i] * (double)static_cast<const PT*>(ps.p[i])[j];
+  p[j] = (PT)v;
 }
 
-// q = A p; scal[out.s[0]] = (p, q), scal[out.s[1]] = (p, r).
+// q = A p; (p, q) and (p, r).
 template <typename VT, typename MT, typename RT>
-__global__ void __launch_bounds__(TPB) k_spmv_dots(Mat<MT> A, const VT* __restrict__ p, VT* __restrict__ q,
-                                                   const RT* __restrict__ rv, double* partials, unsigned* counter,
-                                                   double* scal, Slots out) {
-  using AT = VT;
+__global__ void __launch_bounds__(TPB) k_spmv_dots(Mat<MT> A, const VT* __restrict__ p, VT* q,
+                                                   const RT* __restrict__ rv, Red red) {
   const int r = row_of(A);
   double v[2] = {0.0, 0.0};
-  if (r >= 0) {
-    const AT pr = (AT)p[r];
-    const AT ap = (AT)A.D[r] * pr - offdiag<AT>(A, r, p);
-    q[r] = (VT)ap;
-    v[0] = (double)pr * (double)ap;
-    v[1] = (double)pr * (double)rv[r];
-  }
-  grid_sum_finish<2>(v, partials, counter, scal, out);
+  if (r >= 0) row_spmv_dots<VT, MT, RT>(A, r, p, q, rv, v);
+  grid_sum_finish<2>(v, red);
 }
 
-// alpha = gamma / rho (0 if rho <= 0 or not finite); x (= or +=) alpha p;
-// optionally r -= alpha q and scal[s_rr] = (r, r).
+// alpha = gamma / rho; x (= or +=) alpha p; optionally r -= alpha q and (r, r).
 template <typename VT, typename PT, bool RR>
-__global__ void __launch_bounds__(TPB) k_fcg_xr(int n, const PT* __restrict__ p, const VT* __restrict__ q,
-                                                VT* __restrict__ x, VT* __restrict__ r, const double* scal_in,
-                                                int s_rho, int s_gam, int x_init, int upd_r, double* partials,
-                                                unsigned* counter, double* scal, Slots rr_slot) {
-  const double rho = scal_in[s_rho];
-  const double alpha = (rho > 0.0 && isfinite(rho)) ? scal_in[s_gam] / rho : 0.0;
+__global__ void __launch_bounds__(TPB) k_fcg_xr(int n, const PT* __restrict__ p, const VT* __restrict__ q, VT* x,
+                                                VT* r, const double* scal, int s_rho, int s_gam, int x_init,
+                                                int upd_r, Red red) {
+  const double alpha = fcg_alpha(scal, s_rho, s_gam);
   double v[1] = {0.0};
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
     const double pj = (double)p[j];
     x[j] = (VT)(x_init ? alpha * pj : (double)x[j] + alpha * pj);
     if (upd_r) {
       const double rj = (double)r[j] - alpha * (double)q[j];
       r[j] = (VT)rj;
-      if (RR) v[0] += rj * rj;
+      if (RR) v[0] = rj * rj;
     }
   }
-  if (RR) grid_sum_finish<1>(v, partials, counter, scal, rr_slot);
+  if (RR) grid_sum_finish<1>(v, red);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kFinishThreads) k_finish_sum(int nparts, const double* partials, double* scal,
+                                                               Slots slots) {
+  __shared__ double red[16 * 8];
+  double acc[K];
+  sum_partials<K>(partials, nparts, acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) scal[slots.s[k]] = acc[k];
+  }
 }
 
 template <typename A, typename B>
@@ -308,62 +372,307 @@ __global__ void k_convert(int n, const A* __restrict__ a, B* __restrict__ b) {
 
 __global__ void k_zero_u32(unsigned* c) { *c = 0u; }
 
+// ------------------------------------------------------------------ tail interpreter
+enum OpType : int {
+  OP_CHEB_FIRST = 1,
+  OP_CHEB_NEXT,
+  OP_SCALE_ADD,
+  OP_RESIDUAL,
+  OP_RESTRICT,
+  OP_PROLONG,
+  OP_COARSE,
+  OP_MULTIDOT,
+  OP_FCG_P,
+  OP_SPMV_DOTS,
+  OP_FCG_XR,
+};
+
+struct TailOp {
+  int type, level, n, k;
+  int i0, i1, i2, i3;
+  double f0, f1, f2, f3;
+  const void* a;
+  const void* b;
+  void* c;
+  void* d;
+  VecPtrs w;
+  Slots s0, s1;
+};
+
+// Runs a recorded op program in one workgroup; every op is a data-parallel
+// loop over rows followed by a workgroup barrier.  Reductions are workgroup
+// reductions (no grid synchronization needed).
+template <typename VT, typename MT>
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail(const TailOp* __restrict__ ops, int nops,
+                                                       const Mat<MT>* __restrict__ mats,
+                                                       const Transfer* __restrict__ trs, CoarseView C, double* scal) {
+  __shared__ double red[16 * 8];
+  __shared__ double sb[1024], sy[1024];
+  const int tid = threadIdx.x, bd = blockDim.x;
+  for (int o = 0; o < nops; ++o) {
+    const TailOp& op = ops[o];
+    switch (op.type) {
+      case OP_CHEB_FIRST: {
+        const Mat<MT> A = mats[op.level];
+        for (int r = tid; r < A.n; r += bd)
+          row_cheb_first<VT, MT, VT>(A, r, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.f3, op.i0,
+                                     op.i1);
+        break;
+      }
+      case OP_CHEB_NEXT: {
+        const Mat<MT> A = mats[op.level];
+        for (int r = tid; r < A.n; r += bd)
+          row_cheb_next<VT, MT, VT>(A, r, (const VT*)op.a, (const VT*)op.b, (VT*)op.c, (VT*)op.d, op.f0, op.f1,
+                                    op.f2, op.i0);
+        break;
+      }
+      case OP_SCALE_ADD: {
+        const VT* w0 = (const VT*)op.a;
+        VT* y = (VT*)op.d;
+        for (int i = tid; i < op.n; i += bd) {
+          VT v = (VT)op.f0 * w0[i];
+          if (op.i0) v += y[i];
+          y[i] = v;
+        }
+        break;
+      }
+      case OP_RESIDUAL: {
+        const Mat<MT> A = mats[op.level];
+        for (int r = tid; r < A.n; r += bd)
+          row_residual<VT, MT, VT>(A, r, (const VT*)op.a, (const VT*)op.b, (VT*)op.c);
+        break;
+      }
+      case OP_RESTRICT: {
+        const Transfer T = trs[op.level];
+        for (int I = tid; I < T.nc; I += bd) row_restrict<VT>(T, I, (const VT*)op.a, (VT*)op.c);
+        break;
+      }
+      case OP_PROLONG: {
+        const Transfer T = trs[op.level];
+        for (int i = tid; i < T.n; i += bd) row_prolong<VT>(T, i, (const VT*)op.a, (VT*)op.c);
+        break;
+      }
+      case OP_COARSE:
+        coarse_apply<VT, VT>(C, (const VT*)op.a, (VT*)op.c, sb, sy);
+        break;
+      case OP_MULTIDOT: {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = 0.0;
+        const VT* z = (const VT*)op.a;
+        for (int j = tid; j < op.n; j += bd) {
+          const double zj = (double)z[j];
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (i < op.k) v[i] += zj * (double)((const VT*)op.w.p[i])[j];
+        }
+        block_sum<8>(v, red);
+        if (tid == 0)
+          for (int i = 0; i < op.k; ++i) scal[op.s0.s[i]] = v[i];
+        break;
+      }
+      case OP_FCG_P: {
+        double beta[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) beta[i] = i < op.k ? fcg_beta(scal, op.s0.s[i], op.s1.s[i]) : 0.0;
+        const VT* z = (const VT*)op.a;
+        VT* p = (VT*)op.c;
+        for (int j = tid; j < op.n; j += bd) {
+          double v = (double)z[j];
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (i < op.k) v -= beta[i] * (double)((const VT*)op.w.p[i])[j];
+          p[j] = (VT)v;
+        }
+        break;
+      }
+      case OP_SPMV_DOTS: {
+        const Mat<MT> A = mats[op.level];
+        double v[2] = {0.0, 0.0};
+        for (int r = tid; r < A.n; r += bd)
+          row_spmv_dots<VT, MT, VT>(A, r, (const VT*)op.a, (VT*)op.c, (const VT*)op.b, v);
+        block_sum<2>(v, red);
+        if (tid == 0) {
+          scal[op.s0.s[0]] = v[0];
+          scal[op.s0.s[1]] = v[1];
+        }
+        break;
+      }
+      case OP_FCG_XR: {
+        const double alpha = fcg_alpha(scal, op.i0, op.i1);
+        const VT* p = (const VT*)op.a;
+        const VT* q = (const VT*)op.b;
+        VT* x = (VT*)op.c;
+        VT* r = (VT*)op.d;
+        for (int j = tid; j < op.n; j += bd) {
+          const double pj = (double)p[j];
+          x[j] = (VT)(op.i2 ? alpha * pj : (double)x[j] + alpha * pj);
+          if (op.i3) r[j] = (VT)((double)r[j] - alpha * (double)q[j]);
+        }
+        break;
+      }
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ host orchestration
-Slots slots1(int a) { Slots s; for (int i = 0; i < 8; ++i) s.s[i] = S_DUMMY; s.s[0] = a; return s; }
-Slots slots2(int a, int b) { Slots s = slots1(a); s.s[1] = b; return s; }
+Slots slots1(int a) {
+  Slots s;
+  for (int i = 0; i < 8; ++i) s.s[i] = S_DUMMY;
+  s.s[0] = a;
+  return s;
+}
+Slots slots2(int a, int b) {
+  Slots s = slots1(a);
+  s.s[1] = b;
+  return s;
+}
 Slots slots_range(int base, int k) {
   Slots s;
   for (int i = 0; i < 8; ++i) s.s[i] = i < k ? base + i : S_DUMMY;
   return s;
 }
 
+// Builds the step sequence of the cycle.  With `rec` set, steps are appended
+// to an op program for the tail interpreter instead of being launched.
 template <typename VT, typename MT>
 struct Engine {
   amg_hier* h;
   hipStream_t s;
+  std::vector<TailOp>* rec = nullptr;
 
   Mat<MT> A(int l) const { return mat_of<MT>(h->lv[l]); }
-  VT* wsv(void* p) const { return static_cast<VT*>(p); }
+  static VT* wsv(void* p) { return static_cast<VT*>(p); }
 
-  template <typename RT>
-  int32_t smooth(int l, const RT* r, VT* y, bool accum) {
-    const Level& lv = h->lv[l];
-    const int m = h->p.degree;
-    const auto Am = A(l);
-    const double theta = lv.theta, inv_eta = 1.0 / lv.eta;
-    const double* c = lv.coef.data();
-    if (m == 0) {
-      hipLaunchKernelGGL((k_scale_add<VT, RT>), dim3(nblk(lv.n)), dim3(TPB), 0, s, lv.n, r, y, c[0], (int)accum);
-      AMG_HIP(hipGetLastError());
-      return AMG_OK;
-    }
-    VT* bufA = wsv(h->ws[l].A);
-    VT* bufB = wsv(h->ws[l].B);
-    hipLaunchKernelGGL((k_cheb_first<VT, MT, RT>), dim3(Am.nb), dim3(TPB), 0, s, Am, r, bufA, y, theta, inv_eta,
-                       c[0], c[1], (int)accum, (int)(m > 1));
-    VT* cur = bufA;
-    VT* prevbuf = nullptr;  // buffer holding w_{k-1} for k >= 2
-    for (int k = 1; k < m; ++k) {
-      const int store = (k + 1 < m);
-      VT* next;
-      if (k == 1) {
-        next = bufB;
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, RT>), dim3(Am.nb), dim3(TPB), 0, s, Am, cur, r, next, y, theta,
-                           2.0 * inv_eta, c[k + 1], store);
-      } else {
-        next = prevbuf;
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, VT>), dim3(Am.nb), dim3(TPB), 0, s, Am, cur, prevbuf, next, y,
-                           theta, 2.0 * inv_eta, c[k + 1], store);
-      }
-      prevbuf = cur;
-      cur = next;
-    }
+  static TailOp op(int type, int level, int n) {
+    TailOp o;
+    std::memset(&o, 0, sizeof(o));
+    o.type = type;
+    o.level = level;
+    o.n = n;
+    return o;
+  }
+
+  // reduction destination for a device-wide kernel of `blocks` blocks
+  Red red_for(int blocks, Slots slots) const {
+    return Red{h->partials, h->counter, h->scal, slots, blocks <= LAST_BLOCK_MAX ? 1 : 0};
+  }
+  template <int K>
+  int32_t finish(int blocks, Slots slots) {
+    if (blocks <= LAST_BLOCK_MAX) return AMG_OK;
+    hipLaunchKernelGGL((k_finish_sum<K>), dim3(1), dim3(kFinishThreads), 0, s, blocks, h->partials, h->scal, slots);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
 
   template <typename RT>
+  int32_t cheb_first(int l, const RT* w0, VT* w1, VT* y, double c0, double c1, bool accum, bool store) {
+    const Level& lv = h->lv[l];
+    if (rec) {
+      if constexpr (std::is_same<RT, VT>::value) {
+        TailOp o = op(OP_CHEB_FIRST, l, lv.n);
+        o.a = w0; o.c = w1; o.d = y;
+        o.f0 = lv.theta; o.f1 = 1.0 / lv.eta; o.f2 = c0; o.f3 = c1;
+        o.i0 = accum; o.i1 = store;
+        rec->push_back(o);
+        return AMG_OK;
+      }
+      return AMG_ERR_DEVICE;
+    }
+    const auto Am = A(l);
+    hipLaunchKernelGGL((k_cheb_first<VT, MT, RT>), dim3(Am.nb), dim3(TPB), 0, s, Am, w0, w1, y, lv.theta,
+                       1.0 / lv.eta, c0, c1, (int)accum, (int)store);
+    AMG_HIP(hipGetLastError());
+    return AMG_OK;
+  }
+
+  template <typename PT>
+  int32_t cheb_next(int l, const VT* wk, const PT* wprev, VT* wnext, VT* y, double ck, bool store) {
+    const Level& lv = h->lv[l];
+    if (rec) {
+      if constexpr (std::is_same<PT, VT>::value) {
+        TailOp o = op(OP_CHEB_NEXT, l, lv.n);
+        o.a = wk; o.b = wprev; o.c = wnext; o.d = y;
+        o.f0 = lv.theta; o.f1 = 2.0 / lv.eta; o.f2 = ck;
+        o.i0 = store;
+        rec->push_back(o);
+        return AMG_OK;
+      }
+      return AMG_ERR_DEVICE;
+    }
+    const auto Am = A(l);
+    const bool probe = h->probe && l == 0 && store && h->probe_used + 2 <= (int)h->probe_ev.size();
+    if (probe) AMG_HIP(hipEventRecord(h->probe_ev[h->probe_used], s));
+    hipLaunchKernelGGL((k_cheb_next<VT, MT, PT>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev, wnext, y, lv.theta,
+                       2.0 / lv.eta, ck, (int)store);
+    AMG_HIP(hipGetLastError());
+    if (probe) {
+      AMG_HIP(hipEventRecord(h->probe_ev[h->probe_used + 1], s));
+      h->probe_used += 2;
+    }
+    return AMG_OK;
+  }
+
+  template <typename RT>
+  int32_t scale_add(int l, const RT* w0, VT* y, double c0, bool accum) {
+    const int n = h->lv[l].n;
+    if (rec) {
+      if constexpr (std::is_same<RT, VT>::value) {
+        TailOp o = op(OP_SCALE_ADD, l, n);
+        o.a = w0; o.d = y; o.f0 = c0; o.i0 = accum;
+        rec->push_back(o);
+        return AMG_OK;
+      }
+      return AMG_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL((k_scale_add<VT, RT>), dim3(nblk(n)), dim3(TPB), 0, s, n, w0, y, c0, (int)accum);
+    AMG_HIP(hipGetLastError());
+    return AMG_OK;
+  }
+
+  // y = [y +] q_m(A_l) r: m three-term steps; buffers A, B of the level hold
+  // w_k and w_{k-1} (w_{k+1} overwrites w_{k-1} in place).
+  template <typename RT>
+  int32_t smooth(int l, const RT* r, VT* y, bool accum) {
+    const Level& lv = h->lv[l];
+    const int m = h->p.degree;
+    const double* c = lv.coef.data();
+    if (m == 0) return scale_add(l, r, y, c[0], accum);
+    VT* bufA = wsv(h->ws[l].A);
+    VT* bufB = wsv(h->ws[l].B);
+    AMG_TRY(cheb_first(l, r, bufA, y, c[0], c[1], accum, m > 1));
+    VT* cur = bufA;
+    VT* prevbuf = nullptr;
+    for (int k = 1; k < m; ++k) {
+      const bool store = (k + 1 < m);
+      VT* next;
+      if (k == 1) {
+        next = bufB;
+        AMG_TRY(cheb_next(l, cur, r, next, y, c[k + 1], store));
+      } else {
+        next = prevbuf;
+        AMG_TRY(cheb_next(l, cur, static_cast<const VT*>(prevbuf), next, y, c[k + 1], store));
+      }
+      prevbuf = cur;
+      cur = next;
+    }
+    return AMG_OK;
+  }
+
+  template <typename RT>
   int32_t residual(int l, const RT* f, const VT* x, VT* out) {
+    if (rec) {
+      if constexpr (std::is_same<RT, VT>::value) {
+        TailOp o = op(OP_RESIDUAL, l, h->lv[l].n);
+        o.a = f; o.b = x; o.c = out;
+        rec->push_back(o);
+        return AMG_OK;
+      }
+      return AMG_ERR_DEVICE;
+    }
     const auto Am = A(l);
     hipLaunchKernelGGL((k_residual<VT, MT, RT>), dim3(Am.nb), dim3(TPB), 0, s, Am, f, x, out);
     AMG_HIP(hipGetLastError());
@@ -371,16 +680,27 @@ struct Engine {
   }
 
   int32_t restrict_(int l, const VT* sv, VT* b) {
-    const Level& lv = h->lv[l];
-    const int nc = h->lv[l + 1].n;
-    hipLaunchKernelGGL((k_restrict<VT>), dim3(nblk(nc)), dim3(TPB), 0, s, nc, lv.members, lv.member_off, sv, b);
+    const Transfer T = transfer_of(h, l);
+    if (rec) {
+      TailOp o = op(OP_RESTRICT, l, T.nc);
+      o.a = sv; o.c = b;
+      rec->push_back(o);
+      return AMG_OK;
+    }
+    hipLaunchKernelGGL((k_restrict<VT>), dim3(nblk(T.nc)), dim3(TPB), 0, s, T, sv, b);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
 
   int32_t prolong(int l, const VT* e, VT* x) {
-    const Level& lv = h->lv[l];
-    hipLaunchKernelGGL((k_prolong<VT>), dim3(nblk(lv.n)), dim3(TPB), 0, s, lv.n, lv.agg, e, x);
+    const Transfer T = transfer_of(h, l);
+    if (rec) {
+      TailOp o = op(OP_PROLONG, l, T.n);
+      o.a = e; o.c = x;
+      rec->push_back(o);
+      return AMG_OK;
+    }
+    hipLaunchKernelGGL((k_prolong<VT>), dim3(nblk(T.n)), dim3(TPB), 0, s, T, e, x);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
@@ -388,16 +708,97 @@ struct Engine {
   template <typename RT>
   int32_t coarse(const RT* b, VT* x) {
     const int n = h->nL;
-    if (n <= 64) {
-      hipLaunchKernelGGL((k_chol_solve_wave<VT, RT>), dim3(1), dim3(64), 0, s, n, h->chol, b, x);
+    if (rec) {
+      if constexpr (std::is_same<RT, VT>::value) {
+        TailOp o = op(OP_COARSE, h->L, n);
+        o.a = b; o.c = x;
+        rec->push_back(o);
+        return AMG_OK;
+      }
+      return AMG_ERR_DEVICE;
+    }
+    if (h->chol_inv) {
+      const CoarseView C{n, h->chol_inv, h->chol_invT};
+      hipLaunchKernelGGL((k_coarse_inv<VT, RT>), dim3(1), dim3(TPB), 0, s, C, b, x);
     } else {
-      hipLaunchKernelGGL((k_chol_solve_block<VT, RT>), dim3(1), dim3(TPB), sizeof(double) * n, s, n, h->chol, b, x);
+      hipLaunchKernelGGL((k_coarse_subst<VT, RT>), dim3(1), dim3(TPB), sizeof(double) * n, s, n, h->chol, b, x);
     }
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
 
-  // z = Kcycle(l, r)
+  // (z, q_i), i < k; z of the cycle vector type, q_i of the cycle type
+  // (coarse levels) or FP64 (outer window)
+  int32_t multidot(int level, int n, const void* z, const VecPtrs& qs, int k, Slots out, bool q_fp64) {
+    if (rec) {
+      TailOp o = op(OP_MULTIDOT, level, n);
+      o.a = z; o.w = qs; o.k = k; o.s0 = out;
+      rec->push_back(o);
+      return AMG_OK;
+    }
+    const int nb = nblk(n);
+    const Red rd = red_for(nb, out);
+    if (q_fp64) {
+      hipLaunchKernelGGL((k_multidot<VT, double>), dim3(nb), dim3(TPB), 0, s, n, (const VT*)z, qs, k, rd);
+    } else {
+      hipLaunchKernelGGL((k_multidot<VT, VT>), dim3(nb), dim3(TPB), 0, s, n, (const VT*)z, qs, k, rd);
+    }
+    AMG_HIP(hipGetLastError());
+    return finish<8>(nb, out);
+  }
+
+  // -------- flexible CG steps on a coarse level (cycle vector type)
+  int32_t spmv_dots(int l, const VT* p, VT* q, const VT* rv, Slots out) {
+    if (rec) {
+      TailOp o = op(OP_SPMV_DOTS, l, h->lv[l].n);
+      o.a = p; o.b = rv; o.c = q; o.s0 = out;
+      rec->push_back(o);
+      return AMG_OK;
+    }
+    const auto Am = A(l);
+    hipLaunchKernelGGL((k_spmv_dots<VT, MT, VT>), dim3(Am.nb), dim3(TPB), 0, s, Am, p, q, rv, red_for(Am.nb, out));
+    AMG_HIP(hipGetLastError());
+    return finish<2>(Am.nb, out);
+  }
+
+  int32_t fcg_p(int l, int n, VT* p, const VT* z, const VecPtrs& ps, int k, Slots dots, Slots rhos) {
+    if (rec) {
+      TailOp o = op(OP_FCG_P, l, n);
+      o.a = z; o.c = p; o.w = ps; o.k = k; o.s0 = dots; o.s1 = rhos;
+      rec->push_back(o);
+      return AMG_OK;
+    }
+    hipLaunchKernelGGL((k_fcg_p<VT, VT>), dim3(nblk(n)), dim3(TPB), 0, s, n, p, z, ps, k, h->scal, dots, rhos);
+    AMG_HIP(hipGetLastError());
+    return AMG_OK;
+  }
+
+  int32_t fcg_xr(int l, int n, const VT* p, const VT* q, VT* x, VT* r, int s_rho, int s_gam, bool x_init,
+                 bool upd_r) {
+    if (rec) {
+      TailOp o = op(OP_FCG_XR, l, n);
+      o.a = p; o.b = q; o.c = x; o.d = r;
+      o.i0 = s_rho; o.i1 = s_gam; o.i2 = x_init; o.i3 = upd_r;
+      rec->push_back(o);
+      return AMG_OK;
+    }
+    const int nb = nblk(n);
+    hipLaunchKernelGGL((k_fcg_xr<VT, VT, false>), dim3(nb), dim3(TPB), 0, s, n, p, q, x, r, h->scal, s_rho, s_gam,
+                       (int)x_init, (int)upd_r, red_for(nb, slots1(S_DUMMY)));
+    AMG_HIP(hipGetLastError());
+    return AMG_OK;
+  }
+
+  // the recorded inner solve of the tail level, in one workgroup
+  int32_t tail() {
+    hipLaunchKernelGGL((k_tail<VT, MT>), dim3(1), dim3(TAIL_THREADS), 0, s, (const TailOp*)h->tail_ops,
+                       h->tail_nops, (const Mat<MT>*)h->tail_mats, (const Transfer*)h->tail_trs,
+                       CoarseView{h->nL, h->chol_inv, h->chol_invT}, h->scal);
+    AMG_HIP(hipGetLastError());
+    return AMG_OK;
+  }
+
+  // x = Kcycle(l, r)
   template <typename RT>
   int32_t kcycle(int l, const RT* r, VT* x) {
     if (l == h->L) return coarse(r, x);
@@ -409,6 +810,8 @@ struct Engine {
     AMG_TRY(restrict_(l, S, b));
     if (l + 1 == h->L) {
       AMG_TRY(coarse(static_cast<const VT*>(b), e));
+    } else if (!rec && h->tail_level == l + 1) {
+      AMG_TRY(tail());
     } else {
       AMG_TRY(inner(l + 1));
     }
@@ -421,9 +824,7 @@ struct Engine {
   // exactly nu flexible-CG steps from zero on level l (1 <= l < L): rhs -> sol
   int32_t inner(int l) {
     const int nu = h->p.inner_steps;
-    const Level& lv = h->lv[l];
-    const int n = lv.n;
-    const auto Am = A(l);
+    const int n = h->lv[l].n;
     auto& W = h->ws[l];
     VT* rhs = wsv(W.rhs);
     VT* sol = wsv(W.sol);
@@ -433,19 +834,16 @@ struct Engine {
       AMG_TRY(kcycle(l, static_cast<const VT*>(rhs), z));
       if (k > 0) {
         VecPtrs qs{}, ps{};
-        for (int i = 0; i < k; ++i) { qs.p[i] = W.Q[i]; ps.p[i] = W.Z[i]; }
-        hipLaunchKernelGGL((k_multidot<VT, VT>), dim3(rblk(n)), dim3(TPB), 0, s, n, z, qs, k, h->partials,
-                           h->counter, h->scal, slots_range(base + 16, k));
-        hipLaunchKernelGGL((k_fcg_p<VT, VT>), dim3(rblk(n)), dim3(TPB), 0, s, n, z, z, ps, k, h->scal,
-                           slots_range(base + 16, k), slots_range(base, k));
+        for (int i = 0; i < k; ++i) {
+          qs.p[i] = W.Q[i];
+          ps.p[i] = W.Z[i];
+        }
+        AMG_TRY(multidot(l, n, z, qs, k, slots_range(base + 16, k), false));
+        AMG_TRY(fcg_p(l, n, z, z, ps, k, slots_range(base + 16, k), slots_range(base, k)));
       }
       VT* q = wsv(W.Q[k]);
-      hipLaunchKernelGGL((k_spmv_dots<VT, MT, VT>), dim3(Am.nb), dim3(TPB), 0, s, Am, z, q, rhs, h->partials,
-                         h->counter, h->scal, slots2(base + k, base + 8 + k));
-      hipLaunchKernelGGL((k_fcg_xr<VT, VT, false>), dim3(rblk(n)), dim3(TPB), 0, s, n, z, q, sol, rhs, h->scal,
-                         base + k, base + 8 + k, (int)(k == 0), (int)(k + 1 < nu), h->partials, h->counter,
-                         h->scal, slots1(S_DUMMY));
-      AMG_HIP(hipGetLastError());
+      AMG_TRY(spmv_dots(l, z, q, rhs, slots2(base + k, base + 8 + k)));
+      AMG_TRY(fcg_xr(l, n, z, q, sol, rhs, base + k, base + 8 + k, k == 0, k + 1 < nu));
     }
     return AMG_OK;
   }
@@ -453,26 +851,40 @@ struct Engine {
   // one outer iteration at window position j; u, r FP64 (finest level)
   int32_t outer_iter(int j, double* u) {
     const int n = h->lv[0].n;
+    const int nb = nblk(n);
     const auto A64 = mat_of<double>(h->lv[0]);
     VT* z = wsv(h->z);
     AMG_TRY(kcycle(0, static_cast<const double*>(h->r), z));
     VecPtrs qs{}, ps{};
-    for (int i = 0; i < j; ++i) { qs.p[i] = h->Qo[i]; ps.p[i] = h->P[i]; }
-    if (j > 0) {
-      hipLaunchKernelGGL((k_multidot<VT, double>), dim3(rblk(n)), dim3(TPB), 0, s, n, z, qs, j, h->partials,
-                         h->counter, h->scal, slots_range(S_DOTS, j));
+    for (int i = 0; i < j; ++i) {
+      qs.p[i] = h->Qo[i];
+      ps.p[i] = h->P[i];
     }
-    hipLaunchKernelGGL((k_fcg_p<double, VT>), dim3(rblk(n)), dim3(TPB), 0, s, n, h->P[j], z, ps, j, h->scal,
+    if (j > 0) AMG_TRY(multidot(0, n, z, qs, j, slots_range(S_DOTS, j), true));
+    hipLaunchKernelGGL((k_fcg_p<double, VT>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], z, ps, j, h->scal,
                        slots_range(S_DOTS, j), slots_range(S_RHOW, j));
+    const Slots pq = slots2(S_RHOW + j, S_GAM);
     hipLaunchKernelGGL((k_spmv_dots<double, double, double>), dim3(A64.nb), dim3(TPB), 0, s, A64, h->P[j], h->Qo[j],
-                       h->r, h->partials, h->counter, h->scal, slots2(S_RHOW + j, S_GAM));
-    hipLaunchKernelGGL((k_fcg_xr<double, double, true>), dim3(rblk(n)), dim3(TPB), 0, s, n, h->P[j], h->Qo[j], u,
-                       h->r, h->scal, S_RHOW + j, S_GAM, 0, 1, h->partials, h->counter, h->scal, slots1(S_RR));
+                       h->r, red_for(A64.nb, pq));
+    AMG_TRY(finish<2>(A64.nb, pq));
+    const Slots rr = slots1(S_RR);
+    hipLaunchKernelGGL((k_fcg_xr<double, double, true>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], h->Qo[j], u, h->r,
+                       h->scal, S_RHOW + j, S_GAM, 0, 1, red_for(nb, rr));
+    AMG_TRY(finish<1>(nb, rr));
     AMG_HIP(hipGetLastError());
     // stopping test inputs: (r, r) and rho_j
     AMG_HIP(hipMemcpyAsync(h->host_scal, h->scal + S_RR, sizeof(double), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipMemcpyAsync(h->host_scal + 1, h->scal + S_RHOW + j, sizeof(double), hipMemcpyDeviceToHost, s));
     return AMG_OK;
+  }
+
+  // out = f - A u (FP64) and its squared norm into scal[slot]
+  int32_t residual64(const double* f, const double* u, double* out, int slot) {
+    const auto A64 = mat_of<double>(h->lv[0]);
+    const Slots sl = slots1(slot);
+    hipLaunchKernelGGL(k_residual_dot, dim3(A64.nb), dim3(TPB), 0, s, A64, f, u, out, red_for(A64.nb, sl));
+    AMG_HIP(hipGetLastError());
+    return finish<1>(A64.nb, sl);
   }
 };
 
@@ -500,15 +912,10 @@ int32_t capture_graphs(amg_hier* h, double* u) {
 }
 
 template <typename VT, typename MT>
-int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
+int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info, bool force_eager) {
   auto t0 = clk::now();
-  const int n = h->lv[0].n;
-  const auto A64 = mat_of<double>(h->lv[0]);
   Engine<VT, MT> E{h, s};
-  // r = f - A u, rr0
-  hipLaunchKernelGGL(k_residual_dot, dim3(A64.nb), dim3(TPB), 0, s, A64, f, u, h->r, h->partials, h->counter,
-                     h->scal, slots1(S_RR0));
-  AMG_HIP(hipGetLastError());
+  AMG_TRY(E.residual64(f, u, h->r, S_RR0));
   AMG_HIP(hipMemcpyAsync(h->host_scal, h->scal + S_RR0, sizeof(double), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   const double rho0 = std::sqrt(h->host_scal[0]);
@@ -516,7 +923,7 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
   int it = 0;
   double rel = rho0 > 0.0 ? 1.0 : 0.0;
   if (rho0 > 0.0) {
-    const bool use_graph = h->p.use_graph != 0;
+    const bool use_graph = h->p.use_graph != 0 && !force_eager;
     if (use_graph && (!h->graphs_ready || h->graph_u != u)) {
       AMG_TRY(capture_graphs<VT, MT>(h, u));
       h->graph_u = u;
@@ -544,9 +951,7 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
     if (it > h->p.max_iter) it = h->p.max_iter;
   }
   // true FP64 residual of the returned u
-  hipLaunchKernelGGL(k_residual_dot, dim3(A64.nb), dim3(TPB), 0, s, A64, f, u, h->tmp, h->partials, h->counter,
-                     h->scal, slots1(S_RRT));
-  AMG_HIP(hipGetLastError());
+  AMG_TRY(E.residual64(f, u, h->tmp, S_RRT));
   AMG_HIP(hipMemcpyAsync(h->host_scal + 2, h->scal + S_RRT, sizeof(double), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   if (info) {
@@ -556,8 +961,42 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
     info->rel_res_true = rho0 > 0.0 ? std::sqrt(h->host_scal[2]) / rho0 : 0.0;
     info->solve_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
   }
-  (void)n;
   return status;
+}
+
+// Record the tail program (the inner solve of the tail level and everything
+// below it) and upload it with the level views it refers to.
+template <typename VT, typename MT>
+int32_t prepare_tail(amg_hier* h, hipStream_t s) {
+  h->tail_level = 0;
+  if (h->p.tail_rows <= 0 || h->L < 2 || !h->chol_inv) return AMG_OK;
+  int t = 0;
+  for (int l = 1; l < h->L; ++l) {
+    if (h->lv[l].n <= h->p.tail_rows) {
+      t = l;
+      break;
+    }
+  }
+  if (t == 0) return AMG_OK;
+  std::vector<TailOp> ops;
+  Engine<VT, MT> E{h, s, &ops};
+  AMG_TRY(E.inner(t));
+  std::vector<Mat<MT>> mats(h->L + 1);
+  std::vector<Transfer> trs(h->L + 1);
+  for (int l = t; l < h->L; ++l) {
+    mats[l] = mat_of<MT>(h->lv[l]);
+    trs[l] = transfer_of(h, l);
+  }
+  AMG_TRY(dalloc(h, &h->tail_ops, ops.size() * sizeof(TailOp) + 16));
+  AMG_TRY(dalloc(h, &h->tail_mats, mats.size() * sizeof(Mat<MT>) + 16));
+  AMG_TRY(dalloc(h, &h->tail_trs, trs.size() * sizeof(Transfer) + 16));
+  AMG_HIP(hipMemcpyAsync(h->tail_ops, ops.data(), ops.size() * sizeof(TailOp), hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(h->tail_mats, mats.data(), mats.size() * sizeof(Mat<MT>), hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(h->tail_trs, trs.data(), trs.size() * sizeof(Transfer), hipMemcpyHostToDevice, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  h->tail_nops = (int)ops.size();
+  h->tail_level = t;
+  return AMG_OK;
 }
 
 }  // namespace
@@ -573,7 +1012,8 @@ void destroy_graphs(amg_hier* h) {
 int32_t prepare_solve(amg_hier* h, hipStream_t s) {
   for (int l = 0; l < std::max(h->L, 1); ++l) {
     const Level& lv = h->lv[l];
-    if (!lv.sell_off || !lv.sell_w || !lv.sell_col || !lv.sell_val || !lv.D || (h->mixed && (!lv.sell_valf || !lv.Df))) {
+    if (!lv.sell_off || !lv.sell_w || !lv.sell_col || !lv.sell_val || !lv.D ||
+        (h->mixed && (!lv.sell_valf || !lv.Df))) {
       set_last_error("level " + std::to_string(l) + " has no sliced-ELL form");
       return AMG_ERR_DEVICE;
     }
@@ -607,20 +1047,57 @@ int32_t prepare_solve(amg_hier* h, hipStream_t s) {
     AMG_TRY(dalloc(h, &h->P[j], n0));
     AMG_TRY(dalloc(h, &h->Qo[j], n0));
   }
-  h->max_blocks = std::max(RED_BLOCKS, nblk(n0));
-  AMG_TRY(dalloc(h, &h->partials, (size_t)h->max_blocks * 8));
+  h->max_blocks = nblk(n0);
+  AMG_TRY(dalloc(h, &h->partials, (size_t)std::max(h->max_blocks, 1) * 8));
   AMG_TRY(dalloc(h, &h->scal, SCAL_SIZE));
   AMG_TRY(dalloc(h, &h->counter, 1));
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, h->counter);
   AMG_HIP(hipGetLastError());
   AMG_HIP(hipHostMalloc((void**)&h->host_scal, 64 * sizeof(double), hipHostMallocDefault));
   AMG_HIP(hipStreamSynchronize(s));
+  if (h->mixed) {
+    AMG_TRY(prepare_tail<float, float>(h, s));
+  } else {
+    AMG_TRY(prepare_tail<double, double>(h, s));
+  }
   return AMG_OK;
 }
 
 int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
-  if (h->mixed) return solve_impl<float, float>(h, f, u, s, info);
-  return solve_impl<double, double>(h, f, u, s, info);
+  if (h->mixed) return solve_impl<float, float>(h, f, u, s, info, false);
+  return solve_impl<double, double>(h, f, u, s, info, false);
+}
+
+int32_t profile_solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info,
+                      amg_kernel_timing* t) {
+  constexpr int kPairs = 2048;
+  if (h->probe_ev.empty()) {
+    h->probe_ev.resize(2 * kPairs);
+    for (auto& e : h->probe_ev) AMG_HIP(hipEventCreate(&e));
+  }
+  h->probe = true;
+  h->probe_used = 0;
+  const int32_t st = h->mixed ? solve_impl<float, float>(h, f, u, s, info, true)
+                              : solve_impl<double, double>(h, f, u, s, info, true);
+  h->probe = false;
+  std::memset(t, 0, sizeof(*t));
+  double sum = 0.0, mn = 1e30, mx = 0.0;
+  const int pairs = h->probe_used / 2;
+  for (int i = 0; i < pairs; ++i) {
+    float ms = 0.f;
+    AMG_HIP(hipEventElapsedTime(&ms, h->probe_ev[2 * i], h->probe_ev[2 * i + 1]));
+    sum += ms;
+    mn = std::min(mn, (double)ms);
+    mx = std::max(mx, (double)ms);
+  }
+  t->launches = pairs;
+  t->avg_ms = pairs ? sum / pairs : 0.0;
+  t->min_ms = pairs ? mn : 0.0;
+  t->max_ms = mx;
+  t->rows = h->lv[0].n;
+  t->nnz = h->lv[0].nnz;
+  t->grid = (int32_t)nblk(h->lv[0].n);
+  return st;
 }
 
 // ---- single steps (FP64 hierarchies, except the cycle) ------------------------

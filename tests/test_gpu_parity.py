@@ -225,3 +225,51 @@ def test_determinism(amg):
         sols.append(u.cpu().numpy())
         h.close()
     assert np.array_equal(sols[0], sols[1])
+
+
+@pytest.mark.parametrize("tail_rows", [0, 300, 1100, 70000])
+def test_tail_program_matches_oracle(amg, tail_rows):
+    """The one-workgroup tail interpreter (inner solves of levels with at most
+    tail_rows rows) gives the same cycle as the device-wide kernels."""
+    g = inputs.grid2d(90, 77)
+    p = amg.amg_params_default(degree=4, agg_size=4, tail_rows=tail_rows)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(p))
+    r = inputs.rhs(g.n, 21)
+    z = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    amg.amg_apply_cycle(h, _t(r), z)
+    assert _rel(z, oracle.kcycle(ho, 0, r)) <= 1e-10
+    f = inputs.rhs(g.n, 22)
+    u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, _t(f), u)
+    assert info["status"] == 0 and abs(info["iters"] - oracle.fcg(ho, f).iters) <= 1
+
+
+@pytest.mark.parametrize("make,kw", [
+    (lambda: inputs.tet3d(16), dict(degree=5, agg_size=16)),
+    (lambda: inputs.grid2d(120, 97), dict(degree=3, agg_size=4)),
+    (lambda: inputs.rgg(8000, seed=inputs.seed_for(4, 3)), dict(degree=4, agg_size=8)),
+])
+def test_mixed_precision_solve(amg, make, kw):
+    """FP32 cycle under FP64 flexible CG: true FP64 residual <= 1e-8 and the
+    A-norm error against the FP64 oracle solution <= 1e-6."""
+    g = make()
+    f = inputs.rhs(g.n, 31, "normal")
+    p = amg.amg_params_default(precision=amg.AMG_MIXED, **kw)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(p))
+    # the hierarchy is the same (FP64 setup), only the cycle runs in FP32
+    assert amg.amg_describe(h)["n"] == [l.n for l in ho.levels]
+    r = _t(f)
+    z = torch.zeros_like(r)
+    amg.amg_apply_cycle(h, r, z)
+    assert _rel(z, oracle.kcycle(ho, 0, f)) <= 1e-5
+    u = torch.zeros_like(r)
+    info = amg.amg_solve(h, r, u)
+    res = oracle.fcg(ho, f)
+    assert info["status"] == 0 and info["rel_res_true"] <= 1.05e-8
+    assert info["iters"] <= res.iters + 3
+    lo = ho.levels[0]
+    e = u.cpu().numpy() - res.x
+    errA = np.sqrt(e @ oracle.apply_A(lo, e)) / np.sqrt(res.x @ oracle.apply_A(lo, res.x))
+    assert errA <= 1e-6
