@@ -75,8 +75,10 @@ enum { AMG_KEY_NORMALIZED = 0, AMG_KEY_RAW = 1 };
  *   stagnation    a level that keeps more than this fraction of its rows stops
  *                 the coarsening.
  *   use_graph     1: replay the cycle and the outer iteration as HIP graphs.
- *   tail_rows     levels with at most this many rows run their whole k-cycle in
- *                 one workgroup-resident kernel (0 disables).
+ *   tail_rows     the inner solve of the finest level with at most this many
+ *                 rows whose data (with all coarser levels) fits in one
+ *                 workgroup's LDS runs as one workgroup-resident kernel
+ *                 (0 disables).
  */
 typedef struct {
   int32_t degree;
@@ -126,7 +128,7 @@ typedef struct {
 /* Fill *p with the defaults: degree 4, agg_size 4, coarse_max 64,
  * lambda0_ratio 10, inner_steps 2, restart 5, tol 1e-8, max_iter 200, FP64,
  * normalized key, max_coarsest 2048, stagnation 0.9, use_graph 1,
- * tail_rows 512. */
+ * tail_rows 4096. */
 void amg_params_default(amg_params* p);
 
 /* Human-readable name of a status code (static string). */
@@ -171,26 +173,24 @@ int32_t amg_describe(const amg_hier* h, amg_hier_desc* out);
  */
 int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info);
 
-/* Duration of the finest level's interior Chebyshev step kernel (one fused
- * pass: w_{k+1} = 2 (A w_k - theta w_k)/eta - w_{k-1}, y += c_{k+1} w_{k+1};
- * Section 3 smoother) as measured by HIP events around each launch during a
- * profiled solve. */
+/* Duration of the finest level's interior Chebyshev step (one fused pass over
+ * the level: w_{k+1} = 2 (A w_k - theta w_k)/eta - w_{k-1}, y += c_{k+1} w_{k+1};
+ * the smoother of Section 3), the solve's dominant kernel.  amg_time_step
+ * launches that kernel `reps` times back to back on `stream`, on the
+ * hierarchy's own workspace (it overwrites the finest level's smoother
+ * buffers, not the caller's vectors), between two HIP events, and reports the
+ * mean time per launch.  Needs at least two levels. */
 typedef struct {
-  int32_t launches;   /* timed launches                          */
-  double avg_ms;      /* mean event-to-event duration per launch */
-  double min_ms;
-  double max_ms;
-  int32_t rows;       /* rows of the finest level                */
-  int64_t nnz;        /* stored off-diagonal entries             */
-  int32_t grid;       /* workgroups per launch (256 rows each)   */
+  int32_t launches;     /* timed launches                           */
+  double avg_ms;        /* event-to-event time / launches           */
+  int32_t rows;         /* rows of the finest level                 */
+  int64_t nnz;          /* stored off-diagonal entries              */
+  int64_t entries;      /* sliced-ELL entries including padding     */
+  int32_t grid;         /* workgroups per launch (256 rows each)    */
+  int32_t value_bytes;  /* 8 (FP64 cycle) or 4 (mixed: FP32 cycle)  */
 } amg_kernel_timing;
 
-/* Same as amg_solve, but launched eagerly (no graph replay) with HIP events
- * recorded on `stream` around every interior Chebyshev step of the finest
- * level; fills *timing.  Needs at least two levels and degree >= 3.  For
- * measurement only: the extra events make it slower than amg_solve. */
-int32_t amg_profile_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info,
-                          amg_kernel_timing* timing);
+int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing* timing);
 
 /* ---- Level inspection and single steps (tests and diagnostics) ------------
  * The single steps below (all but amg_apply_cycle) need an AMG_FP64

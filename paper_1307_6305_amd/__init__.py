@@ -91,11 +91,11 @@ class amg_kernel_timing(ctypes.Structure):
     _fields_ = [
         ("launches", ctypes.c_int32),
         ("avg_ms", ctypes.c_double),
-        ("min_ms", ctypes.c_double),
-        ("max_ms", ctypes.c_double),
         ("rows", ctypes.c_int32),
         ("nnz", ctypes.c_int64),
+        ("entries", ctypes.c_int64),
         ("grid", ctypes.c_int32),
+        ("value_bytes", ctypes.c_int32),
     ]
 
 
@@ -118,7 +118,7 @@ SIGNATURES = {
     "amg_free": (None, [_P]),
     "amg_describe": (_I32, [_P, ctypes.POINTER(amg_hier_desc)]),
     "amg_solve": (_I32, [_P, _P, _P, _P, ctypes.POINTER(amg_info)]),
-    "amg_profile_solve": (_I32, [_P, _P, _P, _P, ctypes.POINTER(amg_info), ctypes.POINTER(amg_kernel_timing)]),
+    "amg_time_step": (_I32, [_P, _I32, _P, ctypes.POINTER(amg_kernel_timing)]),
     "amg_level_export": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P]),
     "amg_apply_smoother": (_I32, [_P, _I32, _P, _P, _P]),
     "amg_apply_residual": (_I32, [_P, _I32, _P, _P, _P, _P]),
@@ -257,19 +257,13 @@ def amg_solve(h: Hierarchy, f, u, stream=None, check: bool = False) -> dict:
             "rel_res_true": info.rel_res_true, "solve_ms": info.solve_ms}
 
 
-def amg_profile_solve(h: Hierarchy, f, u, stream=None) -> tuple:
-    """amg_solve launched eagerly with HIP events around the finest level's
-    interior Chebyshev steps; returns (info dict, timing dict)."""
-    info = amg_info()
+def amg_time_step(h: Hierarchy, reps: int = 200, stream=None) -> dict:
+    """Mean duration of the finest level's storing Chebyshev step over ``reps``
+    back-to-back launches between HIP events on ``stream``."""
     t = amg_kernel_timing()
-    code = load_library().amg_profile_solve(h.handle, _dev(f, h.n, "f"), _dev(u, h.n, "u"), _stream(stream),
-                                            ctypes.byref(info), ctypes.byref(t))
-    if code in (AMG_ERR_ARG, AMG_ERR_DEVICE, AMG_ERR_NOMEM):
-        _check(code, "amg_profile_solve")
-    return ({"status": info.status, "iters": info.iters, "rel_res": info.rel_res,
-             "rel_res_true": info.rel_res_true, "solve_ms": info.solve_ms},
-            {"launches": t.launches, "avg_ms": t.avg_ms, "min_ms": t.min_ms, "max_ms": t.max_ms,
-             "rows": t.rows, "nnz": t.nnz, "grid": t.grid})
+    _check(load_library().amg_time_step(h.handle, int(reps), _stream(stream), ctypes.byref(t)), "amg_time_step")
+    return {"launches": t.launches, "avg_ms": t.avg_ms, "rows": t.rows, "nnz": t.nnz, "entries": t.entries,
+            "grid": t.grid, "value_bytes": t.value_bytes}
 
 
 def amg_level_export(h: Hierarchy, level: int) -> dict:

@@ -85,7 +85,7 @@ void amg_params_default(amg_params* p) {
   p->max_coarsest = 2048;
   p->stagnation = 0.9;
   p->use_graph = 1;
-  p->tail_rows = 512;
+  p->tail_rows = 4096;
 }
 
 const char* amg_strerror(int32_t s) {
@@ -142,7 +142,6 @@ void amg_free(amg_hier* h) {
   if (h->graph_stream) (void)hipStreamDestroy(h->graph_stream);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->host_scal) (void)hipHostFree(h->host_scal);
-  for (hipEvent_t e : h->probe_ev) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -157,14 +156,10 @@ int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_inf
   return amg::solve(h, f, u, static_cast<hipStream_t>(stream), info);
 }
 
-int32_t amg_profile_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info,
-                          amg_kernel_timing* timing) {
-  if (!h || !f || !u || !timing) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
-  if (h->L < 1 || h->p.degree < 3) {
-    amg::set_last_error("profiling needs at least two levels and degree >= 3");
-    return AMG_ERR_ARG;
-  }
-  return amg::profile_solve(h, f, u, static_cast<hipStream_t>(stream), info, timing);
+int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing* timing) {
+  if (!h || !timing || reps < 1) { amg::set_last_error("invalid argument"); return AMG_ERR_ARG; }
+  if (h->L < 1) { amg::set_last_error("the finest level is not smoothed in a one-level hierarchy"); return AMG_ERR_ARG; }
+  return amg::time_step(h, reps, static_cast<hipStream_t>(stream), timing);
 }
 
 int32_t amg_level_export(const amg_hier* h, int32_t level, int32_t* row_ptr, int32_t* col, double* W, double* d,

@@ -25,9 +25,10 @@ struct amg_hier {
   // one workgroup (0 = no tail)
   int tail_level = 0;
   int tail_nops = 0;
-  void* tail_ops = nullptr;
-  void* tail_mats = nullptr;
-  void* tail_trs = nullptr;
+  size_t tail_lds_bytes = 0;           // dynamic LDS of the tail kernel
+  int tail_threads = 0;                // workgroup size of the tail kernel
+  const void* tail_prog = nullptr;     // kernel argument block (host copy)
+  std::vector<char> tail_prog_storage;
 
   // Solve workspace.  `vt` buffers hold the cycle's vector type (double, or
   // float in mixed precision); per level: A, B (smoother recurrence), S
@@ -54,18 +55,13 @@ struct amg_hier {
   unsigned* counter = nullptr;  // grid-reduction arrival counter
   double* host_scal = nullptr;  // pinned host mirror of a few scalars
   int max_blocks = 0;
+  int last_block_max = 16;
 
   // replayable outer iterations (one per position in the restart window)
   bool graphs_ready = false;
   hipGraphExec_t iter_exec[8] = {};
   hipStream_t graph_stream = nullptr;  // stream the graphs were captured on
   const void* graph_u = nullptr;       // solution pointer baked into the graphs
-
-  // timing probe of the finest level's Chebyshev step (eager solves only):
-  // events bracket every launch that stores w_{k+1}
-  bool probe = false;
-  std::vector<hipEvent_t> probe_ev;
-  int probe_used = 0;
 
   amg_hier_desc desc{};
   std::vector<void*> allocs;
@@ -98,7 +94,6 @@ int32_t step_coarse(amg_hier* h, const double* b, double* x, hipStream_t s);
 int32_t step_cycle(amg_hier* h, const double* r, double* z, hipStream_t s);
 
 int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info);
-int32_t profile_solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info,
-                      amg_kernel_timing* t);
+int32_t time_step(amg_hier* h, int reps, hipStream_t s, amg_kernel_timing* t);
 
 }  // namespace amg

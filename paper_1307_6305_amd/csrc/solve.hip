@@ -25,6 +25,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 
@@ -36,7 +38,6 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int TAIL_THREADS = 1024;
-constexpr int LAST_BLOCK_MAX = 16;  // grids up to this size finish their reduction in-kernel
 
 // Scalar area.  Outer iteration: rr, (p,r), window dots, window rho.
 // Inner solve on level l: base(l) + [0,8) rho_k, [8,16) gamma_k, [16,24) dots.
@@ -191,11 +192,14 @@ __global__ void __launch_bounds__(TPB) k_cheb_first(Mat<MT> A, const RT* __restr
   if (r >= 0) row_cheb_first<VT, MT, RT>(A, r, w0, w1, y, theta, inv_eta, c0, c1, accum, store);
 }
 
-template <typename VT, typename MT, typename PT>
+// STORE: w_{k+1} is written (every step but the last).  FINE marks launches
+// on the finest level: the same code, a separate instance so that profiles
+// report the finest level's dominant step on its own.
+template <typename VT, typename MT, typename PT, bool STORE, bool FINE>
 __global__ void __launch_bounds__(TPB) k_cheb_next(Mat<MT> A, const VT* __restrict__ wk, const PT* wprev, VT* wnext,
-                                                   VT* y, double theta, double two_inv_eta, double ck, int store) {
+                                                   VT* y, double theta, double two_inv_eta, double ck) {
   const int r = row_of(A);
-  if (r >= 0) row_cheb_next<VT, MT, PT>(A, r, wk, wprev, wnext, y, theta, two_inv_eta, ck, store);
+  if (r >= 0) row_cheb_next<VT, MT, PT>(A, r, wk, wprev, wnext, y, theta, two_inv_eta, ck, STORE);
 }
 
 // degree 0: y = [y +] c0 w0
@@ -399,36 +403,102 @@ struct TailOp {
   Slots s0, s1;
 };
 
+// The tail program runs entirely out of the workgroup's LDS: its op list,
+// the level descriptors, the matrices, transfer maps, coarsest factor,
+// vectors and scalars are laid out in one LDS image that the kernel fills
+// from device memory at start; the tail level's solution is copied back at the
+// end.  Inside the image every operand is a byte offset, recorded with bit 62
+// set (no device address has that bit) so that a recording mistake cannot
+// pass for a device pointer.
+constexpr uint64_t kLdsTag = 1ull << 62;
+
+template <typename T>
+__device__ __forceinline__ T* at(char* lds, const void* tag) {
+  return reinterpret_cast<T*>(lds + (uint32_t)(uint64_t)tag);
+}
+
+template <typename MT>
+__device__ __forceinline__ Mat<MT> lds_mat(const Mat<MT>& A, char* lds) {
+  Mat<MT> B = A;
+  B.off = at<const int>(lds, A.off);
+  B.width = at<const int>(lds, A.width);
+  B.col = at<const int>(lds, A.col);
+  B.val = at<const MT>(lds, A.val);
+  B.D = at<const MT>(lds, A.D);
+  return B;
+}
+
+__device__ __forceinline__ Transfer lds_tr(const Transfer& T, char* lds) {
+  Transfer U = T;
+  U.agg = at<const int>(lds, T.agg);
+  U.members = at<const int>(lds, T.members);
+  U.member_off = at<const int>(lds, T.member_off);
+  return U;
+}
+
+struct TailCopy {
+  const void* src;  // device address
+  uint32_t dst;     // LDS byte offset
+  int bytes;        // multiple of 16
+};
+
+struct TailProgram {
+  int nops;
+  int ncin;
+  uint32_t ops_off;   // LDS offset of the op list
+  uint32_t mats_off;  // LDS offset of Mat<MT>[L + 1]
+  uint32_t trs_off;   // LDS offset of Transfer[L + 1]
+  uint32_t scal_off;  // LDS offset of the scalar area
+  const TailCopy* cin;
+  TailCopy cout;  // solution of the tail level, LDS -> device
+  CoarseView C;   // Linv, LinvT as tagged LDS offsets
+};
+
 // Runs a recorded op program in one workgroup; every op is a data-parallel
 // loop over rows followed by a workgroup barrier.  Reductions are workgroup
 // reductions (no grid synchronization needed).
 template <typename VT, typename MT>
-__global__ void __launch_bounds__(TAIL_THREADS) k_tail(const TailOp* __restrict__ ops, int nops,
-                                                       const Mat<MT>* __restrict__ mats,
-                                                       const Transfer* __restrict__ trs, CoarseView C, double* scal) {
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailProgram P) {
+  extern __shared__ __align__(16) char lds[];
   __shared__ double red[16 * 8];
   __shared__ double sb[1024], sy[1024];
   const int tid = threadIdx.x, bd = blockDim.x;
-  for (int o = 0; o < nops; ++o) {
+  for (int c = 0; c < P.ncin; ++c) {
+    const TailCopy cp = P.cin[c];
+    const int4* src = static_cast<const int4*>(cp.src);
+    int4* dst = reinterpret_cast<int4*>(lds + cp.dst);
+    for (int i = tid; i < (cp.bytes >> 4); i += bd) dst[i] = src[i];
+  }
+  __syncthreads();
+  double* scal = reinterpret_cast<double*>(lds + P.scal_off);
+  const CoarseView C{P.C.n, at<const double>(lds, P.C.Linv), at<const double>(lds, P.C.LinvT)};
+  const TailOp* ops = reinterpret_cast<const TailOp*>(lds + P.ops_off);
+  const Mat<MT>* mats = reinterpret_cast<const Mat<MT>*>(lds + P.mats_off);
+  const Transfer* trs = reinterpret_cast<const Transfer*>(lds + P.trs_off);
+  for (int o = 0; o < P.nops; ++o) {
     const TailOp& op = ops[o];
     switch (op.type) {
       case OP_CHEB_FIRST: {
-        const Mat<MT> A = mats[op.level];
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* w0 = at<const VT>(lds, op.a);
+        VT* w1 = at<VT>(lds, op.c);
+        VT* y = at<VT>(lds, op.d);
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_first<VT, MT, VT>(A, r, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.f3, op.i0,
-                                     op.i1);
+          row_cheb_first<VT, MT, VT>(A, r, w0, w1, y, op.f0, op.f1, op.f2, op.f3, op.i0, op.i1);
         break;
       }
       case OP_CHEB_NEXT: {
-        const Mat<MT> A = mats[op.level];
-        for (int r = tid; r < A.n; r += bd)
-          row_cheb_next<VT, MT, VT>(A, r, (const VT*)op.a, (const VT*)op.b, (VT*)op.c, (VT*)op.d, op.f0, op.f1,
-                                    op.f2, op.i0);
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* wk = at<const VT>(lds, op.a);
+        const VT* wp = at<const VT>(lds, op.b);
+        VT* wn = at<VT>(lds, op.c);
+        VT* y = at<VT>(lds, op.d);
+        for (int r = tid; r < A.n; r += bd) row_cheb_next<VT, MT, VT>(A, r, wk, wp, wn, y, op.f0, op.f1, op.f2, op.i0);
         break;
       }
       case OP_SCALE_ADD: {
-        const VT* w0 = (const VT*)op.a;
-        VT* y = (VT*)op.d;
+        const VT* w0 = at<const VT>(lds, op.a);
+        VT* y = at<VT>(lds, op.d);
         for (int i = tid; i < op.n; i += bd) {
           VT v = (VT)op.f0 * w0[i];
           if (op.i0) v += y[i];
@@ -437,34 +507,40 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(const TailOp* __restrict_
         break;
       }
       case OP_RESIDUAL: {
-        const Mat<MT> A = mats[op.level];
-        for (int r = tid; r < A.n; r += bd)
-          row_residual<VT, MT, VT>(A, r, (const VT*)op.a, (const VT*)op.b, (VT*)op.c);
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* f = at<const VT>(lds, op.a);
+        const VT* x = at<const VT>(lds, op.b);
+        VT* sv = at<VT>(lds, op.c);
+        for (int r = tid; r < A.n; r += bd) row_residual<VT, MT, VT>(A, r, f, x, sv);
         break;
       }
       case OP_RESTRICT: {
-        const Transfer T = trs[op.level];
-        for (int I = tid; I < T.nc; I += bd) row_restrict<VT>(T, I, (const VT*)op.a, (VT*)op.c);
+        const Transfer T = lds_tr(trs[op.level], lds);
+        const VT* sv = at<const VT>(lds, op.a);
+        VT* b = at<VT>(lds, op.c);
+        for (int I = tid; I < T.nc; I += bd) row_restrict<VT>(T, I, sv, b);
         break;
       }
       case OP_PROLONG: {
-        const Transfer T = trs[op.level];
-        for (int i = tid; i < T.n; i += bd) row_prolong<VT>(T, i, (const VT*)op.a, (VT*)op.c);
+        const Transfer T = lds_tr(trs[op.level], lds);
+        const VT* e = at<const VT>(lds, op.a);
+        VT* x = at<VT>(lds, op.c);
+        for (int i = tid; i < T.n; i += bd) row_prolong<VT>(T, i, e, x);
         break;
       }
       case OP_COARSE:
-        coarse_apply<VT, VT>(C, (const VT*)op.a, (VT*)op.c, sb, sy);
+        coarse_apply<VT, VT>(C, at<const VT>(lds, op.a), at<VT>(lds, op.c), sb, sy);
         break;
       case OP_MULTIDOT: {
         double v[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = 0.0;
-        const VT* z = (const VT*)op.a;
+        const VT* z = at<const VT>(lds, op.a);
         for (int j = tid; j < op.n; j += bd) {
           const double zj = (double)z[j];
 #pragma unroll
           for (int i = 0; i < 8; ++i)
-            if (i < op.k) v[i] += zj * (double)((const VT*)op.w.p[i])[j];
+            if (i < op.k) v[i] += zj * (double)at<const VT>(lds, op.w.p[i])[j];
         }
         block_sum<8>(v, red);
         if (tid == 0)
@@ -475,22 +551,24 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(const TailOp* __restrict_
         double beta[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) beta[i] = i < op.k ? fcg_beta(scal, op.s0.s[i], op.s1.s[i]) : 0.0;
-        const VT* z = (const VT*)op.a;
-        VT* p = (VT*)op.c;
+        const VT* z = at<const VT>(lds, op.a);
+        VT* p = at<VT>(lds, op.c);
         for (int j = tid; j < op.n; j += bd) {
           double v = (double)z[j];
 #pragma unroll
           for (int i = 0; i < 8; ++i)
-            if (i < op.k) v -= beta[i] * (double)((const VT*)op.w.p[i])[j];
+            if (i < op.k) v -= beta[i] * (double)at<const VT>(lds, op.w.p[i])[j];
           p[j] = (VT)v;
         }
         break;
       }
       case OP_SPMV_DOTS: {
-        const Mat<MT> A = mats[op.level];
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* p = at<const VT>(lds, op.a);
+        const VT* rv = at<const VT>(lds, op.b);
+        VT* q = at<VT>(lds, op.c);
         double v[2] = {0.0, 0.0};
-        for (int r = tid; r < A.n; r += bd)
-          row_spmv_dots<VT, MT, VT>(A, r, (const VT*)op.a, (VT*)op.c, (const VT*)op.b, v);
+        for (int r = tid; r < A.n; r += bd) row_spmv_dots<VT, MT, VT>(A, r, p, q, rv, v);
         block_sum<2>(v, red);
         if (tid == 0) {
           scal[op.s0.s[0]] = v[0];
@@ -500,10 +578,10 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(const TailOp* __restrict_
       }
       case OP_FCG_XR: {
         const double alpha = fcg_alpha(scal, op.i0, op.i1);
-        const VT* p = (const VT*)op.a;
-        const VT* q = (const VT*)op.b;
-        VT* x = (VT*)op.c;
-        VT* r = (VT*)op.d;
+        const VT* p = at<const VT>(lds, op.a);
+        const VT* q = at<const VT>(lds, op.b);
+        VT* x = at<VT>(lds, op.c);
+        VT* r = at<VT>(lds, op.d);
         for (int j = tid; j < op.n; j += bd) {
           const double pj = (double)p[j];
           x[j] = (VT)(op.i2 ? alpha * pj : (double)x[j] + alpha * pj);
@@ -515,6 +593,11 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(const TailOp* __restrict_
         break;
     }
     __syncthreads();
+  }
+  {
+    const int4* src = reinterpret_cast<const int4*>(lds + P.cout.dst);
+    int4* dst = static_cast<int4*>(const_cast<void*>(P.cout.src));
+    for (int i = tid; i < (P.cout.bytes >> 4); i += bd) dst[i] = src[i];
   }
 }
 
@@ -558,11 +641,11 @@ struct Engine {
 
   // reduction destination for a device-wide kernel of `blocks` blocks
   Red red_for(int blocks, Slots slots) const {
-    return Red{h->partials, h->counter, h->scal, slots, blocks <= LAST_BLOCK_MAX ? 1 : 0};
+    return Red{h->partials, h->counter, h->scal, slots, blocks <= h->last_block_max ? 1 : 0};
   }
   template <int K>
   int32_t finish(int blocks, Slots slots) {
-    if (blocks <= LAST_BLOCK_MAX) return AMG_OK;
+    if (blocks <= h->last_block_max) return AMG_OK;
     hipLaunchKernelGGL((k_finish_sum<K>), dim3(1), dim3(kFinishThreads), 0, s, blocks, h->partials, h->scal, slots);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
@@ -604,15 +687,41 @@ struct Engine {
       return AMG_ERR_DEVICE;
     }
     const auto Am = A(l);
-    const bool probe = h->probe && l == 0 && store && h->probe_used + 2 <= (int)h->probe_ev.size();
-    if (probe) AMG_HIP(hipEventRecord(h->probe_ev[h->probe_used], s));
-    hipLaunchKernelGGL((k_cheb_next<VT, MT, PT>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev, wnext, y, lv.theta,
-                       2.0 / lv.eta, ck, (int)store);
-    AMG_HIP(hipGetLastError());
-    if (probe) {
-      AMG_HIP(hipEventRecord(h->probe_ev[h->probe_used + 1], s));
-      h->probe_used += 2;
+    const double ti = 2.0 / lv.eta;
+    if (l == 0) {
+      if (store)
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, true>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev, wnext,
+                           y, lv.theta, ti, ck);
+      else
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, true>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev,
+                           wnext, y, lv.theta, ti, ck);
+    } else {
+      if (store)
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, false>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev,
+                           wnext, y, lv.theta, ti, ck);
+      else
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, false>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev,
+                           wnext, y, lv.theta, ti, ck);
     }
+    AMG_HIP(hipGetLastError());
+    return AMG_OK;
+  }
+
+  // `reps` back-to-back launches of the finest level's storing Chebyshev step
+  // (w_k fixed in buffer A, w_{k-1} and w_{k+1} in buffer B, y in S) between
+  // two events; values stay bounded (B alternates between two vectors).
+  int32_t time_fine_step(int reps, hipEvent_t e0, hipEvent_t e1) {
+    const Level& lv = h->lv[0];
+    const auto Am = A(0);
+    VT* wk = wsv(h->ws[0].A);
+    VT* wb = wsv(h->ws[0].B);
+    VT* y = wsv(h->ws[0].S);
+    AMG_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i)
+      hipLaunchKernelGGL((k_cheb_next<VT, MT, VT, true, true>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wb, wb, y,
+                         lv.theta, 2.0 / lv.eta, 1e-3);
+    AMG_HIP(hipGetLastError());
+    AMG_HIP(hipEventRecord(e1, s));
     return AMG_OK;
   }
 
@@ -791,9 +900,8 @@ struct Engine {
 
   // the recorded inner solve of the tail level, in one workgroup
   int32_t tail() {
-    hipLaunchKernelGGL((k_tail<VT, MT>), dim3(1), dim3(TAIL_THREADS), 0, s, (const TailOp*)h->tail_ops,
-                       h->tail_nops, (const Mat<MT>*)h->tail_mats, (const Transfer*)h->tail_trs,
-                       CoarseView{h->nL, h->chol_inv, h->chol_invT}, h->scal);
+    hipLaunchKernelGGL((k_tail<VT, MT>), dim3(1), dim3(h->tail_threads), h->tail_lds_bytes, s,
+                       *static_cast<const TailProgram*>(h->tail_prog));
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
@@ -912,7 +1020,7 @@ int32_t capture_graphs(amg_hier* h, double* u) {
 }
 
 template <typename VT, typename MT>
-int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info, bool force_eager) {
+int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
   auto t0 = clk::now();
   Engine<VT, MT> E{h, s};
   AMG_TRY(E.residual64(f, u, h->r, S_RR0));
@@ -923,7 +1031,7 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
   int it = 0;
   double rel = rho0 > 0.0 ? 1.0 : 0.0;
   if (rho0 > 0.0) {
-    const bool use_graph = h->p.use_graph != 0 && !force_eager;
+    const bool use_graph = h->p.use_graph != 0;
     if (use_graph && (!h->graphs_ready || h->graph_u != u)) {
       AMG_TRY(capture_graphs<VT, MT>(h, u));
       h->graph_u = u;
@@ -965,36 +1073,175 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
 }
 
 // Record the tail program (the inner solve of the tail level and everything
-// below it) and upload it with the level views it refers to.
+// below it), place the data it touches in LDS, and upload it.  The tail level
+// is the finest level t >= 1 with at most tail_rows rows whose levels t..L fit
+// in the LDS left over by the kernel's static arrays.
+struct LdsBuf {
+  const void* g;
+  size_t bytes;
+  bool copy_in;
+};
+
+inline size_t round16(size_t b) { return (b + 15) & ~size_t(15); }
+
+template <typename VT, typename MT>
+void tail_buffers(const amg_hier* h, int t, std::vector<LdsBuf>& bufs) {
+  const size_t vt = sizeof(VT), mt = sizeof(MT);
+  const int nu = h->p.inner_steps;
+  for (int l = t; l < h->L; ++l) {
+    const Level& lv = h->lv[l];
+    const size_t n = lv.n;
+    const Mat<MT> A = mat_of<MT>(lv);
+    bufs.push_back({A.off, sizeof(int) * (lv.nslices + 1), true});
+    bufs.push_back({A.width, sizeof(int) * lv.nslices, true});
+    bufs.push_back({A.col, sizeof(int) * lv.sell_entries, true});
+    bufs.push_back({A.val, mt * lv.sell_entries, true});
+    bufs.push_back({A.D, mt * n, true});
+    bufs.push_back({lv.agg, sizeof(int) * n, true});
+    bufs.push_back({lv.members, sizeof(int) * n, true});
+    bufs.push_back({lv.member_off, sizeof(int) * (h->lv[l + 1].n + 1), true});
+    const auto& W = h->ws[l];
+    bufs.push_back({W.A, vt * n, false});
+    bufs.push_back({W.B, vt * n, false});
+    bufs.push_back({W.S, vt * n, false});
+    bufs.push_back({W.rhs, vt * n, l == t});
+    bufs.push_back({W.sol, vt * n, false});
+    for (int k = 0; k < nu; ++k) {
+      bufs.push_back({W.Z[k], vt * n, false});
+      bufs.push_back({W.Q[k], vt * n, false});
+    }
+  }
+  const size_t nL = h->nL;
+  bufs.push_back({h->ws[h->L].rhs, vt * nL, false});
+  bufs.push_back({h->ws[h->L].sol, vt * nL, false});
+  bufs.push_back({h->chol_inv, sizeof(double) * nL * nL, true});
+  bufs.push_back({h->chol_invT, sizeof(double) * nL * nL, true});
+  bufs.push_back({h->scal, sizeof(double) * SCAL_SIZE, false});
+}
+
 template <typename VT, typename MT>
 int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   h->tail_level = 0;
   if (h->p.tail_rows <= 0 || h->L < 2 || !h->chol_inv) return AMG_OK;
+  int max_lds = 0;
+  AMG_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+  const size_t static_lds = sizeof(double) * (16 * 8 + 2 * 1024) + 1024;  // red, sb, sy + margin
+  if ((size_t)max_lds <= static_lds) return AMG_OK;
+  const size_t budget = (size_t)max_lds - static_lds;
+  // LDS image: [op list][Mat descriptors][Transfer descriptors][level data ...]
+  auto program_bytes = [&](int t, size_t* nops_out) -> size_t {
+    std::vector<TailOp> ops;
+    Engine<VT, MT> E{h, s, &ops};
+    if (E.inner(t) != AMG_OK) return SIZE_MAX;
+    *nops_out = ops.size();
+    return round16(ops.size() * sizeof(TailOp)) + round16((h->L + 1) * sizeof(Mat<MT>)) +
+           round16((h->L + 1) * sizeof(Transfer));
+  };
   int t = 0;
-  for (int l = 1; l < h->L; ++l) {
-    if (h->lv[l].n <= h->p.tail_rows) {
-      t = l;
-      break;
-    }
+  for (int cand = h->L - 1; cand >= 1; --cand) {
+    if (h->lv[cand].n > h->p.tail_rows || h->lv[cand].n > TAIL_THREADS * 4) break;
+    std::vector<LdsBuf> bufs;
+    tail_buffers<VT, MT>(h, cand, bufs);
+    size_t nops = 0;
+    size_t tot = program_bytes(cand, &nops);
+    if (tot == SIZE_MAX) break;
+    for (const auto& b : bufs) tot += round16(b.bytes);
+    if (tot > budget) break;
+    t = cand;
   }
   if (t == 0) return AMG_OK;
   std::vector<TailOp> ops;
-  Engine<VT, MT> E{h, s, &ops};
-  AMG_TRY(E.inner(t));
+  {
+    Engine<VT, MT> E{h, s, &ops};
+    AMG_TRY(E.inner(t));
+  }
+  const uint32_t ops_off = 0;
+  const uint32_t mats_off = ops_off + (uint32_t)round16(ops.size() * sizeof(TailOp));
+  const uint32_t trs_off = mats_off + (uint32_t)round16((h->L + 1) * sizeof(Mat<MT>));
+  uint64_t off = trs_off + round16((h->L + 1) * sizeof(Transfer));
+  std::vector<LdsBuf> bufs;
+  tail_buffers<VT, MT>(h, t, bufs);
+  std::vector<std::pair<const void*, uint64_t>> map;
+  std::vector<TailCopy> cin;
+  for (const auto& b : bufs) {
+    map.push_back({b.g, off});
+    if (b.copy_in && b.bytes > 0) cin.push_back({b.g, (uint32_t)off, (int)round16(b.bytes)});
+    off += round16(b.bytes);
+  }
+  const size_t need = off;
+  // every operand of the program must be one of the placed buffers
+  bool ok = true;
+  auto tr = [&](const void* p) -> const void* {
+    if (!p) return p;
+    for (const auto& m : map)
+      if (m.first == p) return (const void*)(kLdsTag | m.second);
+    ok = false;
+    return p;
+  };
+  for (auto& o : ops) {
+    o.a = tr(o.a);
+    o.b = tr(o.b);
+    o.c = const_cast<void*>(tr(o.c));
+    o.d = const_cast<void*>(tr(o.d));
+    for (int i = 0; i < 8; ++i) o.w.p[i] = i < o.k ? tr(o.w.p[i]) : nullptr;
+  }
   std::vector<Mat<MT>> mats(h->L + 1);
   std::vector<Transfer> trs(h->L + 1);
+  std::memset(mats.data(), 0, mats.size() * sizeof(Mat<MT>));
+  std::memset(trs.data(), 0, trs.size() * sizeof(Transfer));
   for (int l = t; l < h->L; ++l) {
-    mats[l] = mat_of<MT>(h->lv[l]);
-    trs[l] = transfer_of(h, l);
+    Mat<MT> A = mat_of<MT>(h->lv[l]);
+    A.off = (const int*)tr(A.off);
+    A.width = (const int*)tr(A.width);
+    A.col = (const int*)tr(A.col);
+    A.val = (const MT*)tr(A.val);
+    A.D = (const MT*)tr(A.D);
+    mats[l] = A;
+    Transfer T = transfer_of(h, l);
+    T.agg = (const int*)tr(T.agg);
+    T.members = (const int*)tr(T.members);
+    T.member_off = (const int*)tr(T.member_off);
+    trs[l] = T;
   }
-  AMG_TRY(dalloc(h, &h->tail_ops, ops.size() * sizeof(TailOp) + 16));
-  AMG_TRY(dalloc(h, &h->tail_mats, mats.size() * sizeof(Mat<MT>) + 16));
-  AMG_TRY(dalloc(h, &h->tail_trs, trs.size() * sizeof(Transfer) + 16));
-  AMG_HIP(hipMemcpyAsync(h->tail_ops, ops.data(), ops.size() * sizeof(TailOp), hipMemcpyHostToDevice, s));
-  AMG_HIP(hipMemcpyAsync(h->tail_mats, mats.data(), mats.size() * sizeof(Mat<MT>), hipMemcpyHostToDevice, s));
-  AMG_HIP(hipMemcpyAsync(h->tail_trs, trs.data(), trs.size() * sizeof(Transfer), hipMemcpyHostToDevice, s));
+  const void* Linv = tr(h->chol_inv);
+  const void* LinvT = tr(h->chol_invT);
+  const void* scal_t = tr(h->scal);
+  const void* sol_t = tr(h->ws[t].sol);
+  if (!ok || need > budget) {
+    set_last_error("tail program refers to data outside its LDS image");
+    return AMG_ERR_DEVICE;
+  }
+  // program header (ops, descriptors) as one device blob copied first
+  std::vector<char> head(trs_off + round16((h->L + 1) * sizeof(Transfer)), 0);
+  std::memcpy(head.data() + ops_off, ops.data(), ops.size() * sizeof(TailOp));
+  std::memcpy(head.data() + mats_off, mats.data(), mats.size() * sizeof(Mat<MT>));
+  std::memcpy(head.data() + trs_off, trs.data(), trs.size() * sizeof(Transfer));
+  void* d_head = nullptr;
+  void* d_cin = nullptr;
+  AMG_TRY(dalloc(h, &d_head, head.size() + 16));
+  cin.insert(cin.begin(), TailCopy{d_head, 0, (int)head.size()});
+  AMG_TRY(dalloc(h, &d_cin, cin.size() * sizeof(TailCopy) + 16));
+  AMG_HIP(hipMemcpyAsync(d_head, head.data(), head.size(), hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(d_cin, cin.data(), cin.size() * sizeof(TailCopy), hipMemcpyHostToDevice, s));
   AMG_HIP(hipStreamSynchronize(s));
-  h->tail_nops = (int)ops.size();
+  TailProgram P;
+  std::memset(&P, 0, sizeof(P));
+  P.nops = (int)ops.size();
+  P.ncin = (int)cin.size();
+  P.ops_off = ops_off;
+  P.mats_off = mats_off;
+  P.trs_off = trs_off;
+  P.scal_off = (uint32_t)(uint64_t)scal_t;
+  P.cin = (const TailCopy*)d_cin;
+  P.cout = TailCopy{h->ws[t].sol, (uint32_t)(uint64_t)sol_t, (int)round16(sizeof(VT) * h->lv[t].n)};
+  P.C = CoarseView{h->nL, (const double*)Linv, (const double*)LinvT};
+  h->tail_prog_storage.resize(sizeof(TailProgram));
+  std::memcpy(h->tail_prog_storage.data(), &P, sizeof(P));
+  h->tail_prog = h->tail_prog_storage.data();
+  h->tail_lds_bytes = need;
+  h->tail_threads = std::min(TAIL_THREADS, std::max(64, (h->lv[t].n + 63) / 64 * 64));
+  (void)hipFuncSetAttribute((const void*)k_tail<VT, MT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+  h->tail_nops = P.nops;
   h->tail_level = t;
   return AMG_OK;
 }
@@ -1048,6 +1295,10 @@ int32_t prepare_solve(amg_hier* h, hipStream_t s) {
     AMG_TRY(dalloc(h, &h->Qo[j], n0));
   }
   h->max_blocks = nblk(n0);
+  // grids of up to this many blocks finish their reductions in-kernel (one
+  // release fence per block); larger grids use the one-block finishing kernel
+  h->last_block_max = 16;
+  if (const char* e = std::getenv("AMG_LAST_BLOCK_MAX")) h->last_block_max = std::max(0, std::atoi(e));
   AMG_TRY(dalloc(h, &h->partials, (size_t)std::max(h->max_blocks, 1) * 8));
   AMG_TRY(dalloc(h, &h->scal, SCAL_SIZE));
   AMG_TRY(dalloc(h, &h->counter, 1));
@@ -1064,39 +1315,41 @@ int32_t prepare_solve(amg_hier* h, hipStream_t s) {
 }
 
 int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
-  if (h->mixed) return solve_impl<float, float>(h, f, u, s, info, false);
-  return solve_impl<double, double>(h, f, u, s, info, false);
+  if (h->mixed) return solve_impl<float, float>(h, f, u, s, info);
+  return solve_impl<double, double>(h, f, u, s, info);
 }
 
-int32_t profile_solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info,
-                      amg_kernel_timing* t) {
-  constexpr int kPairs = 2048;
-  if (h->probe_ev.empty()) {
-    h->probe_ev.resize(2 * kPairs);
-    for (auto& e : h->probe_ev) AMG_HIP(hipEventCreate(&e));
+int32_t time_step(amg_hier* h, int reps, hipStream_t s, amg_kernel_timing* t) {
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  int32_t st;
+  if (h->mixed) {
+    Engine<float, float> E{h, s};
+    st = E.time_fine_step(reps, e0, e1);
+  } else {
+    Engine<double, double> E{h, s};
+    st = E.time_fine_step(reps, e0, e1);
   }
-  h->probe = true;
-  h->probe_used = 0;
-  const int32_t st = h->mixed ? solve_impl<float, float>(h, f, u, s, info, true)
-                              : solve_impl<double, double>(h, f, u, s, info, true);
-  h->probe = false;
+  float ms = 0.f;
+  if (st == AMG_OK) {
+    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      set_last_error(std::string("event timing: ") + hipGetErrorString(e));
+      st = AMG_ERR_DEVICE;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   std::memset(t, 0, sizeof(*t));
-  double sum = 0.0, mn = 1e30, mx = 0.0;
-  const int pairs = h->probe_used / 2;
-  for (int i = 0; i < pairs; ++i) {
-    float ms = 0.f;
-    AMG_HIP(hipEventElapsedTime(&ms, h->probe_ev[2 * i], h->probe_ev[2 * i + 1]));
-    sum += ms;
-    mn = std::min(mn, (double)ms);
-    mx = std::max(mx, (double)ms);
-  }
-  t->launches = pairs;
-  t->avg_ms = pairs ? sum / pairs : 0.0;
-  t->min_ms = pairs ? mn : 0.0;
-  t->max_ms = mx;
+  t->launches = reps;
+  t->avg_ms = ms / reps;
   t->rows = h->lv[0].n;
   t->nnz = h->lv[0].nnz;
+  t->entries = h->lv[0].sell_entries;
   t->grid = (int32_t)nblk(h->lv[0].n);
+  t->value_bytes = h->mixed ? 4 : 8;
   return st;
 }
 
