@@ -192,6 +192,26 @@ typedef struct {
 
 int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing* timing);
 
+/*
+ * Solve nb independent systems together (Section 4's solver for each): item i
+ * uses hierarchy h[i], right-hand side f[i] and initial guess / solution u[i]
+ * (device pointers, n of h[i] doubles each).  A hierarchy may appear several
+ * times (several right-hand sides); each repeat gets its own workspace.  All
+ * items must share precision, degree, inner_steps, restart, tol and max_iter,
+ * and have a coarsest level of at most 1024 rows.
+ * Every cycle step is one launch covering all items that take it; each item's
+ * small levels run as its own one-workgroup LDS-resident program; inner
+ * products and convergence are per item on the device, converged items are
+ * frozen, and one outer iteration of the whole batch is replayed as a HIP
+ * graph.  An item's result does not depend on the other items of the batch.
+ * infos: host array of nb records (may be NULL); solve_ms is the batch's time.
+ * Returns AMG_OK if every item converged, else the first failing item's
+ * status (AMG_ERR_MAXIT, AMG_ERR_BREAKDOWN) or an argument/device error.  The
+ * schedule built for a set of (h, f, u) is reused while the set is unchanged.
+ */
+int32_t amg_solve_batch(int32_t nb, amg_hier* const* h, const double* const* f, double* const* u,
+                        void* stream, amg_info* infos);
+
 /* ---- Level inspection and single steps (tests and diagnostics) ------------
  * The single steps below (all but amg_apply_cycle) need an AMG_FP64
  * hierarchy (AMG_ERR_ARG otherwise); each synchronizes `stream` before it

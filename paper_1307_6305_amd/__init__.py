@@ -118,6 +118,8 @@ SIGNATURES = {
     "amg_free": (None, [_P]),
     "amg_describe": (_I32, [_P, ctypes.POINTER(amg_hier_desc)]),
     "amg_solve": (_I32, [_P, _P, _P, _P, ctypes.POINTER(amg_info)]),
+    "amg_solve_batch": (_I32, [_I32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _P,
+                               ctypes.POINTER(amg_info)]),
     "amg_time_step": (_I32, [_P, _I32, _P, ctypes.POINTER(amg_kernel_timing)]),
     "amg_level_export": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P]),
     "amg_apply_smoother": (_I32, [_P, _I32, _P, _P, _P]),
@@ -255,6 +257,23 @@ def amg_solve(h: Hierarchy, f, u, stream=None, check: bool = False) -> dict:
         _check(code, "amg_solve")
     return {"status": info.status, "iters": info.iters, "rel_res": info.rel_res,
             "rel_res_true": info.rel_res_true, "solve_ms": info.solve_ms}
+
+
+def amg_solve_batch(hs, fs, us, stream=None, check: bool = False) -> list:
+    """Solve len(hs) systems together; hs may repeat (several right-hand
+    sides).  fs/us: float64 device tensors.  Returns one info dict per item."""
+    nb = len(hs)
+    if not (nb == len(fs) == len(us)) or nb < 1:
+        raise ValueError("hs, fs and us must have the same positive length")
+    H = (_P * nb)(*[h.handle.value for h in hs])
+    F = (_P * nb)(*[_dev(f, h.n, "f").value for h, f in zip(hs, fs)])
+    U = (_P * nb)(*[_dev(u, h.n, "u").value for h, u in zip(hs, us)])
+    infos = (amg_info * nb)()
+    code = load_library().amg_solve_batch(nb, H, F, U, _stream(stream), infos)
+    if code in (AMG_ERR_ARG, AMG_ERR_DEVICE, AMG_ERR_NOMEM) or (check and code != AMG_OK):
+        _check(code, "amg_solve_batch")
+    return [{"status": i.status, "iters": i.iters, "rel_res": i.rel_res, "rel_res_true": i.rel_res_true,
+             "solve_ms": i.solve_ms} for i in infos]
 
 
 def amg_time_step(h: Hierarchy, reps: int = 200, stream=None) -> dict:

@@ -27,6 +27,7 @@ SOURCES = [
     ("api.hip", "hipcc", []),
     ("setup.hip", "hipcc", ["-ffp-contract=off"]),
     ("solve.hip", "hipcc", []),
+    ("batch.hip", "hipcc", []),
 ]
 
 

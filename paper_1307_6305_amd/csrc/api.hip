@@ -26,6 +26,38 @@ int32_t dalloc(amg_hier* h, void** p, size_t bytes) {
   return AMG_OK;
 }
 
+int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s) {
+  amg_hier* c = new amg_hier();
+  c->p = h->p;
+  c->device = h->device;
+  c->mixed = h->mixed;
+  c->lv = h->lv;
+  c->L = h->L;
+  c->chol = h->chol;
+  c->chol_inv = h->chol_inv;
+  c->chol_invT = h->chol_invT;
+  c->nL = h->nL;
+  c->desc = h->desc;
+  c->parent = h;
+  const int32_t st = prepare_solve(c, s);
+  if (st != AMG_OK) {
+    free_clone(c);
+    return st;
+  }
+  *out = c;
+  return AMG_OK;
+}
+
+void free_clone(amg_hier* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  destroy_graphs(c);
+  if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->host_scal) (void)hipHostFree(c->host_scal);
+  delete c;
+}
+
 }  // namespace amg
 
 namespace {
@@ -137,6 +169,7 @@ int32_t amg_setup(int32_t n, const int32_t* row_ptr, const int32_t* col, const d
 
 void amg_free(amg_hier* h) {
   if (!h) return;
+  amg::drop_batches_using(h);
   (void)hipDeviceSynchronize();
   amg::destroy_graphs(h);
   if (h->graph_stream) (void)hipStreamDestroy(h->graph_stream);
@@ -154,6 +187,14 @@ int32_t amg_describe(const amg_hier* h, amg_hier_desc* out) {
 int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info) {
   if (!h || !f || !u) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
   return amg::solve(h, f, u, static_cast<hipStream_t>(stream), info);
+}
+
+int32_t amg_solve_batch(int32_t nb, amg_hier* const* h, const double* const* f, double* const* u, void* stream,
+                        amg_info* infos) {
+  if (nb < 1 || !h || !f || !u) { amg::set_last_error("invalid argument"); return AMG_ERR_ARG; }
+  for (int32_t i = 0; i < nb; ++i)
+    if (!h[i] || !f[i] || !u[i]) { amg::set_last_error("null item " + std::to_string(i)); return AMG_ERR_ARG; }
+  return amg::solve_batch(nb, h, f, u, static_cast<hipStream_t>(stream), infos);
 }
 
 int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing* timing) {

@@ -1,0 +1,1009 @@
+// Batched solve: many independent systems (uneven graphs, or several
+// right-hand sides on one hierarchy) advance together through flexible CG with
+// the k-cycle preconditioner (Sections 3-4 of the paper).
+//
+// Execution is level-synchronous over the union of the items' cycles: every
+// step of the cycle (a Chebyshev step on level l, a residual, a restriction,
+// an inner flexible-CG update, ...) is ONE launch that covers that step for
+// every item that takes it, with a block -> item map; each item's small
+// levels run as that item's recorded LDS-resident tail program, one workgroup
+// per item, all items in one launch.  Inner products are per-item fixed-order
+// reductions, convergence is decided per item on the device, and converged
+// items are frozen (their blocks return at once).  An item's arithmetic never
+// depends on which other items share the launches, so its result is the same
+// alone and in any mix.  One outer iteration of the whole batch is captured as
+// a HIP graph and replayed; the host reads one counter per replay.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+
+namespace amg {
+namespace {
+
+struct ItemState {
+  int active;  // 1 while the item iterates
+  int iter;    // completed outer iterations
+  int status;  // AMG_OK, AMG_ERR_MAXIT or AMG_ERR_BREAKDOWN
+  int pad;
+  double rr0, rr, rrt;
+};
+
+enum BatchOpType : int {
+  B_CHEB_FIRST = 1,
+  B_CHEB_NEXT,
+  B_SCALE_ADD,
+  B_RESIDUAL,
+  B_RESTRICT,
+  B_PROLONG,
+  B_COARSE,
+  B_MULTIDOT,
+  B_FCG_P,
+  B_SPMV_DOTS,
+  B_FCG_XR,
+  B_O_RESID,     // r = f - A u (FP64), (r, r) -> rr0; starts the item
+  B_O_MULTIDOT,  // (z, q_i), i < j = iter mod restart
+  B_O_P,         // p_j = z - sum beta_i p_i
+  B_O_SPMV,      // q_j = A p_j (FP64), (p_j, q_j), (p_j, r)
+  B_O_XR,        // u += alpha p_j, r -= alpha q_j, (r, r); convergence
+  B_O_TRUE,      // true residual (f - A u, f - A u)
+};
+
+struct BatchOp {
+  int type;
+  int item;
+  int n;
+  int k;
+  int i0, i1, i2, i3;
+  int first_block;  // first block of this op in its launch
+  int blocks;       // tiles of TPB rows
+  int part;         // first partial-sum tile of this op (8 doubles per tile)
+  int pad;
+  double f0, f1, f2, f3;
+  Mat<double> A64;
+  Mat<float> A32;
+  Transfer T;
+  CoarseView C;
+  const void* a;
+  const void* b;
+  void* c;
+  void* d;
+  VecPtrs w;
+  VecPtrs w2;
+  Slots s0, s1;
+  double* scal;
+};
+
+template <typename MT>
+__device__ __forceinline__ const Mat<MT>& op_mat(const BatchOp& op);
+template <>
+__device__ __forceinline__ const Mat<double>& op_mat<double>(const BatchOp& op) {
+  return op.A64;
+}
+template <>
+__device__ __forceinline__ const Mat<float>& op_mat<float>(const BatchOp& op) {
+  return op.A32;
+}
+
+// Partial sums of K values of this block, for op-local tile `tile`.
+template <int K>
+__device__ __forceinline__ void deposit(double (&v)[K], double* partials, int slot, double* red) {
+  block_sum<K>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) partials[(size_t)slot * 8 + k] = v[k];
+  }
+}
+
+// One step of the cycle for every item of the launch.  Block b works on tile
+// (b - first_block) of op block_op[b].
+template <typename VT, typename MT>
+__global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ ops, const int* __restrict__ block_op,
+                                                    const ItemState* __restrict__ st, double* partials) {
+  __shared__ double red[16 * 8];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const BatchOp& op = ops[block_op[b]];
+  if (!st[op.item].active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
+  const int tile = b - op.first_block;
+  const int r = tile * TPB + threadIdx.x;
+  const bool live = r < op.n;
+  switch (op.type) {
+    case B_CHEB_FIRST: {
+      if (!live) break;
+      const Mat<MT>& A = op_mat<MT>(op);
+      if (op.i2)
+        row_cheb_first<VT, MT, double>(A, r, (const double*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.f3,
+                                       op.i0, op.i1);
+      else
+        row_cheb_first<VT, MT, VT>(A, r, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.f3, op.i0,
+                                   op.i1);
+      break;
+    }
+    case B_CHEB_NEXT: {
+      if (!live) break;
+      const Mat<MT>& A = op_mat<MT>(op);
+      if (op.i2)
+        row_cheb_next<VT, MT, double>(A, r, (const VT*)op.a, (const double*)op.b, (VT*)op.c, (VT*)op.d, op.f0, op.f1,
+                                      op.f2, op.i0);
+      else
+        row_cheb_next<VT, MT, VT>(A, r, (const VT*)op.a, (const VT*)op.b, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2,
+                                  op.i0);
+      break;
+    }
+    case B_SCALE_ADD: {
+      if (!live) break;
+      VT* y = (VT*)op.d;
+      const VT w0 = op.i2 ? (VT)((const double*)op.a)[r] : ((const VT*)op.a)[r];
+      VT v = (VT)op.f0 * w0;
+      if (op.i0) v += y[r];
+      y[r] = v;
+      break;
+    }
+    case B_RESIDUAL: {
+      if (!live) break;
+      const Mat<MT>& A = op_mat<MT>(op);
+      if (op.i2)
+        row_residual<VT, MT, double>(A, r, (const double*)op.a, (const VT*)op.b, (VT*)op.c);
+      else
+        row_residual<VT, MT, VT>(A, r, (const VT*)op.a, (const VT*)op.b, (VT*)op.c);
+      break;
+    }
+    case B_RESTRICT:
+      if (live) row_restrict<VT>(op.T, r, (const VT*)op.a, (VT*)op.c);
+      break;
+    case B_PROLONG:
+      if (live) row_prolong<VT>(op.T, r, (const VT*)op.a, (VT*)op.c);
+      break;
+    case B_MULTIDOT: {
+      double v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0.0;
+      if (live) {
+        const double zr = (double)((const VT*)op.a)[r];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i < op.k) v[i] = zr * (double)((const VT*)op.w.p[i])[r];
+      }
+      deposit<8>(v, partials, op.part + tile, red);
+      break;
+    }
+    case B_FCG_P: {
+      if (!live) break;
+      double acc = (double)((const VT*)op.a)[r];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < op.k) acc -= fcg_beta(op.scal, op.s0.s[i], op.s1.s[i]) * (double)((const VT*)op.w.p[i])[r];
+      ((VT*)op.c)[r] = (VT)acc;
+      break;
+    }
+    case B_SPMV_DOTS: {
+      double v[2] = {0.0, 0.0};
+      if (live) row_spmv_dots<VT, MT, VT>(op_mat<MT>(op), r, (const VT*)op.a, (VT*)op.c, (const VT*)op.b, v);
+      deposit<2>(v, partials, op.part + tile, red);
+      break;
+    }
+    case B_FCG_XR: {
+      if (!live) break;
+      const double alpha = fcg_alpha(op.scal, op.i0, op.i1);
+      const double pr = (double)((const VT*)op.a)[r];
+      VT* x = (VT*)op.c;
+      x[r] = (VT)(op.i2 ? alpha * pr : (double)x[r] + alpha * pr);
+      if (op.i3) {
+        VT* rv = (VT*)op.d;
+        rv[r] = (VT)((double)rv[r] - alpha * (double)((const VT*)op.b)[r]);
+      }
+      break;
+    }
+    case B_O_RESID:
+    case B_O_TRUE: {
+      double v[1] = {0.0};
+      if (live) {
+        double* s = (double*)op.c;
+        row_residual<double, double, double>(op.A64, r, (const double*)op.a, (const double*)op.b, s);
+        v[0] = s[r] * s[r];
+      }
+      deposit<1>(v, partials, op.part + tile, red);
+      break;
+    }
+    case B_O_MULTIDOT: {
+      const int j = st[op.item].iter % op.i0;
+      double v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0.0;
+      if (live) {
+        const double zr = (double)((const VT*)op.a)[r];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (i < j) v[i] = zr * ((const double*)op.w.p[i])[r];
+      }
+      deposit<8>(v, partials, op.part + tile, red);
+      break;
+    }
+    case B_O_P: {
+      if (!live) break;
+      const int j = st[op.item].iter % op.i0;
+      double acc = (double)((const VT*)op.a)[r];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < j) acc -= fcg_beta(op.scal, S_DOTS + i, S_RHOW + i) * ((const double*)op.w2.p[i])[r];
+      ((double*)op.w2.p[j])[r] = acc;
+      break;
+    }
+    case B_O_SPMV: {
+      const int j = st[op.item].iter % op.i0;
+      double v[2] = {0.0, 0.0};
+      if (live)
+        row_spmv_dots<double, double, double>(op.A64, r, (const double*)op.w2.p[j], (double*)op.w.p[j],
+                                              (const double*)op.b, v);
+      deposit<2>(v, partials, op.part + tile, red);
+      break;
+    }
+    case B_O_XR: {
+      const int j = st[op.item].iter % op.i0;
+      double v[1] = {0.0};
+      if (live) {
+        const double alpha = fcg_alpha(op.scal, S_RHOW + j, S_GAM);
+        double* u = (double*)op.c;
+        double* rv = (double*)op.d;
+        u[r] += alpha * ((const double*)op.w2.p[j])[r];
+        const double rn = rv[r] - alpha * ((const double*)op.w.p[j])[r];
+        rv[r] = rn;
+        v[0] = rn * rn;
+      }
+      deposit<1>(v, partials, op.part + tile, red);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Coarsest solves, one block per item.
+template <typename VT>
+__global__ void __launch_bounds__(TPB) k_batch_coarse(const BatchOp* __restrict__ ops, const ItemState* __restrict__ st) {
+  __shared__ double sb[1024], sy[1024];
+  const BatchOp& op = ops[blockIdx.x];
+  if (!st[op.item].active) return;
+  if (op.i2)
+    coarse_apply<VT, double>(op.C, (const double*)op.a, (VT*)op.c, sb, sy);
+  else
+    coarse_apply<VT, VT>(op.C, (const VT*)op.a, (VT*)op.c, sb, sy);
+}
+
+// Tail programs, one workgroup per item.
+template <typename VT, typename MT>
+__global__ void __launch_bounds__(TAIL_THREADS) k_batch_tail(const TailProgram* __restrict__ progs,
+                                                             const int* __restrict__ items,
+                                                             const ItemState* __restrict__ st) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ double red[16 * 8];
+  __shared__ double sb[1024], sy[1024];
+  if (!st[items[blockIdx.x]].active) return;
+  run_tail<VT, MT>(progs[blockIdx.x], lds, red, sb, sy, true);
+}
+
+struct BatchCtl {
+  double tol;
+  int max_iter;
+  int pad;
+  int* nactive;  // device counter of items still iterating
+};
+
+// Fixed-order sums of each reduction op's partials (one block per op), and
+// the per-item bookkeeping of the outer iteration.
+__global__ void __launch_bounds__(kFinishThreads) k_batch_finish(const BatchOp* __restrict__ ops,
+                                                                 const int* __restrict__ fin, ItemState* st,
+                                                                 const double* partials, BatchCtl ctl) {
+  __shared__ double red[16 * 8];
+  const BatchOp& op = ops[fin[blockIdx.x]];
+  ItemState& S = st[op.item];
+  if (!S.active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
+  double acc[8];
+  sum_partials<8>(partials + (size_t)op.part * 8, op.blocks, acc, red);
+  if (threadIdx.x != 0) return;
+  switch (op.type) {
+    case B_MULTIDOT:
+      for (int i = 0; i < op.k; ++i) op.scal[op.s0.s[i]] = acc[i];
+      break;
+    case B_SPMV_DOTS:
+      op.scal[op.s0.s[0]] = acc[0];
+      op.scal[op.s0.s[1]] = acc[1];
+      break;
+    case B_O_MULTIDOT: {
+      const int j = S.iter % op.i0;
+      for (int i = 0; i < j; ++i) op.scal[S_DOTS + i] = acc[i];
+      break;
+    }
+    case B_O_SPMV: {
+      const int j = S.iter % op.i0;
+      op.scal[S_RHOW + j] = acc[0];
+      op.scal[S_GAM] = acc[1];
+      break;
+    }
+    case B_O_RESID:
+      S.rr0 = acc[0];
+      S.rr = acc[0];
+      S.iter = 0;
+      S.status = AMG_OK;
+      S.active = acc[0] > 0.0 ? 1 : 0;
+      if (S.active) atomicAdd(ctl.nactive, 1);
+      break;
+    case B_O_TRUE:
+      S.rrt = acc[0];
+      break;
+    case B_O_XR: {
+      const int j = S.iter % op.i0;
+      const double rho = op.scal[S_RHOW + j];
+      S.iter += 1;
+      S.rr = acc[0];
+      bool stop = false;
+      if (!(rho > 0.0) || !isfinite(rho)) {
+        S.status = AMG_ERR_BREAKDOWN;
+        stop = true;
+      } else if (acc[0] <= ctl.tol * ctl.tol * S.rr0) {
+        S.status = AMG_OK;
+        stop = true;
+      } else if (S.iter >= ctl.max_iter) {
+        S.status = AMG_ERR_MAXIT;
+        stop = true;
+      }
+      if (stop) {
+        S.active = 0;
+        atomicSub(ctl.nactive, 1);
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+__global__ void k_batch_reset(int* nactive) { *nactive = 0; }
+
+// ------------------------------------------------------------------ schedule
+struct Launch {
+  int kind;  // 0 step, 1 coarse, 2 tail, 3 finish
+  int op0, nops;
+  int map0, nblocks;  // block map slice (step) / finish list slice
+  int tail0;          // first tail program (tail)
+  size_t lds;         // dynamic LDS (tail)
+  int threads;
+};
+
+struct Item {
+  amg_hier* h;  // hierarchy with this item's workspace
+  const double* f;
+  double* u;
+};
+
+}  // namespace
+
+struct Batch {
+  std::vector<void*> key;
+  std::vector<amg_hier*> clones;  // workspaces for repeated hierarchies
+  std::vector<Item> items;
+  bool mixed = false;
+  int restart = 5;
+  double tol = 1e-8;
+  int max_iter = 200;
+  // device
+  BatchOp* d_ops = nullptr;
+  int* d_map = nullptr;
+  int* d_fin = nullptr;
+  TailProgram* d_tails = nullptr;
+  int* d_tail_items = nullptr;
+  ItemState* d_state = nullptr;
+  double* d_partials = nullptr;
+  int* d_nactive = nullptr;
+  int* h_nactive = nullptr;
+  std::vector<void*> allocs;
+  std::vector<Launch> init, iter, fini;
+  hipGraphExec_t g_init = nullptr, g_iter = nullptr, g_fini = nullptr;
+  hipStream_t gs = nullptr;
+  ~Batch() {
+    if (g_init) (void)hipGraphExecDestroy(g_init);
+    if (g_iter) (void)hipGraphExecDestroy(g_iter);
+    if (g_fini) (void)hipGraphExecDestroy(g_fini);
+    if (gs) (void)hipStreamDestroy(gs);
+    for (void* p : allocs) (void)hipFree(p);
+    if (h_nactive) (void)hipHostFree(h_nactive);
+    for (amg_hier* c : clones) free_clone(c);
+  }
+};
+
+namespace {
+
+int32_t balloc(Batch* B, void** p, size_t bytes) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes + 16);
+  if (e != hipSuccess) {
+    set_last_error(std::string("hipMalloc (batch): ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
+  }
+  B->allocs.push_back(q);
+  *p = q;
+  return AMG_OK;
+}
+
+// Builds the union schedule of the items' cycles.
+struct Builder {
+  Batch* B;
+  std::vector<BatchOp> ops;
+  std::vector<int> map;
+  std::vector<int> fin;
+  std::vector<TailProgram> tails;
+  std::vector<int> tail_items;
+  std::vector<Launch>* out = nullptr;
+  int parts = 0;      // partial tiles of the current launch
+  int max_parts = 0;  // largest over launches (the partial buffer is reused)
+
+  static BatchOp blank(int type, int item) {
+    BatchOp o;
+    std::memset(&o, 0, sizeof(o));
+    o.type = type;
+    o.item = item;
+    return o;
+  }
+
+  const amg_hier* H(int i) const { return B->items[i].h; }
+
+  void fill_mats(BatchOp& o, int i, int l) const {
+    const Level& lv = H(i)->lv[l];
+    o.A64 = mat_of<double>(lv);
+    if (B->mixed) o.A32 = mat_of<float>(lv);
+  }
+
+  // one step launch over the given ops (each spanning ceil(n / TPB) tiles)
+  void step(std::vector<BatchOp> v, bool reduces) {
+    if (v.empty()) return;
+    Launch L{};
+    L.kind = 0;
+    L.op0 = (int)ops.size();
+    L.nops = (int)v.size();
+    L.map0 = (int)map.size();
+    parts = 0;
+    int blocks = 0;
+    for (size_t q = 0; q < v.size(); ++q) {
+      BatchOp& o = v[q];
+      o.blocks = nblk(o.n);
+      o.first_block = blocks;
+      o.part = parts;
+      blocks += o.blocks;
+      if (reduces) parts += o.blocks;
+      for (int t = 0; t < o.blocks; ++t) map.push_back(L.op0 + (int)q);
+      ops.push_back(o);
+    }
+    L.nblocks = blocks;
+    max_parts = std::max(max_parts, parts);
+    out->push_back(L);
+    if (reduces) {
+      Launch F{};
+      F.kind = 3;
+      F.op0 = 0;
+      F.map0 = (int)fin.size();
+      F.nblocks = L.nops;
+      for (int q = 0; q < L.nops; ++q) fin.push_back(L.op0 + q);
+      out->push_back(F);
+    }
+  }
+
+  // ---------------------------------------------------------------- cycle
+  // Vectors are named per item: the level's rhs, sol, Z[k], S, A, B buffers,
+  // or the outer r / z.
+  enum Src { SRC_OUTER_R, SRC_RHS, SRC_S };
+  enum Dst { DST_OUTER_Z, DST_Z };
+
+  const void* src_ptr(int i, int l, Src s) const {
+    if (s == SRC_OUTER_R) return H(i)->r;
+    if (s == SRC_RHS) return H(i)->ws[l].rhs;
+    return H(i)->ws[l].S;
+  }
+  void* dst_ptr(int i, int l, Dst d, int k) const {
+    if (d == DST_OUTER_Z) return H(i)->z;
+    return H(i)->ws[l].Z[k];
+  }
+
+  void smooth(int l, const std::vector<int>& I, Src src, Dst dst, int k, bool accum) {
+    const int m = B->items[I[0]].h->p.degree;
+    const bool r64 = (src == SRC_OUTER_R) && B->mixed;
+    if (m == 0) {
+      std::vector<BatchOp> v;
+      for (int i : I) {
+        const Level& lv = H(i)->lv[l];
+        BatchOp o = blank(B_SCALE_ADD, i);
+        o.n = lv.n;
+        o.a = src_ptr(i, l, src);
+        o.d = dst_ptr(i, l, dst, k);
+        o.f0 = lv.coef[0];
+        o.i0 = accum;
+        o.i2 = r64;
+        v.push_back(o);
+      }
+      step(v, false);
+      return;
+    }
+    {
+      std::vector<BatchOp> v;
+      for (int i : I) {
+        const Level& lv = H(i)->lv[l];
+        BatchOp o = blank(B_CHEB_FIRST, i);
+        fill_mats(o, i, l);
+        o.n = lv.n;
+        o.a = src_ptr(i, l, src);
+        o.c = H(i)->ws[l].A;
+        o.d = dst_ptr(i, l, dst, k);
+        o.f0 = lv.theta;
+        o.f1 = 1.0 / lv.eta;
+        o.f2 = lv.coef[0];
+        o.f3 = lv.coef[1];
+        o.i0 = accum;
+        o.i1 = m > 1;
+        o.i2 = r64;
+        v.push_back(o);
+      }
+      step(v, false);
+    }
+    for (int s = 1; s < m; ++s) {
+      std::vector<BatchOp> v;
+      for (int i : I) {
+        const Level& lv = H(i)->lv[l];
+        const auto& W = H(i)->ws[l];
+        // buffers: w_1 in A; w_2 in B; w_{k+1} overwrites w_{k-1}
+        const void* cur = (s % 2 == 1) ? W.A : W.B;
+        const void* prev = (s == 1) ? src_ptr(i, l, src) : ((s % 2 == 1) ? W.B : W.A);
+        void* next = (s % 2 == 1) ? W.B : W.A;
+        BatchOp o = blank(B_CHEB_NEXT, i);
+        fill_mats(o, i, l);
+        o.n = lv.n;
+        o.a = cur;
+        o.b = prev;
+        o.c = next;
+        o.d = dst_ptr(i, l, dst, k);
+        o.f0 = lv.theta;
+        o.f1 = 2.0 / lv.eta;
+        o.f2 = lv.coef[s + 1];
+        o.i0 = (s + 1 < m);
+        o.i2 = (s == 1) && r64;
+        v.push_back(o);
+      }
+      step(v, false);
+    }
+  }
+
+  void residual(int l, const std::vector<int>& I, Src src, Dst dst, int k) {
+    std::vector<BatchOp> v;
+    for (int i : I) {
+      BatchOp o = blank(B_RESIDUAL, i);
+      fill_mats(o, i, l);
+      o.n = H(i)->lv[l].n;
+      o.a = src_ptr(i, l, src);
+      o.b = dst_ptr(i, l, dst, k);
+      o.c = H(i)->ws[l].S;
+      o.i2 = (src == SRC_OUTER_R) && B->mixed;
+      v.push_back(o);
+    }
+    step(v, false);
+  }
+
+  void restrict_(int l, const std::vector<int>& I) {
+    std::vector<BatchOp> v;
+    for (int i : I) {
+      BatchOp o = blank(B_RESTRICT, i);
+      o.T = transfer_of(H(i), l);
+      o.n = o.T.nc;
+      o.a = H(i)->ws[l].S;
+      o.c = H(i)->ws[l + 1].rhs;
+      v.push_back(o);
+    }
+    step(v, false);
+  }
+
+  void prolong(int l, const std::vector<int>& I, Dst dst, int k) {
+    std::vector<BatchOp> v;
+    for (int i : I) {
+      BatchOp o = blank(B_PROLONG, i);
+      o.T = transfer_of(H(i), l);
+      o.n = o.T.n;
+      o.a = H(i)->ws[l + 1].sol;
+      o.c = dst_ptr(i, l, dst, k);
+      v.push_back(o);
+    }
+    step(v, false);
+  }
+
+  void coarse(const std::vector<int>& I) {
+    if (I.empty()) return;
+    Launch L{};
+    L.kind = 1;
+    L.op0 = (int)ops.size();
+    L.nops = (int)I.size();
+    for (int i : I) {
+      const amg_hier* h = H(i);
+      BatchOp o = blank(B_COARSE, i);
+      o.C = CoarseView{h->nL, h->chol_inv, h->chol_invT};
+      o.a = h->ws[h->L].rhs;
+      o.c = h->ws[h->L].sol;
+      ops.push_back(o);
+    }
+    out->push_back(L);
+  }
+
+  void tail(const std::vector<int>& I) {
+    if (I.empty()) return;
+    Launch L{};
+    L.kind = 2;
+    L.tail0 = (int)tails.size();
+    L.nops = (int)I.size();
+    L.lds = 0;
+    L.threads = 64;
+    for (int i : I) {
+      const amg_hier* h = H(i);
+      tails.push_back(*static_cast<const TailProgram*>(h->tail_prog));
+      tail_items.push_back(i);
+      L.lds = std::max(L.lds, h->tail_lds_bytes);
+      L.threads = std::max(L.threads, h->tail_threads);
+    }
+    out->push_back(L);
+  }
+
+  // x = Kcycle(l, r) for the items I (all with l < L_i)
+  void kcycle(int l, const std::vector<int>& I, Src src, Dst dst, int k) {
+    std::vector<int> C, T, R;
+    smooth(l, I, src, dst, k, false);
+    residual(l, I, src, dst, k);
+    restrict_(l, I);
+    for (int i : I) {
+      const amg_hier* h = H(i);
+      if (l + 1 == h->L) C.push_back(i);
+      else if (h->tail_level == l + 1) T.push_back(i);
+      else R.push_back(i);
+    }
+    coarse(C);
+    tail(T);
+    if (!R.empty()) inner(l + 1, R);
+    prolong(l, I, dst, k);
+    residual(l, I, src, dst, k);
+    smooth(l, I, SRC_S, dst, k, true);
+  }
+
+  // nu flexible-CG steps from zero on level l for the items I
+  void inner(int l, const std::vector<int>& I) {
+    const int nu = H(I[0])->p.inner_steps;
+    const int base = lbase(l);
+    for (int k = 0; k < nu; ++k) {
+      kcycle(l, I, SRC_RHS, DST_Z, k);
+      if (k > 0) {
+        std::vector<BatchOp> v, w;
+        for (int i : I) {
+          const auto& W = H(i)->ws[l];
+          BatchOp o = blank(B_MULTIDOT, i);
+          o.n = H(i)->lv[l].n;
+          o.k = k;
+          o.a = W.Z[k];
+          for (int q = 0; q < k; ++q) o.w.p[q] = W.Q[q];
+          o.scal = H(i)->scal;
+          for (int q = 0; q < 8; ++q) o.s0.s[q] = q < k ? base + 16 + q : S_DUMMY;
+          v.push_back(o);
+          BatchOp p = blank(B_FCG_P, i);
+          p.n = o.n;
+          p.k = k;
+          p.a = W.Z[k];
+          p.c = W.Z[k];
+          for (int q = 0; q < k; ++q) p.w.p[q] = W.Z[q];
+          p.scal = H(i)->scal;
+          for (int q = 0; q < 8; ++q) {
+            p.s0.s[q] = q < k ? base + 16 + q : S_DUMMY;
+            p.s1.s[q] = q < k ? base + q : S_DUMMY;
+          }
+          w.push_back(p);
+        }
+        step(v, true);
+        step(w, false);
+      }
+      std::vector<BatchOp> v, w;
+      for (int i : I) {
+        const auto& W = H(i)->ws[l];
+        BatchOp o = blank(B_SPMV_DOTS, i);
+        fill_mats(o, i, l);
+        o.n = H(i)->lv[l].n;
+        o.a = W.Z[k];
+        o.b = W.rhs;
+        o.c = W.Q[k];
+        o.scal = H(i)->scal;
+        for (int q = 0; q < 8; ++q) o.s0.s[q] = S_DUMMY;
+        o.s0.s[0] = base + k;
+        o.s0.s[1] = base + 8 + k;
+        v.push_back(o);
+        BatchOp x = blank(B_FCG_XR, i);
+        x.n = o.n;
+        x.a = W.Z[k];
+        x.b = W.Q[k];
+        x.c = W.sol;
+        x.d = W.rhs;
+        x.i0 = base + k;
+        x.i1 = base + 8 + k;
+        x.i2 = (k == 0);
+        x.i3 = (k + 1 < nu);
+        x.scal = H(i)->scal;
+        w.push_back(x);
+      }
+      step(v, true);
+      step(w, false);
+    }
+  }
+
+  // ---------------------------------------------------------------- outer
+  void outer_residual(int type, bool into_r) {
+    std::vector<BatchOp> v;
+    for (int i = 0; i < (int)B->items.size(); ++i) {
+      BatchOp o = blank(type, i);
+      fill_mats(o, i, 0);
+      o.n = H(i)->lv[0].n;
+      o.a = B->items[i].f;
+      o.b = B->items[i].u;
+      o.c = into_r ? (void*)H(i)->r : (void*)H(i)->tmp;
+      v.push_back(o);
+    }
+    step(v, true);
+  }
+
+  void outer_iteration() {
+    std::vector<int> all, C;
+    for (int i = 0; i < (int)B->items.size(); ++i) {
+      if (H(i)->L == 0) C.push_back(i);
+      else all.push_back(i);
+    }
+    // one-level items: the preconditioner is the coarsest solve itself
+    if (!C.empty()) {
+      Launch L{};
+      L.kind = 1;
+      L.op0 = (int)ops.size();
+      L.nops = (int)C.size();
+      for (int i : C) {
+        const amg_hier* h = H(i);
+        BatchOp o = blank(B_COARSE, i);
+        o.C = CoarseView{h->nL, h->chol_inv, h->chol_invT};
+        o.a = h->r;
+        o.c = h->z;
+        o.i2 = B->mixed;
+        ops.push_back(o);
+      }
+      out->push_back(L);
+    }
+    if (!all.empty()) kcycle(0, all, SRC_OUTER_R, DST_OUTER_Z, 0);
+    const int R = B->restart;
+    std::vector<BatchOp> md, pp, sp, xr;
+    for (int i = 0; i < (int)B->items.size(); ++i) {
+      const amg_hier* h = H(i);
+      BatchOp o = blank(B_O_MULTIDOT, i);
+      o.n = h->lv[0].n;
+      o.i0 = R;
+      o.a = h->z;
+      for (int q = 0; q < R; ++q) {
+        o.w.p[q] = h->Qo[q];
+        o.w2.p[q] = h->P[q];
+      }
+      o.scal = h->scal;
+      md.push_back(o);
+      BatchOp p = o;
+      p.type = B_O_P;
+      pp.push_back(p);
+      BatchOp s = o;
+      s.type = B_O_SPMV;
+      fill_mats(s, i, 0);
+      s.b = h->r;
+      sp.push_back(s);
+      BatchOp x = o;
+      x.type = B_O_XR;
+      x.c = B->items[i].u;
+      x.d = h->r;
+      xr.push_back(x);
+    }
+    step(md, true);
+    step(pp, false);
+    step(sp, true);
+    step(xr, true);
+  }
+};
+
+template <typename VT, typename MT>
+int32_t run_launches(Batch* B, const std::vector<Launch>& Ls, hipStream_t s) {
+  const BatchCtl ctl{B->tol, B->max_iter, 0, B->d_nactive};
+  for (const Launch& L : Ls) {
+    switch (L.kind) {
+      case 0:
+        hipLaunchKernelGGL((k_batch_step<VT, MT>), dim3(L.nblocks), dim3(TPB), 0, s, B->d_ops, B->d_map + L.map0,
+                           B->d_state, B->d_partials);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_batch_coarse<VT>), dim3(L.nops), dim3(TPB), 0, s, B->d_ops + L.op0, B->d_state);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_batch_tail<VT, MT>), dim3(L.nops), dim3(L.threads), L.lds, s, B->d_tails + L.tail0,
+                           B->d_tail_items + L.tail0, B->d_state);
+        break;
+      case 3:
+        hipLaunchKernelGGL(k_batch_finish, dim3(L.nblocks), dim3(kFinishThreads), 0, s, B->d_ops, B->d_fin + L.map0,
+                           B->d_state, B->d_partials, ctl);
+        break;
+    }
+    AMG_HIP(hipGetLastError());
+  }
+  return AMG_OK;
+}
+
+template <typename VT, typename MT>
+int32_t capture(Batch* B, const std::vector<Launch>& Ls, hipGraphExec_t* ex, bool copy_count) {
+  hipGraph_t g = nullptr;
+  AMG_HIP(hipStreamBeginCapture(B->gs, hipStreamCaptureModeThreadLocal));
+  int32_t st = run_launches<VT, MT>(B, Ls, B->gs);
+  if (st == AMG_OK && copy_count) {
+    hipError_t e = hipMemcpyAsync(B->h_nactive, B->d_nactive, sizeof(int), hipMemcpyDeviceToHost, B->gs);
+    if (e != hipSuccess) st = AMG_ERR_DEVICE;
+  }
+  hipError_t e = hipStreamEndCapture(B->gs, &g);
+  if (st != AMG_OK) return st;
+  AMG_HIP(e);
+  e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  AMG_HIP(e);
+  return AMG_OK;
+}
+
+template <typename VT, typename MT>
+int32_t build(Batch* B, hipStream_t s) {
+  Builder bd{B};
+  bd.out = &B->init;
+  bd.outer_residual(B_O_RESID, true);
+  bd.out = &B->iter;
+  bd.outer_iteration();
+  bd.out = &B->fini;
+  bd.outer_residual(B_O_TRUE, false);
+  const int nitems = (int)B->items.size();
+  void* p;
+  AMG_TRY(balloc(B, &p, bd.ops.size() * sizeof(BatchOp)));
+  B->d_ops = (BatchOp*)p;
+  AMG_TRY(balloc(B, &p, std::max<size_t>(1, bd.map.size()) * sizeof(int)));
+  B->d_map = (int*)p;
+  AMG_TRY(balloc(B, &p, std::max<size_t>(1, bd.fin.size()) * sizeof(int)));
+  B->d_fin = (int*)p;
+  AMG_TRY(balloc(B, &p, std::max<size_t>(1, bd.tails.size()) * sizeof(TailProgram)));
+  B->d_tails = (TailProgram*)p;
+  AMG_TRY(balloc(B, &p, std::max<size_t>(1, bd.tail_items.size()) * sizeof(int)));
+  B->d_tail_items = (int*)p;
+  AMG_TRY(balloc(B, &p, nitems * sizeof(ItemState)));
+  B->d_state = (ItemState*)p;
+  AMG_TRY(balloc(B, &p, (size_t)std::max(1, bd.max_parts) * 8 * sizeof(double)));
+  B->d_partials = (double*)p;
+  AMG_TRY(balloc(B, &p, sizeof(int)));
+  B->d_nactive = (int*)p;
+  AMG_HIP(hipHostMalloc((void**)&B->h_nactive, sizeof(int), hipHostMallocDefault));
+  AMG_HIP(hipMemcpyAsync(B->d_ops, bd.ops.data(), bd.ops.size() * sizeof(BatchOp), hipMemcpyHostToDevice, s));
+  if (!bd.map.empty())
+    AMG_HIP(hipMemcpyAsync(B->d_map, bd.map.data(), bd.map.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!bd.fin.empty())
+    AMG_HIP(hipMemcpyAsync(B->d_fin, bd.fin.data(), bd.fin.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!bd.tails.empty()) {
+    AMG_HIP(hipMemcpyAsync(B->d_tails, bd.tails.data(), bd.tails.size() * sizeof(TailProgram), hipMemcpyHostToDevice,
+                           s));
+    AMG_HIP(hipMemcpyAsync(B->d_tail_items, bd.tail_items.data(), bd.tail_items.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+  }
+  size_t max_lds = 0;
+  for (const auto& L : B->iter)
+    if (L.kind == 2) max_lds = std::max(max_lds, L.lds);
+  if (max_lds) (void)hipFuncSetAttribute((const void*)k_batch_tail<VT, MT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)max_lds);
+  AMG_HIP(hipStreamSynchronize(s));
+  AMG_HIP(hipStreamCreateWithFlags(&B->gs, hipStreamNonBlocking));
+  AMG_TRY(capture<VT, MT>(B, B->init, &B->g_init, true));
+  AMG_TRY(capture<VT, MT>(B, B->iter, &B->g_iter, true));
+  AMG_TRY(capture<VT, MT>(B, B->fini, &B->g_fini, false));
+  return AMG_OK;
+}
+
+std::mutex g_batch_mu;
+std::unique_ptr<Batch> g_batch;  // the most recent batch (its schedule is reused)
+
+using clk = std::chrono::steady_clock;
+
+}  // namespace
+
+void drop_batches_using(const amg_hier* h) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  if (!g_batch) return;
+  for (const auto& it : g_batch->items)
+    if (it.h == h || (it.h && it.h->parent == h)) {
+      g_batch.reset();
+      return;
+    }
+}
+
+int32_t solve_batch(int nb, amg_hier* const* hs, const double* const* f, double* const* u, hipStream_t s,
+                    amg_info* infos) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto t0 = clk::now();
+  std::vector<void*> key;
+  for (int i = 0; i < nb; ++i) {
+    key.push_back(hs[i]);
+    key.push_back((void*)f[i]);
+    key.push_back(u[i]);
+  }
+  if (!g_batch || g_batch->key != key) {
+    g_batch.reset();
+    auto B = std::make_unique<Batch>();
+    B->key = key;
+    const amg_params& p0 = hs[0]->p;
+    B->mixed = hs[0]->mixed;
+    B->restart = p0.restart;
+    B->tol = p0.tol;
+    B->max_iter = p0.max_iter;
+    std::map<const amg_hier*, int> seen;
+    for (int i = 0; i < nb; ++i) {
+      const amg_hier* h = hs[i];
+      if (h->mixed != B->mixed || h->p.degree != p0.degree || h->p.inner_steps != p0.inner_steps ||
+          h->p.restart != p0.restart || h->p.tol != p0.tol || h->p.max_iter != p0.max_iter) {
+        set_last_error("batched items must share precision, degree, inner steps, restart, tol and max_iter");
+        return AMG_ERR_ARG;
+      }
+      if (!h->chol_inv) {
+        set_last_error("batched items need a coarsest level of at most 1024 rows");
+        return AMG_ERR_ARG;
+      }
+      amg_hier* use = hs[i];
+      if (seen.count(h)) {  // another right-hand side on the same hierarchy: its own workspace
+        amg_hier* c = nullptr;
+        AMG_TRY(make_clone(hs[i], &c, s));
+        B->clones.push_back(c);
+        use = c;
+      }
+      seen[h] = 1;
+      B->items.push_back(Item{use, f[i], u[i]});
+    }
+    if (B->mixed) {
+      AMG_TRY(build<float, float>(B.get(), s));
+    } else {
+      AMG_TRY(build<double, double>(B.get(), s));
+    }
+    g_batch = std::move(B);
+  }
+  Batch* B = g_batch.get();
+  // init: r = f - A u, rr0, activation
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B->d_nactive);
+  AMG_HIP(hipGraphLaunch(B->g_init, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  int active = *B->h_nactive;
+  int launched = 0;
+  while (active > 0 && launched < B->max_iter) {
+    AMG_HIP(hipGraphLaunch(B->g_iter, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    ++launched;
+    active = *B->h_nactive;
+  }
+  AMG_HIP(hipGraphLaunch(B->g_fini, s));
+  std::vector<ItemState> hst(nb);
+  AMG_HIP(hipMemcpyAsync(hst.data(), B->d_state, nb * sizeof(ItemState), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  int32_t worst = AMG_OK;
+  for (int i = 0; i < nb; ++i) {
+    const ItemState& S = hst[i];
+    const double rho0 = std::sqrt(S.rr0);
+    if (infos) {
+      infos[i].status = S.status;
+      infos[i].iters = S.iter;
+      infos[i].rel_res = rho0 > 0 ? std::sqrt(S.rr) / rho0 : 0.0;
+      infos[i].rel_res_true = rho0 > 0 ? std::sqrt(S.rrt) / rho0 : 0.0;
+      infos[i].solve_ms = ms;
+    }
+    if (S.status != AMG_OK && worst == AMG_OK) worst = S.status;
+  }
+  return worst;
+}
+
+}  // namespace amg

@@ -11,6 +11,9 @@
 
 struct amg_hier {
   amg_params p{};
+  // a workspace clone shares the levels of `parent` and owns only its solve
+  // workspace (several right-hand sides of one hierarchy in a batch)
+  const amg_hier* parent = nullptr;
   int device = 0;
   bool mixed = false;
   std::vector<amg::Level> lv;  // finest first; lv.back() is the coarsest
@@ -94,6 +97,13 @@ int32_t step_coarse(amg_hier* h, const double* b, double* x, hipStream_t s);
 int32_t step_cycle(amg_hier* h, const double* r, double* z, hipStream_t s);
 
 int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info);
+
+// batched solves (batch.hip)
+int32_t solve_batch(int nb, amg_hier* const* hs, const double* const* f, double* const* u, hipStream_t s,
+                    amg_info* infos);
+void drop_batches_using(const amg_hier* h);
+int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s);
+void free_clone(amg_hier* c);
 int32_t time_step(amg_hier* h, int reps, hipStream_t s, amg_kernel_timing* t);
 
 }  // namespace amg

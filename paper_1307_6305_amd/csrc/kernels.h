@@ -1,0 +1,400 @@
+// Device code shared by the single-solve and the batched executors: level
+// views, the per-row steps of the cycle, the coarsest solve, and the
+// interpreter of recorded op programs that runs a small level's inner solve
+// out of one workgroup's LDS.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+
+#include "device_util.h"
+#include "hier.h"
+
+namespace amg {
+
+constexpr int TPB = 256;
+constexpr int TAIL_THREADS = 1024;
+
+// Scalar area.  Outer iteration: rr, (p,r), window dots, window rho.
+// Inner solve on level l: base(l) + [0,8) rho_k, [8,16) gamma_k, [16,24) dots.
+constexpr int S_RR = 0, S_GAM = 2, S_RR0 = 3, S_RRT = 4, S_DUMMY = 7, S_DOTS = 8, S_RHOW = 16;
+inline int lbase(int l) { return 64 + 32 * l; }
+constexpr int SCAL_SIZE = 64 + 32 * (AMG_MAX_LEVELS + 1);
+
+inline int nblk(int64_t n, int tpb = TPB) { return (int)std::max<int64_t>(1, (n + tpb - 1) / tpb); }
+
+struct VecPtrs {
+  const void* p[8];
+};
+
+template <typename MT>
+struct Mat {
+  int n;
+  int nb;  // blocks of TPB rows
+  const int* off;
+  const int* width;
+  const int* col;
+  const MT* val;
+  const MT* D;
+};
+
+struct Transfer {
+  int n, nc;
+  const int* agg;
+  const int* members;
+  const int* member_off;
+};
+
+struct CoarseView {
+  int n;
+  const double* Linv;   // inverse of the Cholesky factor, row-major (lower)
+  const double* LinvT;  // its transpose
+};
+
+template <typename MT>
+Mat<MT> mat_of(const Level& lv);
+template <>
+inline Mat<double> mat_of<double>(const Level& lv) {
+  return Mat<double>{lv.n, nblk(lv.n), lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_val, lv.D};
+}
+template <>
+inline Mat<float> mat_of<float>(const Level& lv) {
+  return Mat<float>{lv.n, nblk(lv.n), lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_valf, lv.Df};
+}
+
+inline Transfer transfer_of(const amg_hier* h, int l) {
+  const Level& lv = h->lv[l];
+  return Transfer{lv.n, h->lv[l + 1].n, lv.agg, lv.members, lv.member_off};
+}
+
+// ------------------------------------------------------------------ per-row steps
+// sum_j W_rj x_j over the stored off-diagonal entries of row r.
+template <typename AT, typename MT, typename XT>
+__device__ __forceinline__ AT offdiag(const Mat<MT>& A, int r, const XT* __restrict__ x) {
+  const int s = r >> 6, lane = r & 63;
+  const int* __restrict__ c = A.col + A.off[s] + lane;
+  const MT* __restrict__ v = A.val + A.off[s] + lane;
+  const int wd = A.width[s];
+  AT acc = 0;
+#pragma unroll 4
+  for (int k = 0; k < wd; ++k) acc += (AT)v[k * kWave] * (AT)x[c[k * kWave]];
+  return acc;
+}
+
+// w1 = (A w0 - theta w0) / eta;  y = [y +] c0 w0 + c1 w1   (c already divided by eta)
+template <typename VT, typename MT, typename RT>
+__device__ __forceinline__ void row_cheb_first(const Mat<MT>& A, int r, const RT* __restrict__ w0, VT* w1, VT* y,
+                                               double theta, double inv_eta, double c0, double c1, int accum,
+                                               int store) {
+  using AT = VT;
+  const AT x0 = (AT)w0[r];
+  const AT ax = (AT)A.D[r] * x0 - offdiag<AT>(A, r, w0);
+  const AT t = (ax - (AT)theta * x0) * (AT)inv_eta;
+  if (store) w1[r] = (VT)t;
+  AT yy = (AT)c0 * x0 + (AT)c1 * t;
+  if (accum) yy += (AT)y[r];
+  y[r] = (VT)yy;
+}
+
+// w_{k+1} = 2 (A w_k - theta w_k) / eta - w_{k-1};  y += c_{k+1} w_{k+1}.
+// wnext may alias wprev (each element is read before it is overwritten).
+template <typename VT, typename MT, typename PT>
+__device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int r, const VT* __restrict__ wk, const PT* wprev,
+                                              VT* wnext, VT* y, double theta, double two_inv_eta, double ck,
+                                              int store) {
+  using AT = VT;
+  const AT xk = (AT)wk[r];
+  const AT ax = (AT)A.D[r] * xk - offdiag<AT>(A, r, wk);
+  const AT t = (ax - (AT)theta * xk) * (AT)two_inv_eta - (AT)wprev[r];
+  if (store) wnext[r] = (VT)t;
+  y[r] = (VT)((AT)y[r] + (AT)ck * t);
+}
+
+template <typename VT, typename MT, typename RT>
+__device__ __forceinline__ void row_residual(const Mat<MT>& A, int r, const RT* __restrict__ f,
+                                             const VT* __restrict__ x, VT* s) {
+  using AT = VT;
+  const AT ax = (AT)A.D[r] * (AT)x[r] - offdiag<AT>(A, r, x);
+  s[r] = (VT)((AT)f[r] - ax);
+}
+
+template <typename VT>
+__device__ __forceinline__ void row_restrict(const Transfer& T, int I, const VT* __restrict__ s, VT* b) {
+  VT acc = 0;
+  for (int k = T.member_off[I]; k < T.member_off[I + 1]; ++k) acc += s[T.members[k]];
+  b[I] = acc;
+}
+
+template <typename VT>
+__device__ __forceinline__ void row_prolong(const Transfer& T, int i, const VT* __restrict__ e, VT* x) {
+  x[i] += e[T.agg[i]];
+}
+
+// q_r = (A p)_r; accumulates p_r q_r and p_r rv_r in FP64
+template <typename VT, typename MT, typename RT>
+__device__ __forceinline__ void row_spmv_dots(const Mat<MT>& A, int r, const VT* __restrict__ p, VT* q,
+                                              const RT* __restrict__ rv, double (&v)[2]) {
+  using AT = VT;
+  const AT pr = (AT)p[r];
+  const AT ap = (AT)A.D[r] * pr - offdiag<AT>(A, r, p);
+  q[r] = (VT)ap;
+  v[0] += (double)pr * (double)ap;
+  v[1] += (double)pr * (double)rv[r];
+}
+
+__device__ __forceinline__ double fcg_alpha(const double* scal, int s_rho, int s_gam) {
+  const double rho = scal[s_rho];
+  return (rho > 0.0 && isfinite(rho)) ? scal[s_gam] / rho : 0.0;
+}
+
+__device__ __forceinline__ double fcg_beta(const double* scal, int s_dot, int s_rho) {
+  const double rho = scal[s_rho];
+  return rho > 0.0 ? scal[s_dot] / rho : 0.0;
+}
+
+// Coarsest solve x = L^-T (L^-1 b) with the inverted factor: two triangular
+// products, thread i owning rows i, i + blockDim, ... (n <= 1024).
+template <typename VT, typename RT>
+__device__ __forceinline__ void coarse_apply(const CoarseView& C, const RT* __restrict__ b, VT* x, double* sb,
+                                             double* sy) {
+  const int n = C.n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j <= i; ++j) acc += C.LinvT[(size_t)j * n + i] * sb[j];
+    sy[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double acc = 0.0;
+    for (int j = i; j < n; ++j) acc += C.Linv[(size_t)j * n + i] * sy[j];
+    x[i] = (VT)acc;
+  }
+}
+
+// ------------------------------------------------------------------ tail interpreter
+enum OpType : int {
+  OP_CHEB_FIRST = 1,
+  OP_CHEB_NEXT,
+  OP_SCALE_ADD,
+  OP_RESIDUAL,
+  OP_RESTRICT,
+  OP_PROLONG,
+  OP_COARSE,
+  OP_MULTIDOT,
+  OP_FCG_P,
+  OP_SPMV_DOTS,
+  OP_FCG_XR,
+};
+
+struct TailOp {
+  int type, level, n, k;
+  int i0, i1, i2, i3;
+  double f0, f1, f2, f3;
+  const void* a;
+  const void* b;
+  void* c;
+  void* d;
+  VecPtrs w;
+  Slots s0, s1;
+};
+
+// The tail program runs entirely out of the workgroup's LDS: its op list,
+// the level descriptors, the matrices, transfer maps, coarsest factor,
+// vectors and scalars are laid out in one LDS image that the kernel fills
+// from device memory at start; the tail level's solution is copied back at the
+// end.  Inside the image every operand is a byte offset, recorded with bit 62
+// set (no device address has that bit) so that a recording mistake cannot
+// pass for a device pointer.
+constexpr uint64_t kLdsTag = 1ull << 62;
+
+template <typename T>
+__device__ __forceinline__ T* at(char* lds, const void* tag) {
+  return reinterpret_cast<T*>(lds + (uint32_t)(uint64_t)tag);
+}
+
+template <typename MT>
+__device__ __forceinline__ Mat<MT> lds_mat(const Mat<MT>& A, char* lds) {
+  Mat<MT> B = A;
+  B.off = at<const int>(lds, A.off);
+  B.width = at<const int>(lds, A.width);
+  B.col = at<const int>(lds, A.col);
+  B.val = at<const MT>(lds, A.val);
+  B.D = at<const MT>(lds, A.D);
+  return B;
+}
+
+__device__ __forceinline__ Transfer lds_tr(const Transfer& T, char* lds) {
+  Transfer U = T;
+  U.agg = at<const int>(lds, T.agg);
+  U.members = at<const int>(lds, T.members);
+  U.member_off = at<const int>(lds, T.member_off);
+  return U;
+}
+
+struct TailCopy {
+  const void* src;  // device address
+  uint32_t dst;     // LDS byte offset
+  int bytes;        // multiple of 16
+};
+
+struct TailProgram {
+  int nops;
+  int ncin;
+  uint32_t ops_off;   // LDS offset of the op list
+  uint32_t mats_off;  // LDS offset of Mat<MT>[L + 1]
+  uint32_t trs_off;   // LDS offset of Transfer[L + 1]
+  uint32_t scal_off;  // LDS offset of the scalar area
+  const TailCopy* cin;
+  TailCopy cout;  // solution of the tail level, LDS -> device
+  CoarseView C;   // Linv, LinvT as tagged LDS offsets
+};
+
+// Runs a recorded op program in one workgroup; every op is a data-parallel
+// loop over rows followed by a workgroup barrier.  Reductions are workgroup
+// reductions (no grid synchronization needed).
+template <typename VT, typename MT>
+__device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double* red, double* sb, double* sy,
+                                         bool copy_constants) {
+  const int tid = threadIdx.x, bd = blockDim.x;
+  for (int c = copy_constants ? 0 : P.ncin - 1; c < P.ncin; ++c) {
+    const TailCopy cp = P.cin[c];
+    const int4* src = static_cast<const int4*>(cp.src);
+    int4* dst = reinterpret_cast<int4*>(lds + cp.dst);
+    for (int i = tid; i < (cp.bytes >> 4); i += bd) dst[i] = src[i];
+  }
+  __syncthreads();
+  double* scal = reinterpret_cast<double*>(lds + P.scal_off);
+  const CoarseView C{P.C.n, at<const double>(lds, P.C.Linv), at<const double>(lds, P.C.LinvT)};
+  const TailOp* ops = reinterpret_cast<const TailOp*>(lds + P.ops_off);
+  const Mat<MT>* mats = reinterpret_cast<const Mat<MT>*>(lds + P.mats_off);
+  const Transfer* trs = reinterpret_cast<const Transfer*>(lds + P.trs_off);
+  for (int o = 0; o < P.nops; ++o) {
+    const TailOp& op = ops[o];
+    switch (op.type) {
+      case OP_CHEB_FIRST: {
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* w0 = at<const VT>(lds, op.a);
+        VT* w1 = at<VT>(lds, op.c);
+        VT* y = at<VT>(lds, op.d);
+        for (int r = tid; r < A.n; r += bd)
+          row_cheb_first<VT, MT, VT>(A, r, w0, w1, y, op.f0, op.f1, op.f2, op.f3, op.i0, op.i1);
+        break;
+      }
+      case OP_CHEB_NEXT: {
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* wk = at<const VT>(lds, op.a);
+        const VT* wp = at<const VT>(lds, op.b);
+        VT* wn = at<VT>(lds, op.c);
+        VT* y = at<VT>(lds, op.d);
+        for (int r = tid; r < A.n; r += bd) row_cheb_next<VT, MT, VT>(A, r, wk, wp, wn, y, op.f0, op.f1, op.f2, op.i0);
+        break;
+      }
+      case OP_SCALE_ADD: {
+        const VT* w0 = at<const VT>(lds, op.a);
+        VT* y = at<VT>(lds, op.d);
+        for (int i = tid; i < op.n; i += bd) {
+          VT v = (VT)op.f0 * w0[i];
+          if (op.i0) v += y[i];
+          y[i] = v;
+        }
+        break;
+      }
+      case OP_RESIDUAL: {
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* f = at<const VT>(lds, op.a);
+        const VT* x = at<const VT>(lds, op.b);
+        VT* sv = at<VT>(lds, op.c);
+        for (int r = tid; r < A.n; r += bd) row_residual<VT, MT, VT>(A, r, f, x, sv);
+        break;
+      }
+      case OP_RESTRICT: {
+        const Transfer T = lds_tr(trs[op.level], lds);
+        const VT* sv = at<const VT>(lds, op.a);
+        VT* b = at<VT>(lds, op.c);
+        for (int I = tid; I < T.nc; I += bd) row_restrict<VT>(T, I, sv, b);
+        break;
+      }
+      case OP_PROLONG: {
+        const Transfer T = lds_tr(trs[op.level], lds);
+        const VT* e = at<const VT>(lds, op.a);
+        VT* x = at<VT>(lds, op.c);
+        for (int i = tid; i < T.n; i += bd) row_prolong<VT>(T, i, e, x);
+        break;
+      }
+      case OP_COARSE:
+        coarse_apply<VT, VT>(C, at<const VT>(lds, op.a), at<VT>(lds, op.c), sb, sy);
+        break;
+      case OP_MULTIDOT: {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = 0.0;
+        const VT* z = at<const VT>(lds, op.a);
+        for (int j = tid; j < op.n; j += bd) {
+          const double zj = (double)z[j];
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (i < op.k) v[i] += zj * (double)at<const VT>(lds, op.w.p[i])[j];
+        }
+        block_sum<8>(v, red);
+        if (tid == 0)
+          for (int i = 0; i < op.k; ++i) scal[op.s0.s[i]] = v[i];
+        break;
+      }
+      case OP_FCG_P: {
+        double beta[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) beta[i] = i < op.k ? fcg_beta(scal, op.s0.s[i], op.s1.s[i]) : 0.0;
+        const VT* z = at<const VT>(lds, op.a);
+        VT* p = at<VT>(lds, op.c);
+        for (int j = tid; j < op.n; j += bd) {
+          double v = (double)z[j];
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (i < op.k) v -= beta[i] * (double)at<const VT>(lds, op.w.p[i])[j];
+          p[j] = (VT)v;
+        }
+        break;
+      }
+      case OP_SPMV_DOTS: {
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* p = at<const VT>(lds, op.a);
+        const VT* rv = at<const VT>(lds, op.b);
+        VT* q = at<VT>(lds, op.c);
+        double v[2] = {0.0, 0.0};
+        for (int r = tid; r < A.n; r += bd) row_spmv_dots<VT, MT, VT>(A, r, p, q, rv, v);
+        block_sum<2>(v, red);
+        if (tid == 0) {
+          scal[op.s0.s[0]] = v[0];
+          scal[op.s0.s[1]] = v[1];
+        }
+        break;
+      }
+      case OP_FCG_XR: {
+        const double alpha = fcg_alpha(scal, op.i0, op.i1);
+        const VT* p = at<const VT>(lds, op.a);
+        const VT* q = at<const VT>(lds, op.b);
+        VT* x = at<VT>(lds, op.c);
+        VT* r = at<VT>(lds, op.d);
+        for (int j = tid; j < op.n; j += bd) {
+          const double pj = (double)p[j];
+          x[j] = (VT)(op.i2 ? alpha * pj : (double)x[j] + alpha * pj);
+          if (op.i3) r[j] = (VT)((double)r[j] - alpha * (double)q[j]);
+        }
+        break;
+      }
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+  {
+    const int4* src = reinterpret_cast<const int4*>(lds + P.cout.dst);
+    int4* dst = static_cast<int4*>(const_cast<void*>(P.cout.src));
+    for (int i = tid; i < (P.cout.bytes >> 4); i += bd) dst[i] = src[i];
+  }
+}
+
+
+}  // namespace amg
