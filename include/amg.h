@@ -123,6 +123,7 @@ typedef struct {
   double galerkin_ms;                 /* coarse operators (sort and reduce)     */
   int32_t match_rounds;               /* handshake rounds summed over passes    */
   int32_t precision;
+  double device_bytes;                /* device memory held by the hierarchy    */
 } amg_hier_desc;
 
 /* Fill *p with the defaults: degree 4, agg_size 4, coarse_max 64,
@@ -211,6 +212,77 @@ int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing
  */
 int32_t amg_solve_batch(int32_t nb, amg_hier* const* h, const double* const* f, double* const* u,
                         void* stream, amg_info* infos);
+
+/* ---- Serving ---------------------------------------------------------------
+ * Replay of an open-loop request stream.  A request names a graph by the
+ * caller's graph_id and carries nrhs right-hand sides.  The graph data
+ * (n, row_ptr, col, w, d; host, as for amg_setup) is read when the graph is
+ * not resident (first request, or after an eviction); a request without graph
+ * data for a graph that is not resident fails with AMG_ERR_ARG.
+ * AMG_SERVE_BATCHED: continuous batching -- right-hand sides are admitted as
+ *   slots between rounds of iters_per_step outer iterations, as they arrive
+ *   and as slots (max_slots) and device memory (hbm_budget_bytes: hierarchies,
+ *   slot workspaces and vectors) free up; all in-flight slots advance together
+ *   through the batched executor; converged slots retire at the end of a
+ *   round; new graphs are set up by a worker thread on its own stream while
+ *   solves run; idle hierarchies are evicted least recently used first.
+ * AMG_SERVE_SEQUENTIAL: one right-hand side at a time in arrival order with
+ *   amg_solve (the comparison mode).
+ * realtime = 1: a request becomes visible at its arrival time (seconds from
+ * the start of the call); 0: all requests are visible at once.
+ * out: host array with one record per right-hand side, request-major
+ * (sum of nrhs records); solutions go to reqs[i].u (host, nrhs * n, optional).
+ * Returns AMG_OK when every request was processed (per-RHS status in out),
+ * or an argument/device error. */
+enum { AMG_SERVE_BATCHED = 0, AMG_SERVE_SEQUENTIAL = 1 };
+
+typedef struct {
+  double arrival_s;
+  int32_t graph_id;
+  int32_t n;
+  const int32_t* row_ptr;  /* graph data, may be NULL for a resident graph */
+  const int32_t* col;
+  const double* w;
+  const double* d;
+  int32_t nrhs;
+  const double* f;         /* host, nrhs * n values, right-hand side k at f + k n */
+  double* u;               /* host output, nrhs * n values, or NULL */
+} amg_request;
+
+typedef struct {
+  int32_t request;
+  int32_t rhs;
+  int32_t status;
+  int32_t iters;
+  double rel_res_true;
+  double arrival_s;
+  double admit_s;
+  double finish_s;
+} amg_completion;
+
+typedef struct {
+  amg_params params;        /* parameters of every hierarchy set up */
+  double hbm_budget_bytes;  /* device memory the server may hold */
+  int32_t max_slots;        /* right-hand sides in flight at once */
+  int32_t mode;             /* AMG_SERVE_BATCHED or AMG_SERVE_SEQUENTIAL */
+  int32_t iters_per_step;   /* outer iterations per admission round */
+  int32_t realtime;
+} amg_serve_cfg;
+
+typedef struct {
+  double wall_s;
+  double peak_bytes;        /* largest device memory held by the server */
+  int32_t evictions;
+  int32_t setups;
+  int32_t steps;
+} amg_serve_stats;
+
+/* Defaults: amg_params_default, 200e9 bytes, 256 slots, batched, 2
+ * iterations per round, realtime. */
+void amg_serve_cfg_default(amg_serve_cfg* cfg);
+
+int32_t amg_serve(const amg_serve_cfg* cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
+                  amg_serve_stats* stats, void* stream);
 
 /* ---- Level inspection and single steps (tests and diagnostics) ------------
  * The single steps below (all but amg_apply_cycle) need an AMG_FP64

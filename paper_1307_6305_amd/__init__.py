@@ -84,6 +84,7 @@ class amg_hier_desc(ctypes.Structure):
         ("galerkin_ms", ctypes.c_double),
         ("match_rounds", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+        ("device_bytes", ctypes.c_double),
     ]
 
 
@@ -96,6 +97,59 @@ class amg_kernel_timing(ctypes.Structure):
         ("entries", ctypes.c_int64),
         ("grid", ctypes.c_int32),
         ("value_bytes", ctypes.c_int32),
+    ]
+
+
+AMG_SERVE_BATCHED = 0
+AMG_SERVE_SEQUENTIAL = 1
+
+
+class amg_request(ctypes.Structure):
+    _fields_ = [
+        ("arrival_s", ctypes.c_double),
+        ("graph_id", ctypes.c_int32),
+        ("n", ctypes.c_int32),
+        ("row_ptr", ctypes.c_void_p),
+        ("col", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+        ("d", ctypes.c_void_p),
+        ("nrhs", ctypes.c_int32),
+        ("f", ctypes.c_void_p),
+        ("u", ctypes.c_void_p),
+    ]
+
+
+class amg_completion(ctypes.Structure):
+    _fields_ = [
+        ("request", ctypes.c_int32),
+        ("rhs", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("rel_res_true", ctypes.c_double),
+        ("arrival_s", ctypes.c_double),
+        ("admit_s", ctypes.c_double),
+        ("finish_s", ctypes.c_double),
+    ]
+
+
+class amg_serve_cfg(ctypes.Structure):
+    _fields_ = [
+        ("params", amg_params),
+        ("hbm_budget_bytes", ctypes.c_double),
+        ("max_slots", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("iters_per_step", ctypes.c_int32),
+        ("realtime", ctypes.c_int32),
+    ]
+
+
+class amg_serve_stats(ctypes.Structure):
+    _fields_ = [
+        ("wall_s", ctypes.c_double),
+        ("peak_bytes", ctypes.c_double),
+        ("evictions", ctypes.c_int32),
+        ("setups", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
     ]
 
 
@@ -120,6 +174,9 @@ SIGNATURES = {
     "amg_solve": (_I32, [_P, _P, _P, _P, ctypes.POINTER(amg_info)]),
     "amg_solve_batch": (_I32, [_I32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _P,
                                ctypes.POINTER(amg_info)]),
+    "amg_serve_cfg_default": (None, [ctypes.POINTER(amg_serve_cfg)]),
+    "amg_serve": (_I32, [ctypes.POINTER(amg_serve_cfg), ctypes.POINTER(amg_request), _I32,
+                         ctypes.POINTER(amg_completion), ctypes.POINTER(amg_serve_stats), _P]),
     "amg_time_step": (_I32, [_P, _I32, _P, ctypes.POINTER(amg_kernel_timing)]),
     "amg_level_export": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P]),
     "amg_apply_smoother": (_I32, [_P, _I32, _P, _P, _P]),
@@ -244,6 +301,7 @@ def amg_describe(h: Hierarchy) -> dict:
         "galerkin_ms": ds.galerkin_ms,
         "match_rounds": ds.match_rounds,
         "precision": ds.precision,
+        "device_bytes": ds.device_bytes,
     }
 
 
@@ -274,6 +332,68 @@ def amg_solve_batch(hs, fs, us, stream=None, check: bool = False) -> list:
         _check(code, "amg_solve_batch")
     return [{"status": i.status, "iters": i.iters, "rel_res": i.rel_res, "rel_res_true": i.rel_res_true,
              "solve_ms": i.solve_ms} for i in infos]
+
+
+def amg_serve_cfg_default(params: amg_params | None = None, **overrides) -> amg_serve_cfg:
+    c = amg_serve_cfg()
+    load_library().amg_serve_cfg_default(ctypes.byref(c))
+    if params is not None:
+        c.params = params
+    for k, v in overrides.items():
+        if k == "mode" and isinstance(v, str):
+            v = {"batched": AMG_SERVE_BATCHED, "sequential": AMG_SERVE_SEQUENTIAL}[v]
+        setattr(c, k, v)
+    return c
+
+
+def amg_serve(cfg: amg_serve_cfg, requests: list, stream=None, want_u: bool = True):
+    """Replay a request stream.  Each request is a dict with keys arrival_s,
+    graph_id, graph (an object with n, row_ptr, col, w, d; may be None when the
+    graph is resident) or n, and f (array of shape (nrhs, n) or (n,)).
+    Returns (completions: list of dicts, stats: dict, solutions: list of
+    (nrhs, n) arrays or None)."""
+    keep = []
+    reqs = (amg_request * len(requests))()
+    sols = []
+    for i, rq in enumerate(requests):
+        g = rq.get("graph")
+        f = np.ascontiguousarray(np.atleast_2d(np.asarray(rq["f"], dtype=np.float64)))
+        n = g.n if g is not None else int(rq["n"])
+        if f.shape[1] != n:
+            raise ValueError(f"request {i}: f has {f.shape[1]} columns, graph has {n} vertices")
+        r = reqs[i]
+        r.arrival_s = float(rq.get("arrival_s", 0.0))
+        r.graph_id = int(rq["graph_id"])
+        r.n = n
+        if g is not None:
+            rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+            cl = np.ascontiguousarray(g.col, dtype=np.int32)
+            wv = np.ascontiguousarray(g.w, dtype=np.float64)
+            dv = np.ascontiguousarray(g.d, dtype=np.float64)
+            keep += [rp, cl, wv, dv]
+            r.row_ptr, r.col, r.w, r.d = (a.ctypes.data for a in (rp, cl, wv, dv))
+        r.nrhs = f.shape[0]
+        r.f = f.ctypes.data
+        keep.append(f)
+        if want_u:
+            u = np.zeros_like(f)
+            keep.append(u)
+            r.u = u.ctypes.data
+            sols.append(u)
+        else:
+            sols.append(None)
+    total = sum(reqs[i].nrhs for i in range(len(requests)))
+    out = (amg_completion * total)()
+    stats = amg_serve_stats()
+    code = load_library().amg_serve(ctypes.byref(cfg), reqs, len(requests), out, ctypes.byref(stats),
+                                    _stream(stream))
+    _check(code, "amg_serve")
+    comps = [{"request": c.request, "rhs": c.rhs, "status": c.status, "iters": c.iters,
+              "rel_res_true": c.rel_res_true, "arrival_s": c.arrival_s, "admit_s": c.admit_s,
+              "finish_s": c.finish_s} for c in out]
+    st = {"wall_s": stats.wall_s, "peak_bytes": stats.peak_bytes, "evictions": stats.evictions,
+          "setups": stats.setups, "steps": stats.steps}
+    return comps, st, sols
 
 
 def amg_time_step(h: Hierarchy, reps: int = 200, stream=None) -> dict:

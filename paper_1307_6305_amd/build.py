@@ -28,6 +28,7 @@ SOURCES = [
     ("setup.hip", "hipcc", ["-ffp-contract=off"]),
     ("solve.hip", "hipcc", []),
     ("batch.hip", "hipcc", []),
+    ("serve.hip", "hipcc", []),
 ]
 
 

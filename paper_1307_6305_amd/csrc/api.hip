@@ -22,6 +22,7 @@ int32_t dalloc(amg_hier* h, void** p, size_t bytes) {
     return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
   }
   h->allocs.push_back(q);
+  h->bytes += bytes;
   *p = q;
   return AMG_OK;
 }
@@ -181,6 +182,7 @@ void amg_free(amg_hier* h) {
 int32_t amg_describe(const amg_hier* h, amg_hier_desc* out) {
   if (!h || !out) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
   *out = h->desc;
+  out->device_bytes = (double)h->bytes;
   return AMG_OK;
 }
 
@@ -195,6 +197,45 @@ int32_t amg_solve_batch(int32_t nb, amg_hier* const* h, const double* const* f, 
   for (int32_t i = 0; i < nb; ++i)
     if (!h[i] || !f[i] || !u[i]) { amg::set_last_error("null item " + std::to_string(i)); return AMG_ERR_ARG; }
   return amg::solve_batch(nb, h, f, u, static_cast<hipStream_t>(stream), infos);
+}
+
+void amg_serve_cfg_default(amg_serve_cfg* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  amg_params_default(&c->params);
+  c->hbm_budget_bytes = 200e9;
+  c->max_slots = 256;
+  c->mode = AMG_SERVE_BATCHED;
+  c->iters_per_step = 2;
+  c->realtime = 1;
+}
+
+int32_t amg_serve(const amg_serve_cfg* cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
+                  amg_serve_stats* stats, void* stream) {
+  if (!cfg || !reqs || nreq < 1 || !out) { amg::set_last_error("invalid argument"); return AMG_ERR_ARG; }
+  if (cfg->mode != AMG_SERVE_BATCHED && cfg->mode != AMG_SERVE_SEQUENTIAL) {
+    amg::set_last_error("unknown serve mode");
+    return AMG_ERR_ARG;
+  }
+  if (!(cfg->hbm_budget_bytes > 0) || cfg->max_slots < 1) {
+    amg::set_last_error("budget and max_slots must be positive");
+    return AMG_ERR_ARG;
+  }
+  std::string msg;
+  const int32_t pst = amg::validate_params(cfg->params, msg);
+  if (pst != AMG_OK) {
+    amg::set_last_error(msg);
+    return pst;
+  }
+  for (int32_t i = 0; i < nreq; ++i) {
+    const amg_request& q = reqs[i];
+    if (q.n < 1 || q.nrhs < 1 || !q.f) {
+      amg::set_last_error("request " + std::to_string(i) + ": n, nrhs and f are required");
+      return AMG_ERR_ARG;
+    }
+  }
+  AMG_TRY(check_device());
+  return amg::serve(*cfg, reqs, nreq, out, stats, static_cast<hipStream_t>(stream));
 }
 
 int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing* timing) {

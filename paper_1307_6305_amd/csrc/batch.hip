@@ -21,18 +21,11 @@
 #include <mutex>
 #include <vector>
 
+#include "batch.h"
 #include "kernels.h"
 
 namespace amg {
 namespace {
-
-struct ItemState {
-  int active;  // 1 while the item iterates
-  int iter;    // completed outer iterations
-  int status;  // AMG_OK, AMG_ERR_MAXIT or AMG_ERR_BREAKDOWN
-  int pad;
-  double rr0, rr, rrt;
-};
 
 enum BatchOpType : int {
   B_CHEB_FIRST = 1,
@@ -77,6 +70,7 @@ struct BatchOp {
   VecPtrs w2;
   Slots s0, s1;
   double* scal;
+  ItemState* st;
 };
 
 template <typename MT>
@@ -104,11 +98,11 @@ __device__ __forceinline__ void deposit(double (&v)[K], double* partials, int sl
 // (b - first_block) of op block_op[b].
 template <typename VT, typename MT>
 __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ ops, const int* __restrict__ block_op,
-                                                    const ItemState* __restrict__ st, double* partials) {
+                                                    double* partials) {
   __shared__ double red[16 * 8];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const BatchOp& op = ops[block_op[b]];
-  if (!st[op.item].active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
+  if (!op.st->active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
   const int tile = b - op.first_block;
   const int r = tile * TPB + threadIdx.x;
   const bool live = r < op.n;
@@ -211,7 +205,7 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
       break;
     }
     case B_O_MULTIDOT: {
-      const int j = st[op.item].iter % op.i0;
+      const int j = op.st->iter % op.i0;
       double v[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = 0.0;
@@ -226,7 +220,7 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
     }
     case B_O_P: {
       if (!live) break;
-      const int j = st[op.item].iter % op.i0;
+      const int j = op.st->iter % op.i0;
       double acc = (double)((const VT*)op.a)[r];
 #pragma unroll
       for (int i = 0; i < 8; ++i)
@@ -235,7 +229,7 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
       break;
     }
     case B_O_SPMV: {
-      const int j = st[op.item].iter % op.i0;
+      const int j = op.st->iter % op.i0;
       double v[2] = {0.0, 0.0};
       if (live)
         row_spmv_dots<double, double, double>(op.A64, r, (const double*)op.w2.p[j], (double*)op.w.p[j],
@@ -244,7 +238,7 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
       break;
     }
     case B_O_XR: {
-      const int j = st[op.item].iter % op.i0;
+      const int j = op.st->iter % op.i0;
       double v[1] = {0.0};
       if (live) {
         const double alpha = fcg_alpha(op.scal, S_RHOW + j, S_GAM);
@@ -265,10 +259,10 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
 
 // Coarsest solves, one block per item.
 template <typename VT>
-__global__ void __launch_bounds__(TPB) k_batch_coarse(const BatchOp* __restrict__ ops, const ItemState* __restrict__ st) {
+__global__ void __launch_bounds__(TPB) k_batch_coarse(const BatchOp* __restrict__ ops) {
   __shared__ double sb[1024], sy[1024];
   const BatchOp& op = ops[blockIdx.x];
-  if (!st[op.item].active) return;
+  if (!op.st->active) return;
   if (op.i2)
     coarse_apply<VT, double>(op.C, (const double*)op.a, (VT*)op.c, sb, sy);
   else
@@ -278,30 +272,22 @@ __global__ void __launch_bounds__(TPB) k_batch_coarse(const BatchOp* __restrict_
 // Tail programs, one workgroup per item.
 template <typename VT, typename MT>
 __global__ void __launch_bounds__(TAIL_THREADS) k_batch_tail(const TailProgram* __restrict__ progs,
-                                                             const int* __restrict__ items,
-                                                             const ItemState* __restrict__ st) {
+                                                             ItemState* const* __restrict__ states) {
   extern __shared__ __align__(16) char lds[];
   __shared__ double red[16 * 8];
   __shared__ double sb[1024], sy[1024];
-  if (!st[items[blockIdx.x]].active) return;
+  if (!states[blockIdx.x]->active) return;
   run_tail<VT, MT>(progs[blockIdx.x], lds, red, sb, sy, true);
 }
-
-struct BatchCtl {
-  double tol;
-  int max_iter;
-  int pad;
-  int* nactive;  // device counter of items still iterating
-};
 
 // Fixed-order sums of each reduction op's partials (one block per op), and
 // the per-item bookkeeping of the outer iteration.
 __global__ void __launch_bounds__(kFinishThreads) k_batch_finish(const BatchOp* __restrict__ ops,
-                                                                 const int* __restrict__ fin, ItemState* st,
-                                                                 const double* partials, BatchCtl ctl) {
+                                                                 const int* __restrict__ fin, const double* partials,
+                                                                 BatchCtl ctl) {
   __shared__ double red[16 * 8];
   const BatchOp& op = ops[fin[blockIdx.x]];
-  ItemState& S = st[op.item];
+  ItemState& S = *op.st;
   if (!S.active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
   double acc[8];
   sum_partials<8>(partials + (size_t)op.part * 8, op.blocks, acc, red);
@@ -366,6 +352,8 @@ __global__ void __launch_bounds__(kFinishThreads) k_batch_finish(const BatchOp* 
 __global__ void k_batch_reset(int* nactive) { *nactive = 0; }
 
 // ------------------------------------------------------------------ schedule
+}  // namespace
+
 struct Launch {
   int kind;  // 0 step, 1 coarse, 2 tail, 3 finish
   int op0, nops;
@@ -375,87 +363,47 @@ struct Launch {
   int threads;
 };
 
-struct Item {
-  amg_hier* h;  // hierarchy with this item's workspace
-  const double* f;
-  double* u;
-};
-
-}  // namespace
-
-struct Batch {
-  std::vector<void*> key;
-  std::vector<amg_hier*> clones;  // workspaces for repeated hierarchies
-  std::vector<Item> items;
-  bool mixed = false;
-  int restart = 5;
-  double tol = 1e-8;
-  int max_iter = 200;
-  // device
-  BatchOp* d_ops = nullptr;
-  int* d_map = nullptr;
-  int* d_fin = nullptr;
-  TailProgram* d_tails = nullptr;
-  int* d_tail_items = nullptr;
-  ItemState* d_state = nullptr;
-  double* d_partials = nullptr;
-  int* d_nactive = nullptr;
-  int* h_nactive = nullptr;
+struct ScheduleDev {
+  BatchOp* ops = nullptr;
+  int* map = nullptr;
+  int* fin = nullptr;
+  TailProgram* tails = nullptr;
+  ItemState** tail_states = nullptr;
+  double* partials = nullptr;
   std::vector<void*> allocs;
-  std::vector<Launch> init, iter, fini;
-  hipGraphExec_t g_init = nullptr, g_iter = nullptr, g_fini = nullptr;
-  hipStream_t gs = nullptr;
-  ~Batch() {
-    if (g_init) (void)hipGraphExecDestroy(g_init);
-    if (g_iter) (void)hipGraphExecDestroy(g_iter);
-    if (g_fini) (void)hipGraphExecDestroy(g_fini);
-    if (gs) (void)hipStreamDestroy(gs);
-    for (void* p : allocs) (void)hipFree(p);
-    if (h_nactive) (void)hipHostFree(h_nactive);
-    for (amg_hier* c : clones) free_clone(c);
-  }
 };
 
 namespace {
 
-int32_t balloc(Batch* B, void** p, size_t bytes) {
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, bytes + 16);
-  if (e != hipSuccess) {
-    set_last_error(std::string("hipMalloc (batch): ") + hipGetErrorString(e));
-    return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
-  }
-  B->allocs.push_back(q);
-  *p = q;
-  return AMG_OK;
-}
-
 // Builds the union schedule of the items' cycles.
 struct Builder {
-  Batch* B;
+  const std::vector<BatchItem>& items;
+  bool mixed;
+  std::vector<Launch>* out;
   std::vector<BatchOp> ops;
   std::vector<int> map;
   std::vector<int> fin;
   std::vector<TailProgram> tails;
-  std::vector<int> tail_items;
-  std::vector<Launch>* out = nullptr;
-  int parts = 0;      // partial tiles of the current launch
-  int max_parts = 0;  // largest over launches (the partial buffer is reused)
+  std::vector<ItemState*> tail_states;
+  int max_parts = 0;  // largest partial-sum need over launches (the buffer is reused)
 
-  static BatchOp blank(int type, int item) {
+  Builder(const std::vector<BatchItem>& it, bool mx, std::vector<Launch>* o) : items(it), mixed(mx), out(o) {}
+
+  BatchOp blank(int type, int item) const {
     BatchOp o;
     std::memset(&o, 0, sizeof(o));
     o.type = type;
     o.item = item;
+    o.st = items[item].st;
     return o;
   }
 
-  const amg_hier* H(int i) const { return B->items[i].h; }
+  const amg_hier* H(int i) const { return items[i].h; }
 
   void fill_mats(BatchOp& o, int i, int l) const {
     const Level& lv = H(i)->lv[l];
     o.A64 = mat_of<double>(lv);
-    if (B->mixed) o.A32 = mat_of<float>(lv);
+    if (mixed) o.A32 = mat_of<float>(lv);
   }
 
   // one step launch over the given ops (each spanning ceil(n / TPB) tiles)
@@ -466,8 +414,7 @@ struct Builder {
     L.op0 = (int)ops.size();
     L.nops = (int)v.size();
     L.map0 = (int)map.size();
-    parts = 0;
-    int blocks = 0;
+    int parts = 0, blocks = 0;
     for (size_t q = 0; q < v.size(); ++q) {
       BatchOp& o = v[q];
       o.blocks = nblk(o.n);
@@ -484,7 +431,6 @@ struct Builder {
     if (reduces) {
       Launch F{};
       F.kind = 3;
-      F.op0 = 0;
       F.map0 = (int)fin.size();
       F.nblocks = L.nops;
       for (int q = 0; q < L.nops; ++q) fin.push_back(L.op0 + q);
@@ -492,7 +438,6 @@ struct Builder {
     }
   }
 
-  // ---------------------------------------------------------------- cycle
   // Vectors are named per item: the level's rhs, sol, Z[k], S, A, B buffers,
   // or the outer r / z.
   enum Src { SRC_OUTER_R, SRC_RHS, SRC_S };
@@ -509,8 +454,8 @@ struct Builder {
   }
 
   void smooth(int l, const std::vector<int>& I, Src src, Dst dst, int k, bool accum) {
-    const int m = B->items[I[0]].h->p.degree;
-    const bool r64 = (src == SRC_OUTER_R) && B->mixed;
+    const int m = H(I[0])->p.degree;
+    const bool r64 = (src == SRC_OUTER_R) && mixed;
     if (m == 0) {
       std::vector<BatchOp> v;
       for (int i : I) {
@@ -584,7 +529,7 @@ struct Builder {
       o.a = src_ptr(i, l, src);
       o.b = dst_ptr(i, l, dst, k);
       o.c = H(i)->ws[l].S;
-      o.i2 = (src == SRC_OUTER_R) && B->mixed;
+      o.i2 = (src == SRC_OUTER_R) && mixed;
       v.push_back(o);
     }
     step(v, false);
@@ -616,21 +561,27 @@ struct Builder {
     step(v, false);
   }
 
-  void coarse(const std::vector<int>& I) {
-    if (I.empty()) return;
+  void coarse_launch(const std::vector<BatchOp>& v) {
+    if (v.empty()) return;
     Launch L{};
     L.kind = 1;
     L.op0 = (int)ops.size();
-    L.nops = (int)I.size();
+    L.nops = (int)v.size();
+    ops.insert(ops.end(), v.begin(), v.end());
+    out->push_back(L);
+  }
+
+  void coarse(const std::vector<int>& I) {
+    std::vector<BatchOp> v;
     for (int i : I) {
       const amg_hier* h = H(i);
       BatchOp o = blank(B_COARSE, i);
       o.C = CoarseView{h->nL, h->chol_inv, h->chol_invT};
       o.a = h->ws[h->L].rhs;
       o.c = h->ws[h->L].sol;
-      ops.push_back(o);
+      v.push_back(o);
     }
-    out->push_back(L);
+    coarse_launch(v);
   }
 
   void tail(const std::vector<int>& I) {
@@ -644,7 +595,7 @@ struct Builder {
     for (int i : I) {
       const amg_hier* h = H(i);
       tails.push_back(*static_cast<const TailProgram*>(h->tail_prog));
-      tail_items.push_back(i);
+      tail_states.push_back(items[i].st);
       L.lds = std::max(L.lds, h->tail_lds_bytes);
       L.threads = std::max(L.threads, h->tail_threads);
     }
@@ -737,15 +688,14 @@ struct Builder {
     }
   }
 
-  // ---------------------------------------------------------------- outer
   void outer_residual(int type, bool into_r) {
     std::vector<BatchOp> v;
-    for (int i = 0; i < (int)B->items.size(); ++i) {
+    for (int i = 0; i < (int)items.size(); ++i) {
       BatchOp o = blank(type, i);
       fill_mats(o, i, 0);
       o.n = H(i)->lv[0].n;
-      o.a = B->items[i].f;
-      o.b = B->items[i].u;
+      o.a = items[i].f;
+      o.b = items[i].u;
       o.c = into_r ? (void*)H(i)->r : (void*)H(i)->tmp;
       v.push_back(o);
     }
@@ -753,33 +703,28 @@ struct Builder {
   }
 
   void outer_iteration() {
-    std::vector<int> all, C;
-    for (int i = 0; i < (int)B->items.size(); ++i) {
-      if (H(i)->L == 0) C.push_back(i);
-      else all.push_back(i);
-    }
-    // one-level items: the preconditioner is the coarsest solve itself
-    if (!C.empty()) {
-      Launch L{};
-      L.kind = 1;
-      L.op0 = (int)ops.size();
-      L.nops = (int)C.size();
-      for (int i : C) {
-        const amg_hier* h = H(i);
-        BatchOp o = blank(B_COARSE, i);
-        o.C = CoarseView{h->nL, h->chol_inv, h->chol_invT};
-        o.a = h->r;
-        o.c = h->z;
-        o.i2 = B->mixed;
-        ops.push_back(o);
-      }
-      out->push_back(L);
-    }
-    if (!all.empty()) kcycle(0, all, SRC_OUTER_R, DST_OUTER_Z, 0);
-    const int R = B->restart;
-    std::vector<BatchOp> md, pp, sp, xr;
-    for (int i = 0; i < (int)B->items.size(); ++i) {
+    std::vector<int> all;
+    std::vector<BatchOp> one_level;
+    for (int i = 0; i < (int)items.size(); ++i) {
       const amg_hier* h = H(i);
+      if (h->L > 0) {
+        all.push_back(i);
+        continue;
+      }
+      // one-level item: the preconditioner is the coarsest solve itself
+      BatchOp o = blank(B_COARSE, i);
+      o.C = CoarseView{h->nL, h->chol_inv, h->chol_invT};
+      o.a = h->r;
+      o.c = h->z;
+      o.i2 = mixed;
+      one_level.push_back(o);
+    }
+    coarse_launch(one_level);
+    if (!all.empty()) kcycle(0, all, SRC_OUTER_R, DST_OUTER_Z, 0);
+    std::vector<BatchOp> md, pp, sp, xr;
+    for (int i = 0; i < (int)items.size(); ++i) {
+      const amg_hier* h = H(i);
+      const int R = h->p.restart;
       BatchOp o = blank(B_O_MULTIDOT, i);
       o.n = h->lv[0].n;
       o.i0 = R;
@@ -793,14 +738,14 @@ struct Builder {
       BatchOp p = o;
       p.type = B_O_P;
       pp.push_back(p);
-      BatchOp s = o;
-      s.type = B_O_SPMV;
-      fill_mats(s, i, 0);
-      s.b = h->r;
-      sp.push_back(s);
+      BatchOp sv = o;
+      sv.type = B_O_SPMV;
+      fill_mats(sv, i, 0);
+      sv.b = h->r;
+      sp.push_back(sv);
       BatchOp x = o;
       x.type = B_O_XR;
-      x.c = B->items[i].u;
+      x.c = items[i].u;
       x.d = h->r;
       xr.push_back(x);
     }
@@ -812,24 +757,24 @@ struct Builder {
 };
 
 template <typename VT, typename MT>
-int32_t run_launches(Batch* B, const std::vector<Launch>& Ls, hipStream_t s) {
-  const BatchCtl ctl{B->tol, B->max_iter, 0, B->d_nactive};
-  for (const Launch& L : Ls) {
+int32_t run_impl(const Schedule* S, const BatchCtl& ctl, hipStream_t s) {
+  const ScheduleDev* D = S->dev;
+  for (const Launch& L : *S->launches) {
     switch (L.kind) {
       case 0:
-        hipLaunchKernelGGL((k_batch_step<VT, MT>), dim3(L.nblocks), dim3(TPB), 0, s, B->d_ops, B->d_map + L.map0,
-                           B->d_state, B->d_partials);
+        hipLaunchKernelGGL((k_batch_step<VT, MT>), dim3(L.nblocks), dim3(TPB), 0, s, D->ops, D->map + L.map0,
+                           D->partials);
         break;
       case 1:
-        hipLaunchKernelGGL((k_batch_coarse<VT>), dim3(L.nops), dim3(TPB), 0, s, B->d_ops + L.op0, B->d_state);
+        hipLaunchKernelGGL((k_batch_coarse<VT>), dim3(L.nops), dim3(TPB), 0, s, D->ops + L.op0);
         break;
       case 2:
-        hipLaunchKernelGGL((k_batch_tail<VT, MT>), dim3(L.nops), dim3(L.threads), L.lds, s, B->d_tails + L.tail0,
-                           B->d_tail_items + L.tail0, B->d_state);
+        hipLaunchKernelGGL((k_batch_tail<VT, MT>), dim3(L.nops), dim3(L.threads), L.lds, s, D->tails + L.tail0,
+                           D->tail_states + L.tail0);
         break;
       case 3:
-        hipLaunchKernelGGL(k_batch_finish, dim3(L.nblocks), dim3(kFinishThreads), 0, s, B->d_ops, B->d_fin + L.map0,
-                           B->d_state, B->d_partials, ctl);
+        hipLaunchKernelGGL(k_batch_finish, dim3(L.nblocks), dim3(kFinishThreads), 0, s, D->ops, D->fin + L.map0,
+                           D->partials, ctl);
         break;
     }
     AMG_HIP(hipGetLastError());
@@ -837,80 +782,187 @@ int32_t run_launches(Batch* B, const std::vector<Launch>& Ls, hipStream_t s) {
   return AMG_OK;
 }
 
-template <typename VT, typename MT>
-int32_t capture(Batch* B, const std::vector<Launch>& Ls, hipGraphExec_t* ex, bool copy_count) {
+int32_t sdalloc(ScheduleDev* D, Schedule* S, void** p, size_t bytes) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes + 16);
+  if (e != hipSuccess) {
+    set_last_error(std::string("hipMalloc (batch schedule): ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
+  }
+  D->allocs.push_back(q);
+  S->bytes += bytes + 16;
+  *p = q;
+  return AMG_OK;
+}
+
+template <typename T>
+int32_t upload(ScheduleDev* D, Schedule* S, T** dst, const std::vector<T>& v, hipStream_t s) {
+  void* p = nullptr;
+  AMG_TRY(sdalloc(D, S, &p, std::max<size_t>(1, v.size()) * sizeof(T)));
+  *dst = static_cast<T*>(p);
+  if (!v.empty()) AMG_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return AMG_OK;
+}
+
+}  // namespace
+
+int32_t batch_compatible(const std::vector<amg_hier*>& hs) {
+  if (hs.empty()) {
+    set_last_error("empty batch");
+    return AMG_ERR_ARG;
+  }
+  const amg_params& p0 = hs[0]->p;
+  for (size_t i = 0; i < hs.size(); ++i) {
+    const amg_hier* h = hs[i];
+    if (h->mixed != hs[0]->mixed || h->p.degree != p0.degree || h->p.inner_steps != p0.inner_steps ||
+        h->p.restart != p0.restart) {
+      set_last_error("batched items must share precision, degree, inner steps and restart");
+      return AMG_ERR_ARG;
+    }
+    if (!h->chol_inv) {
+      set_last_error("batched items need a coarsest level of at most 1024 rows");
+      return AMG_ERR_ARG;
+    }
+  }
+  return AMG_OK;
+}
+
+int32_t schedule_build(Schedule* S, SchedKind kind, const std::vector<BatchItem>& items, hipStream_t s) {
+  schedule_free(S);
+  S->kind = kind;
+  S->mixed = items.empty() ? false : items[0].h->mixed;
+  S->launches = new std::vector<Launch>();
+  S->dev = new ScheduleDev();
+  if (items.empty()) return AMG_OK;
+  Builder bd(items, S->mixed, S->launches);
+  if (kind == SCHED_INIT) bd.outer_residual(B_O_RESID, true);
+  else if (kind == SCHED_FINAL) bd.outer_residual(B_O_TRUE, false);
+  else bd.outer_iteration();
+  ScheduleDev* D = S->dev;
+  AMG_TRY(upload(D, S, &D->ops, bd.ops, s));
+  AMG_TRY(upload(D, S, &D->map, bd.map, s));
+  AMG_TRY(upload(D, S, &D->fin, bd.fin, s));
+  AMG_TRY(upload(D, S, &D->tails, bd.tails, s));
+  AMG_TRY(upload(D, S, &D->tail_states, bd.tail_states, s));
+  void* p = nullptr;
+  AMG_TRY(sdalloc(D, S, &p, (size_t)std::max(1, bd.max_parts) * 8 * sizeof(double)));
+  D->partials = static_cast<double*>(p);
+  size_t max_lds = 0;
+  for (const auto& L : *S->launches)
+    if (L.kind == 2) max_lds = std::max(max_lds, L.lds);
+  if (max_lds) {
+    const void* fn = S->mixed ? (const void*)k_batch_tail<float, float> : (const void*)k_batch_tail<double, double>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+  }
+  AMG_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+  return AMG_OK;
+}
+
+int32_t schedule_run(const Schedule* S, const BatchCtl& ctl, hipStream_t s) {
+  if (!S->launches || S->launches->empty()) return AMG_OK;
+  return S->mixed ? run_impl<float, float>(S, ctl, s) : run_impl<double, double>(S, ctl, s);
+}
+
+void schedule_free(Schedule* S) {
+  if (S->dev) {
+    for (void* p : S->dev->allocs) (void)hipFree(p);
+    delete S->dev;
+    S->dev = nullptr;
+  }
+  delete S->launches;
+  S->launches = nullptr;
+  S->bytes = 0;
+}
+
+namespace {
+
+__global__ void k_reset_count(int* c) { *c = 0; }
+
+// State of the batched entry point: the items of the last call, their
+// workspaces and states, and the three phase schedules (the iteration replayed
+// as a graph).  Reused while the same (h, f, u) are passed.
+struct Batch {
+  std::vector<void*> key;
+  std::vector<amg_hier*> clones;  // workspaces for repeated hierarchies
+  std::vector<BatchItem> items;
+  ItemState* d_state = nullptr;
+  int* d_nactive = nullptr;
+  int* h_nactive = nullptr;
+  Schedule init, iter, fini;
+  hipGraphExec_t g_iter = nullptr;
+  hipStream_t gs = nullptr;
+  double tol = 1e-8;
+  int max_iter = 200;
+  ~Batch() {
+    (void)hipDeviceSynchronize();
+    if (g_iter) (void)hipGraphExecDestroy(g_iter);
+    if (gs) (void)hipStreamDestroy(gs);
+    schedule_free(&init);
+    schedule_free(&iter);
+    schedule_free(&fini);
+    if (d_state) (void)hipFree(d_state);
+    if (d_nactive) (void)hipFree(d_nactive);
+    if (h_nactive) (void)hipHostFree(h_nactive);
+    for (amg_hier* c : clones) free_clone(c);
+  }
+  BatchCtl ctl() const { return BatchCtl{tol, max_iter, 0, d_nactive}; }
+};
+
+std::mutex g_batch_mu;
+std::unique_ptr<Batch> g_batch;  // the most recent batch (its schedule is reused)
+
+using clk = std::chrono::steady_clock;
+
+int32_t make_batch(int nb, amg_hier* const* hs, const double* const* f, double* const* u, hipStream_t s,
+                   std::unique_ptr<Batch>* out) {
+  auto B = std::make_unique<Batch>();
+  std::vector<amg_hier*> hv(hs, hs + nb);
+  AMG_TRY(batch_compatible(hv));
+  for (int i = 0; i < nb; ++i) {
+    if (hs[i]->p.tol != hs[0]->p.tol || hs[i]->p.max_iter != hs[0]->p.max_iter) {
+      set_last_error("batched items must share tol and max_iter");
+      return AMG_ERR_ARG;
+    }
+  }
+  B->tol = hs[0]->p.tol;
+  B->max_iter = hs[0]->p.max_iter;
+  AMG_HIP(hipMalloc(&B->d_state, sizeof(ItemState) * nb));
+  AMG_HIP(hipMalloc(&B->d_nactive, sizeof(int)));
+  AMG_HIP(hipHostMalloc((void**)&B->h_nactive, sizeof(int), hipHostMallocDefault));
+  std::map<const amg_hier*, int> seen;
+  for (int i = 0; i < nb; ++i) {
+    amg_hier* use = hs[i];
+    if (seen.count(hs[i])) {  // another right-hand side on the same hierarchy: its own workspace
+      amg_hier* c = nullptr;
+      AMG_TRY(make_clone(hs[i], &c, s));
+      B->clones.push_back(c);
+      use = c;
+    }
+    seen[hs[i]] = 1;
+    B->items.push_back(BatchItem{use, f[i], u[i], B->d_state + i});
+  }
+  AMG_TRY(schedule_build(&B->init, SCHED_INIT, B->items, s));
+  AMG_TRY(schedule_build(&B->iter, SCHED_ITER, B->items, s));
+  AMG_TRY(schedule_build(&B->fini, SCHED_FINAL, B->items, s));
+  // one outer iteration of the whole batch as a graph, with the count of
+  // items still iterating copied to pinned host memory at its end
+  AMG_HIP(hipStreamCreateWithFlags(&B->gs, hipStreamNonBlocking));
   hipGraph_t g = nullptr;
   AMG_HIP(hipStreamBeginCapture(B->gs, hipStreamCaptureModeThreadLocal));
-  int32_t st = run_launches<VT, MT>(B, Ls, B->gs);
-  if (st == AMG_OK && copy_count) {
+  int32_t st = schedule_run(&B->iter, B->ctl(), B->gs);
+  if (st == AMG_OK) {
     hipError_t e = hipMemcpyAsync(B->h_nactive, B->d_nactive, sizeof(int), hipMemcpyDeviceToHost, B->gs);
     if (e != hipSuccess) st = AMG_ERR_DEVICE;
   }
   hipError_t e = hipStreamEndCapture(B->gs, &g);
   if (st != AMG_OK) return st;
   AMG_HIP(e);
-  e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&B->g_iter, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   AMG_HIP(e);
+  *out = std::move(B);
   return AMG_OK;
 }
-
-template <typename VT, typename MT>
-int32_t build(Batch* B, hipStream_t s) {
-  Builder bd{B};
-  bd.out = &B->init;
-  bd.outer_residual(B_O_RESID, true);
-  bd.out = &B->iter;
-  bd.outer_iteration();
-  bd.out = &B->fini;
-  bd.outer_residual(B_O_TRUE, false);
-  const int nitems = (int)B->items.size();
-  void* p;
-  AMG_TRY(balloc(B, &p, bd.ops.size() * sizeof(BatchOp)));
-  B->d_ops = (BatchOp*)p;
-  AMG_TRY(balloc(B, &p, std::max<size_t>(1, bd.map.size()) * sizeof(int)));
-  B->d_map = (int*)p;
-  AMG_TRY(balloc(B, &p, std::max<size_t>(1, bd.fin.size()) * sizeof(int)));
-  B->d_fin = (int*)p;
-  AMG_TRY(balloc(B, &p, std::max<size_t>(1, bd.tails.size()) * sizeof(TailProgram)));
-  B->d_tails = (TailProgram*)p;
-  AMG_TRY(balloc(B, &p, std::max<size_t>(1, bd.tail_items.size()) * sizeof(int)));
-  B->d_tail_items = (int*)p;
-  AMG_TRY(balloc(B, &p, nitems * sizeof(ItemState)));
-  B->d_state = (ItemState*)p;
-  AMG_TRY(balloc(B, &p, (size_t)std::max(1, bd.max_parts) * 8 * sizeof(double)));
-  B->d_partials = (double*)p;
-  AMG_TRY(balloc(B, &p, sizeof(int)));
-  B->d_nactive = (int*)p;
-  AMG_HIP(hipHostMalloc((void**)&B->h_nactive, sizeof(int), hipHostMallocDefault));
-  AMG_HIP(hipMemcpyAsync(B->d_ops, bd.ops.data(), bd.ops.size() * sizeof(BatchOp), hipMemcpyHostToDevice, s));
-  if (!bd.map.empty())
-    AMG_HIP(hipMemcpyAsync(B->d_map, bd.map.data(), bd.map.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!bd.fin.empty())
-    AMG_HIP(hipMemcpyAsync(B->d_fin, bd.fin.data(), bd.fin.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!bd.tails.empty()) {
-    AMG_HIP(hipMemcpyAsync(B->d_tails, bd.tails.data(), bd.tails.size() * sizeof(TailProgram), hipMemcpyHostToDevice,
-                           s));
-    AMG_HIP(hipMemcpyAsync(B->d_tail_items, bd.tail_items.data(), bd.tail_items.size() * sizeof(int),
-                           hipMemcpyHostToDevice, s));
-  }
-  size_t max_lds = 0;
-  for (const auto& L : B->iter)
-    if (L.kind == 2) max_lds = std::max(max_lds, L.lds);
-  if (max_lds) (void)hipFuncSetAttribute((const void*)k_batch_tail<VT, MT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)max_lds);
-  AMG_HIP(hipStreamSynchronize(s));
-  AMG_HIP(hipStreamCreateWithFlags(&B->gs, hipStreamNonBlocking));
-  AMG_TRY(capture<VT, MT>(B, B->init, &B->g_init, true));
-  AMG_TRY(capture<VT, MT>(B, B->iter, &B->g_iter, true));
-  AMG_TRY(capture<VT, MT>(B, B->fini, &B->g_fini, false));
-  return AMG_OK;
-}
-
-std::mutex g_batch_mu;
-std::unique_ptr<Batch> g_batch;  // the most recent batch (its schedule is reused)
-
-using clk = std::chrono::steady_clock;
 
 }  // namespace
 
@@ -918,7 +970,7 @@ void drop_batches_using(const amg_hier* h) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
   if (!g_batch) return;
   for (const auto& it : g_batch->items)
-    if (it.h == h || (it.h && it.h->parent == h)) {
+    if (it.h == h || it.h->parent == h) {
       g_batch.reset();
       return;
     }
@@ -936,46 +988,15 @@ int32_t solve_batch(int nb, amg_hier* const* hs, const double* const* f, double*
   }
   if (!g_batch || g_batch->key != key) {
     g_batch.reset();
-    auto B = std::make_unique<Batch>();
+    std::unique_ptr<Batch> B;
+    AMG_TRY(make_batch(nb, hs, f, u, s, &B));
     B->key = key;
-    const amg_params& p0 = hs[0]->p;
-    B->mixed = hs[0]->mixed;
-    B->restart = p0.restart;
-    B->tol = p0.tol;
-    B->max_iter = p0.max_iter;
-    std::map<const amg_hier*, int> seen;
-    for (int i = 0; i < nb; ++i) {
-      const amg_hier* h = hs[i];
-      if (h->mixed != B->mixed || h->p.degree != p0.degree || h->p.inner_steps != p0.inner_steps ||
-          h->p.restart != p0.restart || h->p.tol != p0.tol || h->p.max_iter != p0.max_iter) {
-        set_last_error("batched items must share precision, degree, inner steps, restart, tol and max_iter");
-        return AMG_ERR_ARG;
-      }
-      if (!h->chol_inv) {
-        set_last_error("batched items need a coarsest level of at most 1024 rows");
-        return AMG_ERR_ARG;
-      }
-      amg_hier* use = hs[i];
-      if (seen.count(h)) {  // another right-hand side on the same hierarchy: its own workspace
-        amg_hier* c = nullptr;
-        AMG_TRY(make_clone(hs[i], &c, s));
-        B->clones.push_back(c);
-        use = c;
-      }
-      seen[h] = 1;
-      B->items.push_back(Item{use, f[i], u[i]});
-    }
-    if (B->mixed) {
-      AMG_TRY(build<float, float>(B.get(), s));
-    } else {
-      AMG_TRY(build<double, double>(B.get(), s));
-    }
     g_batch = std::move(B);
   }
   Batch* B = g_batch.get();
-  // init: r = f - A u, rr0, activation
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B->d_nactive);
-  AMG_HIP(hipGraphLaunch(B->g_init, s));
+  hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, s, B->d_nactive);
+  AMG_TRY(schedule_run(&B->init, B->ctl(), s));
+  AMG_HIP(hipMemcpyAsync(B->h_nactive, B->d_nactive, sizeof(int), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   int active = *B->h_nactive;
   int launched = 0;
@@ -985,7 +1006,7 @@ int32_t solve_batch(int nb, amg_hier* const* hs, const double* const* f, double*
     ++launched;
     active = *B->h_nactive;
   }
-  AMG_HIP(hipGraphLaunch(B->g_fini, s));
+  AMG_TRY(schedule_run(&B->fini, B->ctl(), s));
   std::vector<ItemState> hst(nb);
   AMG_HIP(hipMemcpyAsync(hst.data(), B->d_state, nb * sizeof(ItemState), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));

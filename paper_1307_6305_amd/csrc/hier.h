@@ -68,6 +68,8 @@ struct amg_hier {
 
   amg_hier_desc desc{};
   std::vector<void*> allocs;
+  size_t bytes = 0;     // device bytes owned (allocs)
+  size_t ws_bytes = 0;  // of which the solve workspace (what a clone costs)
 };
 
 namespace amg {
@@ -104,6 +106,10 @@ int32_t solve_batch(int nb, amg_hier* const* hs, const double* const* f, double*
 void drop_batches_using(const amg_hier* h);
 int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s);
 void free_clone(amg_hier* c);
+
+// serving (serve.hip)
+int32_t serve(const amg_serve_cfg& cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
+              amg_serve_stats* stats, hipStream_t s);
 int32_t time_step(amg_hier* h, int reps, hipStream_t s, amg_kernel_timing* t);
 
 }  // namespace amg

@@ -1,0 +1,547 @@
+// Serving: replay of an open-loop request stream with continuous batching.
+//
+// Requests arrive at given times.  A request names a graph (by the caller's
+// id; its data is set up once and the hierarchy stays resident) and carries
+// one or more right-hand sides.  The batched mode keeps a set of in-flight
+// right-hand sides ("slots"): between rounds of outer iterations it admits
+// newly arrived right-hand sides as slots and device memory free up, and
+// retires the converged ones; every round advances all in-flight slots
+// together through the batched executor, so work of requests on different
+// graphs overlaps on the device.  Hierarchies of new graphs are built by a
+// setup thread on its own stream while the solves run.  Admission is against a
+// device-memory budget (hierarchies, slot workspaces, schedules); idle
+// hierarchies are evicted least recently used first.  The sequential mode
+// solves one right-hand side at a time in arrival order with amg_solve, for
+// comparison.  Each slot's arithmetic is independent of the other slots, so a
+// result is the same alone and in the mix.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "batch.h"
+#include "hier.h"
+
+namespace amg {
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+__global__ void k_zero_count(int* c) { *c = 0; }
+
+struct Resident {
+  amg_hier* h = nullptr;
+  size_t bytes = 0;
+  int in_flight = 0;  // slots using it
+  double last_use = 0.0;
+  std::vector<amg_hier*> spare;  // workspace clones kept for reuse
+  size_t clone_bytes = 0;
+  bool own_lent = false;         // the hierarchy's own workspace serves a slot
+  bool failed = false;
+  int32_t status = AMG_OK;
+};
+
+struct Slot {
+  int req = -1, rhs = -1;
+  Resident* res = nullptr;
+  amg_hier* ws = nullptr;  // hierarchy or clone whose workspace it uses
+  bool own_ws = false;     // ws is the resident hierarchy itself
+  double* f = nullptr;
+  double* u = nullptr;
+  ItemState* st = nullptr;
+  double admit_s = 0.0;
+};
+
+size_t hier_bytes(const amg_hier* h) { return h->bytes; }
+
+struct Server {
+  amg_serve_cfg cfg;
+  const amg_request* reqs;
+  int nreq;
+  amg_completion* out;
+  std::vector<int> out_base;  // first completion record of each request
+  hipStream_t s = nullptr;       // solve stream
+  hipStream_t s_setup = nullptr; // setup stream
+  clk::time_point t0;
+  size_t bytes = 0, peak = 0;
+  int evictions = 0, setups = 0, steps = 0;
+
+  std::map<int, Resident*> resident;
+  std::mutex mu;                    // guards `resident` entries' setup fields and the setup queue
+  std::condition_variable cv;
+  std::deque<int> setup_queue;      // request indices whose graph needs a setup
+  std::map<int, size_t> setup_pending;  // graph id -> bytes reserved while queued or running
+  bool stop_worker = false;
+
+  double now() const { return std::chrono::duration<double>(clk::now() - t0).count(); }
+
+  void note_bytes() { peak = std::max(peak, bytes); }
+
+  // ---------------------------------------------------------------- setup thread
+  void worker() {
+    (void)hipSetDevice(0);
+    for (;;) {
+      int r;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stop_worker || !setup_queue.empty(); });
+        if (stop_worker && setup_queue.empty()) return;
+        r = setup_queue.front();
+        setup_queue.pop_front();
+      }
+      const amg_request& q = reqs[r];
+      amg_hier* h = nullptr;
+      const int32_t st = amg_setup(q.n, q.row_ptr, q.col, q.w, q.d, &cfg.params, s_setup, &h);
+      std::lock_guard<std::mutex> lk(mu);
+      Resident* R = new Resident();
+      R->h = h;
+      R->status = st;
+      R->failed = st != AMG_OK;
+      R->bytes = h ? hier_bytes(h) : 0;
+      R->last_use = now();
+      resident[q.graph_id] = R;
+      // the reservation made when the setup was queued becomes the actual size
+      bytes -= setup_pending[q.graph_id];
+      setup_pending.erase(q.graph_id);
+      ++setups;
+      bytes += R->bytes;
+      note_bytes();
+      cv.notify_all();
+    }
+  }
+
+  // ---------------------------------------------------------------- memory
+  // Upper bound of a hierarchy's device bytes from the graph size: level data
+  // (CSR, sliced ELL, FP32 copies, aggregation maps) over all levels and the
+  // solve workspace, with room for coarse levels and padding.
+  size_t setup_estimate(const amg_request& q) const {
+    const size_t n = (size_t)q.n, nnz = (size_t)q.row_ptr[q.n];
+    const bool mixed = cfg.params.precision == AMG_MIXED;
+    const size_t vt = mixed ? 4 : 8;
+    // finest level: CSR + d, D; sliced ELL (5 % padding); FP32 copies; aggregation maps
+    size_t level0 = 4 * (n + 1) + 12 * nnz + 16 * n + (126 * nnz) / 10 + 12 * n;
+    if (mixed) level0 += (42 * nnz) / 10 + 4 * n;
+    // coarser levels shrink at least twofold per level: at most as much again
+    const size_t data = 2 * level0;
+    // outer FCG vectors, the finest level's cycle vectors, coarse-level vectors
+    const size_t work = (16 + 16 * (size_t)cfg.params.restart + 4 * vt) * n +
+                        (5 + 2 * (size_t)cfg.params.inner_steps) * vt * n;
+    return data + work + (64 << 10);
+  }
+
+  int resident_busy() const {
+    int b = 0;
+    for (const auto& kv : resident) b += kv.second->in_flight;
+    return b;
+  }
+
+  // Evict idle hierarchies (least recently used first) until `need` more
+  // bytes fit the budget.  Caller holds mu.
+  bool make_room(size_t need) {
+    while ((double)(bytes + need) > cfg.hbm_budget_bytes) {
+      Resident* victim = nullptr;
+      int vid = 0;
+      for (auto& kv : resident) {
+        Resident* R = kv.second;
+        if (R->in_flight == 0 && !R->failed && (!victim || R->last_use < victim->last_use)) {
+          victim = R;
+          vid = kv.first;
+        }
+      }
+      if (!victim) return false;
+      for (amg_hier* c : victim->spare) free_clone(c);
+      bytes -= victim->bytes + victim->clone_bytes;
+      amg_free(victim->h);
+      delete victim;
+      resident.erase(vid);
+      ++evictions;
+    }
+    return true;
+  }
+
+  void complete(const Slot& sl, int32_t status, int iters, double rel_true) {
+    amg_completion& c = out[out_base[sl.req] + sl.rhs];
+    c.request = sl.req;
+    c.rhs = sl.rhs;
+    c.status = status;
+    c.iters = iters;
+    c.rel_res_true = rel_true;
+    c.arrival_s = reqs[sl.req].arrival_s;
+    c.admit_s = sl.admit_s;
+    c.finish_s = now();
+  }
+
+  void fail_request(int r, int32_t status) {
+    const double t = now();
+    for (int k = 0; k < reqs[r].nrhs; ++k) {
+      amg_completion& c = out[out_base[r] + k];
+      c.request = r;
+      c.rhs = k;
+      c.status = status;
+      c.iters = 0;
+      c.rel_res_true = 0.0;
+      c.arrival_s = reqs[r].arrival_s;
+      c.admit_s = t;
+      c.finish_s = t;
+    }
+  }
+
+  // ---------------------------------------------------------------- batched mode
+  int32_t run_batched() {
+    std::thread th([this] { worker(); });
+    struct Joiner {
+      Server* S;
+      std::thread* t;
+      ~Joiner() {
+        {
+          std::lock_guard<std::mutex> lk(S->mu);
+          S->stop_worker = true;
+        }
+        S->cv.notify_all();
+        t->join();
+      }
+    } joiner{this, &th};
+
+    std::vector<int> order(nreq);
+    for (int i = 0; i < nreq; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+    size_t next = 0;                 // next request (in arrival order) not yet admitted
+    int next_rhs = 0;                // first right-hand side of it not yet admitted
+    std::vector<Slot> active;
+    ItemState* d_states = nullptr;   // pool of item states, one per slot position
+    int* d_nactive = nullptr;
+    const int max_slots = std::max(1, cfg.max_slots);
+    AMG_HIP(hipMalloc(&d_states, sizeof(ItemState) * max_slots));
+    AMG_HIP(hipMalloc(&d_nactive, sizeof(int)));
+    std::vector<int> free_state(max_slots);
+    for (int i = 0; i < max_slots; ++i) free_state[i] = max_slots - 1 - i;
+    std::map<const void*, int> state_index;
+    Schedule sched_iter, sched_aux;
+    bool membership_changed = true;
+    const BatchCtl ctl{cfg.params.tol, cfg.params.max_iter, 0, d_nactive};
+    int32_t result = AMG_OK;
+
+    auto cleanup = [&]() {
+      (void)hipStreamSynchronize(s);
+      schedule_free(&sched_iter);
+      schedule_free(&sched_aux);
+      for (Slot& sl : active) {
+        (void)hipFree(sl.f);
+        (void)hipFree(sl.u);
+      }
+      (void)hipFree(d_states);
+      (void)hipFree(d_nactive);
+    };
+
+    while (true) {
+      const double t = now();
+      // --- queue setups for arrived requests whose graph is not resident,
+      //     reserving a conservative size estimate against the budget
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t k = next; k < order.size(); ++k) {
+          const amg_request& q = reqs[order[k]];
+          if (cfg.realtime && q.arrival_s > t) break;
+          if (resident.count(q.graph_id) || setup_pending.count(q.graph_id)) continue;
+          if (!q.row_ptr) continue;  // no data to set up: fails at admission
+          const size_t est = setup_estimate(q);
+          if (!make_room(est)) {
+            if (active.empty() && resident_busy() == 0 && setup_pending.empty()) {
+              // larger than the whole budget: nothing can ever make room
+              setup_pending[q.graph_id] = 0;
+              Resident* R = new Resident();
+              R->failed = true;
+              R->status = AMG_ERR_BUDGET;
+              resident[q.graph_id] = R;
+              setup_pending.erase(q.graph_id);
+            }
+            break;  // keep arrival order: later graphs wait for room too
+          }
+          bytes += est;
+          note_bytes();
+          setup_pending[q.graph_id] = est;
+          setup_queue.push_back(order[k]);
+        }
+      }
+      cv.notify_all();
+      // --- admit arrived right-hand sides (arrival order) while slots and memory allow
+      std::vector<Slot> fresh;
+      while (next < order.size()) {
+        const int r = order[next];
+        const amg_request& q = reqs[r];
+        if (cfg.realtime && q.arrival_s > t) break;
+        if ((int)(active.size() + fresh.size()) >= max_slots) break;
+        std::unique_lock<std::mutex> lk(mu);
+        auto it = resident.find(q.graph_id);
+        if (it == resident.end()) {
+          if (!q.row_ptr && !setup_pending.count(q.graph_id)) {  // evicted and no data: fail
+            lk.unlock();
+            fail_request(r, AMG_ERR_ARG);
+            ++next;
+            next_rhs = 0;
+            continue;
+          }
+          break;  // setup still running: keep arrival order
+        }
+        Resident* R = it->second;
+        if (R->failed) {
+          lk.unlock();
+          fail_request(r, R->status);
+          ++next;
+          next_rhs = 0;
+          continue;
+        }
+        // one slot: workspace (spare clone, the hierarchy's own, or a new clone) + f, u
+        const size_t n = (size_t)q.n;
+        amg_hier* ws = nullptr;
+        bool own = false;
+        size_t extra = 2 * n * sizeof(double) + 64;
+        if (!R->spare.empty()) {
+          ws = R->spare.back();
+        } else if (!R->own_lent) {
+          own = true;  // the hierarchy's own workspace is free
+        } else {
+          extra += R->h->ws_bytes;
+        }
+        if (!make_room(extra)) {
+          if (active.empty() && fresh.empty()) {  // nothing will ever free memory: give up on it
+            lk.unlock();
+            fail_request(r, AMG_ERR_BUDGET);
+            ++next;
+            next_rhs = 0;
+            continue;
+          }
+          break;
+        }
+        if (!R->spare.empty()) {
+          R->spare.pop_back();
+        } else if (!own) {
+          const int32_t st = make_clone(R->h, &ws, s);
+          if (st != AMG_OK) {
+            lk.unlock();
+            result = st;
+            cleanup();
+            return st;
+          }
+          R->clone_bytes += ws->bytes;
+          bytes += ws->bytes;
+        }
+        if (own) {
+          ws = R->h;
+          R->own_lent = true;
+        }
+        bytes += 2 * n * sizeof(double);
+        note_bytes();
+        Slot sl;
+        sl.req = r;
+        sl.rhs = next_rhs;
+        sl.res = R;
+        sl.ws = ws;
+        sl.own_ws = own;
+        sl.admit_s = t;
+        R->in_flight++;
+        R->last_use = t;
+        lk.unlock();
+        AMG_HIP(hipMalloc(&sl.f, n * sizeof(double)));
+        AMG_HIP(hipMalloc(&sl.u, n * sizeof(double)));
+        AMG_HIP(hipMemcpyAsync(sl.f, q.f + (size_t)next_rhs * n, n * sizeof(double), hipMemcpyHostToDevice, s));
+        AMG_HIP(hipMemsetAsync(sl.u, 0, n * sizeof(double), s));
+        const int si = free_state.back();
+        free_state.pop_back();
+        sl.st = d_states + si;
+        state_index[sl.st] = si;
+        fresh.push_back(sl);
+        if (++next_rhs >= q.nrhs) {
+          ++next;
+          next_rhs = 0;
+        }
+      }
+      // --- start the new slots: r = f - A u, activation
+      if (!fresh.empty()) {
+        std::vector<BatchItem> items;
+        for (const Slot& sl : fresh) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+        AMG_TRY(schedule_build(&sched_aux, SCHED_INIT, items, s));
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, d_nactive);
+        AMG_TRY(schedule_run(&sched_aux, ctl, s));
+        for (const Slot& sl : fresh) active.push_back(sl);
+        membership_changed = true;
+      }
+      if (active.empty()) {
+        if (next >= order.size()) break;
+        // wait for the next arrival or a setup
+        std::unique_lock<std::mutex> lk(mu);
+        const double wait = cfg.realtime ? std::max(0.0, reqs[order[next]].arrival_s - now()) : 0.0;
+        cv.wait_for(lk, std::chrono::duration<double>(std::min(wait, 0.002) + 1e-4));
+        continue;
+      }
+      // --- one round of outer iterations over every in-flight slot
+      if (membership_changed) {
+        std::vector<BatchItem> items;
+        for (const Slot& sl : active) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+        AMG_TRY(schedule_build(&sched_iter, SCHED_ITER, items, s));
+        membership_changed = false;
+      }
+      for (int k = 0; k < std::max(1, cfg.iters_per_step); ++k) AMG_TRY(schedule_run(&sched_iter, ctl, s));
+      ++steps;
+      // --- retire converged slots
+      std::vector<ItemState> hst(active.size());
+      for (size_t i = 0; i < active.size(); ++i)
+        AMG_HIP(hipMemcpyAsync(&hst[i], active[i].st, sizeof(ItemState), hipMemcpyDeviceToHost, s));
+      AMG_HIP(hipStreamSynchronize(s));
+      std::vector<Slot> done, keep;
+      for (size_t i = 0; i < active.size(); ++i) (hst[i].active ? keep : done).push_back(active[i]);
+      if (!done.empty()) {
+        std::vector<BatchItem> items;
+        for (const Slot& sl : done) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+        AMG_TRY(schedule_build(&sched_aux, SCHED_FINAL, items, s));
+        AMG_TRY(schedule_run(&sched_aux, ctl, s));
+        std::vector<ItemState> fst(done.size());
+        for (size_t i = 0; i < done.size(); ++i)
+          AMG_HIP(hipMemcpyAsync(&fst[i], done[i].st, sizeof(ItemState), hipMemcpyDeviceToHost, s));
+        for (const Slot& sl : done) {
+          const amg_request& q = reqs[sl.req];
+          if (q.u)
+            AMG_HIP(hipMemcpyAsync(q.u + (size_t)sl.rhs * q.n, sl.u, sizeof(double) * q.n, hipMemcpyDeviceToHost,
+                                   s));
+        }
+        AMG_HIP(hipStreamSynchronize(s));
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t i = 0; i < done.size(); ++i) {
+          const Slot& sl = done[i];
+          const double rho0 = std::sqrt(fst[i].rr0);
+          complete(sl, fst[i].status, fst[i].iter, rho0 > 0 ? std::sqrt(fst[i].rrt) / rho0 : 0.0);
+          (void)hipFree(sl.f);
+          (void)hipFree(sl.u);
+          bytes -= 2 * (size_t)reqs[sl.req].n * sizeof(double);
+          sl.res->in_flight--;
+          sl.res->last_use = now();
+          if (sl.own_ws) sl.res->own_lent = false;
+          else sl.res->spare.push_back(sl.ws);
+          free_state.push_back(state_index[sl.st]);
+          state_index.erase(sl.st);
+        }
+        active.swap(keep);
+        membership_changed = true;
+      }
+      if (active.empty() && next >= order.size()) break;
+    }
+    cleanup();
+    return result;
+  }
+
+  // ---------------------------------------------------------------- sequential mode
+  int32_t run_sequential() {
+    std::vector<int> order(nreq);
+    for (int i = 0; i < nreq; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+    double* f = nullptr;
+    double* u = nullptr;
+    size_t cap = 0;
+    for (int r : order) {
+      const amg_request& q = reqs[r];
+      if (cfg.realtime) {
+        const double wait = q.arrival_s - now();
+        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+      }
+      Resident* R = nullptr;
+      auto it = resident.find(q.graph_id);
+      if (it != resident.end()) {
+        R = it->second;
+      } else if (q.row_ptr) {
+        R = new Resident();
+        R->status = amg_setup(q.n, q.row_ptr, q.col, q.w, q.d, &cfg.params, s, &R->h);
+        R->failed = R->status != AMG_OK;
+        R->bytes = R->h ? hier_bytes(R->h) : 0;
+        ++setups;
+        if (!R->failed && !make_room(R->bytes)) {
+          amg_free(R->h);
+          R->h = nullptr;
+          R->failed = true;
+          R->status = AMG_ERR_BUDGET;
+        }
+        if (!R->failed) bytes += R->bytes;
+        note_bytes();
+        resident[q.graph_id] = R;
+      }
+      if (!R || R->failed) {
+        fail_request(r, R ? R->status : AMG_ERR_ARG);
+        continue;
+      }
+      R->last_use = now();
+      const double admit = now();
+      if ((size_t)q.n > cap) {
+        if (f) (void)hipFree(f);
+        if (u) (void)hipFree(u);
+        cap = q.n;
+        AMG_HIP(hipMalloc(&f, cap * sizeof(double)));
+        AMG_HIP(hipMalloc(&u, cap * sizeof(double)));
+      }
+      for (int k = 0; k < q.nrhs; ++k) {
+        AMG_HIP(hipMemcpyAsync(f, q.f + (size_t)k * q.n, q.n * sizeof(double), hipMemcpyHostToDevice, s));
+        AMG_HIP(hipMemsetAsync(u, 0, q.n * sizeof(double), s));
+        amg_info info{};
+        const int32_t st = solve(R->h, f, u, s, &info);
+        if (q.u) AMG_HIP(hipMemcpyAsync(q.u + (size_t)k * q.n, u, q.n * sizeof(double), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        Slot sl;
+        sl.req = r;
+        sl.rhs = k;
+        sl.admit_s = admit;
+        complete(sl, st == AMG_OK || st == AMG_ERR_MAXIT || st == AMG_ERR_BREAKDOWN ? info.status : st, info.iters,
+                 info.rel_res_true);
+        ++steps;
+      }
+    }
+    if (f) (void)hipFree(f);
+    if (u) (void)hipFree(u);
+    return AMG_OK;
+  }
+
+  ~Server() {
+    for (auto& kv : resident) {
+      Resident* R = kv.second;
+      for (amg_hier* c : R->spare) free_clone(c);
+      if (R->h) amg_free(R->h);
+      delete R;
+    }
+    if (s_setup) (void)hipStreamDestroy(s_setup);
+  }
+};
+
+}  // namespace
+
+int32_t serve(const amg_serve_cfg& cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
+              amg_serve_stats* stats, hipStream_t s) {
+  Server S;
+  S.cfg = cfg;
+  S.reqs = reqs;
+  S.nreq = nreq;
+  S.out = out;
+  S.s = s;
+  int total = 0;
+  for (int i = 0; i < nreq; ++i) {
+    S.out_base.push_back(total);
+    total += reqs[i].nrhs;
+  }
+  std::memset(out, 0, sizeof(amg_completion) * total);
+  AMG_HIP(hipStreamCreateWithFlags(&S.s_setup, hipStreamNonBlocking));
+  S.t0 = clk::now();
+  const int32_t st = cfg.mode == AMG_SERVE_SEQUENTIAL ? S.run_sequential() : S.run_batched();
+  if (stats) {
+    stats->wall_s = S.now();
+    stats->peak_bytes = (double)S.peak;
+    stats->evictions = S.evictions;
+    stats->setups = S.setups;
+    stats->steps = S.steps;
+  }
+  return st;
+}
+
+}  // namespace amg

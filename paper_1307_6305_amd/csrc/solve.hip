@@ -891,7 +891,16 @@ void destroy_graphs(amg_hier* h) {
   h->graphs_ready = false;
 }
 
+int32_t prepare_solve_impl(amg_hier* h, hipStream_t s);
+
 int32_t prepare_solve(amg_hier* h, hipStream_t s) {
+  const size_t before = h->bytes;
+  const int32_t st = prepare_solve_impl(h, s);
+  h->ws_bytes = h->bytes - before;
+  return st;
+}
+
+int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
   for (int l = 0; l < std::max(h->L, 1); ++l) {
     const Level& lv = h->lv[l];
     if (!lv.sell_off || !lv.sell_w || !lv.sell_col || !lv.sell_val || !lv.D ||
