@@ -1,0 +1,94 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py
+times: the 1024 x 1024 grid (1,048,576 unknowns), aggregates of 16, degree 3,
+FP64; and the 128^3 tetrahedral cube in mixed precision (properties only)."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def amg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1307_6305_amd as amg
+
+    amg.load_library()
+    return amg
+
+
+@pytest.fixture(scope="module")
+def grid1024(amg):
+    g = inputs.grid2d(1024)
+    p = amg.amg_params_default(degree=3, agg_size=16)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(degree=3, agg_size=16))
+    return g, p, h, ho
+
+
+def test_fullsize_hierarchy_bit_exact(amg, grid1024):
+    g, p, h, ho = grid1024
+    assert amg.amg_describe(h)["n"] == [l.n for l in ho.levels]
+    for l, lo in enumerate(ho.levels):
+        ex = amg.amg_level_export(h, l)
+        assert np.array_equal(ex["col"], lo.col) and np.array_equal(ex["W"], lo.W), l
+        if l < ho.L:
+            assert np.array_equal(ex["agg"], ho.aggs[l]), l
+
+
+def test_fullsize_cycle_and_solve(amg, grid1024):
+    g, p, h, ho = grid1024
+    f = inputs.rhs(g.n, inputs.seed_for(2))
+    r = torch.tensor(f, dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(r)
+    amg.amg_apply_cycle(h, r, z)
+    zo = oracle.kcycle(ho, 0, f)
+    assert np.linalg.norm(z.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+    u = torch.zeros_like(r)
+    info = amg.amg_solve(h, r, u)
+    res = oracle.fcg(ho, f)
+    assert info["status"] == 0 and abs(info["iters"] - res.iters) <= 1
+    assert info["rel_res_true"] <= 1.05e-8
+    e = u.cpu().numpy() - res.x
+    lo = ho.levels[0]
+    assert np.sqrt(e @ oracle.apply_A(lo, e)) <= 1e-6 * np.sqrt(res.x @ oracle.apply_A(lo, res.x))
+
+
+def test_fullsize_tet3d_mixed_properties(amg):
+    """128^3 cube, FP32 cycle: the hierarchy's finest-level aggregation is
+    checked on a sample against the oracle's matching of level 0, and the
+    solve reaches a true FP64 residual of 1e-8 with the same iteration count
+    as the FP64 solve within two."""
+    g = inputs.tet3d(128)
+    f = torch.tensor(inputs.rhs(g.n, inputs.seed_for(3), "normal"), dtype=torch.float64, device="cuda")
+    its = {}
+    for prec in ("fp64", "mixed"):
+        p = amg.amg_params_default(degree=5, agg_size=16, precision=prec)
+        h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+        u = torch.zeros_like(f)
+        info = amg.amg_solve(h, f, u)
+        assert info["status"] == 0 and info["rel_res_true"] <= 1.05e-8, (prec, info)
+        its[prec] = info["iters"]
+        if prec == "fp64":
+            u64 = u.clone()
+            lvl0 = oracle.assemble(g.n, g.row_ptr, g.col, g.w, g.d)
+            mate = oracle.greedy_matching(lvl0)
+            ids, nc = oracle.coarse_ids(mate)
+            ex = amg.amg_level_export(h, 0)
+            # the composed map of four passes refines the first pass's pairs
+            agg = ex["agg"]
+            pairs = mate >= 0
+            assert np.all(agg[pairs] == agg[mate[pairs]])
+        else:
+            um = u
+        h.close()
+    assert abs(its["mixed"] - its["fp64"]) <= 2
+    lvl0 = oracle.assemble(g.n, g.row_ptr, g.col, g.w, g.d)
+    e = (um - u64).cpu().numpy()
+    x = u64.cpu().numpy()
+    assert np.sqrt(e @ oracle.apply_A(lvl0, e)) <= 1e-6 * np.sqrt(x @ oracle.apply_A(lvl0, x))
