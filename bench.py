@@ -44,6 +44,9 @@ WORKLOADS = {
     "grid2d-64": (lambda: inputs.grid2d(64), "uniform", 1, dict(degree=3, agg_size=4)),
     "tet3d-128": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16)),
     "tet3d-128-mixed": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16, precision=1)),
+    # one random geometric graph of the batched form's kind, at 2M points
+    "rgg-2m-mixed": (lambda: inputs.rgg(2_000_000, inputs.seed_for(4, 999)), "uniform", 4,
+                     dict(degree=4, agg_size=8, precision=1)),
 }
 
 
@@ -51,7 +54,7 @@ def kernel_source_hash() -> str:
     """Hash of the solve kernels' source: stored traffic counters are only
     reported while the kernel they were taken on is unchanged."""
     h = hashlib.sha256()
-    for fn in ("solve.hip", "device_util.h"):
+    for fn in ("solve.hip", "kernels.h", "device_util.h"):
         with open(os.path.join(ROOT, "paper_1307_6305_amd", "csrc", fn), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -103,6 +106,35 @@ def run_cpu_baseline(g, f, params: dict, sample: str):
     }, res
 
 
+def layout_kw(args) -> dict:
+    """Parameters for a fixed layout (--layout H,K,S), else the autotuner."""
+    if not args.layout:
+        return {}
+    h, k, srt = (int(x) for x in args.layout.split(","))
+    return dict(autotune=0, slice_height=h, lanes_per_row=k, sort_rows=srt)
+
+
+LAYOUTS = [(h, k, s) for (h, k) in [(64, 1), (32, 1), (16, 1), (8, 1), (32, 2), (16, 4)] for s in (0, 1)]
+
+
+def layout_sweep(amg, g, pkw: dict, mixed: bool) -> list:
+    """Time the finest level's storing Chebyshev step in every fixed layout."""
+    rows = []
+    for lay in LAYOUTS:
+        p = amg.amg_params_default(**dict(pkw, autotune=0, slice_height=lay[0], lanes_per_row=lay[1],
+                                          sort_rows=lay[2]))
+        h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+        kt = amg.amg_time_step(h, reps=100)
+        b = cheb_step_bytes(kt["rows"], kt["nnz"], mixed)
+        rows.append({"slice_height": lay[0], "lanes_per_row": lay[1], "sorted_rows": lay[2],
+                     "entries": kt["entries"], "avg_us": round(kt["avg_ms"] * 1e3, 2),
+                     "gbs": round(b / (kt["avg_ms"] * 1e-3) / 1e9, 1)})
+        print(f"[bench] layout {lay}: {rows[-1]['avg_us']} us, {rows[-1]['gbs']} GB/s, entries {kt['entries']}",
+              file=sys.stderr, flush=True)
+        h.close()
+    return rows
+
+
 def run_batch(args, amg, torch):
     """Batched form: 256 random geometric graphs (point counts log-uniform in
     [1e3, 2e5], largest component kept), aggregates of 8, degree 4, FP32 cycle
@@ -115,12 +147,18 @@ def run_batch(args, amg, torch):
     t_gen = time.perf_counter() - t0
     dof = sum(g.n for g in graphs)
     print(f"[bench] {count} graphs, {dof} unknowns (generated in {t_gen:.1f} s)", file=sys.stderr, flush=True)
-    params = amg.amg_params_default(degree=4, agg_size=8, precision="mixed")
+    params = amg.amg_params_default(degree=4, agg_size=8, precision="mixed", **layout_kw(args))
     t0 = time.perf_counter()
     hs = [amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, params) for g in graphs]
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     print(f"[bench] setup of all hierarchies {t_setup:.2f} s", file=sys.stderr, flush=True)
+    # layouts the autotuner chose for the finest levels, counted over the items
+    chosen = {}
+    for h in hs:
+        lay = amg.amg_describe(h)["layouts"][0]
+        key = f"{lay['slice_height']}x{lay['lanes_per_row']}{'s' if lay['sorted_rows'] else ''}"
+        chosen[key] = chosen.get(key, 0) + 1
     dev = torch.device("cuda:0")
     fs = [torch.tensor(inputs.rhs(g.n, inputs.seed_for(4, 1000 + i)), dtype=torch.float64, device=dev)
           for i, g in enumerate(graphs)]
@@ -186,6 +224,7 @@ def run_batch(args, amg, torch):
             "worst_rel_res_true": worst,
             "all_converged": ok,
             "setup_s_all": round(t_setup, 2),
+            "finest_layouts": chosen,
             "one_at_a_time_fp64": single,
         },
     }
@@ -324,6 +363,11 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-iters-per-step", type=int, default=2)
     ap.add_argument("--serve-slots", type=int, default=512)
+    ap.add_argument("--layout", default=None,
+                    help="fixed sliced-ELL layout 'H,K,S' (slice height, lanes per row, sorted 0/1) "
+                         "instead of the autotuner")
+    ap.add_argument("--layout-sweep", action="store_true",
+                    help="also time the dominant kernel in every fixed layout (reported under layout_sweep)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -352,6 +396,7 @@ def main():
         pkw["use_graph"] = 0
     if args.tail_rows is not None:
         pkw["tail_rows"] = args.tail_rows
+    pkw.update(layout_kw(args))
     params = amg.amg_params_default(**pkw)
     mixed = params.precision == amg.AMG_MIXED
     print(f"[bench] workload {args.workload}: n={g.n} nnz={g.nnz}", file=sys.stderr, flush=True)
@@ -403,6 +448,8 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    sweep = layout_sweep(amg, g, pkw, mixed) if args.layout_sweep else None
+
     cpu = None
     err_vs_oracle = None
     if not args.no_cpu_baseline:
@@ -445,10 +492,14 @@ def main():
             "operator_complexity": round(desc["operator_complexity"], 4),
             "hip_graphs": not args.no_graph,
             "tail_rows": params.tail_rows,
+            "layouts": desc["layouts"],
+            "layout_ms": round(desc["layout_ms"], 2),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if sweep is not None:
+        out["layout_sweep"] = sweep
     print(json.dumps(out), flush=True)
     h.close()
 

@@ -79,6 +79,16 @@ enum { AMG_KEY_NORMALIZED = 0, AMG_KEY_RAW = 1 };
  *                 rows whose data (with all coarser levels) fits in one
  *                 workgroup's LDS runs as one workgroup-resident kernel
  *                 (0 disables).
+ *   autotune      1: choose every level's sliced-ELL layout at setup -- levels
+ *                 of at least 32768 rows by timing the Chebyshev step on each
+ *                 candidate layout, smaller ones by the bytes a pass moves;
+ *                 0: use slice_height / lanes_per_row / sort_rows everywhere.
+ *                 The layout never changes results: row sums are added in a
+ *                 fixed order of classes and inner products in row order.
+ *   slice_height  rows per slice: 8, 16, 32 or 64 (autotune = 0).
+ *   lanes_per_row lanes that share one row's entries: 1, 2 or 4 (autotune = 0).
+ *   sort_rows     1: rows ordered by decreasing length inside each group of 64
+ *                 rows, which cuts padding on uneven degrees (autotune = 0).
  */
 typedef struct {
   int32_t degree;
@@ -95,6 +105,10 @@ typedef struct {
   double stagnation;
   int32_t use_graph;
   int32_t tail_rows;
+  int32_t autotune;
+  int32_t slice_height;
+  int32_t lanes_per_row;
+  int32_t sort_rows;
 } amg_params;
 
 typedef struct amg_hier amg_hier;
@@ -124,12 +138,18 @@ typedef struct {
   int32_t match_rounds;               /* handshake rounds summed over passes    */
   int32_t precision;
   double device_bytes;                /* device memory held by the hierarchy    */
+  double layout_ms;                   /* sliced-ELL layouts incl. autotuning    */
+  int32_t slice_height[AMG_MAX_LEVELS];  /* chosen layout per smoothed level     */
+  int32_t lanes_per_row[AMG_MAX_LEVELS];
+  int32_t sorted_rows[AMG_MAX_LEVELS];
+  int64_t sell_entries[AMG_MAX_LEVELS];  /* stored entries including padding    */
 } amg_hier_desc;
 
 /* Fill *p with the defaults: degree 4, agg_size 4, coarse_max 64,
  * lambda0_ratio 10, inner_steps 2, restart 5, tol 1e-8, max_iter 200, FP64,
  * normalized key, max_coarsest 2048, stagnation 0.9, use_graph 1,
- * tail_rows 4096. */
+ * tail_rows 4096, autotune 1 (fixed layout: slice_height 64, lanes_per_row 1,
+ * sort_rows 0). */
 void amg_params_default(amg_params* p);
 
 /* Human-readable name of a status code (static string). */

@@ -58,6 +58,10 @@ class amg_params(ctypes.Structure):
         ("stagnation", ctypes.c_double),
         ("use_graph", ctypes.c_int32),
         ("tail_rows", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
+        ("slice_height", ctypes.c_int32),
+        ("lanes_per_row", ctypes.c_int32),
+        ("sort_rows", ctypes.c_int32),
     ]
 
 
@@ -85,6 +89,11 @@ class amg_hier_desc(ctypes.Structure):
         ("match_rounds", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("device_bytes", ctypes.c_double),
+        ("layout_ms", ctypes.c_double),
+        ("slice_height", ctypes.c_int32 * AMG_MAX_LEVELS),
+        ("lanes_per_row", ctypes.c_int32 * AMG_MAX_LEVELS),
+        ("sorted_rows", ctypes.c_int32 * AMG_MAX_LEVELS),
+        ("sell_entries", ctypes.c_int64 * AMG_MAX_LEVELS),
     ]
 
 
@@ -236,7 +245,10 @@ def amg_last_error() -> str:
 def amg_params_default(**overrides) -> amg_params:
     p = amg_params()
     load_library().amg_params_default(ctypes.byref(p))
+    names = {f[0] for f in amg_params._fields_}
     for k, v in overrides.items():
+        if k not in names:
+            raise TypeError(f"amg_params has no field {k!r}")
         if k == "precision" and isinstance(v, str):
             v = {"fp64": AMG_FP64, "mixed": AMG_MIXED}[v]
         if k == "match_key" and isinstance(v, str):
@@ -302,6 +314,11 @@ def amg_describe(h: Hierarchy) -> dict:
         "match_rounds": ds.match_rounds,
         "precision": ds.precision,
         "device_bytes": ds.device_bytes,
+        "layout_ms": ds.layout_ms,
+        # sliced-ELL layout of every smoothed level (the finest at least)
+        "layouts": [{"slice_height": ds.slice_height[l], "lanes_per_row": ds.lanes_per_row[l],
+                     "sorted_rows": ds.sorted_rows[l], "entries": ds.sell_entries[l]}
+                    for l in range(max(L - 1, 1))],
     }
 
 

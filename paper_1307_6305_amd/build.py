@@ -1,9 +1,9 @@
 """Build the HIP library ``libamg.so`` in-tree for gfx950.
 
 Every HIP source is compiled with hipcc for ``--offload-arch=gfx950`` with
-packed FP32 instructions disabled; the setup translation unit additionally
-forbids floating-point contraction so that matching keys and coarse sums are
-correctly rounded binary64 operations.  Host-only C++ goes through g++.
+packed FP32 instructions disabled.  Floating-point contraction is off in the
+setup unit, so that matching keys and coarse sums are correctly rounded
+binary64 operations.  Host-only C++ goes through g++.
 """
 from __future__ import annotations
 

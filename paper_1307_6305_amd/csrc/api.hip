@@ -119,6 +119,10 @@ void amg_params_default(amg_params* p) {
   p->stagnation = 0.9;
   p->use_graph = 1;
   p->tail_rows = 4096;
+  p->autotune = 1;
+  p->slice_height = 64;
+  p->lanes_per_row = 1;
+  p->sort_rows = 0;
 }
 
 const char* amg_strerror(int32_t s) {

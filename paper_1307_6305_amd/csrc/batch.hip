@@ -47,14 +47,21 @@ enum BatchOpType : int {
   B_O_TRUE,      // true residual (f - A u, f - A u)
 };
 
+// Rows per tile (= block) of a batched step: one wavefront, so that many
+// blocks -- each first fetching its op's descriptor -- are in flight per CU.
+// Reductions leave one partial sum per tile; the rows of a tile are added in
+// row order whatever the layout (sorting never moves a row across 64-row
+// groups).
+constexpr int kBatchRows = 64;
+
 struct BatchOp {
   int type;
   int item;
   int n;
   int k;
   int i0, i1, i2, i3;
-  int first_block;  // first block of this op in its launch
-  int blocks;       // tiles of TPB rows
+  int first_block;  // first block (= tile) of this op in its launch
+  int blocks;       // tiles of kBatchRows rows
   int part;         // first partial-sum tile of this op (8 doubles per tile)
   int pad;
   double f0, f1, f2, f3;
@@ -94,41 +101,93 @@ __device__ __forceinline__ void deposit(double (&v)[K], double* partials, int sl
   }
 }
 
-// One step of the cycle for every item of the launch.  Block b works on tile
-// (b - first_block) of op block_op[b].
+// Steps that multiply by a level's matrix: one tile (kBatchRows rows) of one
+// op, with K = 2^lk lanes per row (the launch has kBatchRows << lk threads).
+// Reductions leave one partial sum per tile, added in row order.
 template <typename VT, typename MT>
-__global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ ops, const int* __restrict__ block_op,
-                                                    double* partials) {
-  __shared__ double red[16 * 8];
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const BatchOp& op = ops[block_op[b]];
-  if (!op.st->active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
-  const int tile = b - op.first_block;
-  const int r = tile * TPB + threadIdx.x;
-  const bool live = r < op.n;
+__device__ __forceinline__ void batch_mat_tile(const BatchOp& op, int tile, double* partials, double* red,
+                                               double* stage) {
+  const int lk = op.A64.lk;
+  const int slot = tile * kBatchRows + (threadIdx.x >> lk);
+  const int lane = threadIdx.x & ((1 << lk) - 1);
+  const bool slive = threadIdx.x < (kBatchRows << lk) && slot < op.n;
+  const bool stage_rows = needs_stage(op.A64);
   switch (op.type) {
     case B_CHEB_FIRST: {
-      if (!live) break;
+      if (!slive) break;
       const Mat<MT>& A = op_mat<MT>(op);
       if (op.i2)
-        row_cheb_first<VT, MT, double>(A, r, (const double*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.f3,
-                                       op.i0, op.i1);
+        row_cheb_first<VT, MT, double>(A, slot, lane, (const double*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2,
+                                       op.f3, op.i0, op.i1);
       else
-        row_cheb_first<VT, MT, VT>(A, r, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.f3, op.i0,
-                                   op.i1);
+        row_cheb_first<VT, MT, VT>(A, slot, lane, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.f3,
+                                   op.i0, op.i1);
       break;
     }
     case B_CHEB_NEXT: {
-      if (!live) break;
+      if (!slive) break;
       const Mat<MT>& A = op_mat<MT>(op);
       if (op.i2)
-        row_cheb_next<VT, MT, double>(A, r, (const VT*)op.a, (const double*)op.b, (VT*)op.c, (VT*)op.d, op.f0, op.f1,
-                                      op.f2, op.i0);
+        row_cheb_next<VT, MT, double>(A, slot, lane, (const VT*)op.a, (const double*)op.b, (VT*)op.c, (VT*)op.d,
+                                      op.f0, op.f1, op.f2, op.i0);
       else
-        row_cheb_next<VT, MT, VT>(A, r, (const VT*)op.a, (const VT*)op.b, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2,
-                                  op.i0);
+        row_cheb_next<VT, MT, VT>(A, slot, lane, (const VT*)op.a, (const VT*)op.b, (VT*)op.c, (VT*)op.d, op.f0, op.f1,
+                                  op.f2, op.i0);
       break;
     }
+    case B_RESIDUAL: {
+      if (!slive) break;
+      const Mat<MT>& A = op_mat<MT>(op);
+      if (op.i2)
+        (void)row_residual<VT, MT, double>(A, slot, lane, (const double*)op.a, (const VT*)op.b, (VT*)op.c);
+      else
+        (void)row_residual<VT, MT, VT>(A, slot, lane, (const VT*)op.a, (const VT*)op.b, (VT*)op.c);
+      break;
+    }
+    case B_SPMV_DOTS: {
+      double v[2] = {0.0, 0.0};
+      int row = -1;
+      if (slive)
+        row = row_spmv_dots<VT, MT, VT>(op_mat<MT>(op), slot, lane, (const VT*)op.a, (VT*)op.c, (const VT*)op.b, v);
+      if (stage_rows) tile_stage<2, kBatchRows>(v, row >= 0 ? row - tile * kBatchRows : -1, stage);
+      deposit<2>(v, partials, op.part + tile, red);
+      break;
+    }
+    case B_O_RESID:
+    case B_O_TRUE: {
+      double v[1] = {0.0};
+      int row = -1;
+      if (slive) {
+        double* s = (double*)op.c;
+        row = row_residual<double, double, double>(op.A64, slot, lane, (const double*)op.a, (const double*)op.b, s);
+        if (row >= 0) v[0] = s[row] * s[row];
+      }
+      if (stage_rows) tile_stage<1, kBatchRows>(v, row >= 0 ? row - tile * kBatchRows : -1, stage);
+      deposit<1>(v, partials, op.part + tile, red);
+      break;
+    }
+    case B_O_SPMV: {
+      const int j = op.st->iter % op.i0;
+      double v[2] = {0.0, 0.0};
+      int row = -1;
+      if (slive)
+        row = row_spmv_dots<double, double, double>(op.A64, slot, lane, (const double*)op.w2.p[j],
+                                                    (double*)op.w.p[j], (const double*)op.b, v);
+      if (stage_rows) tile_stage<2, kBatchRows>(v, row >= 0 ? row - tile * kBatchRows : -1, stage);
+      deposit<2>(v, partials, op.part + tile, red);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Vector steps: row r of the tile in thread r - tile * kBatchRows.
+template <typename VT>
+__device__ __forceinline__ void batch_vec_tile(const BatchOp& op, int tile, double* partials, double* red) {
+  const int r = tile * kBatchRows + threadIdx.x;
+  const bool live = r < op.n;
+  switch (op.type) {
     case B_SCALE_ADD: {
       if (!live) break;
       VT* y = (VT*)op.d;
@@ -136,15 +195,6 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
       VT v = (VT)op.f0 * w0;
       if (op.i0) v += y[r];
       y[r] = v;
-      break;
-    }
-    case B_RESIDUAL: {
-      if (!live) break;
-      const Mat<MT>& A = op_mat<MT>(op);
-      if (op.i2)
-        row_residual<VT, MT, double>(A, r, (const double*)op.a, (const VT*)op.b, (VT*)op.c);
-      else
-        row_residual<VT, MT, VT>(A, r, (const VT*)op.a, (const VT*)op.b, (VT*)op.c);
       break;
     }
     case B_RESTRICT:
@@ -175,12 +225,6 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
       ((VT*)op.c)[r] = (VT)acc;
       break;
     }
-    case B_SPMV_DOTS: {
-      double v[2] = {0.0, 0.0};
-      if (live) row_spmv_dots<VT, MT, VT>(op_mat<MT>(op), r, (const VT*)op.a, (VT*)op.c, (const VT*)op.b, v);
-      deposit<2>(v, partials, op.part + tile, red);
-      break;
-    }
     case B_FCG_XR: {
       if (!live) break;
       const double alpha = fcg_alpha(op.scal, op.i0, op.i1);
@@ -191,17 +235,6 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
         VT* rv = (VT*)op.d;
         rv[r] = (VT)((double)rv[r] - alpha * (double)((const VT*)op.b)[r]);
       }
-      break;
-    }
-    case B_O_RESID:
-    case B_O_TRUE: {
-      double v[1] = {0.0};
-      if (live) {
-        double* s = (double*)op.c;
-        row_residual<double, double, double>(op.A64, r, (const double*)op.a, (const double*)op.b, s);
-        v[0] = s[r] * s[r];
-      }
-      deposit<1>(v, partials, op.part + tile, red);
       break;
     }
     case B_O_MULTIDOT: {
@@ -228,15 +261,6 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
       ((double*)op.w2.p[j])[r] = acc;
       break;
     }
-    case B_O_SPMV: {
-      const int j = op.st->iter % op.i0;
-      double v[2] = {0.0, 0.0};
-      if (live)
-        row_spmv_dots<double, double, double>(op.A64, r, (const double*)op.w2.p[j], (double*)op.w.p[j],
-                                              (const double*)op.b, v);
-      deposit<2>(v, partials, op.part + tile, red);
-      break;
-    }
     case B_O_XR: {
       const int j = op.st->iter % op.i0;
       double v[1] = {0.0};
@@ -255,6 +279,35 @@ __global__ void __launch_bounds__(TPB) k_batch_step(const BatchOp* __restrict__ 
     default:
       break;
   }
+}
+
+bool is_matrix_step(int type) {
+  return type == B_CHEB_FIRST || type == B_CHEB_NEXT || type == B_RESIDUAL || type == B_SPMV_DOTS ||
+         type == B_O_RESID || type == B_O_TRUE || type == B_O_SPMV;
+}
+
+// One step of the cycle for every item of the launch.  Block b works on tile
+// (b - first_block) of op block_op[b].  Matrix and vector steps are separate
+// kernels, each with the registers its own code needs.
+template <typename VT, typename MT>
+__global__ void __launch_bounds__(kBatchRows * 4) k_batch_mat(const BatchOp* __restrict__ ops,
+                                                       const int* __restrict__ block_op, double* partials) {
+  __shared__ double red[16 * 8];
+  __shared__ double stage[2 * kBatchRows];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const BatchOp& op = ops[block_op[b]];
+  if (!op.st->active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
+  batch_mat_tile<VT, MT>(op, b - op.first_block, partials, red, stage);
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(kBatchRows) k_batch_vec(const BatchOp* __restrict__ ops, const int* __restrict__ block_op,
+                                                   double* partials) {
+  __shared__ double red[16 * 8];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const BatchOp& op = ops[block_op[b]];
+  if (!op.st->active) return;
+  batch_vec_tile<VT>(op, b - op.first_block, partials, red);
 }
 
 // Coarsest solves, one block per item.
@@ -355,7 +408,7 @@ __global__ void k_batch_reset(int* nactive) { *nactive = 0; }
 }  // namespace
 
 struct Launch {
-  int kind;  // 0 step, 1 coarse, 2 tail, 3 finish
+  int kind;  // 0 vector step, 4 matrix step, 1 coarse, 2 tail, 3 finish
   int op0, nops;
   int map0, nblocks;  // block map slice (step) / finish list slice
   int tail0;          // first tail program (tail)
@@ -406,9 +459,26 @@ struct Builder {
     if (mixed) o.A32 = mat_of<float>(lv);
   }
 
-  // one step launch over the given ops (each spanning ceil(n / TPB) tiles)
+  // One step over the given ops (each spanning ceil(n / kBatchRows) tiles): one
+  // launch per lanes-per-row value among them, so that every block has the
+  // thread count its op's layout uses.
   void step(std::vector<BatchOp> v, bool reduces) {
     if (v.empty()) return;
+    int present = 0;
+    for (const BatchOp& o : v) present |= 1 << o.A64.lk;
+    if ((present & (present - 1)) == 0) {
+      step_launch(std::move(v), reduces);
+      return;
+    }
+    for (int lk = 0; lk <= 2; ++lk) {
+      std::vector<BatchOp> part;
+      for (const BatchOp& o : v)
+        if (o.A64.lk == lk) part.push_back(o);
+      if (!part.empty()) step_launch(std::move(part), reduces);
+    }
+  }
+
+  void step_launch(std::vector<BatchOp> v, bool reduces) {
     Launch L{};
     L.kind = 0;
     L.op0 = (int)ops.size();
@@ -417,7 +487,7 @@ struct Builder {
     int parts = 0, blocks = 0;
     for (size_t q = 0; q < v.size(); ++q) {
       BatchOp& o = v[q];
-      o.blocks = nblk(o.n);
+      o.blocks = nblk(o.n, kBatchRows);
       o.first_block = blocks;
       o.part = parts;
       blocks += o.blocks;
@@ -426,6 +496,9 @@ struct Builder {
       ops.push_back(o);
     }
     L.nblocks = blocks;
+    L.kind = is_matrix_step(v[0].type) ? 4 : 0;
+    L.threads = kBatchRows;
+    for (const BatchOp& o : v) L.threads = std::max(L.threads, kBatchRows << o.A64.lk);
     max_parts = std::max(max_parts, parts);
     out->push_back(L);
     if (reduces) {
@@ -762,8 +835,12 @@ int32_t run_impl(const Schedule* S, const BatchCtl& ctl, hipStream_t s) {
   for (const Launch& L : *S->launches) {
     switch (L.kind) {
       case 0:
-        hipLaunchKernelGGL((k_batch_step<VT, MT>), dim3(L.nblocks), dim3(TPB), 0, s, D->ops, D->map + L.map0,
+        hipLaunchKernelGGL((k_batch_vec<VT>), dim3(L.nblocks), dim3(kBatchRows), 0, s, D->ops, D->map + L.map0,
                            D->partials);
+        break;
+      case 4:
+        hipLaunchKernelGGL((k_batch_mat<VT, MT>), dim3(L.nblocks), dim3(L.threads), 0, s, D->ops,
+                           D->map + L.map0, D->partials);
         break;
       case 1:
         hipLaunchKernelGGL((k_batch_coarse<VT>), dim3(L.nops), dim3(TPB), 0, s, D->ops + L.op0);

@@ -14,6 +14,9 @@
 namespace amg {
 
 constexpr int kWave = 64;  // CDNA wavefront width
+// Largest level the one-workgroup tail program takes (its plain layout is
+// kept for levels up to this size).
+constexpr int kTailMaxRows = 4096;
 
 struct Status {
   int32_t code = AMG_OK;
@@ -45,9 +48,14 @@ struct DevBuf {
 };
 
 // Off-diagonal part of a level in CSR (setup form, also kept for export) and
-// in sliced ELL with slice height 64 (solve form): slice s holds rows
-// [64 s, 64 s + 64); entry k of lane l sits at sell_off[s] + 64 k + l.  Padding
-// entries point at the row itself with weight 0.
+// in sliced ELL (solve form).  The sliced-ELL layout has three knobs, chosen
+// per level at setup: the slice height C (rows per slice), the lanes per row
+// K, and whether rows are sorted by length inside each 64-row group.  Slot q
+// holds row perm[q] (q itself when unsorted); slot q lies in slice q / C at
+// position p = q mod C, and entry k of its row sits at
+// sell_off[s] + (k / K) * C * K + p * K + (k mod K).  sell_w[s] is the number
+// of steps (entries per lane) of slice s.  Padding entries point at the row
+// itself with weight 0.
 struct Level {
   int32_t n = 0;
   int64_t nnz = 0;
@@ -66,6 +74,20 @@ struct Level {
   float* sell_valf = nullptr;    // FP32 weights (mixed precision)
   float* Df = nullptr;           // FP32 diagonal (mixed precision)
   int64_t sell_entries = 0;
+  int32_t sell_lc = 6;           // log2 slice height
+  int32_t sell_lk = 0;           // log2 lanes per row
+  int32_t* sell_perm = nullptr;  // slot -> row (sorted layouts), else null
+  // The plain layout (64-row slices, rows in order, one lane per row) of a
+  // small level: the layout the one-workgroup tail program runs on, so that
+  // the tail does not depend on the layout chosen for the level (the arrays
+  // above when that is the plain layout).
+  int32_t plain_nslices = 0;
+  int64_t plain_entries = 0;
+  int32_t* plain_off = nullptr;
+  int32_t* plain_w = nullptr;
+  int32_t* plain_col = nullptr;
+  double* plain_val = nullptr;
+  float* plain_valf = nullptr;
   // aggregation into the next level (device), l < L
   int32_t* agg = nullptr;        // n
   int32_t* members = nullptr;    // n: vertices grouped by aggregate, increasing index

@@ -85,6 +85,11 @@ int32_t dalloc(amg_hier* h, T** p, size_t count) {
   return dalloc(h, reinterpret_cast<void**>(p), count * sizeof(T) + 16);
 }
 
+struct Level;
+// Mean time of one storing Chebyshev step on `lv` (its current layout), on
+// zero vectors wk, wb, y of the level's cycle precision (layout autotuner).
+int32_t time_cheb_layout(const Level& lv, bool mixed, void* wk, void* wb, void* y, hipStream_t s, float* ms);
+
 int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const int32_t* col,
                         const double* w, const double* d, hipStream_t s);
 int32_t prepare_solve(amg_hier* h, hipStream_t s);

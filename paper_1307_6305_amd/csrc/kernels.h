@@ -27,15 +27,21 @@ struct VecPtrs {
   const void* p[8];
 };
 
+// A level's matrix in its sliced-ELL layout.  Row-parallel kernels cover the
+// level in tiles of TPB rows, with (TPB << lk) threads per tile: K = 2^lk
+// lanes per row.
 template <typename MT>
 struct Mat {
   int n;
-  int nb;  // blocks of TPB rows
+  int nb;  // tiles of TPB rows
+  int lc;  // log2 slice height
+  int lk;  // log2 lanes per row
   const int* off;
   const int* width;
   const int* col;
   const MT* val;
   const MT* D;
+  const int* perm;  // slot -> row inside each 64-row group, or null (identity)
 };
 
 struct Transfer {
@@ -55,11 +61,25 @@ template <typename MT>
 Mat<MT> mat_of(const Level& lv);
 template <>
 inline Mat<double> mat_of<double>(const Level& lv) {
-  return Mat<double>{lv.n, nblk(lv.n), lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_val, lv.D};
+  return Mat<double>{lv.n, nblk(lv.n), lv.sell_lc, lv.sell_lk, lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_val,
+                     lv.D, lv.sell_perm};
 }
 template <>
 inline Mat<float> mat_of<float>(const Level& lv) {
-  return Mat<float>{lv.n, nblk(lv.n), lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_valf, lv.Df};
+  return Mat<float>{lv.n, nblk(lv.n), lv.sell_lc, lv.sell_lk, lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_valf,
+                    lv.Df, lv.sell_perm};
+}
+
+// The level's plain layout (the tail program's); null arrays if it has none.
+template <typename MT>
+Mat<MT> plain_mat_of(const Level& lv);
+template <>
+inline Mat<double> plain_mat_of<double>(const Level& lv) {
+  return Mat<double>{lv.n, nblk(lv.n), 6, 0, lv.plain_off, lv.plain_w, lv.plain_col, lv.plain_val, lv.D, nullptr};
+}
+template <>
+inline Mat<float> plain_mat_of<float>(const Level& lv) {
+  return Mat<float>{lv.n, nblk(lv.n), 6, 0, lv.plain_off, lv.plain_w, lv.plain_col, lv.plain_valf, lv.Df, nullptr};
 }
 
 inline Transfer transfer_of(const amg_hier* h, int l) {
@@ -68,54 +88,149 @@ inline Transfer transfer_of(const amg_hier* h, int l) {
 }
 
 // ------------------------------------------------------------------ per-row steps
-// sum_j W_rj x_j over the stored off-diagonal entries of row r.
-template <typename AT, typename MT, typename XT>
-__device__ __forceinline__ AT offdiag(const Mat<MT>& A, int r, const XT* __restrict__ x) {
-  const int s = r >> 6, lane = r & 63;
-  const int* __restrict__ c = A.col + A.off[s] + lane;
-  const MT* __restrict__ v = A.val + A.off[s] + lane;
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// sum_j W_rj x_j over the stored entries of the row in `slot`, computed by
+// the K lanes j = 0..K-1 of the slot together (every lane gets the sum).
+// Entry k of the row goes to class k mod 8; each class is summed in order
+// of k with fused multiply-adds, and the eight class sums are combined by the
+// fixed tree ((c0 + c4) + (c2 + c6)) + ((c1 + c5) + (c3 + c7)).  Lane j holds
+// the classes j, j + K, ..., so every K, slice height and row order gives the
+// same bits.  The loads of U steps are issued together: steps past the slice
+// width re-read its last step (a cache hit) and are not added.
+template <int K, typename AT, typename MT, typename XT>
+__device__ __forceinline__ AT offdiag_k(const Mat<MT>& A, int slot, int j, const XT* __restrict__ x) {
+  constexpr int U = 8 / K;
+  const int s = slot >> A.lc, p = slot & ((1 << A.lc) - 1);
+  const int stride = K << A.lc;
+  const int base = A.off[s] + p * K + j;
+  const int* __restrict__ c = A.col + base;
+  const MT* __restrict__ v = A.val + base;
   const int wd = A.width[s];
-  AT acc = 0;
+  AT acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) acc[u] = (AT)0;
+  for (int t = 0; t < wd; t += U) {
+    int cv[U];
+    MT vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int tt = min(t + u, wd - 1) * stride;
+      cv[u] = c[tt];
+      vv[u] = v[tt];
+    }
+    XT xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[cv[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (t + u < wd) acc[u] = fmadd((AT)vv[u], (AT)xv[u], acc[u]);
+  }
+  AT sum;
+  if constexpr (K == 1) {
+    sum = ((acc[0] + acc[4]) + (acc[2] + acc[6])) + ((acc[1] + acc[5]) + (acc[3] + acc[7]));
+  } else if constexpr (K == 2) {
+    sum = (acc[0] + acc[2]) + (acc[1] + acc[3]);
+    sum += __shfl_xor(sum, 1, 64);
+  } else {
+    sum = acc[0] + acc[1];
+    sum += __shfl_xor(sum, 2, 64);
+    sum += __shfl_xor(sum, 1, 64);
+  }
+  return sum;
+}
+
+// The same sum on the plain layout (one lane per row) in LDS, where the
+// one-workgroup tail program runs: entries added in order.  The tail always
+// uses the plain layout, so its results do not depend on the level's layout.
+template <typename AT, typename MT, typename XT>
+__device__ __forceinline__ AT offdiag_seq(const Mat<MT>& A, int r, const XT* __restrict__ x) {
+  const int s = r >> 6, p = r & 63;
+  const int* __restrict__ c = A.col + A.off[s] + p;
+  const MT* __restrict__ v = A.val + A.off[s] + p;
+  const int wd = A.width[s];
+  AT acc = (AT)0;
 #pragma unroll 4
-  for (int k = 0; k < wd; ++k) acc += (AT)v[k * kWave] * (AT)x[c[k * kWave]];
+  for (int t = 0; t < wd; ++t) acc += (AT)v[t * 64] * (AT)x[c[t * 64]];
   return acc;
 }
 
+// GLOBAL: device-wide kernels on the level's layout; otherwise the tail
+// program on the plain layout.
+template <typename AT, bool GLOBAL = true, typename MT, typename XT>
+__device__ __forceinline__ AT offdiag(const Mat<MT>& A, int slot, int j, const XT* __restrict__ x) {
+  if constexpr (!GLOBAL) {
+    return offdiag_seq<AT>(A, slot, x);
+  } else {
+    if (A.lk == 0) return offdiag_k<1, AT>(A, slot, j, x);
+    if (A.lk == 1) return offdiag_k<2, AT>(A, slot, j, x);
+    return offdiag_k<4, AT>(A, slot, j, x);
+  }
+}
+
+template <typename MT>
+__device__ __forceinline__ int row_at(const Mat<MT>& A, int slot) {
+  return A.perm ? A.perm[slot] : slot;
+}
+
+// The row steps below are called by all K lanes of a slot; lane 0 writes the
+// row's results.
+//
 // w1 = (A w0 - theta w0) / eta;  y = [y +] c0 w0 + c1 w1   (c already divided by eta)
-template <typename VT, typename MT, typename RT>
-__device__ __forceinline__ void row_cheb_first(const Mat<MT>& A, int r, const RT* __restrict__ w0, VT* w1, VT* y,
-                                               double theta, double inv_eta, double c0, double c1, int accum,
+template <typename VT, typename MT, typename RT, bool G = true>
+__device__ __forceinline__ void row_cheb_first(const Mat<MT>& A, int slot, int j, const RT* __restrict__ w0, VT* w1,
+                                               VT* y, double theta, double inv_eta, double c0, double c1, int accum,
                                                int store) {
   using AT = VT;
+  const int r = row_at(A, slot);
   const AT x0 = (AT)w0[r];
-  const AT ax = (AT)A.D[r] * x0 - offdiag<AT>(A, r, w0);
+  const AT d = (AT)A.D[r];
+  const AT y0 = accum ? (AT)y[r] : (AT)0;
+  const AT off = offdiag<AT, G>(A, slot, j, w0);
+  if (j) return;
+  const AT ax = d * x0 - off;
   const AT t = (ax - (AT)theta * x0) * (AT)inv_eta;
   if (store) w1[r] = (VT)t;
   AT yy = (AT)c0 * x0 + (AT)c1 * t;
-  if (accum) yy += (AT)y[r];
+  if (accum) yy += y0;
   y[r] = (VT)yy;
 }
 
 // w_{k+1} = 2 (A w_k - theta w_k) / eta - w_{k-1};  y += c_{k+1} w_{k+1}.
 // wnext may alias wprev (each element is read before it is overwritten).
-template <typename VT, typename MT, typename PT>
-__device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int r, const VT* __restrict__ wk, const PT* wprev,
-                                              VT* wnext, VT* y, double theta, double two_inv_eta, double ck,
-                                              int store) {
+template <typename VT, typename MT, typename PT, bool G = true>
+__device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int slot, int j, const VT* __restrict__ wk,
+                                              const PT* wprev, VT* wnext, VT* y, double theta, double two_inv_eta,
+                                              double ck, int store) {
   using AT = VT;
+  const int r = row_at(A, slot);
   const AT xk = (AT)wk[r];
-  const AT ax = (AT)A.D[r] * xk - offdiag<AT>(A, r, wk);
-  const AT t = (ax - (AT)theta * xk) * (AT)two_inv_eta - (AT)wprev[r];
+  const AT d = (AT)A.D[r];
+  const AT wp = (AT)wprev[r];
+  const AT y0 = (AT)y[r];
+  const AT off = offdiag<AT, G>(A, slot, j, wk);
+  if (j) return;
+  const AT ax = d * xk - off;
+  const AT t = (ax - (AT)theta * xk) * (AT)two_inv_eta - wp;
   if (store) wnext[r] = (VT)t;
-  y[r] = (VT)((AT)y[r] + (AT)ck * t);
+  y[r] = (VT)(y0 + (AT)ck * t);
 }
 
-template <typename VT, typename MT, typename RT>
-__device__ __forceinline__ void row_residual(const Mat<MT>& A, int r, const RT* __restrict__ f,
-                                             const VT* __restrict__ x, VT* s) {
+// s = f - A x; returns the row in the writing lane, -1 in the others
+template <typename VT, typename MT, typename RT, bool G = true>
+__device__ __forceinline__ int row_residual(const Mat<MT>& A, int slot, int j, const RT* __restrict__ f,
+                                            const VT* __restrict__ x, VT* s) {
   using AT = VT;
-  const AT ax = (AT)A.D[r] * (AT)x[r] - offdiag<AT>(A, r, x);
-  s[r] = (VT)((AT)f[r] - ax);
+  const int r = row_at(A, slot);
+  const AT xr = (AT)x[r];
+  const AT d = (AT)A.D[r];
+  const AT fr = (AT)f[r];
+  const AT off = offdiag<AT, G>(A, slot, j, x);
+  if (j) return -1;
+  const AT ax = d * xr - off;
+  s[r] = (VT)(fr - ax);
+  return r;
 }
 
 template <typename VT>
@@ -130,16 +245,46 @@ __device__ __forceinline__ void row_prolong(const Transfer& T, int i, const VT* 
   x[i] += e[T.agg[i]];
 }
 
-// q_r = (A p)_r; accumulates p_r q_r and p_r rv_r in FP64
-template <typename VT, typename MT, typename RT>
-__device__ __forceinline__ void row_spmv_dots(const Mat<MT>& A, int r, const VT* __restrict__ p, VT* q,
-                                              const RT* __restrict__ rv, double (&v)[2]) {
+// q = A p for the row in `slot`; the writing lane returns the row and sets
+// v = (p_r q_r, p_r rv_r) in FP64, the other lanes return -1.
+template <typename VT, typename MT, typename RT, bool G = true>
+__device__ __forceinline__ int row_spmv_dots(const Mat<MT>& A, int slot, int j, const VT* __restrict__ p, VT* q,
+                                             const RT* __restrict__ rv, double (&v)[2]) {
   using AT = VT;
+  const int r = row_at(A, slot);
   const AT pr = (AT)p[r];
-  const AT ap = (AT)A.D[r] * pr - offdiag<AT>(A, r, p);
+  const AT d = (AT)A.D[r];
+  const double rr = (double)rv[r];
+  const AT off = offdiag<AT, G>(A, slot, j, p);
+  if (j) return -1;
+  const AT ap = d * pr - off;
   q[r] = (VT)ap;
-  v[0] += (double)pr * (double)ap;
-  v[1] += (double)pr * (double)rv[r];
+  v[0] = (double)pr * (double)ap;
+  v[1] = (double)pr * rr;
+  return r;
+}
+
+// Per-row values of one tile of ROWS rows, moved so that thread t < ROWS
+// holds those of row tile * ROWS + t (zero elsewhere): a following block
+// reduction then adds them in row order whatever the layout.  `rel` is the
+// tile-relative row of the calling lane's values, or -1.  Call from every
+// thread of the block.
+template <int NV, int ROWS = TPB>
+__device__ __forceinline__ void tile_stage(double (&v)[NV], int rel, double* stage) {
+  for (int i = threadIdx.x; i < NV * ROWS; i += blockDim.x) stage[i] = 0.0;
+  __syncthreads();
+  if (rel >= 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) stage[k * ROWS + rel] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = threadIdx.x < ROWS ? stage[k * ROWS + threadIdx.x] : 0.0;
+}
+
+template <typename MT>
+__device__ __forceinline__ bool needs_stage(const Mat<MT>& A) {
+  return A.perm != nullptr || A.lk != 0;
 }
 
 __device__ __forceinline__ double fcg_alpha(const double* scal, int s_rho, int s_gam) {
@@ -279,7 +424,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         VT* w1 = at<VT>(lds, op.c);
         VT* y = at<VT>(lds, op.d);
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_first<VT, MT, VT>(A, r, w0, w1, y, op.f0, op.f1, op.f2, op.f3, op.i0, op.i1);
+          row_cheb_first<VT, MT, VT, false>(A, r, 0, w0, w1, y, op.f0, op.f1, op.f2, op.f3, op.i0, op.i1);
         break;
       }
       case OP_CHEB_NEXT: {
@@ -288,7 +433,8 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* wp = at<const VT>(lds, op.b);
         VT* wn = at<VT>(lds, op.c);
         VT* y = at<VT>(lds, op.d);
-        for (int r = tid; r < A.n; r += bd) row_cheb_next<VT, MT, VT>(A, r, wk, wp, wn, y, op.f0, op.f1, op.f2, op.i0);
+        for (int r = tid; r < A.n; r += bd)
+          row_cheb_next<VT, MT, VT, false>(A, r, 0, wk, wp, wn, y, op.f0, op.f1, op.f2, op.i0);
         break;
       }
       case OP_SCALE_ADD: {
@@ -306,7 +452,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* f = at<const VT>(lds, op.a);
         const VT* x = at<const VT>(lds, op.b);
         VT* sv = at<VT>(lds, op.c);
-        for (int r = tid; r < A.n; r += bd) row_residual<VT, MT, VT>(A, r, f, x, sv);
+        for (int r = tid; r < A.n; r += bd) (void)row_residual<VT, MT, VT, false>(A, r, 0, f, x, sv);
         break;
       }
       case OP_RESTRICT: {
@@ -363,7 +509,12 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* rv = at<const VT>(lds, op.b);
         VT* q = at<VT>(lds, op.c);
         double v[2] = {0.0, 0.0};
-        for (int r = tid; r < A.n; r += bd) row_spmv_dots<VT, MT, VT>(A, r, p, q, rv, v);
+        for (int r = tid; r < A.n; r += bd) {
+          double w[2];
+          (void)row_spmv_dots<VT, MT, VT, false>(A, r, 0, p, q, rv, w);
+          v[0] += w[0];
+          v[1] += w[1];
+        }
         block_sum<2>(v, red);
         if (tid == 0) {
           scal[op.s0.s[0]] = v[0];

@@ -123,9 +123,18 @@ struct Server {
     const size_t n = (size_t)q.n, nnz = (size_t)q.row_ptr[q.n];
     const bool mixed = cfg.params.precision == AMG_MIXED;
     const size_t vt = mixed ? 4 : 8;
-    // finest level: CSR + d, D; sliced ELL (5 % padding); FP32 copies; aggregation maps
-    size_t level0 = 4 * (n + 1) + 12 * nnz + 16 * n + (126 * nnz) / 10 + 12 * n;
-    if (mixed) level0 += (42 * nnz) / 10 + 4 * n;
+    // sliced-ELL entries of the plain layout (64-row slices, rows in order);
+    // the layout the autotuner keeps stores at most 1.5x that many
+    size_t e64 = 0;
+    for (size_t s0 = 0; s0 < n; s0 += 64) {
+      int w = 0;
+      for (size_t r = s0; r < std::min(n, s0 + 64); ++r) w = std::max(w, q.row_ptr[r + 1] - q.row_ptr[r]);
+      e64 += 64 * (size_t)w;
+    }
+    const size_t sell = (3 * e64) / 2 + 64;
+    // finest level: CSR + d, D; sliced ELL (+ row order); FP32 copies; aggregation maps
+    size_t level0 = 4 * (n + 1) + 12 * nnz + 16 * n + 12 * sell + 4 * n + 12 * n;
+    if (mixed) level0 += 4 * sell + 4 * n;
     // coarser levels shrink at least twofold per level: at most as much again
     const size_t data = 2 * level0;
     // outer FCG vectors, the finest level's cycle vectors, coarse-level vectors
@@ -141,14 +150,15 @@ struct Server {
   }
 
   // Evict idle hierarchies (least recently used first) until `need` more
-  // bytes fit the budget.  Caller holds mu.
-  bool make_room(size_t need) {
+  // bytes fit the budget; `keep` (the hierarchy the room is for) is never
+  // evicted.  Caller holds mu.
+  bool make_room(size_t need, const Resident* keep = nullptr) {
     while ((double)(bytes + need) > cfg.hbm_budget_bytes) {
       Resident* victim = nullptr;
       int vid = 0;
       for (auto& kv : resident) {
         Resident* R = kv.second;
-        if (R->in_flight == 0 && !R->failed && (!victim || R->last_use < victim->last_use)) {
+        if (R != keep && R->in_flight == 0 && !R->failed && (!victim || R->last_use < victim->last_use)) {
           victim = R;
           vid = kv.first;
         }
@@ -242,7 +252,10 @@ struct Server {
     while (true) {
       const double t = now();
       // --- queue setups for arrived requests whose graph is not resident,
-      //     reserving a conservative size estimate against the budget
+      //     reserving a conservative size estimate against the budget.  Only
+      //     the head-of-line request's setup may evict idle hierarchies; later
+      //     ones start early only in free room (otherwise they could evict the
+      //     hierarchy the head needs, and the two would evict each other).
       {
         std::lock_guard<std::mutex> lk(mu);
         for (size_t k = next; k < order.size(); ++k) {
@@ -251,7 +264,9 @@ struct Server {
           if (resident.count(q.graph_id) || setup_pending.count(q.graph_id)) continue;
           if (!q.row_ptr) continue;  // no data to set up: fails at admission
           const size_t est = setup_estimate(q);
-          if (!make_room(est)) {
+          if (k > next) {
+            if ((double)(bytes + est) > cfg.hbm_budget_bytes) break;
+          } else if (!make_room(est)) {
             if (active.empty() && resident_busy() == 0 && setup_pending.empty()) {
               // larger than the whole budget: nothing can ever make room
               setup_pending[q.graph_id] = 0;
@@ -309,7 +324,7 @@ struct Server {
         } else {
           extra += R->h->ws_bytes;
         }
-        if (!make_room(extra)) {
+        if (!make_room(extra, R)) {
           if (active.empty() && fresh.empty()) {  // nothing will ever free memory: give up on it
             lk.unlock();
             fail_request(r, AMG_ERR_BUDGET);

@@ -46,6 +46,16 @@ struct Temps {
     *p = static_cast<T*>(q);
     return AMG_OK;
   }
+  // frees one temporary before the end of the setup
+  void release(void* p) {
+    if (!p) return;
+    for (auto& q : ptrs)
+      if (q == p) {
+        (void)hipFree(q);
+        q = nullptr;
+        return;
+      }
+  }
 };
 
 // ------------------------------------------------------------------ generic kernels
@@ -397,37 +407,74 @@ __global__ void k_sort_members(int nc, const int* __restrict__ off, int* __restr
 }
 
 // ------------------------------------------------------------------ sliced ELL
-__global__ void k_sell_width(int nrows_pad, int n, const int* __restrict__ rp, int* __restrict__ w) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  int deg = (r < n) ? rp[r + 1] - rp[r] : 0;
-  deg = wave_max(deg);
-  if (r < nrows_pad && (threadIdx.x & 63) == 0) w[r >> 6] = deg;
+// Row order of a sorted layout: inside each group of 64 rows (the rows one
+// wavefront covers), rows by decreasing length, ties by index.  A wavefront
+// then still touches the same vector cache lines as in row order.
+__global__ void __launch_bounds__(256) k_sell_perm(int n, const int* __restrict__ rp, int* __restrict__ perm) {
+  __shared__ int deg[256];
+  const int i = threadIdx.x, r = blockIdx.x * 256 + i;
+  const int di = r < n ? rp[r + 1] - rp[r] : -1;
+  deg[i] = di;
+  __syncthreads();
+  if (r >= n) return;
+  const int g0 = i & ~63;
+  int rank = 0;
+  for (int k = g0; k < g0 + 64; ++k) {
+    const int dk = deg[k];
+    rank += (dk > di) || (dk == di && k < i);
+  }
+  perm[blockIdx.x * 256 + g0 + rank] = r;
 }
 
-__global__ void k_sell_len(int ns, const int* __restrict__ w, int* __restrict__ len) {
+__device__ __forceinline__ int sell_row(int q, int n, const int* __restrict__ perm) {
+  return q < n ? (perm ? perm[q] : q) : -1;
+}
+
+// Steps per slice: the longest row of the slice, in units of K entries.
+__global__ void k_sell_width(int nslots, int n, const int* __restrict__ rp, const int* __restrict__ perm, int lc,
+                             int lk, int* __restrict__ w) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = sell_row(q, n, perm);
+  int deg = r >= 0 ? rp[r + 1] - rp[r] : 0;
+  for (int off = (1 << lc) >> 1; off > 0; off >>= 1) {
+    const int o = __shfl_xor(deg, off, 64);
+    deg = o > deg ? o : deg;
+  }
+  if (q < nslots && (q & ((1 << lc) - 1)) == 0) w[q >> lc] = (deg + (1 << lk) - 1) >> lk;
+}
+
+__global__ void k_sell_len(int ns, const int* __restrict__ w, int shift, int* __restrict__ len) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < ns) len[s] = w[s] * kWave;
+  if (s < ns) len[s] = w[s] << shift;
 }
 
-__global__ void k_sell_fill(int nrows_pad, int n, const int* __restrict__ rp, const int* __restrict__ col,
-                            const double* __restrict__ W, const int* __restrict__ off,
-                            const int* __restrict__ width, int* __restrict__ scol, double* __restrict__ sval,
-                            float* __restrict__ svalf) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows_pad) return;
-  const int s = r >> 6, lane = r & 63;
-  const int base = off[s] + lane, wd = width[s];
-  const int b = r < n ? rp[r] : 0;
-  const int deg = r < n ? rp[r + 1] - b : 0;
-  const int self = r < n ? r : 0;
-  for (int k = 0; k < wd; ++k) {
-    const int idx = base + k * kWave;
-    int c = self;
-    double v = 0.0;
-    if (k < deg) { c = col[b + k]; v = W[b + k]; }
-    scol[idx] = c;
-    sval[idx] = v;
-    if (svalf) svalf[idx] = (float)v;
+// Either weight array may be null (not wanted).
+__global__ void k_sell_fill(int nslots, int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const double* __restrict__ W, const int* __restrict__ perm, int lc, int lk,
+                            const int* __restrict__ off, const int* __restrict__ width, int* __restrict__ scol,
+                            double* __restrict__ sval, float* __restrict__ svalf) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nslots) return;
+  const int r = sell_row(q, n, perm);
+  const int s = q >> lc, p = q & ((1 << lc) - 1), K = 1 << lk;
+  const int wd = width[s], stride = K << lc;
+  const int b = r >= 0 ? rp[r] : 0;
+  const int deg = r >= 0 ? rp[r + 1] - b : 0;
+  const int self = r >= 0 ? r : 0;
+  for (int t = 0; t < wd; ++t) {
+    for (int j = 0; j < K; ++j) {
+      const int k = t * K + j;
+      const int idx = off[s] + t * stride + p * K + j;
+      int c = self;
+      double v = 0.0;
+      if (k < deg) {
+        c = col[b + k];
+        v = W[b + k];
+      }
+      scol[idx] = c;
+      if (sval) sval[idx] = v;
+      if (svalf) svalf[idx] = (float)v;
+    }
   }
 }
 
@@ -635,38 +682,210 @@ int32_t build_members(amg_hier* h, Temps& T, Level& lv, int nc, hipStream_t s) {
   return AMG_OK;
 }
 
-int32_t build_sell(amg_hier* h, Temps& T, Level& lv, bool mixed, hipStream_t s) {
-  lv.nslices = (lv.n + kWave - 1) / kWave;
-  const int rows_pad = lv.nslices * kWave;
+// ------------------------------------------------------------------ layouts and their autotuner
+struct SellLayout {
+  int lc, lk, sort;  // log2 slice height, log2 lanes per row, rows sorted inside 64-row groups
+};
+
+// Device arrays of one sliced-ELL layout of a level.
+struct SellArrays {
+  int nslices = 0;
+  int64_t entries = 0;
+  int* w = nullptr;
+  int* off = nullptr;
+  int* perm = nullptr;
+  int* col = nullptr;
+  double* val = nullptr;
+  float* valf = nullptr;
+};
+
+// Row order and slice widths of a layout, and its entry count (padding
+// included).  `alloc(void**, bytes)` provides the arrays that are kept.
+template <typename Alloc>
+int32_t layout_shape(Temps& T, const Level& lv, SellLayout L, Alloc&& alloc, SellArrays* A, hipStream_t s) {
+  const int C = 1 << L.lc;
+  A->nslices = (lv.n + C - 1) / C;
+  const int nslots = A->nslices * C;
+  if (L.sort) {
+    AMG_TRY(alloc((void**)&A->perm, sizeof(int) * (size_t)lv.n + 16));
+    hipLaunchKernelGGL(k_sell_perm, dim3(nblk(lv.n)), dim3(256), 0, s, lv.n, lv.row_ptr, A->perm);
+  }
+  AMG_TRY(alloc((void**)&A->w, sizeof(int) * (size_t)A->nslices + 16));
+  AMG_TRY(alloc((void**)&A->off, sizeof(int) * ((size_t)A->nslices + 1) + 16));
   int* len = nullptr;
-  AMG_TRY(dalloc(h, &lv.sell_w, lv.nslices));
-  AMG_TRY(dalloc(h, &lv.sell_off, lv.nslices + 1));
-  AMG_TRY(T.get(&len, lv.nslices));
-  hipLaunchKernelGGL(k_sell_width, dim3(nblk(rows_pad)), dim3(TPB), 0, s, rows_pad, lv.n, lv.row_ptr, lv.sell_w);
-  hipLaunchKernelGGL(k_sell_len, dim3(nblk(lv.nslices)), dim3(TPB), 0, s, lv.nslices, lv.sell_w, len);
+  AMG_TRY(T.get(&len, A->nslices));
+  hipLaunchKernelGGL(k_sell_width, dim3(nblk(nslots)), dim3(TPB), 0, s, nslots, lv.n, lv.row_ptr, A->perm, L.lc,
+                     L.lk, A->w);
+  hipLaunchKernelGGL(k_sell_len, dim3(nblk(A->nslices)), dim3(TPB), 0, s, A->nslices, A->w, L.lc + L.lk, len);
   AMG_HIP(hipGetLastError());
   // total entries in int64 to guard against overflow of the int32 offsets
-  std::vector<int> wh(lv.nslices);
-  AMG_HIP(hipMemcpyAsync(wh.data(), lv.sell_w, sizeof(int) * lv.nslices, hipMemcpyDeviceToHost, s));
+  std::vector<int> wh(A->nslices);
+  AMG_HIP(hipMemcpyAsync(wh.data(), A->w, sizeof(int) * A->nslices, hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   int64_t total = 0;
-  for (int x : wh) total += (int64_t)x * kWave;
+  for (int x : wh) total += (int64_t)x << (L.lc + L.lk);
   if (total >= (int64_t)1 << 31) {
     set_last_error("level too large for 32-bit sliced-ELL offsets");
     return AMG_ERR_ARG;
   }
-  lv.sell_entries = total;
-  AMG_TRY(scan_excl(T, len, lv.nslices, lv.sell_off, s));
-  AMG_TRY(dalloc(h, &lv.sell_col, std::max<int64_t>(total, 1)));
-  AMG_TRY(dalloc(h, &lv.sell_val, std::max<int64_t>(total, 1)));
+  A->entries = total;
+  AMG_TRY(scan_excl(T, len, A->nslices, A->off, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  T.release(len);
+  return AMG_OK;
+}
+
+// Column indices and weights of a layout whose shape is known.
+template <typename Alloc>
+int32_t layout_fill(const Level& lv, SellLayout L, bool f64, bool f32, Alloc&& alloc, SellArrays* A, hipStream_t s) {
+  const size_t e = (size_t)std::max<int64_t>(A->entries, 1);
+  AMG_TRY(alloc((void**)&A->col, sizeof(int) * e + 16));
+  if (f64) AMG_TRY(alloc((void**)&A->val, sizeof(double) * e + 16));
+  if (f32) AMG_TRY(alloc((void**)&A->valf, sizeof(float) * e + 16));
+  const int nslots = A->nslices << L.lc;
+  hipLaunchKernelGGL(k_sell_fill, dim3(nblk(nslots)), dim3(TPB), 0, s, nslots, lv.n, lv.row_ptr, lv.col, lv.W,
+                     A->perm, L.lc, L.lk, A->off, A->w, A->col, A->val, A->valf);
+  AMG_HIP(hipGetLastError());
+  return AMG_OK;
+}
+
+void install(Level& lv, SellLayout L, const SellArrays& A) {
+  lv.nslices = A.nslices;
+  lv.sell_entries = A.entries;
+  lv.sell_lc = L.lc;
+  lv.sell_lk = L.lk;
+  lv.sell_perm = A.perm;
+  lv.sell_w = A.w;
+  lv.sell_off = A.off;
+  lv.sell_col = A.col;
+  lv.sell_val = A.val;
+  lv.sell_valf = A.valf;
+}
+
+// Candidate layouts: slice heights 64/32/16/8 with one lane per row, 32 rows
+// x 2 lanes, 16 rows x 4 lanes; each unsorted and sorted.  The first is the
+// plain layout (one wavefront per slice, rows in order).
+constexpr SellLayout kLayouts[] = {{6, 0, 0}, {5, 0, 0}, {4, 0, 0}, {3, 0, 0}, {6, 0, 1}, {5, 0, 1}, {4, 0, 1},
+                                   {3, 0, 1}, {5, 1, 0}, {5, 1, 1}, {4, 2, 0}, {4, 2, 1}};
+constexpr int kNumLayouts = sizeof(kLayouts) / sizeof(kLayouts[0]);
+// Levels with at least this many rows are tuned by timing; on smaller ones a
+// launch takes a few microseconds, mostly latency, and the byte model decides.
+constexpr int kTuneMinRows = 1 << 18;
+// A sorted layout reads the row order and stages its reductions: the model
+// takes it only when it saves more than this fraction of the bytes.
+constexpr double kSortedPenalty = 1.10;
+// The timed best replaces the model's choice only when faster by this factor.
+constexpr double kTimedMargin = 0.97;
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+
+// Chooses the layout of a level.  Model: bytes of one pass over the layout
+// (column index and weight per stored entry, plus the row order when
+// sorted), the fewest winning.  Tuning (large levels): the storing Chebyshev
+// step -- the solve's dominant kernel -- timed on each candidate whose model
+// is within 1.5x of the best; the fastest replaces the model's choice if it
+// is clearly faster.  Every layout gives the same results bit for bit (the row
+// sums and the reductions have a fixed order), so the choice only affects
+// speed.
+int32_t choose_layout(amg_hier* h, Temps& T, Level& lv, bool mixed, hipStream_t s, SellLayout* best) {
+  const amg_params& p = h->p;
+  if (!p.autotune) {
+    *best = SellLayout{ilog2(p.slice_height), ilog2(p.lanes_per_row), p.sort_rows ? 1 : 0};
+    return AMG_OK;
+  }
+  auto tmp = [&](void** q, size_t bytes) -> int32_t {
+    char* c = nullptr;
+    AMG_TRY(T.get(&c, bytes));
+    *q = c;
+    return AMG_OK;
+  };
+  const double mt = mixed ? 4.0 : 8.0;
+  double model[kNumLayouts];
+  double best_model = 0.0;
+  for (int c = 0; c < kNumLayouts; ++c) {
+    SellArrays A;
+    AMG_TRY(layout_shape(T, lv, kLayouts[c], tmp, &A, s));
+    model[c] = ((double)A.entries * (4.0 + mt) + (kLayouts[c].sort ? 4.0 * lv.n : 0.0)) *
+               (kLayouts[c].sort ? kSortedPenalty : 1.0);
+    if (c == 0 || model[c] < best_model) best_model = model[c];
+    T.release(A.perm);
+    T.release(A.w);
+    T.release(A.off);
+  }
+  int mi = 0;
+  for (int c = 1; c < kNumLayouts; ++c)
+    if (model[c] < model[mi]) mi = c;
+  if (lv.n < kTuneMinRows) {
+    *best = kLayouts[mi];
+    return AMG_OK;
+  }
+  const size_t vt = mixed ? sizeof(float) : sizeof(double);
+  char *wk = nullptr, *wb = nullptr, *y = nullptr;
+  AMG_TRY(T.get(&wk, vt * lv.n));
+  AMG_TRY(T.get(&wb, vt * lv.n));
+  AMG_TRY(T.get(&y, vt * lv.n));
+  AMG_HIP(hipMemsetAsync(wk, 0, vt * lv.n, s));
+  AMG_HIP(hipMemsetAsync(wb, 0, vt * lv.n, s));
+  AMG_HIP(hipMemsetAsync(y, 0, vt * lv.n, s));
+  int bi = mi;
+  float best_ms = 0.f, model_ms = 0.f;
+  for (int c = 0; c < kNumLayouts; ++c) {
+    if (c != mi && model[c] > 1.5 * best_model) continue;
+    SellArrays A;
+    AMG_TRY(layout_shape(T, lv, kLayouts[c], tmp, &A, s));
+    AMG_TRY(layout_fill(lv, kLayouts[c], !mixed, mixed, tmp, &A, s));
+    Level cand = lv;
+    install(cand, kLayouts[c], A);
+    float ms = 0.f;
+    AMG_TRY(time_cheb_layout(cand, mixed, wk, wb, y, s, &ms));
+    if (c == mi) model_ms = ms;
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      bi = c;
+    }
+    for (void* q : {(void*)A.perm, (void*)A.w, (void*)A.off, (void*)A.col, (void*)A.val, (void*)A.valf}) T.release(q);
+  }
+  T.release(wk);
+  T.release(wb);
+  T.release(y);
+  *best = (best_ms < kTimedMargin * model_ms) ? kLayouts[bi] : kLayouts[mi];
+  return AMG_OK;
+}
+
+int32_t build_sell(amg_hier* h, Temps& T, Level& lv, bool mixed, hipStream_t s) {
   if (mixed) {
-    AMG_TRY(dalloc(h, &lv.sell_valf, std::max<int64_t>(total, 1)));
     AMG_TRY(dalloc(h, &lv.Df, lv.n));
     hipLaunchKernelGGL(k_to_float, dim3(nblk(lv.n)), dim3(TPB), 0, s, lv.n, lv.D, lv.Df);
+    AMG_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_sell_fill, dim3(nblk(rows_pad)), dim3(TPB), 0, s, rows_pad, lv.n, lv.row_ptr, lv.col,
-                     lv.W, lv.sell_off, lv.sell_w, lv.sell_col, lv.sell_val, lv.sell_valf);
-  AMG_HIP(hipGetLastError());
+  SellLayout L;
+  AMG_TRY(choose_layout(h, T, lv, mixed, s, &L));
+  auto keep = [&](void** q, size_t bytes) -> int32_t { return dalloc(h, q, bytes); };
+  SellArrays A;
+  AMG_TRY(layout_shape(T, lv, L, keep, &A, s));
+  AMG_TRY(layout_fill(lv, L, true, mixed, keep, &A, s));
+  install(lv, L, A);
+  // the tail program's plain layout of small levels
+  if (lv.n <= kTailMaxRows) {
+    const SellLayout P{6, 0, 0};
+    SellArrays B = A;
+    if (L.lc != P.lc || L.lk != P.lk || L.sort != P.sort) {
+      B = SellArrays{};
+      AMG_TRY(layout_shape(T, lv, P, keep, &B, s));
+      AMG_TRY(layout_fill(lv, P, true, mixed, keep, &B, s));
+    }
+    lv.plain_nslices = B.nslices;
+    lv.plain_entries = B.entries;
+    lv.plain_off = B.off;
+    lv.plain_w = B.w;
+    lv.plain_col = B.col;
+    lv.plain_val = B.val;
+    lv.plain_valf = B.valf;
+  }
   return AMG_OK;
 }
 
@@ -810,8 +1029,10 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
   }
   // solve-phase layouts: every level that is smoothed, and always the finest
   // level (outer-iteration products and residuals), even when it is the coarsest
+  auto t_tune = clk::now();
   for (int l = 0; l < std::max(h->L, 1); ++l) AMG_TRY(build_sell(h, T, h->lv[l], h->mixed, s));
   AMG_HIP(hipStreamSynchronize(s));
+  const double layout_ms = ms_since(t_tune);
 
   amg_hier_desc& ds = h->desc;
   std::memset(&ds, 0, sizeof(ds));
@@ -830,6 +1051,14 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
   ds.galerkin_ms = t_gal;
   ds.match_rounds = total_rounds;
   ds.precision = p.precision;
+  ds.layout_ms = layout_ms;
+  for (int l = 0; l < std::max(h->L, 1); ++l) {
+    const Level& lv = h->lv[l];
+    ds.slice_height[l] = 1 << lv.sell_lc;
+    ds.lanes_per_row[l] = 1 << lv.sell_lk;
+    ds.sorted_rows[l] = lv.sell_perm ? 1 : 0;
+    ds.sell_entries[l] = lv.sell_entries;
+  }
   ds.setup_ms = ms_since(t_setup);
   return AMG_OK;
 }

@@ -36,29 +36,38 @@ namespace amg {
 namespace {
 
 // ------------------------------------------------------------------ device-wide kernels
+// Row-parallel kernels: one block per tile of TPB rows (XCD-aware order),
+// K = 2^lk lanes per row, so blockDim = TPB << lk.
+constexpr int kMaxRowThreads = TPB * 4;
+
+struct SlotLane {
+  int tile, slot, lane;
+};
+
 template <typename MT>
-__device__ __forceinline__ int row_of(const Mat<MT>& A) {
+__device__ __forceinline__ SlotLane slot_of(const Mat<MT>& A) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int r = tile * TPB + threadIdx.x;
-  return r < A.n ? r : -1;
+  const int slot = tile * TPB + (threadIdx.x >> A.lk);
+  return SlotLane{tile, slot < A.n ? slot : -1, (int)threadIdx.x & ((1 << A.lk) - 1)};
 }
 
 template <typename VT, typename MT, typename RT>
-__global__ void __launch_bounds__(TPB) k_cheb_first(Mat<MT> A, const RT* __restrict__ w0, VT* w1, VT* y,
-                                                    double theta, double inv_eta, double c0, double c1, int accum,
-                                                    int store) {
-  const int r = row_of(A);
-  if (r >= 0) row_cheb_first<VT, MT, RT>(A, r, w0, w1, y, theta, inv_eta, c0, c1, accum, store);
+__global__ void __launch_bounds__(kMaxRowThreads) k_cheb_first(Mat<MT> A, const RT* __restrict__ w0, VT* w1, VT* y,
+                                                               double theta, double inv_eta, double c0, double c1,
+                                                               int accum, int store) {
+  const SlotLane q = slot_of(A);
+  if (q.slot >= 0) row_cheb_first<VT, MT, RT>(A, q.slot, q.lane, w0, w1, y, theta, inv_eta, c0, c1, accum, store);
 }
 
 // STORE: w_{k+1} is written (every step but the last).  FINE marks launches
 // on the finest level: the same code, a separate instance so that profiles
 // report the finest level's dominant step on its own.
 template <typename VT, typename MT, typename PT, bool STORE, bool FINE>
-__global__ void __launch_bounds__(TPB) k_cheb_next(Mat<MT> A, const VT* __restrict__ wk, const PT* wprev, VT* wnext,
-                                                   VT* y, double theta, double two_inv_eta, double ck) {
-  const int r = row_of(A);
-  if (r >= 0) row_cheb_next<VT, MT, PT>(A, r, wk, wprev, wnext, y, theta, two_inv_eta, ck, STORE);
+__global__ void __launch_bounds__(kMaxRowThreads) k_cheb_next(Mat<MT> A, const VT* __restrict__ wk, const PT* wprev,
+                                                              VT* wnext, VT* y, double theta, double two_inv_eta,
+                                                              double ck) {
+  const SlotLane q = slot_of(A);
+  if (q.slot >= 0) row_cheb_next<VT, MT, PT>(A, q.slot, q.lane, wk, wprev, wnext, y, theta, two_inv_eta, ck, STORE);
 }
 
 // degree 0: y = [y +] c0 w0
@@ -72,21 +81,24 @@ __global__ void k_scale_add(int n, const RT* __restrict__ w0, VT* y, double c0, 
 }
 
 template <typename VT, typename MT, typename RT>
-__global__ void __launch_bounds__(TPB) k_residual(Mat<MT> A, const RT* __restrict__ f, const VT* __restrict__ x,
-                                                  VT* s) {
-  const int r = row_of(A);
-  if (r >= 0) row_residual<VT, MT, RT>(A, r, f, x, s);
+__global__ void __launch_bounds__(kMaxRowThreads) k_residual(Mat<MT> A, const RT* __restrict__ f,
+                                                             const VT* __restrict__ x, VT* s) {
+  const SlotLane q = slot_of(A);
+  if (q.slot >= 0) (void)row_residual<VT, MT, RT>(A, q.slot, q.lane, f, x, s);
 }
 
 // FP64 residual with its squared norm: s = f - A x, (s, s).
-__global__ void __launch_bounds__(TPB) k_residual_dot(Mat<double> A, const double* __restrict__ f,
-                                                      const double* __restrict__ x, double* s, Red red) {
-  const int r = row_of(A);
+__global__ void __launch_bounds__(kMaxRowThreads) k_residual_dot(Mat<double> A, const double* __restrict__ f,
+                                                                 const double* __restrict__ x, double* s, Red red) {
+  __shared__ double stage[TPB];
+  const SlotLane q = slot_of(A);
   double v[1] = {0.0};
-  if (r >= 0) {
-    row_residual<double, double, double>(A, r, f, x, s);
-    v[0] = s[r] * s[r];
+  int r = -1;
+  if (q.slot >= 0) {
+    r = row_residual<double, double, double>(A, q.slot, q.lane, f, x, s);
+    if (r >= 0) v[0] = s[r] * s[r];
   }
+  if (needs_stage(A)) tile_stage<1>(v, r >= 0 ? r - q.tile * TPB : -1, stage);
   grid_sum_finish<1>(v, red);
 }
 
@@ -164,13 +176,16 @@ __global__ void __launch_bounds__(TPB) k_fcg_p(int n, PT* p, const ZT* z, VecPtr
   p[j] = (PT)v;
 }
 
-// q = A p; (p, q) and (p, r).
+// q = A p; (p, q) and (p, r), added per tile in row order.
 template <typename VT, typename MT, typename RT>
-__global__ void __launch_bounds__(TPB) k_spmv_dots(Mat<MT> A, const VT* __restrict__ p, VT* q,
-                                                   const RT* __restrict__ rv, Red red) {
-  const int r = row_of(A);
+__global__ void __launch_bounds__(kMaxRowThreads) k_spmv_dots(Mat<MT> A, const VT* __restrict__ p, VT* q,
+                                                              const RT* __restrict__ rv, Red red) {
+  __shared__ double stage[2 * TPB];
+  const SlotLane sl = slot_of(A);
   double v[2] = {0.0, 0.0};
-  if (r >= 0) row_spmv_dots<VT, MT, RT>(A, r, p, q, rv, v);
+  int r = -1;
+  if (sl.slot >= 0) r = row_spmv_dots<VT, MT, RT>(A, sl.slot, sl.lane, p, q, rv, v);
+  if (needs_stage(A)) tile_stage<2>(v, r >= 0 ? r - sl.tile * TPB : -1, stage);
   grid_sum_finish<2>(v, red);
 }
 
@@ -288,7 +303,7 @@ struct Engine {
       return AMG_ERR_DEVICE;
     }
     const auto Am = A(l);
-    hipLaunchKernelGGL((k_cheb_first<VT, MT, RT>), dim3(Am.nb), dim3(TPB), 0, s, Am, w0, w1, y, lv.theta,
+    hipLaunchKernelGGL((k_cheb_first<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, w0, w1, y, lv.theta,
                        1.0 / lv.eta, c0, c1, (int)accum, (int)store);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
@@ -312,17 +327,17 @@ struct Engine {
     const double ti = 2.0 / lv.eta;
     if (l == 0) {
       if (store)
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, true>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev, wnext,
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, true>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev, wnext,
                            y, lv.theta, ti, ck);
       else
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, true>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev,
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, true>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
                            wnext, y, lv.theta, ti, ck);
     } else {
       if (store)
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, false>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev,
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, false>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
                            wnext, y, lv.theta, ti, ck);
       else
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, false>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wprev,
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, false>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
                            wnext, y, lv.theta, ti, ck);
     }
     AMG_HIP(hipGetLastError());
@@ -340,7 +355,7 @@ struct Engine {
     VT* y = wsv(h->ws[0].S);
     AMG_HIP(hipEventRecord(e0, s));
     for (int i = 0; i < reps; ++i)
-      hipLaunchKernelGGL((k_cheb_next<VT, MT, VT, true, true>), dim3(Am.nb), dim3(TPB), 0, s, Am, wk, wb, wb, y,
+      hipLaunchKernelGGL((k_cheb_next<VT, MT, VT, true, true>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wb, wb, y,
                          lv.theta, 2.0 / lv.eta, 1e-3);
     AMG_HIP(hipGetLastError());
     AMG_HIP(hipEventRecord(e1, s));
@@ -405,7 +420,7 @@ struct Engine {
       return AMG_ERR_DEVICE;
     }
     const auto Am = A(l);
-    hipLaunchKernelGGL((k_residual<VT, MT, RT>), dim3(Am.nb), dim3(TPB), 0, s, Am, f, x, out);
+    hipLaunchKernelGGL((k_residual<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, f, x, out);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
@@ -487,7 +502,7 @@ struct Engine {
       return AMG_OK;
     }
     const auto Am = A(l);
-    hipLaunchKernelGGL((k_spmv_dots<VT, MT, VT>), dim3(Am.nb), dim3(TPB), 0, s, Am, p, q, rv, red_for(Am.nb, out));
+    hipLaunchKernelGGL((k_spmv_dots<VT, MT, VT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, p, q, rv, red_for(Am.nb, out));
     AMG_HIP(hipGetLastError());
     return finish<2>(Am.nb, out);
   }
@@ -594,7 +609,7 @@ struct Engine {
     hipLaunchKernelGGL((k_fcg_p<double, VT>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], z, ps, j, h->scal,
                        slots_range(S_DOTS, j), slots_range(S_RHOW, j));
     const Slots pq = slots2(S_RHOW + j, S_GAM);
-    hipLaunchKernelGGL((k_spmv_dots<double, double, double>), dim3(A64.nb), dim3(TPB), 0, s, A64, h->P[j], h->Qo[j],
+    hipLaunchKernelGGL((k_spmv_dots<double, double, double>), dim3(A64.nb), dim3(TPB << A64.lk), 0, s, A64, h->P[j], h->Qo[j],
                        h->r, red_for(A64.nb, pq));
     AMG_TRY(finish<2>(A64.nb, pq));
     const Slots rr = slots1(S_RR);
@@ -612,7 +627,7 @@ struct Engine {
   int32_t residual64(const double* f, const double* u, double* out, int slot) {
     const auto A64 = mat_of<double>(h->lv[0]);
     const Slots sl = slots1(slot);
-    hipLaunchKernelGGL(k_residual_dot, dim3(A64.nb), dim3(TPB), 0, s, A64, f, u, out, red_for(A64.nb, sl));
+    hipLaunchKernelGGL(k_residual_dot, dim3(A64.nb), dim3(TPB << A64.lk), 0, s, A64, f, u, out, red_for(A64.nb, sl));
     AMG_HIP(hipGetLastError());
     return finish<1>(A64.nb, sl);
   }
@@ -713,11 +728,11 @@ void tail_buffers(const amg_hier* h, int t, std::vector<LdsBuf>& bufs) {
   for (int l = t; l < h->L; ++l) {
     const Level& lv = h->lv[l];
     const size_t n = lv.n;
-    const Mat<MT> A = mat_of<MT>(lv);
-    bufs.push_back({A.off, sizeof(int) * (lv.nslices + 1), true});
-    bufs.push_back({A.width, sizeof(int) * lv.nslices, true});
-    bufs.push_back({A.col, sizeof(int) * lv.sell_entries, true});
-    bufs.push_back({A.val, mt * lv.sell_entries, true});
+    const Mat<MT> A = plain_mat_of<MT>(lv);
+    bufs.push_back({A.off, sizeof(int) * (lv.plain_nslices + 1), true});
+    bufs.push_back({A.width, sizeof(int) * lv.plain_nslices, true});
+    bufs.push_back({A.col, sizeof(int) * lv.plain_entries, true});
+    bufs.push_back({A.val, mt * lv.plain_entries, true});
     bufs.push_back({A.D, mt * n, true});
     bufs.push_back({lv.agg, sizeof(int) * n, true});
     bufs.push_back({lv.members, sizeof(int) * n, true});
@@ -761,7 +776,7 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   };
   int t = 0;
   for (int cand = h->L - 1; cand >= 1; --cand) {
-    if (h->lv[cand].n > h->p.tail_rows || h->lv[cand].n > TAIL_THREADS * 4) break;
+    if (h->lv[cand].n > h->p.tail_rows || h->lv[cand].n > kTailMaxRows || !h->lv[cand].plain_off) break;
     std::vector<LdsBuf> bufs;
     tail_buffers<VT, MT>(h, cand, bufs);
     size_t nops = 0;
@@ -825,7 +840,7 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   std::memset(mats.data(), 0, mats.size() * sizeof(Mat<MT>));
   std::memset(trs.data(), 0, trs.size() * sizeof(Transfer));
   for (int l = t; l < h->L; ++l) {
-    Mat<MT> A = mat_of<MT>(h->lv[l]);
+    Mat<MT> A = plain_mat_of<MT>(h->lv[l]);
     A.off = (const int*)tr(A.off);
     A.width = (const int*)tr(A.width);
     A.col = (const int*)tr(A.col);
@@ -961,6 +976,43 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
 int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
   if (h->mixed) return solve_impl<float, float>(h, f, u, s, info);
   return solve_impl<double, double>(h, f, u, s, info);
+}
+
+template <typename VT>
+int32_t time_layout_impl(const Level& lv, void* wk, void* wb, void* y, hipStream_t s, float* ms) {
+  const Mat<VT> A = mat_of<VT>(lv);
+  const dim3 grid(A.nb), block(TPB << A.lk);
+  auto launch = [&]() {
+    hipLaunchKernelGGL((k_cheb_next<VT, VT, VT, true, false>), grid, block, 0, s, A, (const VT*)wk, (const VT*)wb,
+                       (VT*)wb, (VT*)y, lv.theta, lv.eta > 0.0 ? 2.0 / lv.eta : 1.0, 1e-3);
+  };
+  launch();
+  launch();
+  AMG_HIP(hipGetLastError());
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  constexpr int kReps = 5;
+  float best = 0.f;
+  hipError_t e = hipSuccess;
+  for (int trial = 0; trial < 3 && e == hipSuccess; ++trial) {
+    e = hipEventRecord(e0, s);
+    for (int i = 0; i < kReps; ++i) launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (trial == 0 || t < best) best = t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  AMG_HIP(e);
+  *ms = best / kReps;
+  return AMG_OK;
+}
+
+int32_t time_cheb_layout(const Level& lv, bool mixed, void* wk, void* wb, void* y, hipStream_t s, float* ms) {
+  return mixed ? time_layout_impl<float>(lv, wk, wb, y, s, ms) : time_layout_impl<double>(lv, wk, wb, y, s, ms);
 }
 
 int32_t time_step(amg_hier* h, int reps, hipStream_t s, amg_kernel_timing* t) {

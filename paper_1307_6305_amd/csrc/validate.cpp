@@ -24,6 +24,16 @@ int32_t validate_params(const amg_params& p, std::string& msg) {
   if (p.max_coarsest < 1 || p.max_coarsest > 4096) { msg = "max_coarsest out of range [1, 4096]"; return AMG_ERR_ARG; }
   if (!(p.stagnation > 0.0) || !(p.stagnation < 1.0)) { msg = "stagnation must lie in (0, 1)"; return AMG_ERR_ARG; }
   if (p.tail_rows < 0) { msg = "tail_rows must be >= 0"; return AMG_ERR_ARG; }
+  if (p.autotune != 0 && p.autotune != 1) { msg = "autotune must be 0 or 1"; return AMG_ERR_ARG; }
+  if (p.slice_height != 8 && p.slice_height != 16 && p.slice_height != 32 && p.slice_height != 64) {
+    msg = "slice_height must be 8, 16, 32 or 64";
+    return AMG_ERR_ARG;
+  }
+  if (p.lanes_per_row != 1 && p.lanes_per_row != 2 && p.lanes_per_row != 4) {
+    msg = "lanes_per_row must be 1, 2 or 4";
+    return AMG_ERR_ARG;
+  }
+  if (p.sort_rows != 0 && p.sort_rows != 1) { msg = "sort_rows must be 0 or 1"; return AMG_ERR_ARG; }
   // Smoother damping on [lambda0, lambda1]: E_m = delta^m (kappa - 1) / 2 must be < 1.
   const double kappa = p.lambda0_ratio;
   const double sk = std::sqrt(kappa);

@@ -48,6 +48,9 @@ def test_params_default(amg):
     p = amg.amg_params_default()
     assert (p.degree, p.agg_size, p.coarse_max, p.inner_steps, p.restart) == (4, 4, 64, 2, 5)
     assert p.lambda0_ratio == 10.0 and p.tol == 1e-8 and p.precision == amg.AMG_FP64
+    assert (p.autotune, p.slice_height, p.lanes_per_row, p.sort_rows) == (1, 64, 1, 0)
+    with pytest.raises(TypeError):
+        amg.amg_params_default(no_such_field=1)
 
 
 def test_strerror(amg):
@@ -101,6 +104,10 @@ def test_validation_errors_before_device(amg):
     assert _setup_code(amg, g.n, g.row_ptr, g.col, g.w, g.d, amg.amg_params_default(restart=0))[0] == \
         amg.AMG_ERR_ARG
     assert _setup_code(amg, 0, g.row_ptr, g.col, g.w, g.d)[0] == amg.AMG_ERR_ARG
+    for bad in (dict(slice_height=4), dict(slice_height=48), dict(lanes_per_row=3), dict(lanes_per_row=8),
+                dict(sort_rows=2), dict(autotune=-1)):
+        code = _setup_code(amg, g.n, g.row_ptr, g.col, g.w, g.d, amg.amg_params_default(**bad))[0]
+        assert code == amg.AMG_ERR_ARG, bad
     # unsorted columns
     col = g.col.copy()
     col[g.row_ptr[7]], col[g.row_ptr[7] + 1] = col[g.row_ptr[7] + 1], col[g.row_ptr[7]]
