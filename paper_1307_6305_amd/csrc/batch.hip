@@ -91,10 +91,10 @@ __device__ __forceinline__ const Mat<float>& op_mat<float>(const BatchOp& op) {
   return op.A32;
 }
 
-// Partial sums of K values of this block, for op-local tile `tile`.
+// Partial sums of the first kn of K values of this block, for op-local tile `tile`.
 template <int K>
-__device__ __forceinline__ void deposit(double (&v)[K], double* partials, int slot, double* red) {
-  block_sum<K>(v, red);
+__device__ __forceinline__ void deposit(double (&v)[K], double* partials, int slot, double* red, int kn = K) {
+  block_sum_k<K>(v, kn, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) partials[(size_t)slot * 8 + k] = v[k];
@@ -116,12 +116,15 @@ __device__ __forceinline__ void batch_mat_tile(const BatchOp& op, int tile, doub
     case B_CHEB_FIRST: {
       if (!slive) break;
       const Mat<MT>& A = op_mat<MT>(op);
+      // w.p[0]: a coarse correction whose prolongation is folded into y
+      const VT* e = (const VT*)op.w.p[0];
+      const int* agg = e ? op.T.agg : nullptr;
       if (op.i2)
         row_cheb_first<VT, MT, double>(A, slot, lane, (const double*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2,
-                                       op.f3, op.i0, op.i1);
+                                       op.f3, op.i0, op.i1, e, agg);
       else
         row_cheb_first<VT, MT, VT>(A, slot, lane, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.f3,
-                                   op.i0, op.i1);
+                                   op.i0, op.i1, e, agg);
       break;
     }
     case B_CHEB_NEXT: {
@@ -138,10 +141,18 @@ __device__ __forceinline__ void batch_mat_tile(const BatchOp& op, int tile, doub
     case B_RESIDUAL: {
       if (!slive) break;
       const Mat<MT>& A = op_mat<MT>(op);
-      if (op.i2)
+      const VT* e = (const VT*)op.w.p[0];  // residual after the prolongation of e
+      if (e) {
+        if (op.i2)
+          (void)row_residual_p<VT, MT, double>(A, slot, lane, (const double*)op.a, (const VT*)op.b, e, op.T.agg,
+                                               (VT*)op.c);
+        else
+          (void)row_residual_p<VT, MT, VT>(A, slot, lane, (const VT*)op.a, (const VT*)op.b, e, op.T.agg, (VT*)op.c);
+      } else if (op.i2) {
         (void)row_residual<VT, MT, double>(A, slot, lane, (const double*)op.a, (const VT*)op.b, (VT*)op.c);
-      else
+      } else {
         (void)row_residual<VT, MT, VT>(A, slot, lane, (const VT*)op.a, (const VT*)op.b, (VT*)op.c);
+      }
       break;
     }
     case B_SPMV_DOTS: {
@@ -213,7 +224,7 @@ __device__ __forceinline__ void batch_vec_tile(const BatchOp& op, int tile, doub
         for (int i = 0; i < 8; ++i)
           if (i < op.k) v[i] = zr * (double)((const VT*)op.w.p[i])[r];
       }
-      deposit<8>(v, partials, op.part + tile, red);
+      deposit<8>(v, partials, op.part + tile, red, op.k);
       break;
     }
     case B_FCG_P: {
@@ -248,7 +259,7 @@ __device__ __forceinline__ void batch_vec_tile(const BatchOp& op, int tile, doub
         for (int i = 0; i < 8; ++i)
           if (i < j) v[i] = zr * ((const double*)op.w.p[i])[r];
       }
-      deposit<8>(v, partials, op.part + tile, red);
+      deposit<8>(v, partials, op.part + tile, red, j);
       break;
     }
     case B_O_P: {
@@ -526,7 +537,8 @@ struct Builder {
     return H(i)->ws[l].Z[k];
   }
 
-  void smooth(int l, const std::vector<int>& I, Src src, Dst dst, int k, bool accum) {
+  // fold: y is x before the prolongation of the level's coarse correction
+  void smooth(int l, const std::vector<int>& I, Src src, Dst dst, int k, bool accum, bool fold = false) {
     const int m = H(I[0])->p.degree;
     const bool r64 = (src == SRC_OUTER_R) && mixed;
     if (m == 0) {
@@ -562,6 +574,10 @@ struct Builder {
         o.i0 = accum;
         o.i1 = m > 1;
         o.i2 = r64;
+        if (fold) {
+          o.w.p[0] = H(i)->ws[l + 1].sol;
+          o.T = transfer_of(H(i), l);
+        }
         v.push_back(o);
       }
       step(v, false);
@@ -593,7 +609,9 @@ struct Builder {
     }
   }
 
-  void residual(int l, const std::vector<int>& I, Src src, Dst dst, int k) {
+  // s = src - A dst; with fold, s = src - A (dst + P e) for the level's
+  // coarse correction e (the prolongation itself is left to smooth())
+  void residual(int l, const std::vector<int>& I, Src src, Dst dst, int k, bool fold = false) {
     std::vector<BatchOp> v;
     for (int i : I) {
       BatchOp o = blank(B_RESIDUAL, i);
@@ -603,6 +621,10 @@ struct Builder {
       o.b = dst_ptr(i, l, dst, k);
       o.c = H(i)->ws[l].S;
       o.i2 = (src == SRC_OUTER_R) && mixed;
+      if (fold) {
+        o.w.p[0] = H(i)->ws[l + 1].sol;
+        o.T = transfer_of(H(i), l);
+      }
       v.push_back(o);
     }
     step(v, false);
@@ -690,6 +712,12 @@ struct Builder {
     coarse(C);
     tail(T);
     if (!R.empty()) inner(l + 1, R);
+    if (H(I[0])->p.degree > 0) {
+      // the prolongation folded into the residual and the first smoothing step
+      residual(l, I, src, dst, k, true);
+      smooth(l, I, SRC_S, dst, k, true, true);
+      return;
+    }
     prolong(l, I, dst, k);
     residual(l, I, src, dst, k);
     smooth(l, I, SRC_S, dst, k, true);

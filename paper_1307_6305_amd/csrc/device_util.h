@@ -60,6 +60,32 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
   }
 }
 
+// block_sum for the first kn of K values (the others are left as they are):
+// the same tree, without the wavefront reductions of unused values.
+template <int K>
+__device__ __forceinline__ void block_sum_k(double (&v)[K], int kn, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (k < kn) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < kn) red[wid * K + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k < kn) {
+        double s = red[k];
+        for (int w = 1; w < nw; ++w) s += red[w * K + k];
+        v[k] = s;
+      }
+    }
+  }
+}
+
 // Up to 8 destination slots of a reduction in the hierarchy's scalar area.
 struct Slots {
   int s[8];
@@ -98,11 +124,12 @@ __device__ __forceinline__ void sum_partials(const double* partials, int nparts,
   block_sum<K>(acc, red);
 }
 
+// kn: only the first kn values are summed (the rest are written as given).
 template <int K>
-__device__ __forceinline__ void grid_sum_finish(double (&v)[K], const Red& r) {
+__device__ __forceinline__ void grid_sum_finish(double (&v)[K], const Red& r, int kn = K) {
   __shared__ double red[16 * 8];
   __shared__ bool last;
-  block_sum<K>(v, red);
+  block_sum_k<K>(v, kn, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) r.partials[blockIdx.x * K + k] = v[k];

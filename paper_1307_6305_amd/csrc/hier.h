@@ -58,7 +58,7 @@ struct amg_hier {
   unsigned* counter = nullptr;  // grid-reduction arrival counter
   double* host_scal = nullptr;  // pinned host mirror of a few scalars
   int max_blocks = 0;
-  int last_block_max = 16;
+  int last_block_max = 32;
 
   // replayable outer iterations (one per position in the restart window)
   bool graphs_ready = false;

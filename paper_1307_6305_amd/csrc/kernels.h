@@ -91,6 +91,23 @@ inline Transfer transfer_of(const amg_hier* h, int l) {
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// A vector operand read at row j: the vector itself, or the vector plus the
+// prolongation of a coarse correction, x_j + e_{agg(j)} (P piecewise
+// constant), computed where it is read instead of in a pass of its own.
+template <typename XT>
+struct XPlain {
+  const XT* __restrict__ x;
+  __device__ __forceinline__ XT operator()(int j) const { return x[j]; }
+};
+
+template <typename VT>
+struct XProlong {
+  const VT* __restrict__ x;
+  const VT* __restrict__ e;
+  const int* __restrict__ agg;
+  __device__ __forceinline__ VT operator()(int j) const { return x[j] + e[agg[j]]; }
+};
+
 // sum_j W_rj x_j over the stored entries of the row in `slot`, computed by
 // the K lanes j = 0..K-1 of the slot together (every lane gets the sum).
 // Entry k of the row goes to class k mod 8; each class is summed in order
@@ -99,8 +116,8 @@ __device__ __forceinline__ float fmadd(float a, float b, float c) { return __bui
 // the classes j, j + K, ..., so every K, slice height and row order gives the
 // same bits.  The loads of U steps are issued together: steps past the slice
 // width re-read its last step (a cache hit) and are not added.
-template <int K, typename AT, typename MT, typename XT>
-__device__ __forceinline__ AT offdiag_k(const Mat<MT>& A, int slot, int j, const XT* __restrict__ x) {
+template <int K, typename AT, typename MT, typename XA>
+__device__ __forceinline__ AT offdiag_k(const Mat<MT>& A, int slot, int j, const XA& x) {
   constexpr int U = 8 / K;
   const int s = slot >> A.lc, p = slot & ((1 << A.lc) - 1);
   const int stride = K << A.lc;
@@ -120,9 +137,9 @@ __device__ __forceinline__ AT offdiag_k(const Mat<MT>& A, int slot, int j, const
       cv[u] = c[tt];
       vv[u] = v[tt];
     }
-    XT xv[U];
+    AT xv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = x[cv[u]];
+    for (int u = 0; u < U; ++u) xv[u] = (AT)x(cv[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (t + u < wd) acc[u] = fmadd((AT)vv[u], (AT)xv[u], acc[u]);
@@ -144,22 +161,22 @@ __device__ __forceinline__ AT offdiag_k(const Mat<MT>& A, int slot, int j, const
 // The same sum on the plain layout (one lane per row) in LDS, where the
 // one-workgroup tail program runs: entries added in order.  The tail always
 // uses the plain layout, so its results do not depend on the level's layout.
-template <typename AT, typename MT, typename XT>
-__device__ __forceinline__ AT offdiag_seq(const Mat<MT>& A, int r, const XT* __restrict__ x) {
+template <typename AT, typename MT, typename XA>
+__device__ __forceinline__ AT offdiag_seq(const Mat<MT>& A, int r, const XA& x) {
   const int s = r >> 6, p = r & 63;
   const int* __restrict__ c = A.col + A.off[s] + p;
   const MT* __restrict__ v = A.val + A.off[s] + p;
   const int wd = A.width[s];
   AT acc = (AT)0;
 #pragma unroll 4
-  for (int t = 0; t < wd; ++t) acc += (AT)v[t * 64] * (AT)x[c[t * 64]];
+  for (int t = 0; t < wd; ++t) acc += (AT)v[t * 64] * (AT)x(c[t * 64]);
   return acc;
 }
 
 // GLOBAL: device-wide kernels on the level's layout; otherwise the tail
 // program on the plain layout.
-template <typename AT, bool GLOBAL = true, typename MT, typename XT>
-__device__ __forceinline__ AT offdiag(const Mat<MT>& A, int slot, int j, const XT* __restrict__ x) {
+template <typename AT, bool GLOBAL = true, typename MT, typename XA>
+__device__ __forceinline__ AT offdiag_a(const Mat<MT>& A, int slot, int j, const XA& x) {
   if constexpr (!GLOBAL) {
     return offdiag_seq<AT>(A, slot, x);
   } else {
@@ -167,6 +184,11 @@ __device__ __forceinline__ AT offdiag(const Mat<MT>& A, int slot, int j, const X
     if (A.lk == 1) return offdiag_k<2, AT>(A, slot, j, x);
     return offdiag_k<4, AT>(A, slot, j, x);
   }
+}
+
+template <typename AT, bool GLOBAL = true, typename MT, typename XT>
+__device__ __forceinline__ AT offdiag(const Mat<MT>& A, int slot, int j, const XT* __restrict__ x) {
+  return offdiag_a<AT, GLOBAL>(A, slot, j, XPlain<XT>{x});
 }
 
 template <typename MT>
@@ -178,15 +200,19 @@ __device__ __forceinline__ int row_at(const Mat<MT>& A, int slot) {
 // row's results.
 //
 // w1 = (A w0 - theta w0) / eta;  y = [y +] c0 w0 + c1 w1   (c already divided by eta)
+//
+// With e and agg given (accumulating steps only), y holds x before the
+// prolongation of a coarse correction: y is read as y_r + e_{agg(r)}.
 template <typename VT, typename MT, typename RT, bool G = true>
 __device__ __forceinline__ void row_cheb_first(const Mat<MT>& A, int slot, int j, const RT* __restrict__ w0, VT* w1,
                                                VT* y, double theta, double inv_eta, double c0, double c1, int accum,
-                                               int store) {
+                                               int store, const VT* __restrict__ e = nullptr,
+                                               const int* __restrict__ agg = nullptr) {
   using AT = VT;
   const int r = row_at(A, slot);
   const AT x0 = (AT)w0[r];
   const AT d = (AT)A.D[r];
-  const AT y0 = accum ? (AT)y[r] : (AT)0;
+  const AT y0 = accum ? (AT)(e ? (VT)(y[r] + e[agg[r]]) : y[r]) : (AT)0;
   const AT off = offdiag<AT, G>(A, slot, j, w0);
   if (j) return;
   const AT ax = d * x0 - off;
@@ -227,6 +253,25 @@ __device__ __forceinline__ int row_residual(const Mat<MT>& A, int slot, int j, c
   const AT d = (AT)A.D[r];
   const AT fr = (AT)f[r];
   const AT off = offdiag<AT, G>(A, slot, j, x);
+  if (j) return -1;
+  const AT ax = d * xr - off;
+  s[r] = (VT)(fr - ax);
+  return r;
+}
+
+// s = f - A (x + P e): the residual after the prolongation of the coarse
+// correction e, without writing x + P e (the next smoothing step adds e).
+template <typename VT, typename MT, typename RT, bool G = true>
+__device__ __forceinline__ int row_residual_p(const Mat<MT>& A, int slot, int j, const RT* __restrict__ f,
+                                              const VT* __restrict__ x, const VT* __restrict__ e,
+                                              const int* __restrict__ agg, VT* s) {
+  using AT = VT;
+  const XProlong<VT> X{x, e, agg};
+  const int r = row_at(A, slot);
+  const AT xr = (AT)X(r);
+  const AT d = (AT)A.D[r];
+  const AT fr = (AT)f[r];
+  const AT off = offdiag_a<AT, G>(A, slot, j, X);
   if (j) return -1;
   const AT ax = d * xr - off;
   s[r] = (VT)(fr - ax);
@@ -298,22 +343,29 @@ __device__ __forceinline__ double fcg_beta(const double* scal, int s_dot, int s_
 }
 
 // Coarsest solve x = L^-T (L^-1 b) with the inverted factor: two triangular
-// products, thread i owning rows i, i + blockDim, ... (n <= 1024).
+// products, thread i owning rows i, i + blockDim, ... (n <= 1024).  For small
+// n every thread runs the full range of j -- the factor's other triangle
+// holds exact zeros, so the sums are unchanged -- which keeps the loop
+// uniform across the wavefront and lets its loads be issued ahead.
 template <typename VT, typename RT>
 __device__ __forceinline__ void coarse_apply(const CoarseView& C, const RT* __restrict__ b, VT* x, double* sb,
                                              double* sy) {
   const int n = C.n;
+  const bool full = n <= 256;
   for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[i];
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double acc = 0.0;
-    for (int j = 0; j <= i; ++j) acc += C.LinvT[(size_t)j * n + i] * sb[j];
+    const int j1 = full ? n : i + 1;
+#pragma unroll 8
+    for (int j = 0; j < j1; ++j) acc += C.LinvT[(size_t)j * n + i] * sb[j];
     sy[i] = acc;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double acc = 0.0;
-    for (int j = i; j < n; ++j) acc += C.Linv[(size_t)j * n + i] * sy[j];
+#pragma unroll 8
+    for (int j = full ? 0 : i; j < n; ++j) acc += C.Linv[(size_t)j * n + i] * sy[j];
     x[i] = (VT)acc;
   }
 }
@@ -331,6 +383,7 @@ enum OpType : int {
   OP_FCG_P,
   OP_SPMV_DOTS,
   OP_FCG_XR,
+  OP_RESIDUAL_P,
 };
 
 struct TailOp {
@@ -405,9 +458,18 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
   const int tid = threadIdx.x, bd = blockDim.x;
   for (int c = copy_constants ? 0 : P.ncin - 1; c < P.ncin; ++c) {
     const TailCopy cp = P.cin[c];
-    const int4* src = static_cast<const int4*>(cp.src);
+    const int4* __restrict__ src = static_cast<const int4*>(cp.src);
     int4* dst = reinterpret_cast<int4*>(lds + cp.dst);
-    for (int i = tid; i < (cp.bytes >> 4); i += bd) dst[i] = src[i];
+    const int n16 = cp.bytes >> 4;
+    int i = tid;
+    for (; i + 3 * bd < n16; i += 4 * bd) {  // four loads in flight per thread
+      const int4 a = src[i], b = src[i + bd], c2 = src[i + 2 * bd], d = src[i + 3 * bd];
+      dst[i] = a;
+      dst[i + bd] = b;
+      dst[i + 2 * bd] = c2;
+      dst[i + 3 * bd] = d;
+    }
+    for (; i < n16; i += bd) dst[i] = src[i];
   }
   __syncthreads();
   double* scal = reinterpret_cast<double*>(lds + P.scal_off);
@@ -423,8 +485,10 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* w0 = at<const VT>(lds, op.a);
         VT* w1 = at<VT>(lds, op.c);
         VT* y = at<VT>(lds, op.d);
+        const VT* e = op.i2 ? at<const VT>(lds, op.w.p[0]) : nullptr;
+        const int* agg = op.i2 ? lds_tr(trs[op.level], lds).agg : nullptr;
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_first<VT, MT, VT, false>(A, r, 0, w0, w1, y, op.f0, op.f1, op.f2, op.f3, op.i0, op.i1);
+          row_cheb_first<VT, MT, VT, false>(A, r, 0, w0, w1, y, op.f0, op.f1, op.f2, op.f3, op.i0, op.i1, e, agg);
         break;
       }
       case OP_CHEB_NEXT: {
@@ -455,6 +519,16 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         for (int r = tid; r < A.n; r += bd) (void)row_residual<VT, MT, VT, false>(A, r, 0, f, x, sv);
         break;
       }
+      case OP_RESIDUAL_P: {
+        const Mat<MT> A = lds_mat(mats[op.level], lds);
+        const VT* f = at<const VT>(lds, op.a);
+        const VT* x = at<const VT>(lds, op.b);
+        const VT* e = at<const VT>(lds, op.w.p[0]);
+        const int* agg = lds_tr(trs[op.level], lds).agg;
+        VT* sv = at<VT>(lds, op.c);
+        for (int r = tid; r < A.n; r += bd) (void)row_residual_p<VT, MT, VT, false>(A, r, 0, f, x, e, agg, sv);
+        break;
+      }
       case OP_RESTRICT: {
         const Transfer T = lds_tr(trs[op.level], lds);
         const VT* sv = at<const VT>(lds, op.a);
@@ -483,7 +557,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
           for (int i = 0; i < 8; ++i)
             if (i < op.k) v[i] += zj * (double)at<const VT>(lds, op.w.p[i])[j];
         }
-        block_sum<8>(v, red);
+        block_sum_k<8>(v, op.k, red);
         if (tid == 0)
           for (int i = 0; i < op.k; ++i) scal[op.s0.s[i]] = v[i];
         break;

@@ -39,6 +39,8 @@ namespace {
 // Row-parallel kernels: one block per tile of TPB rows (XCD-aware order),
 // K = 2^lk lanes per row, so blockDim = TPB << lk.
 constexpr int kMaxRowThreads = TPB * 4;
+// Levels below this many rows fold the prolongation into the next steps.
+constexpr int kFoldProlongRows = 1 << 18;
 
 struct SlotLane {
   int tile, slot, lane;
@@ -54,9 +56,11 @@ __device__ __forceinline__ SlotLane slot_of(const Mat<MT>& A) {
 template <typename VT, typename MT, typename RT>
 __global__ void __launch_bounds__(kMaxRowThreads) k_cheb_first(Mat<MT> A, const RT* __restrict__ w0, VT* w1, VT* y,
                                                                double theta, double inv_eta, double c0, double c1,
-                                                               int accum, int store) {
+                                                               int accum, int store, const VT* __restrict__ e,
+                                                               const int* __restrict__ agg) {
   const SlotLane q = slot_of(A);
-  if (q.slot >= 0) row_cheb_first<VT, MT, RT>(A, q.slot, q.lane, w0, w1, y, theta, inv_eta, c0, c1, accum, store);
+  if (q.slot >= 0)
+    row_cheb_first<VT, MT, RT>(A, q.slot, q.lane, w0, w1, y, theta, inv_eta, c0, c1, accum, store, e, agg);
 }
 
 // STORE: w_{k+1} is written (every step but the last).  FINE marks launches
@@ -85,6 +89,15 @@ __global__ void __launch_bounds__(kMaxRowThreads) k_residual(Mat<MT> A, const RT
                                                              const VT* __restrict__ x, VT* s) {
   const SlotLane q = slot_of(A);
   if (q.slot >= 0) (void)row_residual<VT, MT, RT>(A, q.slot, q.lane, f, x, s);
+}
+
+// s = f - A (x + P e)
+template <typename VT, typename MT, typename RT>
+__global__ void __launch_bounds__(kMaxRowThreads) k_residual_p(Mat<MT> A, const RT* __restrict__ f,
+                                                               const VT* __restrict__ x, const VT* __restrict__ e,
+                                                               const int* __restrict__ agg, VT* s) {
+  const SlotLane q = slot_of(A);
+  if (q.slot >= 0) (void)row_residual_p<VT, MT, RT>(A, q.slot, q.lane, f, x, e, agg, s);
 }
 
 // FP64 residual with its squared norm: s = f - A x, (s, s).
@@ -157,7 +170,7 @@ __global__ void __launch_bounds__(TPB) k_multidot(int n, const ZT* __restrict__ 
     for (int i = 0; i < 8; ++i)
       if (i < k) v[i] += zj * (double)static_cast<const QT*>(qs.p[i])[j];
   }
-  grid_sum_finish<8>(v, red);
+  grid_sum_finish<8>(v, red, k);
 }
 
 // p = z - sum_i (dots_i / rho_i) p_i  (term dropped when rho_i <= 0); FP64 arithmetic.
@@ -288,8 +301,10 @@ struct Engine {
     return AMG_OK;
   }
 
+  // fold_e: y holds x before the prolongation of the coarse correction fold_e
   template <typename RT>
-  int32_t cheb_first(int l, const RT* w0, VT* w1, VT* y, double c0, double c1, bool accum, bool store) {
+  int32_t cheb_first(int l, const RT* w0, VT* w1, VT* y, double c0, double c1, bool accum, bool store,
+                     const VT* fold_e = nullptr) {
     const Level& lv = h->lv[l];
     if (rec) {
       if constexpr (std::is_same<RT, VT>::value) {
@@ -297,14 +312,20 @@ struct Engine {
         o.a = w0; o.c = w1; o.d = y;
         o.f0 = lv.theta; o.f1 = 1.0 / lv.eta; o.f2 = c0; o.f3 = c1;
         o.i0 = accum; o.i1 = store;
+        if (fold_e) {
+          o.i2 = 1;
+          o.k = 1;
+          o.w.p[0] = fold_e;
+        }
         rec->push_back(o);
         return AMG_OK;
       }
       return AMG_ERR_DEVICE;
     }
     const auto Am = A(l);
+    const int* agg = fold_e ? transfer_of(h, l).agg : nullptr;
     hipLaunchKernelGGL((k_cheb_first<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, w0, w1, y, lv.theta,
-                       1.0 / lv.eta, c0, c1, (int)accum, (int)store);
+                       1.0 / lv.eta, c0, c1, (int)accum, (int)store, fold_e, agg);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
@@ -380,16 +401,17 @@ struct Engine {
   }
 
   // y = [y +] q_m(A_l) r: m three-term steps; buffers A, B of the level hold
-  // w_k and w_{k-1} (w_{k+1} overwrites w_{k-1} in place).
+  // w_k and w_{k-1} (w_{k+1} overwrites w_{k-1} in place).  fold_e (m >= 1,
+  // accumulating): y is x before the prolongation x += P fold_e.
   template <typename RT>
-  int32_t smooth(int l, const RT* r, VT* y, bool accum) {
+  int32_t smooth(int l, const RT* r, VT* y, bool accum, const VT* fold_e = nullptr) {
     const Level& lv = h->lv[l];
     const int m = h->p.degree;
     const double* c = lv.coef.data();
     if (m == 0) return scale_add(l, r, y, c[0], accum);
     VT* bufA = wsv(h->ws[l].A);
     VT* bufB = wsv(h->ws[l].B);
-    AMG_TRY(cheb_first(l, r, bufA, y, c[0], c[1], accum, m > 1));
+    AMG_TRY(cheb_first(l, r, bufA, y, c[0], c[1], accum, m > 1, fold_e));
     VT* cur = bufA;
     VT* prevbuf = nullptr;
     for (int k = 1; k < m; ++k) {
@@ -421,6 +443,27 @@ struct Engine {
     }
     const auto Am = A(l);
     hipLaunchKernelGGL((k_residual<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, f, x, out);
+    AMG_HIP(hipGetLastError());
+    return AMG_OK;
+  }
+
+  // out = f - A (x + P e), x itself unchanged
+  template <typename RT>
+  int32_t residual_p(int l, const RT* f, const VT* x, const VT* e, VT* out) {
+    if (rec) {
+      if constexpr (std::is_same<RT, VT>::value) {
+        TailOp o = op(OP_RESIDUAL_P, l, h->lv[l].n);
+        o.a = f; o.b = x; o.c = out;
+        o.k = 1;
+        o.w.p[0] = e;
+        rec->push_back(o);
+        return AMG_OK;
+      }
+      return AMG_ERR_DEVICE;
+    }
+    const auto Am = A(l);
+    hipLaunchKernelGGL((k_residual_p<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, f, x, e,
+                       transfer_of(h, l).agg, out);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
@@ -559,6 +602,14 @@ struct Engine {
       AMG_TRY(tail());
     } else {
       AMG_TRY(inner(l + 1));
+    }
+    // on launch-bound levels (and in recorded programs) the prolongation
+    // x += P e is folded into the residual and the first smoothing step that
+    // follow it: the same roundings, one pass fewer
+    if (h->p.degree > 0 && (rec || h->lv[l].n < kFoldProlongRows)) {
+      AMG_TRY(residual_p(l, r, x, e, S));
+      AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true, e));
+      return AMG_OK;
     }
     AMG_TRY(prolong(l, e, x));
     AMG_TRY(residual(l, r, x, S));
@@ -798,27 +849,27 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   uint64_t off = trs_off + round16((h->L + 1) * sizeof(Transfer));
   std::vector<LdsBuf> bufs;
   tail_buffers<VT, MT>(h, t, bufs);
+  // image order: the header, then every constant buffer (one contiguous
+  // region, copied in from one packed device blob), then the tail level's
+  // right-hand side (the only per-call input), then the work vectors
+  const void* rhs_t = h->ws[t].rhs;
+  std::stable_partition(bufs.begin(), bufs.end(), [&](const LdsBuf& b) { return b.copy_in && b.g != rhs_t; });
+  std::stable_partition(bufs.begin(), bufs.end(), [&](const LdsBuf& b) { return b.copy_in; });
   std::vector<std::pair<const void*, uint64_t>> map;
-  std::vector<TailCopy> cin;
+  std::vector<std::pair<const LdsBuf*, uint64_t>> consts;
+  uint64_t rhs_off = 0, rhs_bytes = 0, const_end = 0;
   for (const auto& b : bufs) {
     map.push_back({b.g, off});
-    if (b.copy_in && b.bytes > 0) cin.push_back({b.g, (uint32_t)off, (int)round16(b.bytes)});
+    if (b.copy_in && b.g != rhs_t) {
+      consts.push_back({&b, off});
+      const_end = off + round16(b.bytes);
+    } else if (b.g == rhs_t) {
+      rhs_off = off;
+      rhs_bytes = round16(b.bytes);
+    }
     off += round16(b.bytes);
   }
   const size_t need = off;
-  // the tail level's right-hand side is the only per-call input: keep it last
-  // so that a caller that keeps the LDS image can refresh it alone
-  {
-    const void* rhs_t = h->ws[t].rhs;
-    for (size_t i = 0; i < cin.size(); ++i) {
-      if (cin[i].src == rhs_t) {
-        TailCopy c = cin[i];
-        cin.erase(cin.begin() + i);
-        cin.push_back(c);
-        break;
-      }
-    }
-  }
   // every operand of the program must be one of the placed buffers
   bool ok = true;
   auto tr = [&](const void* p) -> const void* {
@@ -861,17 +912,24 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
     set_last_error("tail program refers to data outside its LDS image");
     return AMG_ERR_DEVICE;
   }
-  // program header (ops, descriptors) as one device blob copied first
+  // the header (ops, descriptors) and the constant buffers packed into one
+  // device blob laid out as the start of the LDS image
   std::vector<char> head(trs_off + round16((h->L + 1) * sizeof(Transfer)), 0);
   std::memcpy(head.data() + ops_off, ops.data(), ops.size() * sizeof(TailOp));
   std::memcpy(head.data() + mats_off, mats.data(), mats.size() * sizeof(Mat<MT>));
   std::memcpy(head.data() + trs_off, trs.data(), trs.size() * sizeof(Transfer));
-  void* d_head = nullptr;
+  const size_t blob_bytes = std::max<size_t>(head.size(), const_end);
+  char* d_blob = nullptr;
   void* d_cin = nullptr;
-  AMG_TRY(dalloc(h, &d_head, head.size() + 16));
-  cin.insert(cin.begin(), TailCopy{d_head, 0, (int)head.size()});
+  AMG_TRY(dalloc(h, (void**)&d_blob, blob_bytes + 16));
+  AMG_HIP(hipMemcpyAsync(d_blob, head.data(), head.size(), hipMemcpyHostToDevice, s));
+  for (const auto& c : consts)
+    if (c.first->bytes > 0)
+      AMG_HIP(hipMemcpyAsync(d_blob + c.second, c.first->g, c.first->bytes, hipMemcpyDeviceToDevice, s));
+  std::vector<TailCopy> cin;
+  cin.push_back(TailCopy{d_blob, 0, (int)round16(blob_bytes)});
+  if (rhs_bytes) cin.push_back(TailCopy{rhs_t, (uint32_t)rhs_off, (int)rhs_bytes});
   AMG_TRY(dalloc(h, &d_cin, cin.size() * sizeof(TailCopy) + 16));
-  AMG_HIP(hipMemcpyAsync(d_head, head.data(), head.size(), hipMemcpyHostToDevice, s));
   AMG_HIP(hipMemcpyAsync(d_cin, cin.data(), cin.size() * sizeof(TailCopy), hipMemcpyHostToDevice, s));
   AMG_HIP(hipStreamSynchronize(s));
   TailProgram P;
@@ -956,7 +1014,7 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
   h->max_blocks = nblk(n0);
   // grids of up to this many blocks finish their reductions in-kernel (one
   // release fence per block); larger grids use the one-block finishing kernel
-  h->last_block_max = 16;
+  h->last_block_max = 32;
   if (const char* e = std::getenv("AMG_LAST_BLOCK_MAX")) h->last_block_max = std::max(0, std::atoi(e));
   AMG_TRY(dalloc(h, &h->partials, (size_t)std::max(h->max_blocks, 1) * 8));
   AMG_TRY(dalloc(h, &h->scal, SCAL_SIZE));
