@@ -211,64 +211,153 @@ __device__ __forceinline__ int best_free_neighbour(int v, const int* __restrict_
   return best;
 }
 
-__global__ void k_match_propose(int n, const int* __restrict__ rp, const int* __restrict__ col,
-                                const double* __restrict__ S, const int* __restrict__ mate,
-                                int* __restrict__ cand, int* cnt, int slot) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  int proposed = 0;
-  if (v < n && mate[v] == -1) {
-    const int b = best_free_neighbour(v, rp, col, S, mate);
-    cand[v] = b >= 0 ? b : -2;
-    proposed = b >= 0;
+// ---- handshake matching on worklists
+//
+// Every free vertex points at its best free neighbour (cand); mutual pairs
+// match, vertices with no free neighbour become singletons (mate = -2).  A
+// free vertex's best free neighbour can only change when that neighbour
+// leaves the free set (removing any other vertex does not change a maximum),
+// so each round re-evaluates only the vertices whose candidate has just left
+// it.  The proposals of every round are therefore those of the full
+// handshake, and so is the result: the unique locally dominant matching,
+// which is the greedy matching in the strict edge order.
+//
+// Round r: evaluate the list W_r (cand = best free neighbour or -2); accept
+// (mutual pairs and singletons leave the free set, listed in `fresh`); push
+// the free vertices whose candidate is in `fresh` onto W_{r+1}.  stamp[v] is
+// the round of the list v was last put on (round 0 = every vertex).
+
+// Appends v to list when `take`, one atomic per wavefront.
+__device__ __forceinline__ void list_push(int* list, int* size, bool take, int v) {
+  const unsigned long long m = __ballot(take);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(size, __popcll(m));
+  base = __shfl(base, leader, 64);
+  if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
+}
+
+struct MatchState {
+  const int* rp;
+  const int* col;
+  const double* S;
+  int* mate;
+  int* cand;
+  int* stamp;
+  int* W[2];    // the round's list and the next one
+  int* fresh;   // vertices that left the free set this round
+  int* size;    // size[0], size[1]: |W[0]|, |W[1]|; size[2]: |fresh|; size[3]: rounds with work
+};
+
+__device__ __forceinline__ void mw_eval_one(const MatchState& M, int v) {
+  const int b = best_free_neighbour(v, M.rp, M.col, M.S, M.mate);
+  M.cand[v] = b >= 0 ? b : -2;
+}
+
+__device__ __forceinline__ void mw_accept_one(const MatchState& M, int v, int round, int* fresh, int* fsize,
+                                              bool valid) {
+  bool leave_v = false, leave_u = false;
+  int u = -1;
+  if (valid) {
+    u = M.cand[v];
+    if (u == -2) {
+      M.mate[v] = -2;
+      leave_v = true;
+    } else if (M.cand[u] == v) {
+      M.mate[v] = u;
+      M.mate[u] = v;
+      leave_v = true;
+      leave_u = M.stamp[u] != round;  // a partner not on this round's list is listed by v
+    }
   }
-  proposed = wave_sum(proposed);
-  if ((threadIdx.x & 63) == 0 && proposed) atomicAdd(&cnt[slot], proposed);
+  list_push(fresh, fsize, leave_v, v);
+  list_push(fresh, fsize, leave_u, u);
 }
 
-__global__ void k_match_accept(int n, int* __restrict__ mate, const int* __restrict__ cand, int* cnt,
-                               int clear_slot) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v == 0) cnt[clear_slot] = 0;
-  if (v >= n || mate[v] != -1) return;
-  const int u = cand[v];
-  if (u == -2) mate[v] = -2;
-  else if (cand[u] == v) mate[v] = u;
+__device__ __forceinline__ void mw_push_one(const MatchState& M, int m, int next_round, int* W, int* wsize) {
+  for (int k = M.rp[m]; k < M.rp[m + 1]; ++k) {
+    const int x = M.col[k];
+    const bool take = M.mate[x] == -1 && M.cand[x] == m;
+    if (take) M.stamp[x] = next_round;
+    list_push(W, wsize, take, x);
+  }
 }
 
-// Whole matching in one workgroup (small graphs): rounds separated by
-// workgroup barriers; stops after a round without proposals.
-__global__ void __launch_bounds__(1024) k_match_small(int n, const int* __restrict__ rp,
-                                                      const int* __restrict__ col,
-                                                      const double* __restrict__ S, int* mate,
-                                                      int* cand, int* rounds_out) {
-  __shared__ int act[2];
-  if (threadIdx.x == 0) { act[0] = 0; act[1] = 0; }
+// Multi-block rounds (large lists): grid-stride over the list held on the
+// device; `implicit_n` > 0 stands for the list 0..n-1 (round 0).
+__global__ void __launch_bounds__(256) k_mw_eval(MatchState M, int cur, int implicit_n) {
+  const int sz = implicit_n > 0 ? implicit_n : M.size[cur];
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) {
+    M.size[cur ^ 1] = 0;
+    M.size[2] = 0;
+    if (sz > 0) M.size[3] += 1;
+  }
+  for (int i = g; i < sz; i += gridDim.x * blockDim.x) mw_eval_one(M, implicit_n > 0 ? i : M.W[cur][i]);
+}
+
+__global__ void __launch_bounds__(256) k_mw_accept(MatchState M, int cur, int implicit_n, int round) {
+  const int sz = implicit_n > 0 ? implicit_n : M.size[cur];
+  const int stride = gridDim.x * blockDim.x;
+  // whole wavefronts iterate together (list_push needs the wavefront)
+  const int lim = (sz + 63) & ~63;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < lim; i += stride) {
+    const bool valid = i < sz;
+    const int v = valid ? (implicit_n > 0 ? i : M.W[cur][i]) : 0;
+    mw_accept_one(M, v, round, M.fresh, &M.size[2], valid);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mw_push(MatchState M, int cur, int round) {
+  const int sz = M.size[2];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < sz; i += gridDim.x * blockDim.x)
+    mw_push_one(M, M.fresh[i], round + 1, M.W[cur ^ 1], &M.size[cur ^ 1]);
+}
+
+// Rounds in one workgroup while the list is short: workgroup barriers
+// instead of launches.  The counters live in LDS.  Stops when the list is
+// empty, longer than `max_list`, or after `max_rounds` rounds; io[0] (round)
+// and io[1] (current list) carry the position in and out.
+__global__ void __launch_bounds__(1024) k_mw_small(MatchState M, int* io, int max_list, int max_rounds) {
+  __shared__ int s_size[2], s_fresh, s_work;
+  int round = io[0], cur = io[1];
+  if (threadIdx.x == 0) {
+    s_size[0] = M.size[0];
+    s_size[1] = M.size[1];
+    s_work = M.size[3];
+  }
   __syncthreads();
-  int round = 0;
-  for (;; ++round) {
-    const int slot = round & 1;
-    int c = 0;
-    for (int v = threadIdx.x; v < n; v += blockDim.x) {
-      if (mate[v] != -1) continue;
-      const int b = best_free_neighbour(v, rp, col, S, mate);
-      cand[v] = b >= 0 ? b : -2;
-      c += b >= 0;
-    }
-    c = wave_sum(c);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&act[slot], c);
-    __syncthreads();
-    const int a = act[slot];
-    if (threadIdx.x == 0) act[slot ^ 1] = 0;
-    for (int v = threadIdx.x; v < n; v += blockDim.x) {
-      if (mate[v] != -1) continue;
-      const int u = cand[v];
-      if (u == -2) mate[v] = -2;
-      else if (cand[u] == v) mate[v] = u;
+  for (int it = 0; it < max_rounds; ++it) {
+    const int sz = s_size[cur];
+    if (sz == 0 || sz > max_list) break;  // uniform: read after a barrier
+    for (int i = threadIdx.x; i < sz; i += blockDim.x) mw_eval_one(M, M.W[cur][i]);
+    if (threadIdx.x == 0) {
+      s_size[cur ^ 1] = 0;
+      s_fresh = 0;
+      s_work += 1;
     }
     __syncthreads();
-    if (a == 0) break;
+    const int lim = (sz + 63) & ~63;
+    for (int i = threadIdx.x; i < lim; i += blockDim.x) {
+      const bool valid = i < sz;
+      mw_accept_one(M, valid ? M.W[cur][i] : 0, round, M.fresh, &s_fresh, valid);
+    }
+    __syncthreads();
+    const int nf = s_fresh;
+    for (int i = threadIdx.x; i < nf; i += blockDim.x) mw_push_one(M, M.fresh[i], round + 1, M.W[cur ^ 1], &s_size[cur ^ 1]);
+    __syncthreads();
+    cur ^= 1;
+    ++round;
   }
-  if (threadIdx.x == 0) *rounds_out = round + 1;
+  if (threadIdx.x == 0) {
+    M.size[0] = s_size[0];
+    M.size[1] = s_size[1];
+    M.size[3] = s_work;
+    io[0] = round;
+    io[1] = cur;
+  }
 }
 
 // ------------------------------------------------------------------ coarse numbering
@@ -562,43 +651,69 @@ struct Graph {  // a pass graph on the device (not owned)
 // One matching pass on g: mate[] (device) and the number of rounds.
 int32_t match_pass(Temps& T, const Graph& g, int raw, int* mate, int* rounds, hipStream_t s) {
   double* S = nullptr;
-  int* cand = nullptr;
+  int *cand = nullptr, *stamp = nullptr, *w0 = nullptr, *w1 = nullptr, *fresh = nullptr, *size = nullptr,
+      *io = nullptr;
   AMG_TRY(T.get(&S, std::max(g.nnz, 1)));
   AMG_TRY(T.get(&cand, g.n));
+  AMG_TRY(T.get(&stamp, g.n));
+  AMG_TRY(T.get(&w0, g.n));
+  AMG_TRY(T.get(&w1, g.n));
+  AMG_TRY(T.get(&fresh, g.n));
+  AMG_TRY(T.get(&size, 4));
+  AMG_TRY(T.get(&io, 2));
   hipLaunchKernelGGL(k_strength, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, g.rp, g.col, g.W, g.D, raw, S);
   hipLaunchKernelGGL(k_fill<int>, dim3(nblk(g.n)), dim3(TPB), 0, s, (size_t)g.n, mate, -1);
+  hipLaunchKernelGGL(k_fill<int>, dim3(nblk(g.n)), dim3(TPB), 0, s, (size_t)g.n, stamp, 0);
+  hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (size_t)4, size, 0);
   AMG_HIP(hipGetLastError());
-  constexpr int kSmall = 8192;
-  if (g.n <= kSmall) {
-    int* r = nullptr;
-    AMG_TRY(T.get(&r, 1));
-    hipLaunchKernelGGL(k_match_small, dim3(1), dim3(1024), 0, s, g.n, g.rp, g.col, S, mate, cand, r);
-    AMG_HIP(hipGetLastError());
-    AMG_TRY(read_int(r, rounds, s));
-    return AMG_OK;
+  const MatchState M{g.rp, g.col, S, mate, cand, stamp, {w0, w1}, fresh, size};
+  // lists up to this long run in one workgroup; multi-block rounds otherwise
+  constexpr int kSmallList = 4096, kBatch = 8, kSmallRounds = 4096;
+  const int grid = std::min(nblk(g.n), 2048);
+  int round = 0, cur = 0;
+  if (g.n <= kSmallList) {
+    hipLaunchKernelGGL(k_iota, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, w0);
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (size_t)1, size, g.n);
+  } else {
+    // round 0: every vertex
+    hipLaunchKernelGGL(k_mw_eval, dim3(grid), dim3(256), 0, s, M, cur, g.n);
+    hipLaunchKernelGGL(k_mw_accept, dim3(grid), dim3(256), 0, s, M, cur, g.n, round);
+    hipLaunchKernelGGL(k_mw_push, dim3(grid), dim3(256), 0, s, M, cur, round);
+    cur ^= 1;
+    ++round;
   }
-  constexpr int kRing = 64, kBatch = 16;
-  int* cnt = nullptr;
-  AMG_TRY(T.get(&cnt, kRing));
-  hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(kRing), 0, s, (size_t)kRing, cnt, 0);
-  int round = 0;
+  AMG_HIP(hipGetLastError());
   for (;;) {
-    for (int b = 0; b < kBatch; ++b, ++round) {
-      hipLaunchKernelGGL(k_match_propose, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, g.rp, g.col, S, mate,
-                         cand, cnt, round % kRing);
-      hipLaunchKernelGGL(k_match_accept, dim3(nblk(g.n)), dim3(TPB), 0, s, g.n, mate, cand, cnt,
-                         (round + 1) % kRing);
+    int h[4];
+    AMG_HIP(hipMemcpyAsync(h, size, sizeof(h), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    if (h[cur] == 0) {
+      *rounds = h[3];
+      break;
     }
-    AMG_HIP(hipGetLastError());
-    int last = 0;
-    AMG_TRY(read_int(cnt + (round - 1) % kRing, &last, s));
-    if (last == 0) break;
     if (round > 4 * g.n + 64) {
       set_last_error("matching did not terminate");
       return AMG_ERR_DEVICE;
     }
+    if (h[cur] <= kSmallList) {
+      const int hio[2] = {round, cur};
+      AMG_HIP(hipMemcpyAsync(io, hio, sizeof(hio), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_mw_small, dim3(1), dim3(1024), 0, s, M, io, kSmallList, kSmallRounds);
+      AMG_HIP(hipGetLastError());
+      int oio[2];
+      AMG_HIP(hipMemcpyAsync(oio, io, sizeof(oio), hipMemcpyDeviceToHost, s));
+      AMG_HIP(hipStreamSynchronize(s));
+      round = oio[0];
+      cur = oio[1];
+      continue;
+    }
+    for (int b = 0; b < kBatch; ++b, ++round, cur ^= 1) {
+      hipLaunchKernelGGL(k_mw_eval, dim3(grid), dim3(256), 0, s, M, cur, 0);
+      hipLaunchKernelGGL(k_mw_accept, dim3(grid), dim3(256), 0, s, M, cur, 0, round);
+      hipLaunchKernelGGL(k_mw_push, dim3(grid), dim3(256), 0, s, M, cur, round);
+    }
+    AMG_HIP(hipGetLastError());
   }
-  *rounds = round;
   return AMG_OK;
 }
 
