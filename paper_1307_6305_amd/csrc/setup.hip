@@ -29,32 +29,60 @@ constexpr int TPB = 256;
 inline int nblk(int64_t n, int tpb = TPB) { return (int)std::max<int64_t>(1, (n + tpb - 1) / tpb); }
 
 // ------------------------------------------------------------------ temporaries
+// Setup temporaries come from an arena: a few large device chunks carved
+// into 256-byte aligned pieces, all returned when the arena goes out of
+// scope (hipFree synchronizes the device; one per chunk instead of one per
+// temporary).  release() gives a piece back when it and everything after it
+// in its chunk have been released.
 struct Temps {
-  std::vector<void*> ptrs;
+  struct Piece {
+    size_t off, bytes;
+    bool freed;
+  };
+  struct Chunk {
+    char* base;
+    size_t size, used;
+    std::vector<Piece> pieces;
+  };
+  std::vector<Chunk> chunks;
+  static constexpr size_t kMinChunk = size_t(64) << 20;
   ~Temps() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (auto& c : chunks) (void)hipFree(c.base);
   }
   template <typename T>
   int32_t get(T** p, size_t count) {
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T) + 16);
-    if (e != hipSuccess) {
-      set_last_error(std::string("hipMalloc (setup temporary): ") + hipGetErrorString(e));
-      return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
+    const size_t bytes = (count * sizeof(T) + 16 + 255) & ~size_t(255);
+    Chunk* c = chunks.empty() ? nullptr : &chunks.back();
+    if (!c || c->used + bytes > c->size) {
+      const size_t want = std::max(bytes, chunks.empty() ? kMinChunk : 2 * chunks.back().size);
+      void* q = nullptr;
+      hipError_t e = hipMalloc(&q, want);
+      if (e != hipSuccess) {
+        set_last_error(std::string("hipMalloc (setup temporary): ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
+      }
+      chunks.push_back(Chunk{static_cast<char*>(q), want, 0, {}});
+      c = &chunks.back();
     }
-    ptrs.push_back(q);
-    *p = static_cast<T*>(q);
+    c->pieces.push_back(Piece{c->used, bytes, false});
+    *p = reinterpret_cast<T*>(c->base + c->used);
+    c->used += bytes;
     return AMG_OK;
   }
-  // frees one temporary before the end of the setup
   void release(void* p) {
     if (!p) return;
-    for (auto& q : ptrs)
-      if (q == p) {
-        (void)hipFree(q);
-        q = nullptr;
-        return;
+    for (auto& c : chunks) {
+      char* q = static_cast<char*>(p);
+      if (q < c.base || q >= c.base + c.size) continue;
+      const size_t off = (size_t)(q - c.base);
+      for (auto& pc : c.pieces)
+        if (pc.off == off) pc.freed = true;
+      while (!c.pieces.empty() && c.pieces.back().freed) {
+        c.used = c.pieces.back().off;
+        c.pieces.pop_back();
       }
+      return;
+    }
   }
 };
 
