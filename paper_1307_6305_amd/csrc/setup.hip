@@ -222,18 +222,37 @@ __device__ __forceinline__ bool edge_first(double s1, int a1, int b1, double s2,
   return b1 < b2;
 }
 
-// mate[v]: -1 free, -2 finished single, >= 0 partner.
+// mate[v]: -1 free, -2 finished single, >= 0 partner.  The neighbours are
+// read in chunks of 8 (all column indices and strengths of a chunk, then all
+// their mates) so that the loads of a chunk are in flight together; the best
+// edge is a maximum in a strict order, so the scan order does not matter.
 __device__ __forceinline__ int best_free_neighbour(int v, const int* __restrict__ rp, const int* __restrict__ col,
                                                    const double* __restrict__ S, const int* mate) {
+  constexpr int U = 8;
   int best = -1, ba = 0, bb = 0;
   double bs = 0.0;
-  for (int k = rp[v]; k < rp[v + 1]; ++k) {
-    const int u = col[k];
-    if (mate[u] != -1) continue;
-    const double s = S[k];
-    const int a = u < v ? u : v, b = u < v ? v : u;
-    if (best < 0 || edge_first(s, a, b, bs, ba, bb)) {
-      best = u; bs = s; ba = a; bb = b;
+  const int k0 = rp[v], k1 = rp[v + 1];
+  for (int k = k0; k < k1; k += U) {
+    int u[U], mu[U];
+    double sv[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int kk = min(k + j, k1 - 1);
+      u[j] = col[kk];
+      sv[j] = S[kk];
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) mu[j] = mate[u[j]];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (k + j >= k1 || mu[j] != -1) continue;
+      const int a = u[j] < v ? u[j] : v, b = u[j] < v ? v : u[j];
+      if (best < 0 || edge_first(sv[j], a, b, bs, ba, bb)) {
+        best = u[j];
+        bs = sv[j];
+        ba = a;
+        bb = b;
+      }
     }
   }
   return best;
@@ -304,12 +323,25 @@ __device__ __forceinline__ void mw_accept_one(const MatchState& M, int v, int ro
   list_push(fresh, fsize, leave_u, u);
 }
 
+// neighbours in chunks of 8, as in best_free_neighbour
 __device__ __forceinline__ void mw_push_one(const MatchState& M, int m, int next_round, int* W, int* wsize) {
-  for (int k = M.rp[m]; k < M.rp[m + 1]; ++k) {
-    const int x = M.col[k];
-    const bool take = M.mate[x] == -1 && M.cand[x] == m;
-    if (take) M.stamp[x] = next_round;
-    list_push(W, wsize, take, x);
+  constexpr int U = 8;
+  const int k0 = M.rp[m], k1 = M.rp[m + 1];
+  for (int k = k0; k < k1; k += U) {
+    int x[U], mx[U], cx[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) x[j] = M.col[min(k + j, k1 - 1)];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      mx[j] = M.mate[x[j]];
+      cx[j] = M.cand[x[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const bool take = k + j < k1 && mx[j] == -1 && cx[j] == m;
+      if (take) M.stamp[x[j]] = next_round;
+      list_push(W, wsize, take, x[j]);
+    }
   }
 }
 
