@@ -41,6 +41,7 @@ WORKLOADS = {
     "grid2d-1024-m5": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=5, agg_size=16)),
     "grid2d-1024-m7": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=7, agg_size=16)),
     "grid2d-1024-agg4": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=3, agg_size=4)),
+    "grid2d-1024-hash": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=3, agg_size=16, tie_break=1)),
     "grid2d-64": (lambda: inputs.grid2d(64), "uniform", 1, dict(degree=3, agg_size=4)),
     "tet3d-128": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16)),
     "tet3d-128-mixed": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16, precision=1)),
@@ -495,6 +496,7 @@ def main():
             "setup_ms": round(desc["setup_ms"], 2),
             "setup_ms_cold": round(setup_cold, 2),
             "aggregation_ms": round(desc["aggregation_ms"], 2),
+            "match_rounds": desc["match_rounds"],
             "galerkin_ms": round(desc["galerkin_ms"], 2),
             "grid_complexity": round(desc["grid_complexity"], 4),
             "operator_complexity": round(desc["operator_complexity"], 4),

@@ -51,6 +51,7 @@ typedef enum {
 
 enum { AMG_FP64 = 0, AMG_MIXED = 1 };
 enum { AMG_KEY_NORMALIZED = 0, AMG_KEY_RAW = 1 };
+enum { AMG_TIE_INDEX = 0, AMG_TIE_HASH = 1 };
 
 #define AMG_MAX_LEVELS 32
 
@@ -89,6 +90,12 @@ enum { AMG_KEY_NORMALIZED = 0, AMG_KEY_RAW = 1 };
  *   lanes_per_row lanes that share one row's entries: 1, 2 or 4 (autotune = 0).
  *   sort_rows     1: rows ordered by decreasing length inside each group of 64
  *                 rows, which cuts padding on uneven degrees (autotune = 0).
+ *   tie_break     order of edges of equal strength in the matching:
+ *                 AMG_TIE_INDEX: by the vertex indices (i, j) (default);
+ *                 AMG_TIE_HASH: by h(i, j), then (i, j), where h is MurmurHash3's
+ *                 32-bit finalizer of (i * 2654435761 + j) mod 2^32 -- on
+ *                 structured meshes this breaks the long index chains, so the
+ *                 handshake needs far fewer rounds (a different hierarchy).
  */
 typedef struct {
   int32_t degree;
@@ -109,6 +116,7 @@ typedef struct {
   int32_t slice_height;
   int32_t lanes_per_row;
   int32_t sort_rows;
+  int32_t tie_break;
 } amg_params;
 
 typedef struct amg_hier amg_hier;
@@ -149,7 +157,7 @@ typedef struct {
  * lambda0_ratio 10, inner_steps 2, restart 5, tol 1e-8, max_iter 200, FP64,
  * normalized key, max_coarsest 2048, stagnation 0.9, use_graph 1,
  * tail_rows 4096, autotune 1 (fixed layout: slice_height 64, lanes_per_row 1,
- * sort_rows 0). */
+ * sort_rows 0), index tie-breaking. */
 void amg_params_default(amg_params* p);
 
 /* Human-readable name of a status code (static string). */

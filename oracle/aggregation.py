@@ -17,10 +17,13 @@ built here use matching passes instead):
   correctly rounded division -- no square root, no fused multiply-add.  ``raw``:
   s_ij = W_ij.
 * Tie-breaking.  Edges (i < j) are totally ordered by the key (-s_ij, i, j),
-  ascending; the matching is the greedy one that scans edges in that order and
-  takes an edge when both endpoints are still free.  This is the matching that
-  every locally-dominant (handshake) algorithm produces under the same strict
-  order, so it does not depend on how the work is scheduled.
+  ascending ("index" ties, the default); the matching is the greedy one that
+  scans edges in that order and takes an edge when both endpoints are still
+  free.  This is the matching that every locally-dominant (handshake) algorithm
+  produces under the same strict order, so it does not depend on how the work
+  is scheduled.  "hash" ties order equal strengths by a fixed hash of the
+  endpoints first, key (-s_ij, h(i, j), i, j) with h = the 32-bit finalizer of
+  MurmurHash3 applied to (i * 2654435761 + j) mod 2^32 (see ``tie_hash``).
 * Unmatched vertices stay singleton aggregates.
 * Coarse numbering: rep(i) = min(i, mate(i)) (i itself if unmatched); coarse ids
   are assigned in increasing order of rep, i.e. by smallest member.
@@ -53,10 +56,30 @@ def edge_strengths(lvl: Level, key: str = "normalized"):
     return i, j, s
 
 
-def greedy_matching(lvl: Level, key: str = "normalized") -> np.ndarray:
-    """Greedy matching in the strict edge order (-s, i, j): mate[i] = j, or -1."""
+def tie_hash(i: np.ndarray, j: np.ndarray) -> np.ndarray:
+    """h(i, j): x = (i * 2654435761 + j) mod 2^32, then MurmurHash3's 32-bit
+    finalizer (x ^= x >> 16; x *= 0x85ebca6b; x ^= x >> 13; x *= 0xc2b2ae35;
+    x ^= x >> 16, all mod 2^32)."""
+    m = np.uint64(0xFFFFFFFF)
+    x = (i.astype(np.uint64) * np.uint64(2654435761) + j.astype(np.uint64)) & m
+    x ^= x >> np.uint64(16)
+    x = (x * np.uint64(0x85EBCA6B)) & m
+    x ^= x >> np.uint64(13)
+    x = (x * np.uint64(0xC2B2AE35)) & m
+    x ^= x >> np.uint64(16)
+    return x
+
+
+def greedy_matching(lvl: Level, key: str = "normalized", tie: str = "index") -> np.ndarray:
+    """Greedy matching in the strict edge order (-s, i, j) -- or (-s, h(i, j), i,
+    j) with hash ties: mate[i] = j, or -1."""
     i, j, s = edge_strengths(lvl, key)
-    order = np.lexsort((j, i, -s))
+    if tie == "index":
+        order = np.lexsort((j, i, -s))
+    elif tie == "hash":
+        order = np.lexsort((j, i, tie_hash(i, j), -s))
+    else:
+        raise ValueError(tie)
     mate = [-1] * lvl.n
     for a, b in zip(i[order].tolist(), j[order].tolist()):
         if mate[a] < 0 and mate[b] < 0:
@@ -115,12 +138,12 @@ def quotient(lvl: Level, ids: np.ndarray, nc: int) -> Level:
     return assemble(nc, row_ptr, JH, WH, dH)
 
 
-def aggregate_level(lvl: Level, passes: int, key: str = "normalized"):
+def aggregate_level(lvl: Level, passes: int, key: str = "normalized", tie: str = "index"):
     """``passes`` matching passes; returns (composite aggregate map, coarse level)."""
     agg = np.arange(lvl.n, dtype=np.int64)
     g = lvl
     for _ in range(passes):
-        mate = greedy_matching(g, key)
+        mate = greedy_matching(g, key, tie)
         ids, nc = coarse_ids(mate)
         g = quotient(g, ids, nc)
         agg = ids[agg]

@@ -60,6 +60,7 @@ class Params:
     tol: float = 1e-8
     max_iter: int = 200
     match_key: str = "normalized"
+    tie_break: str = "index"
     max_coarsest: int = 2048
     stagnation: float = 0.9
 
@@ -101,7 +102,7 @@ def build_hierarchy(n, row_ptr, col, w, d, params: Params | None = None) -> Hier
     aggs = []
     while levels[-1].n > p.coarse_max:
         cur = levels[-1]
-        agg, coarse = aggregate_level(cur, p.passes, p.match_key)
+        agg, coarse = aggregate_level(cur, p.passes, p.match_key, p.tie_break)
         if coarse.n > p.stagnation * cur.n:
             break
         aggs.append(agg)

@@ -39,6 +39,8 @@ AMG_FP64 = 0
 AMG_MIXED = 1
 AMG_KEY_NORMALIZED = 0
 AMG_KEY_RAW = 1
+AMG_TIE_INDEX = 0
+AMG_TIE_HASH = 1
 AMG_MAX_LEVELS = 32
 
 
@@ -62,6 +64,7 @@ class amg_params(ctypes.Structure):
         ("slice_height", ctypes.c_int32),
         ("lanes_per_row", ctypes.c_int32),
         ("sort_rows", ctypes.c_int32),
+        ("tie_break", ctypes.c_int32),
     ]
 
 
@@ -253,6 +256,8 @@ def amg_params_default(**overrides) -> amg_params:
             v = {"fp64": AMG_FP64, "mixed": AMG_MIXED}[v]
         if k == "match_key" and isinstance(v, str):
             v = {"normalized": AMG_KEY_NORMALIZED, "raw": AMG_KEY_RAW}[v]
+        if k == "tie_break" and isinstance(v, str):
+            v = {"index": AMG_TIE_INDEX, "hash": AMG_TIE_HASH}[v]
         setattr(p, k, v)
     return p
 

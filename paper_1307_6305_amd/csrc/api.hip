@@ -123,6 +123,7 @@ void amg_params_default(amg_params* p) {
   p->slice_height = 64;
   p->lanes_per_row = 1;
   p->sort_rows = 0;
+  p->tie_break = AMG_TIE_INDEX;
 }
 
 const char* amg_strerror(int32_t s) {

@@ -214,10 +214,26 @@ __global__ void k_strength(int n, const int* __restrict__ rp, const int* __restr
   }
 }
 
-// Edge order: (-s, min endpoint, max endpoint) ascending.  True if edge 1
-// comes first.
-__device__ __forceinline__ bool edge_first(double s1, int a1, int b1, double s2, int a2, int b2) {
+// Hash of an edge for hash tie-breaking: MurmurHash3's 32-bit finalizer of
+// (a * 2654435761 + b) mod 2^32.
+__device__ __forceinline__ uint32_t tie_hash(uint32_t a, uint32_t b) {
+  uint32_t x = a * 2654435761u + b;
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+
+// Edge order: (-s, [hash,] min endpoint, max endpoint) ascending.  True if
+// edge 1 comes first.
+__device__ __forceinline__ bool edge_first(double s1, int a1, int b1, double s2, int a2, int b2, bool hashed) {
   if (s1 != s2) return s1 > s2;
+  if (hashed) {
+    const uint32_t h1 = tie_hash((uint32_t)a1, (uint32_t)b1), h2 = tie_hash((uint32_t)a2, (uint32_t)b2);
+    if (h1 != h2) return h1 < h2;
+  }
   if (a1 != a2) return a1 < a2;
   return b1 < b2;
 }
@@ -227,7 +243,7 @@ __device__ __forceinline__ bool edge_first(double s1, int a1, int b1, double s2,
 // their mates) so that the loads of a chunk are in flight together; the best
 // edge is a maximum in a strict order, so the scan order does not matter.
 __device__ __forceinline__ int best_free_neighbour(int v, const int* __restrict__ rp, const int* __restrict__ col,
-                                                   const double* __restrict__ S, const int* mate) {
+                                                   const double* __restrict__ S, const int* mate, bool hashed) {
   constexpr int U = 8;
   int best = -1, ba = 0, bb = 0;
   double bs = 0.0;
@@ -247,7 +263,7 @@ __device__ __forceinline__ int best_free_neighbour(int v, const int* __restrict_
     for (int j = 0; j < U; ++j) {
       if (k + j >= k1 || mu[j] != -1) continue;
       const int a = u[j] < v ? u[j] : v, b = u[j] < v ? v : u[j];
-      if (best < 0 || edge_first(sv[j], a, b, bs, ba, bb)) {
+      if (best < 0 || edge_first(sv[j], a, b, bs, ba, bb, hashed)) {
         best = u[j];
         bs = sv[j];
         ba = a;
@@ -296,10 +312,11 @@ struct MatchState {
   int* W[2];    // the round's list and the next one
   int* fresh;   // vertices that left the free set this round
   int* size;    // size[0], size[1]: |W[0]|, |W[1]|; size[2]: |fresh|; size[3]: rounds with work
+  int hashed;   // hash tie-breaking
 };
 
 __device__ __forceinline__ void mw_eval_one(const MatchState& M, int v) {
-  const int b = best_free_neighbour(v, M.rp, M.col, M.S, M.mate);
+  const int b = best_free_neighbour(v, M.rp, M.col, M.S, M.mate, M.hashed != 0);
   M.cand[v] = b >= 0 ? b : -2;
 }
 
@@ -709,7 +726,7 @@ struct Graph {  // a pass graph on the device (not owned)
 };
 
 // One matching pass on g: mate[] (device) and the number of rounds.
-int32_t match_pass(Temps& T, const Graph& g, int raw, int* mate, int* rounds, hipStream_t s) {
+int32_t match_pass(Temps& T, const Graph& g, int raw, int hashed, int* mate, int* rounds, hipStream_t s) {
   double* S = nullptr;
   int *cand = nullptr, *stamp = nullptr, *w0 = nullptr, *w1 = nullptr, *fresh = nullptr, *size = nullptr,
       *io = nullptr;
@@ -726,7 +743,7 @@ int32_t match_pass(Temps& T, const Graph& g, int raw, int* mate, int* rounds, hi
   hipLaunchKernelGGL(k_fill<int>, dim3(nblk(g.n)), dim3(TPB), 0, s, (size_t)g.n, stamp, 0);
   hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (size_t)4, size, 0);
   AMG_HIP(hipGetLastError());
-  const MatchState M{g.rp, g.col, S, mate, cand, stamp, {w0, w1}, fresh, size};
+  const MatchState M{g.rp, g.col, S, mate, cand, stamp, {w0, w1}, fresh, size, hashed};
   // lists up to this long run in one workgroup; multi-block rounds otherwise
   constexpr int kSmallList = 4096, kBatch = 8, kSmallRounds = 4096;
   const int grid = std::min(nblk(g.n), 2048);
@@ -1132,7 +1149,7 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
       int* mate = nullptr;
       AMG_TRY(TL.get(&mate, g.n));
       int rounds = 0;
-      AMG_TRY(match_pass(TL, g, raw, mate, &rounds, s));
+      AMG_TRY(match_pass(TL, g, raw, p.tie_break == AMG_TIE_HASH, mate, &rounds, s));
       total_rounds += rounds;
       t_agg += ms_since(ta);
       Graph c;

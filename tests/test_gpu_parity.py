@@ -30,6 +30,7 @@ def _oracle_params(p):
                          lambda0_ratio=p.lambda0_ratio, inner_steps=p.inner_steps, restart=p.restart,
                          tol=p.tol, max_iter=p.max_iter,
                          match_key="raw" if p.match_key == 1 else "normalized",
+                         tie_break="hash" if p.tie_break == 1 else "index",
                          max_coarsest=p.max_coarsest, stagnation=p.stagnation)
 
 
@@ -42,6 +43,9 @@ CASES = {
     "random_weighted_agg4": (lambda: inputs.random_graph(700, 0.006, seed=5, weighted=True),
                              dict(degree=4, agg_size=4, coarse_max=40)),
     "grid130_agg4_m7_inner3": (lambda: inputs.grid2d(130), dict(degree=7, agg_size=4, inner_steps=3, restart=3)),
+    "grid120_hash_agg16": (lambda: inputs.grid2d(120), dict(degree=3, agg_size=16, tie_break=1)),
+    "rgg_6000_hash_raw_agg8": (lambda: inputs.rgg(6000, seed=inputs.seed_for(4, 2)),
+                               dict(degree=4, agg_size=8, tie_break=1, match_key=1)),
 }
 
 _cache = {}
@@ -273,3 +277,19 @@ def test_mixed_precision_solve(amg, make, kw):
     e = u.cpu().numpy() - res.x
     errA = np.sqrt(e @ oracle.apply_A(lo, e)) / np.sqrt(res.x @ oracle.apply_A(lo, res.x))
     assert errA <= 1e-6
+
+
+def test_hash_ties_fewer_rounds(amg):
+    # index ties chain along a structured grid; hashed ties break the chains
+    g = inputs.grid2d(256)
+    rounds = {}
+    for tie in ("index", "hash"):
+        p = amg.amg_params_default(degree=3, agg_size=16, tie_break=tie)
+        h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+        rounds[tie] = amg.amg_describe(h)["match_rounds"]
+        f = _t(inputs.rhs(g.n, 3))
+        u = torch.zeros_like(f)
+        info = amg.amg_solve(h, f, u)
+        assert info["status"] == 0 and info["rel_res_true"] <= 1.05e-8
+        h.close()
+    assert rounds["hash"] * 4 < rounds["index"], rounds

@@ -13,14 +13,27 @@ import oracle
 from oracle.aggregation import edge_strengths
 
 
-def handshake_matching(lvl, key):
+def murmur_fmix32(a, b):
+    """Written here from MurmurHash3's published 32-bit finalizer, on
+    x = a * 2654435761 + b (mod 2^32), independently of the oracle's numpy
+    version."""
+    x = (a * 2654435761 + b) % (1 << 32)
+    x ^= x >> 16
+    x = (x * 0x85EBCA6B) % (1 << 32)
+    x ^= x >> 13
+    x = (x * 0xC2B2AE35) % (1 << 32)
+    x ^= x >> 16
+    return x
+
+
+def handshake_matching(lvl, key, tie="index"):
     """Rounds of: every free vertex points at its best free neighbour; mutual
     pointers become matched.  Stops when no free vertex has a free neighbour."""
     n = lvl.n
     i, j, s = edge_strengths(lvl, key)
     nbrs = [[] for _ in range(n)]
     for a, b, sv in zip(i.tolist(), j.tolist(), s.tolist()):
-        k = (-sv, a, b)
+        k = (-sv, a, b) if tie == "index" else (-sv, murmur_fmix32(a, b), a, b)
         nbrs[a].append((k, b))
         nbrs[b].append((k, a))
     mate = [-1] * n
@@ -65,7 +78,58 @@ def test_greedy_equals_handshake_on_grid_ties():
     for g in (inputs.grid2d(11, 8), inputs.tet3d(4)):
         lvl = _level(g)
         for key in ("normalized", "raw"):
-            assert np.array_equal(oracle.greedy_matching(lvl, key), handshake_matching(lvl, key))
+            for tie in ("index", "hash"):
+                assert np.array_equal(oracle.greedy_matching(lvl, key, tie), handshake_matching(lvl, key, tie))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_greedy_equals_handshake_hash_ties(seed):
+    g = inputs.random_graph(25 + seed, 0.1, seed=100 + seed, weighted=False)  # unit weights: many ties
+    lvl = _level(g)
+    for key in ("normalized", "raw"):
+        assert np.array_equal(oracle.greedy_matching(lvl, key, "hash"), handshake_matching(lvl, key, "hash"))
+
+
+def test_tie_hash_known_values_and_spread():
+    # fmix32 maps 0 to 0 and is a bijection on 32-bit words; on the edges of a grid
+    # the hashes are (almost) all distinct, which is what breaks the index chains
+    from oracle.aggregation import tie_hash
+    assert int(tie_hash(np.array([0]), np.array([0]))[0]) == 0
+    i = np.arange(0, 5000)
+    j = i + 1
+    h = tie_hash(i, j)
+    assert [int(x) for x in h[:64]] == [murmur_fmix32(int(a), int(b)) for a, b in zip(i[:64], j[:64])]
+    assert len(np.unique(h)) == len(h)
+
+
+def test_hash_ties_need_fewer_rounds_on_grids():
+    # index ties chain along the grid (rounds grow with the side); hashed ties do not
+    def rounds(lvl, tie):
+        n = lvl.n
+        i, j, s = edge_strengths(lvl, "normalized")
+        keys = {}
+        nbrs = [[] for _ in range(n)]
+        for a, b, sv in zip(i.tolist(), j.tolist(), s.tolist()):
+            k = (-sv, a, b) if tie == "index" else (-sv, murmur_fmix32(a, b), a, b)
+            nbrs[a].append((k, b))
+            nbrs[b].append((k, a))
+        free = [True] * n
+        r = 0
+        while True:
+            r += 1
+            cand = {}
+            for v in range(n):
+                if free[v]:
+                    opts = [(k, u) for k, u in nbrs[v] if free[u]]
+                    if opts:
+                        cand[v] = min(opts)[1]
+            pairs = [(v, u) for v, u in cand.items() if cand.get(u) == v and v < u]
+            if not pairs:
+                return r
+            for v, u in pairs:
+                free[v] = free[u] = False
+    lvl = _level(inputs.grid2d(40))
+    assert rounds(lvl, "hash") * 3 < rounds(lvl, "index")
 
 
 @pytest.mark.parametrize("seed", range(10))
