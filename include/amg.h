@@ -312,6 +312,30 @@ void amg_serve_cfg_default(amg_serve_cfg* cfg);
 int32_t amg_serve(const amg_serve_cfg* cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
                   amg_serve_stats* stats, void* stream);
 
+/* ---- Incremental server ------------------------------------------------------
+ * The server behind amg_serve, for callers that receive requests one by one.
+ * amg_server_create starts a server thread (continuous batching or the
+ * sequential mode of cfg; cfg->realtime is not used: a request arrives when it
+ * is submitted) that solves on `stream` and sets hierarchies up on a stream of
+ * its own.  amg_server_submit copies the request's right-hand sides and graph
+ * data (when given), stamps its arrival time (seconds since create) and
+ * returns its ticket (0, 1, 2, ... in submission order); the solution of
+ * right-hand side k goes to req->u + k n (host), which must stay valid until
+ * that completion has been polled (or the server destroyed).
+ * amg_server_poll moves up to `max` finished completions (oldest first;
+ * `request` = ticket) into out and sets *count; with wait_s > 0 it waits up to
+ * that long for the first one.  It returns the server thread's status (a
+ * device error stops the server).  amg_server_destroy waits until every
+ * submitted request has completed, stops the threads, frees the device memory
+ * and reports stats (may be NULL); completions not yet polled are dropped.
+ * Calls on one server may come from different threads. */
+typedef struct amg_server amg_server;
+
+int32_t amg_server_create(const amg_serve_cfg* cfg, void* stream, amg_server** out);
+int32_t amg_server_submit(amg_server* srv, const amg_request* req, int32_t* ticket);
+int32_t amg_server_poll(amg_server* srv, amg_completion* out, int32_t max, double wait_s, int32_t* count);
+int32_t amg_server_destroy(amg_server* srv, amg_serve_stats* stats);
+
 /* ---- Level inspection and single steps (tests and diagnostics) ------------
  * The single steps below (all but amg_apply_cycle) need an AMG_FP64
  * hierarchy (AMG_ERR_ARG otherwise); each synchronizes `stream` before it

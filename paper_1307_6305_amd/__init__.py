@@ -189,6 +189,10 @@ SIGNATURES = {
     "amg_serve_cfg_default": (None, [ctypes.POINTER(amg_serve_cfg)]),
     "amg_serve": (_I32, [ctypes.POINTER(amg_serve_cfg), ctypes.POINTER(amg_request), _I32,
                          ctypes.POINTER(amg_completion), ctypes.POINTER(amg_serve_stats), _P]),
+    "amg_server_create": (_I32, [ctypes.POINTER(amg_serve_cfg), _P, ctypes.POINTER(_P)]),
+    "amg_server_submit": (_I32, [_P, ctypes.POINTER(amg_request), ctypes.POINTER(_I32)]),
+    "amg_server_poll": (_I32, [_P, ctypes.POINTER(amg_completion), _I32, ctypes.c_double, ctypes.POINTER(_I32)]),
+    "amg_server_destroy": (_I32, [_P, ctypes.POINTER(amg_serve_stats)]),
     "amg_time_step": (_I32, [_P, _I32, _P, ctypes.POINTER(amg_kernel_timing)]),
     "amg_level_export": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P]),
     "amg_apply_smoother": (_I32, [_P, _I32, _P, _P, _P]),
@@ -368,6 +372,98 @@ def amg_serve_cfg_default(params: amg_params | None = None, **overrides) -> amg_
     return c
 
 
+def _completion_dict(c) -> dict:
+    return {"request": c.request, "rhs": c.rhs, "status": c.status, "iters": c.iters,
+            "rel_res_true": c.rel_res_true, "arrival_s": c.arrival_s, "admit_s": c.admit_s,
+            "finish_s": c.finish_s}
+
+
+def _stats_dict(stats) -> dict:
+    return {"wall_s": stats.wall_s, "peak_bytes": stats.peak_bytes, "evictions": stats.evictions,
+            "setups": stats.setups, "steps": stats.steps}
+
+
+class Server:
+    """Incremental server (amg_server_create/submit/poll/destroy): requests
+    are submitted one at a time while earlier ones are being solved.  The
+    solution buffers of a request are kept here until all of its completions
+    have been polled."""
+
+    def __init__(self, cfg: amg_serve_cfg, stream=None):
+        self._lib = load_library()
+        self._cfg = cfg
+        hnd = _P()
+        _check(self._lib.amg_server_create(ctypes.byref(cfg), _stream(stream), ctypes.byref(hnd)),
+               "amg_server_create")
+        self.handle = hnd
+        self._pending = {}  # ticket -> [solution array, completions still to come]
+        self._polled = 0
+
+    def submit(self, graph_id: int, f, graph=None, n: int | None = None) -> int:
+        """Submit right-hand sides f ((nrhs, n) or (n,)) for graph ``graph_id``;
+        ``graph`` (n, row_ptr, col, w, d) is needed unless that graph is
+        resident.  Returns the ticket."""
+        f = np.ascontiguousarray(np.atleast_2d(np.asarray(f, dtype=np.float64)))
+        nn = graph.n if graph is not None else int(n if n is not None else f.shape[1])
+        if f.shape[1] != nn:
+            raise ValueError(f"f has {f.shape[1]} columns, graph has {nn} vertices")
+        r = amg_request()
+        r.graph_id = int(graph_id)
+        r.n = nn
+        keep = []
+        if graph is not None:
+            rp = np.ascontiguousarray(graph.row_ptr, dtype=np.int32)
+            cl = np.ascontiguousarray(graph.col, dtype=np.int32)
+            wv = np.ascontiguousarray(graph.w, dtype=np.float64)
+            dv = np.ascontiguousarray(graph.d, dtype=np.float64)
+            keep += [rp, cl, wv, dv]
+            r.row_ptr, r.col, r.w, r.d = (a.ctypes.data for a in (rp, cl, wv, dv))
+        r.nrhs = f.shape[0]
+        r.f = f.ctypes.data
+        u = np.zeros_like(f)
+        r.u = u.ctypes.data
+        ticket = _I32(-1)
+        _check(self._lib.amg_server_submit(self.handle, ctypes.byref(r), ctypes.byref(ticket)), "amg_server_submit")
+        self._pending[ticket.value] = [u, f.shape[0]]
+        return ticket.value
+
+    def poll(self, max_count: int = 64, wait_s: float = 0.0):
+        """Finished completions (oldest first), each a dict with the ticket
+        in "request" and the solution row in "u"."""
+        out = (amg_completion * max_count)()
+        cnt = _I32(0)
+        code = self._lib.amg_server_poll(self.handle, out, max_count, float(wait_s), ctypes.byref(cnt))
+        res = []
+        for c in out[:cnt.value]:
+            d = _completion_dict(c)
+            ent = self._pending[c.request]
+            d["u"] = ent[0][c.rhs]
+            ent[1] -= 1
+            if ent[1] == 0:
+                del self._pending[c.request]
+            res.append(d)
+        _check(code, "amg_server_poll")
+        return res
+
+    def close(self) -> dict:
+        """Finish every submitted request, stop the server, return its stats."""
+        if self.handle is None:
+            return {}
+        stats = amg_serve_stats()
+        code = self._lib.amg_server_destroy(self.handle, ctypes.byref(stats))
+        self.handle = None
+        self._pending.clear()
+        _check(code, "amg_server_destroy")
+        return _stats_dict(stats)
+
+    def __del__(self):
+        try:
+            if self.handle is not None:
+                self._lib.amg_server_destroy(self.handle, None)
+        except Exception:
+            pass
+
+
 def amg_serve(cfg: amg_serve_cfg, requests: list, stream=None, want_u: bool = True):
     """Replay a request stream.  Each request is a dict with keys arrival_s,
     graph_id, graph (an object with n, row_ptr, col, w, d; may be None when the
@@ -410,12 +506,7 @@ def amg_serve(cfg: amg_serve_cfg, requests: list, stream=None, want_u: bool = Tr
     code = load_library().amg_serve(ctypes.byref(cfg), reqs, len(requests), out, ctypes.byref(stats),
                                     _stream(stream))
     _check(code, "amg_serve")
-    comps = [{"request": c.request, "rhs": c.rhs, "status": c.status, "iters": c.iters,
-              "rel_res_true": c.rel_res_true, "arrival_s": c.arrival_s, "admit_s": c.admit_s,
-              "finish_s": c.finish_s} for c in out]
-    st = {"wall_s": stats.wall_s, "peak_bytes": stats.peak_bytes, "evictions": stats.evictions,
-          "setups": stats.setups, "steps": stats.steps}
-    return comps, st, sols
+    return [_completion_dict(c) for c in out], _stats_dict(stats), sols
 
 
 def amg_time_step(h: Hierarchy, reps: int = 200, stream=None) -> dict:

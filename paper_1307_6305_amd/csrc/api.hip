@@ -215,9 +215,10 @@ void amg_serve_cfg_default(amg_serve_cfg* c) {
   c->realtime = 1;
 }
 
-int32_t amg_serve(const amg_serve_cfg* cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
-                  amg_serve_stats* stats, void* stream) {
-  if (!cfg || !reqs || nreq < 1 || !out) { amg::set_last_error("invalid argument"); return AMG_ERR_ARG; }
+namespace {
+
+int32_t check_serve_cfg(const amg_serve_cfg* cfg) {
+  if (!cfg) { amg::set_last_error("null configuration"); return AMG_ERR_ARG; }
   if (cfg->mode != AMG_SERVE_BATCHED && cfg->mode != AMG_SERVE_SEQUENTIAL) {
     amg::set_last_error("unknown serve mode");
     return AMG_ERR_ARG;
@@ -232,15 +233,57 @@ int32_t amg_serve(const amg_serve_cfg* cfg, const amg_request* reqs, int32_t nre
     amg::set_last_error(msg);
     return pst;
   }
-  for (int32_t i = 0; i < nreq; ++i) {
-    const amg_request& q = reqs[i];
-    if (q.n < 1 || q.nrhs < 1 || !q.f) {
-      amg::set_last_error("request " + std::to_string(i) + ": n, nrhs and f are required");
-      return AMG_ERR_ARG;
-    }
+  return AMG_OK;
+}
+
+int32_t check_request(const amg_request& q, int32_t i) {
+  if (q.n < 1 || q.nrhs < 1 || !q.f) {
+    amg::set_last_error("request " + std::to_string(i) + ": n, nrhs and f are required");
+    return AMG_ERR_ARG;
   }
+  if (q.row_ptr && (!q.col || !q.w || !q.d)) {
+    amg::set_last_error("request " + std::to_string(i) + ": graph data needs row_ptr, col, w and d");
+    return AMG_ERR_ARG;
+  }
+  return AMG_OK;
+}
+
+}  // namespace
+
+int32_t amg_serve(const amg_serve_cfg* cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
+                  amg_serve_stats* stats, void* stream) {
+  if (!reqs || nreq < 1 || !out) { amg::set_last_error("invalid argument"); return AMG_ERR_ARG; }
+  AMG_TRY(check_serve_cfg(cfg));
+  for (int32_t i = 0; i < nreq; ++i) AMG_TRY(check_request(reqs[i], i));
   AMG_TRY(check_device());
   return amg::serve(*cfg, reqs, nreq, out, stats, static_cast<hipStream_t>(stream));
+}
+
+int32_t amg_server_create(const amg_serve_cfg* cfg, void* stream, amg_server** out) {
+  if (!out) { amg::set_last_error("null output handle"); return AMG_ERR_ARG; }
+  *out = nullptr;
+  AMG_TRY(check_serve_cfg(cfg));
+  AMG_TRY(check_device());
+  void* p = nullptr;
+  AMG_TRY(amg::server_create(*cfg, static_cast<hipStream_t>(stream), &p));
+  *out = static_cast<amg_server*>(p);
+  return AMG_OK;
+}
+
+int32_t amg_server_submit(amg_server* srv, const amg_request* req, int32_t* ticket) {
+  if (!srv || !req) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
+  AMG_TRY(check_request(*req, 0));
+  return amg::server_submit(srv, *req, ticket);
+}
+
+int32_t amg_server_poll(amg_server* srv, amg_completion* out, int32_t max, double wait_s, int32_t* count) {
+  if (!srv || !out || max < 1 || !count) { amg::set_last_error("invalid argument"); return AMG_ERR_ARG; }
+  return amg::server_poll(srv, out, max, wait_s, count);
+}
+
+int32_t amg_server_destroy(amg_server* srv, amg_serve_stats* stats) {
+  if (!srv) return AMG_OK;
+  return amg::server_destroy(srv, stats);
 }
 
 int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing* timing) {

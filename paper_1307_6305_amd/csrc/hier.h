@@ -115,6 +115,10 @@ void free_clone(amg_hier* c);
 // serving (serve.hip)
 int32_t serve(const amg_serve_cfg& cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
               amg_serve_stats* stats, hipStream_t s);
+int32_t server_create(const amg_serve_cfg& cfg, hipStream_t s, void** out);
+int32_t server_submit(void* srv, const amg_request& q, int32_t* ticket);
+int32_t server_poll(void* srv, amg_completion* out, int32_t max, double wait_s, int32_t* count);
+int32_t server_destroy(void* srv, amg_serve_stats* stats);
 int32_t time_step(amg_hier* h, int reps, hipStream_t s, amg_kernel_timing* t);
 
 }  // namespace amg

@@ -1,6 +1,9 @@
-// Serving: replay of an open-loop request stream with continuous batching.
+// Serving with continuous batching: an incremental server (create, submit
+// requests as they come, poll completions, destroy) and, built on it, the
+// replay of an open-loop request stream.
 //
-// Requests arrive at given times.  A request names a graph (by the caller's
+// A server thread runs the loop below over the requests submitted so far, in
+// submission order.  A request names a graph (by the caller's
 // id; its data is set up once and the hierarchy stays resident) and carries
 // one or more right-hand sides.  The batched mode keeps a set of in-flight
 // right-hand sides ("slots"): between rounds of outer iterations it admits
@@ -20,6 +23,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -46,8 +50,11 @@ struct Resident {
   int32_t status = AMG_OK;
 };
 
+struct Req;
+
 struct Slot {
-  int req = -1, rhs = -1;
+  Req* rq = nullptr;
+  int rhs = -1;
   Resident* res = nullptr;
   amg_hier* ws = nullptr;  // hierarchy or clone whose workspace it uses
   bool own_ws = false;     // ws is the resident hierarchy itself
@@ -59,24 +66,38 @@ struct Slot {
 
 size_t hier_bytes(const amg_hier* h) { return h->bytes; }
 
+// One submitted request: the caller's record, with the right-hand sides and
+// (when given) the graph copied in; u stays the caller's.
+struct Req {
+  amg_request q;
+  int ticket = 0;
+  std::vector<double> f;
+  std::vector<int32_t> rp, col;
+  std::vector<double> w, d;
+};
+
 struct Server {
   amg_serve_cfg cfg;
-  const amg_request* reqs;
-  int nreq;
-  amg_completion* out;
-  std::vector<int> out_base;  // first completion record of each request
   hipStream_t s = nullptr;       // solve stream
   hipStream_t s_setup = nullptr; // setup stream
+  int device = 0;
   clk::time_point t0;
   size_t bytes = 0, peak = 0;
   int evictions = 0, setups = 0, steps = 0;
 
   std::map<int, Resident*> resident;
-  std::mutex mu;                    // guards `resident` entries' setup fields and the setup queue
-  std::condition_variable cv;
-  std::deque<int> setup_queue;      // request indices whose graph needs a setup
+  std::mutex mu;                    // guards the request list, outbox, `resident` setup fields, setup queue
+  std::condition_variable cv;       // new request, setup done, closing
+  std::condition_variable cv_out;   // new completions
+  std::deque<std::unique_ptr<Req>> reqs;  // submitted requests (elements never move)
+  bool closing = false;             // no more submissions: finish and stop
+  std::deque<amg_completion> outbox;
+  int outstanding = 0;              // right-hand sides submitted and not yet completed
+  std::deque<Req*> setup_queue;     // requests whose graph needs a setup
   std::map<int, size_t> setup_pending;  // graph id -> bytes reserved while queued or running
   bool stop_worker = false;
+  std::thread loop_thread;
+  int32_t loop_status = AMG_OK;
 
   double now() const { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
@@ -84,17 +105,17 @@ struct Server {
 
   // ---------------------------------------------------------------- setup thread
   void worker() {
-    (void)hipSetDevice(0);
+    (void)hipSetDevice(device);
     for (;;) {
-      int r;
+      Req* rq;
       {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait(lk, [&] { return stop_worker || !setup_queue.empty(); });
         if (stop_worker && setup_queue.empty()) return;
-        r = setup_queue.front();
+        rq = setup_queue.front();
         setup_queue.pop_front();
       }
-      const amg_request& q = reqs[r];
+      const amg_request& q = rq->q;
       amg_hier* h = nullptr;
       const int32_t st = amg_setup(q.n, q.row_ptr, q.col, q.w, q.d, &cfg.params, s_setup, &h);
       std::lock_guard<std::mutex> lk(mu);
@@ -174,31 +195,47 @@ struct Server {
     return true;
   }
 
+  // Records a finished right-hand side in the outbox.  Caller holds mu.
   void complete(const Slot& sl, int32_t status, int iters, double rel_true) {
-    amg_completion& c = out[out_base[sl.req] + sl.rhs];
-    c.request = sl.req;
+    amg_completion c;
+    c.request = sl.rq->ticket;
     c.rhs = sl.rhs;
     c.status = status;
     c.iters = iters;
     c.rel_res_true = rel_true;
-    c.arrival_s = reqs[sl.req].arrival_s;
+    c.arrival_s = sl.rq->q.arrival_s;
     c.admit_s = sl.admit_s;
     c.finish_s = now();
+    outbox.push_back(c);
+    --outstanding;
+    cv_out.notify_all();
   }
 
-  void fail_request(int r, int32_t status) {
+  // Caller holds mu.
+  void fail_request(Req* rq, int32_t status, int first_rhs = 0) {
     const double t = now();
-    for (int k = 0; k < reqs[r].nrhs; ++k) {
-      amg_completion& c = out[out_base[r] + k];
-      c.request = r;
+    for (int k = first_rhs; k < rq->q.nrhs; ++k) {
+      amg_completion c;
+      c.request = rq->ticket;
       c.rhs = k;
       c.status = status;
       c.iters = 0;
       c.rel_res_true = 0.0;
-      c.arrival_s = reqs[r].arrival_s;
+      c.arrival_s = rq->q.arrival_s;
       c.admit_s = t;
       c.finish_s = t;
+      outbox.push_back(c);
+      --outstanding;
     }
+    cv_out.notify_all();
+  }
+
+  // The request at position i of the submission order, or null if not (yet)
+  // submitted; `done` tells whether nothing more will come.
+  Req* request_at(size_t i, bool* done) {
+    std::lock_guard<std::mutex> lk(mu);
+    *done = closing && i >= reqs.size();
+    return i < reqs.size() ? reqs[i].get() : nullptr;
   }
 
   // ---------------------------------------------------------------- batched mode
@@ -217,11 +254,7 @@ struct Server {
       }
     } joiner{this, &th};
 
-    std::vector<int> order(nreq);
-    for (int i = 0; i < nreq; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
-    size_t next = 0;                 // next request (in arrival order) not yet admitted
+    size_t next = 0;                 // next request (submission order) not yet fully admitted
     int next_rhs = 0;                // first right-hand side of it not yet admitted
     std::vector<Slot> active;
     ItemState* d_states = nullptr;   // pool of item states, one per slot position
@@ -258,9 +291,9 @@ struct Server {
       //     hierarchy the head needs, and the two would evict each other).
       {
         std::lock_guard<std::mutex> lk(mu);
-        for (size_t k = next; k < order.size(); ++k) {
-          const amg_request& q = reqs[order[k]];
-          if (cfg.realtime && q.arrival_s > t) break;
+        for (size_t k = next; k < reqs.size(); ++k) {
+          Req* rq = reqs[k].get();
+          const amg_request& q = rq->q;
           if (resident.count(q.graph_id) || setup_pending.count(q.graph_id)) continue;
           if (!q.row_ptr) continue;  // no data to set up: fails at admission
           const size_t est = setup_estimate(q);
@@ -281,33 +314,34 @@ struct Server {
           bytes += est;
           note_bytes();
           setup_pending[q.graph_id] = est;
-          setup_queue.push_back(order[k]);
+          setup_queue.push_back(rq);
         }
       }
       cv.notify_all();
-      // --- admit arrived right-hand sides (arrival order) while slots and memory allow
+      // --- admit submitted right-hand sides (in order) while slots and memory allow
       std::vector<Slot> fresh;
-      while (next < order.size()) {
-        const int r = order[next];
-        const amg_request& q = reqs[r];
-        if (cfg.realtime && q.arrival_s > t) break;
+      for (;;) {
+        bool no_more = false;
+        Req* rq = request_at(next, &no_more);
+        if (!rq) break;
+        const amg_request& q = rq->q;
         if ((int)(active.size() + fresh.size()) >= max_slots) break;
         std::unique_lock<std::mutex> lk(mu);
         auto it = resident.find(q.graph_id);
         if (it == resident.end()) {
           if (!q.row_ptr && !setup_pending.count(q.graph_id)) {  // evicted and no data: fail
+            fail_request(rq, AMG_ERR_ARG, next_rhs);
             lk.unlock();
-            fail_request(r, AMG_ERR_ARG);
             ++next;
             next_rhs = 0;
             continue;
           }
-          break;  // setup still running: keep arrival order
+          break;  // setup still running: keep submission order
         }
         Resident* R = it->second;
         if (R->failed) {
+          fail_request(rq, R->status, next_rhs);
           lk.unlock();
-          fail_request(r, R->status);
           ++next;
           next_rhs = 0;
           continue;
@@ -326,8 +360,8 @@ struct Server {
         }
         if (!make_room(extra, R)) {
           if (active.empty() && fresh.empty()) {  // nothing will ever free memory: give up on it
+            fail_request(rq, AMG_ERR_BUDGET, next_rhs);
             lk.unlock();
-            fail_request(r, AMG_ERR_BUDGET);
             ++next;
             next_rhs = 0;
             continue;
@@ -354,12 +388,12 @@ struct Server {
         bytes += 2 * n * sizeof(double);
         note_bytes();
         Slot sl;
-        sl.req = r;
+        sl.rq = rq;
         sl.rhs = next_rhs;
         sl.res = R;
         sl.ws = ws;
         sl.own_ws = own;
-        sl.admit_s = t;
+        sl.admit_s = std::max(t, q.arrival_s);  // submitted after this round began
         R->in_flight++;
         R->last_use = t;
         lk.unlock();
@@ -388,11 +422,11 @@ struct Server {
         membership_changed = true;
       }
       if (active.empty()) {
-        if (next >= order.size()) break;
-        // wait for the next arrival or a setup
+        bool no_more = false;
+        if (!request_at(next, &no_more) && no_more) break;  // closing and everything done
+        // wait for a submission, a setup or the close
         std::unique_lock<std::mutex> lk(mu);
-        const double wait = cfg.realtime ? std::max(0.0, reqs[order[next]].arrival_s - now()) : 0.0;
-        cv.wait_for(lk, std::chrono::duration<double>(std::min(wait, 0.002) + 1e-4));
+        cv.wait_for(lk, std::chrono::milliseconds(2));
         continue;
       }
       // --- one round of outer iterations over every in-flight slot
@@ -420,7 +454,7 @@ struct Server {
         for (size_t i = 0; i < done.size(); ++i)
           AMG_HIP(hipMemcpyAsync(&fst[i], done[i].st, sizeof(ItemState), hipMemcpyDeviceToHost, s));
         for (const Slot& sl : done) {
-          const amg_request& q = reqs[sl.req];
+          const amg_request& q = sl.rq->q;
           if (q.u)
             AMG_HIP(hipMemcpyAsync(q.u + (size_t)sl.rhs * q.n, sl.u, sizeof(double) * q.n, hipMemcpyDeviceToHost,
                                    s));
@@ -433,7 +467,7 @@ struct Server {
           complete(sl, fst[i].status, fst[i].iter, rho0 > 0 ? std::sqrt(fst[i].rrt) / rho0 : 0.0);
           (void)hipFree(sl.f);
           (void)hipFree(sl.u);
-          bytes -= 2 * (size_t)reqs[sl.req].n * sizeof(double);
+          bytes -= 2 * (size_t)sl.rq->q.n * sizeof(double);
           sl.res->in_flight--;
           sl.res->last_use = now();
           if (sl.own_ws) sl.res->own_lent = false;
@@ -444,7 +478,6 @@ struct Server {
         active.swap(keep);
         membership_changed = true;
       }
-      if (active.empty() && next >= order.size()) break;
     }
     cleanup();
     return result;
@@ -452,19 +485,20 @@ struct Server {
 
   // ---------------------------------------------------------------- sequential mode
   int32_t run_sequential() {
-    std::vector<int> order(nreq);
-    for (int i = 0; i < nreq; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
     double* f = nullptr;
     double* u = nullptr;
     size_t cap = 0;
-    for (int r : order) {
-      const amg_request& q = reqs[r];
-      if (cfg.realtime) {
-        const double wait = q.arrival_s - now();
-        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+    for (size_t next = 0;; ++next) {
+      Req* rq = nullptr;
+      for (;;) {  // the next submission, or the end
+        bool no_more = false;
+        rq = request_at(next, &no_more);
+        if (rq || no_more) break;
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait_for(lk, std::chrono::milliseconds(2));
       }
+      if (!rq) break;
+      const amg_request& q = rq->q;
       Resident* R = nullptr;
       auto it = resident.find(q.graph_id);
       if (it != resident.end()) {
@@ -486,7 +520,8 @@ struct Server {
         resident[q.graph_id] = R;
       }
       if (!R || R->failed) {
-        fail_request(r, R ? R->status : AMG_ERR_ARG);
+        std::lock_guard<std::mutex> lk(mu);
+        fail_request(rq, R ? R->status : AMG_ERR_ARG);
         continue;
       }
       R->last_use = now();
@@ -506,9 +541,10 @@ struct Server {
         if (q.u) AMG_HIP(hipMemcpyAsync(q.u + (size_t)k * q.n, u, q.n * sizeof(double), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
         Slot sl;
-        sl.req = r;
+        sl.rq = rq;
         sl.rhs = k;
         sl.admit_s = admit;
+        std::lock_guard<std::mutex> lk(mu);
         complete(sl, st == AMG_OK || st == AMG_ERR_MAXIT || st == AMG_ERR_BREAKDOWN ? info.status : st, info.iters,
                  info.rel_res_true);
         ++steps;
@@ -520,6 +556,7 @@ struct Server {
   }
 
   ~Server() {
+    if (loop_thread.joinable()) (void)finish();
     for (auto& kv : resident) {
       Resident* R = kv.second;
       for (amg_hier* c : R->spare) free_clone(c);
@@ -528,34 +565,158 @@ struct Server {
     }
     if (s_setup) (void)hipStreamDestroy(s_setup);
   }
+
+  // ---------------------------------------------------------------- the server thread
+  void run() {
+    (void)hipSetDevice(device);
+    const int32_t st = cfg.mode == AMG_SERVE_SEQUENTIAL ? run_sequential() : run_batched();
+    // a device error stops the loop; pollers see it in poll's return value
+    std::lock_guard<std::mutex> lk(mu);
+    loop_status = st;
+    if (st != AMG_OK) closing = true;
+    cv_out.notify_all();
+  }
+
+  int32_t start(const amg_serve_cfg& c, hipStream_t stream) {
+    cfg = c;
+    s = stream;
+    (void)hipGetDevice(&device);
+    AMG_HIP(hipStreamCreateWithFlags(&s_setup, hipStreamNonBlocking));
+    t0 = clk::now();
+    loop_thread = std::thread([this] { run(); });
+    return AMG_OK;
+  }
+
+  // Copies the request in and queues it; `arrival` < 0 stamps the current time.
+  int32_t submit(const amg_request& in, double arrival, int32_t* ticket) {
+    auto rq = std::make_unique<Req>();
+    rq->q = in;
+    const size_t n = (size_t)in.n;
+    rq->f.assign(in.f, in.f + (size_t)in.nrhs * n);
+    rq->q.f = rq->f.data();
+    if (in.row_ptr) {
+      const size_t nnz = (size_t)in.row_ptr[in.n];
+      rq->rp.assign(in.row_ptr, in.row_ptr + n + 1);
+      rq->col.assign(in.col, in.col + nnz);
+      rq->w.assign(in.w, in.w + nnz);
+      rq->d.assign(in.d, in.d + n);
+      rq->q.row_ptr = rq->rp.data();
+      rq->q.col = rq->col.data();
+      rq->q.w = rq->w.data();
+      rq->q.d = rq->d.data();
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (closing) {
+      set_last_error("server is closing");
+      return AMG_ERR_ARG;
+    }
+    rq->q.arrival_s = arrival < 0 ? now() : arrival;
+    rq->ticket = (int32_t)reqs.size();
+    if (ticket) *ticket = rq->ticket;
+    outstanding += in.nrhs;
+    reqs.push_back(std::move(rq));
+    cv.notify_all();
+    return AMG_OK;
+  }
+
+  int32_t poll(amg_completion* out, int32_t max, double wait_s, int32_t* count) {
+    std::unique_lock<std::mutex> lk(mu);
+    if (outbox.empty() && wait_s > 0) {
+      cv_out.wait_for(lk, std::chrono::duration<double>(wait_s),
+                      [&] { return !outbox.empty() || (closing && outstanding == 0) || loop_status != AMG_OK; });
+    }
+    int32_t k = 0;
+    while (k < max && !outbox.empty()) {
+      out[k++] = outbox.front();
+      outbox.pop_front();
+    }
+    *count = k;
+    return loop_status;
+  }
+
+  // No more submissions: finish every submitted request and stop the thread.
+  int32_t finish() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      closing = true;
+    }
+    cv.notify_all();
+    if (loop_thread.joinable()) loop_thread.join();
+    return loop_status;
+  }
+
+  void stats(amg_serve_stats* st) {
+    if (!st) return;
+    st->wall_s = now();
+    st->peak_bytes = (double)peak;
+    st->evictions = evictions;
+    st->setups = setups;
+    st->steps = steps;
+  }
 };
 
 }  // namespace
 
+int32_t server_create(const amg_serve_cfg& cfg, hipStream_t s, void** out) {
+  auto S = std::make_unique<Server>();
+  AMG_TRY(S->start(cfg, s));
+  *out = S.release();
+  return AMG_OK;
+}
+
+int32_t server_submit(void* srv, const amg_request& q, int32_t* ticket) {
+  return static_cast<Server*>(srv)->submit(q, -1.0, ticket);
+}
+
+int32_t server_poll(void* srv, amg_completion* out, int32_t max, double wait_s, int32_t* count) {
+  return static_cast<Server*>(srv)->poll(out, max, wait_s, count);
+}
+
+int32_t server_destroy(void* srv, amg_serve_stats* stats) {
+  Server* S = static_cast<Server*>(srv);
+  const int32_t st = S->finish();
+  S->stats(stats);
+  delete S;
+  return st;
+}
+
+// Replay of a request stream on the incremental server: requests are
+// submitted in arrival order -- at their arrival times when realtime, all at
+// once otherwise -- and their completions gathered request-major.
 int32_t serve(const amg_serve_cfg& cfg, const amg_request* reqs, int32_t nreq, amg_completion* out,
               amg_serve_stats* stats, hipStream_t s) {
-  Server S;
-  S.cfg = cfg;
-  S.reqs = reqs;
-  S.nreq = nreq;
-  S.out = out;
-  S.s = s;
+  std::vector<int> order(nreq), base(nreq);
   int total = 0;
   for (int i = 0; i < nreq; ++i) {
-    S.out_base.push_back(total);
+    order[i] = i;
+    base[i] = total;
     total += reqs[i].nrhs;
   }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
   std::memset(out, 0, sizeof(amg_completion) * total);
-  AMG_HIP(hipStreamCreateWithFlags(&S.s_setup, hipStreamNonBlocking));
-  S.t0 = clk::now();
-  const int32_t st = cfg.mode == AMG_SERVE_SEQUENTIAL ? S.run_sequential() : S.run_batched();
-  if (stats) {
-    stats->wall_s = S.now();
-    stats->peak_bytes = (double)S.peak;
-    stats->evictions = S.evictions;
-    stats->setups = S.setups;
-    stats->steps = S.steps;
+  Server S;
+  AMG_TRY(S.start(cfg, s));
+  std::vector<int> of_ticket(nreq);
+  int32_t st = AMG_OK;
+  for (int k = 0; k < nreq && st == AMG_OK; ++k) {
+    const amg_request& q = reqs[order[k]];
+    if (cfg.realtime) {
+      const double wait = q.arrival_s - S.now();
+      if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+    }
+    int32_t ticket = 0;
+    st = S.submit(q, q.arrival_s, &ticket);
+    of_ticket[ticket] = order[k];
   }
+  const int32_t fst = S.finish();
+  if (st == AMG_OK) st = fst;
+  for (const amg_completion& c : S.outbox) {
+    const int r = of_ticket[c.request];
+    amg_completion cc = c;
+    cc.request = r;
+    out[base[r] + c.rhs] = cc;
+  }
+  S.stats(stats);
   return st;
 }
 

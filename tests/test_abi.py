@@ -124,3 +124,32 @@ def test_valid_input_without_gpu_reports_device(amg):
     g = inputs.grid2d(5)
     code, out = _setup_code(amg, g.n, g.row_ptr, g.col, g.w, g.d)
     assert code == amg.AMG_ERR_DEVICE and not out.value
+
+
+def test_server_argument_errors_before_device(amg):
+    lib = amg.load_library()
+    hnd = ctypes.c_void_p()
+    assert lib.amg_server_create(None, None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG and not hnd.value
+    for bad in (dict(mode=7), dict(max_slots=0), dict(hbm_budget_bytes=0.0)):
+        cfg = amg.amg_serve_cfg_default(**bad)
+        assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG, bad
+        assert not hnd.value
+    cfg = amg.amg_serve_cfg_default(amg.amg_params_default(restart=0))
+    assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
+    assert lib.amg_server_create(ctypes.byref(amg.amg_serve_cfg_default()), None, None) == amg.AMG_ERR_ARG
+    cnt = ctypes.c_int32()
+    out = (amg.amg_completion * 2)()
+    assert lib.amg_server_submit(None, None, None) == amg.AMG_ERR_ARG
+    assert lib.amg_server_poll(None, out, 2, 0.0, ctypes.byref(cnt)) == amg.AMG_ERR_ARG
+    assert lib.amg_server_destroy(None, None) == amg.AMG_OK
+
+
+def test_server_without_gpu_reports_device(amg):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    hnd = ctypes.c_void_p()
+    cfg = amg.amg_serve_cfg_default()
+    assert amg.load_library().amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_DEVICE
+    assert not hnd.value

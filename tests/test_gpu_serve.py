@@ -138,3 +138,78 @@ def test_serve_unknown_graph_without_data_fails_cleanly(amg, graphs):
     comps, _, _ = amg.amg_serve(cfg, reqs)
     assert comps[0]["status"] == amg.AMG_ERR_ARG
     assert comps[1]["status"] == 0
+
+
+def _drain(srv, expect, wait_s=0.5, limit_s=60.0):
+    """Poll until `expect` completions have come back (bounded)."""
+    import time
+
+    got = []
+    t0 = time.monotonic()
+    while len(got) < expect and time.monotonic() - t0 < limit_s:
+        got += srv.poll(16, wait_s)
+    return got
+
+
+@pytest.mark.parametrize("mode", ["batched", "sequential"])
+def test_server_incremental_submit_poll(amg, graphs, mode):
+    # requests submitted one by one while earlier ones are in flight; every
+    # solution equals the one the request gets on its own
+    reqs = _stream(graphs)
+    cfg = amg.amg_serve_cfg_default(_params(amg), mode=mode, iters_per_step=2)
+    srv = amg.Server(cfg)
+    tickets, comps = [], []
+    for i, r in enumerate(reqs):
+        tickets.append(srv.submit(r["graph_id"], r["f"], graph=r["graph"]))
+        if i % 3 == 2:
+            comps += srv.poll(16, 0.0)
+    assert tickets == list(range(len(reqs)))
+    total = sum(np.atleast_2d(r["f"]).shape[0] for r in reqs)
+    comps += _drain(srv, total - len(comps))
+    stats = srv.close()
+    assert len(comps) == total
+    assert sorted((c["request"], c["rhs"]) for c in comps) == [
+        (i, j) for i, r in enumerate(reqs) for j in range(np.atleast_2d(r["f"]).shape[0])]
+    assert stats["setups"] == len(graphs)
+    for c in comps:
+        assert c["status"] == 0 and c["rel_res_true"] <= 1.05e-8, c
+        assert c["finish_s"] >= c["admit_s"] >= c["arrival_s"] - 1e-9
+    alone_cfg = amg.amg_serve_cfg_default(_params(amg), mode=mode, realtime=0, iters_per_step=1)
+    by = {(c["request"], c["rhs"]): c["u"] for c in comps}
+    for i in (0, 6, 8):
+        _, _, alone = amg.amg_serve(alone_cfg, [dict(reqs[i], arrival_s=0.0)])
+        for j in range(alone[0].shape[0]):
+            if mode == "batched":
+                assert np.array_equal(alone[0][j], by[(i, j)]), (i, j)
+            else:
+                assert np.linalg.norm(alone[0][j] - by[(i, j)]) <= 1e-12 * np.linalg.norm(alone[0][j])
+
+
+def test_server_resident_graph_and_errors(amg, graphs):
+    g = graphs[0]
+    cfg = amg.amg_serve_cfg_default(_params(amg, "fp64"))
+    srv = amg.Server(cfg)
+    f = inputs.rhs(g.n, 31)
+    t0 = srv.submit(0, f, graph=g)
+    c0 = _drain(srv, 1)
+    # the graph stays resident: a later request needs no graph data
+    t1 = srv.submit(0, np.stack([f, inputs.rhs(g.n, 32)]), n=g.n)
+    c1 = _drain(srv, 2)
+    # an unknown graph without data fails, the server goes on
+    t2 = srv.submit(9, inputs.rhs(50, 33), n=50)
+    c2 = _drain(srv, 1)
+    with pytest.raises(amg.AmgError):
+        srv.submit(0, np.zeros((1, 0)), n=0)
+    assert srv.poll(4, 0.05) == []
+    stats = srv.close()
+    assert (t0, t1, t2) == (0, 1, 2)
+    assert c0[0]["status"] == 0 and c0[0]["request"] == 0
+    assert sorted(c["rhs"] for c in c1) == [0, 1] and all(c["status"] == 0 for c in c1)
+    assert np.array_equal(c0[0]["u"], [c for c in c1 if c["rhs"] == 0][0]["u"])
+    assert c2[0]["status"] == amg.AMG_ERR_ARG and c2[0]["request"] == 2
+    assert stats["setups"] == 1
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(degree=4, agg_size=8))
+    uo = oracle.fcg(ho, f).x
+    e = c0[0]["u"] - uo
+    lo = ho.levels[0]
+    assert np.sqrt(e @ oracle.apply_A(lo, e)) / np.sqrt(uo @ oracle.apply_A(lo, uo)) <= 1e-6
