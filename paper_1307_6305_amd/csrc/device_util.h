@@ -17,6 +17,35 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// A double moved across lanes by a DPP pattern (both 32-bit halves); lanes
+// of rows outside ROWS get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// The double sum over the 64 lanes through DPP lane moves (no LDS traffic):
+// quad butterflies, the mirrors within 8 and 16 lanes, then the row
+// broadcasts into rows 1, 3 and 2, 3; lane 63 ends with
+// (R3 + R2) + (R1 + R0) of the row sums, which every lane returns.  The tree
+// is fixed, so the result is deterministic.
+template <>
+__device__ __forceinline__ double wave_sum<double>(double v) {
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_move<0x140, 0xF>(v);  // row_mirror
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll

@@ -159,8 +159,9 @@ __device__ __forceinline__ AT offdiag_k(const Mat<MT>& A, int slot, int j, const
 }
 
 // The same sum on the plain layout (one lane per row) in LDS, where the
-// one-workgroup tail program runs: entries added in order.  The tail always
-// uses the plain layout, so its results do not depend on the level's layout.
+// one-workgroup tail program runs: entries added in order.  A wavefront's rows
+// share one slice, so the trip count is uniform.  The tail always uses the
+// plain layout, so its results do not depend on the level's layout.
 template <typename AT, typename MT, typename XA>
 __device__ __forceinline__ AT offdiag_seq(const Mat<MT>& A, int r, const XA& x) {
   const int s = r >> 6, p = r & 63;
@@ -386,6 +387,7 @@ enum OpType : int {
   OP_RESIDUAL_P,
 };
 
+// One op as the solver records it (host side, device addresses).
 struct TailOp {
   int type, level, n, k;
   int i0, i1, i2, i3;
@@ -398,37 +400,87 @@ struct TailOp {
   Slots s0, s1;
 };
 
-// The tail program runs entirely out of the workgroup's LDS: its op list,
-// the level descriptors, the matrices, transfer maps, coarsest factor,
-// vectors and scalars are laid out in one LDS image that the kernel fills
-// from device memory at start; the tail level's solution is copied back at the
-// end.  Inside the image every operand is a byte offset, recorded with bit 62
-// set (no device address has that bit) so that a recording mistake cannot
-// pass for a device pointer.
-constexpr uint64_t kLdsTag = 1ull << 62;
+// One op as the tail interpreter reads it from LDS: every operand is a byte
+// offset into the workgroup's LDS image, with the op's matrix (plain layout)
+// and transfer map resolved when the program is laid out, so that an op costs
+// a few scalar loads for its description.  Fields by op:
+//   CHEB_FIRST  a w0, c w1, d y, f0 theta, f1 1/eta, f2 c0, f3 c1, i0 accum,
+//               i1 store, i2 fold (e = coarse correction, agg)
+//   CHEB_NEXT   a w_k, b w_k-1, c w_k+1, d y, f0 theta, f1 2/eta, f2 c, i0 store
+//   SCALE_ADD   a w0, d y, f0 c0, i0 accum
+//   RESIDUAL    a f, b x, c s;  RESIDUAL_P the same with e, agg
+//   RESTRICT    a s, c b, n coarse rows (members, member_off)
+//   PROLONG     a e, c x (agg)
+//   COARSE      a b, c x
+//   MULTIDOT    a z, k; aux: k vector offsets, k destination slots
+//   SPMV_DOTS   a p, b r, c q, i0 i1 destination slots
+//   FCG_P       a z, c p, k; aux: k vector offsets, k dot slots, k rho slots
+//   FCG_XR      a p, b q, c x, d r, i0 rho slot, i1 gamma slot, i2 x_init, i3 update r
+struct TailInstr {
+  int type, n, k, i0;
+  int i1, i2, i3;
+  uint32_t aux;
+  uint32_t a, b, c, d;
+  uint32_t off, width, col, val;
+  uint32_t D, agg, members, member_off;
+  uint32_t e, pad0, pad1, pad2;
+  double f0, f1, f2, f3;
+};
+static_assert(sizeof(TailInstr) == 128, "tail instructions are 128 bytes");
 
-template <typename T>
-__device__ __forceinline__ T* at(char* lds, const void* tag) {
-  return reinterpret_cast<T*>(lds + (uint32_t)(uint64_t)tag);
+// The packed form the kernel reads: LDS offsets (multiples of 16 below 1 MiB)
+// in 16-byte units, two to a word; flags and k beside the op type.
+//   w0 type | k << 8 | i2 << 16 | i3 << 17    w1 n    w2 i0    w3 i1
+//   w4 a | b     w5 c | d     w6 off | width     w7 col | val
+//   w8 D | agg   w9 members | member_off     w10 e | aux     w11 unused
+struct TailCode {
+  uint32_t w[12];
+  double f[4];
+};
+static_assert(sizeof(TailCode) == 80, "packed tail instructions are 80 bytes");
+
+// Instructions are read with scalar loads from the program's device copy
+// (constant address space: uniform, read-only), so an op's description costs
+// neither LDS bandwidth nor vector registers; the next op's is loaded while
+// the current one runs.
+typedef __attribute__((address_space(4))) const TailCode ConstCode;
+
+__device__ __forceinline__ void code_fetch(const ConstCode* p, TailCode& c) {
+#pragma unroll
+  for (int i = 0; i < 12; ++i) c.w[i] = p->w[i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) c.f[i] = p->f[i];
 }
 
-template <typename MT>
-__device__ __forceinline__ Mat<MT> lds_mat(const Mat<MT>& A, char* lds) {
-  Mat<MT> B = A;
-  B.off = at<const int>(lds, A.off);
-  B.width = at<const int>(lds, A.width);
-  B.col = at<const int>(lds, A.col);
-  B.val = at<const MT>(lds, A.val);
-  B.D = at<const MT>(lds, A.D);
-  return B;
-}
-
-__device__ __forceinline__ Transfer lds_tr(const Transfer& T, char* lds) {
-  Transfer U = T;
-  U.agg = at<const int>(lds, T.agg);
-  U.members = at<const int>(lds, T.members);
-  U.member_off = at<const int>(lds, T.member_off);
-  return U;
+__device__ __forceinline__ TailInstr code_unpack(const TailCode& c) {
+  TailInstr I;
+  I.type = (int)(c.w[0] & 0xFF);
+  I.k = (int)((c.w[0] >> 8) & 0xFF);
+  I.i2 = (int)((c.w[0] >> 16) & 1);
+  I.i3 = (int)((c.w[0] >> 17) & 1);
+  I.n = (int)c.w[1];
+  I.i0 = (int)c.w[2];
+  I.i1 = (int)c.w[3];
+  I.a = (c.w[4] & 0xFFFF) << 4;
+  I.b = (c.w[4] >> 16) << 4;
+  I.c = (c.w[5] & 0xFFFF) << 4;
+  I.d = (c.w[5] >> 16) << 4;
+  I.off = (c.w[6] & 0xFFFF) << 4;
+  I.width = (c.w[6] >> 16) << 4;
+  I.col = (c.w[7] & 0xFFFF) << 4;
+  I.val = (c.w[7] >> 16) << 4;
+  I.D = (c.w[8] & 0xFFFF) << 4;
+  I.agg = (c.w[8] >> 16) << 4;
+  I.members = (c.w[9] & 0xFFFF) << 4;
+  I.member_off = (c.w[9] >> 16) << 4;
+  I.e = (c.w[10] & 0xFFFF) << 4;
+  I.aux = (c.w[10] >> 16) << 4;
+  I.pad0 = I.pad1 = I.pad2 = 0;
+  I.f0 = c.f[0];
+  I.f1 = c.f[1];
+  I.f2 = c.f[2];
+  I.f3 = c.f[3];
+  return I;
 }
 
 struct TailCopy {
@@ -437,21 +489,36 @@ struct TailCopy {
   int bytes;        // multiple of 16
 };
 
+// The tail program runs entirely out of the workgroup's LDS: its instruction
+// list, the matrices, transfer maps, coarsest factor, vectors and scalars are
+// laid out in one LDS image that the kernel fills from device memory at start;
+// the tail level's solution is copied back at the end.
 struct TailProgram {
   int nops;
   int ncin;
-  uint32_t ops_off;   // LDS offset of the op list
-  uint32_t mats_off;  // LDS offset of Mat<MT>[L + 1]
-  uint32_t trs_off;   // LDS offset of Transfer[L + 1]
-  uint32_t scal_off;  // LDS offset of the scalar area
+  const TailCode* ops;   // instruction list (device memory)
+  uint32_t scal_off;     // LDS offset of the scalar area
   const TailCopy* cin;
   TailCopy cout;  // solution of the tail level, LDS -> device
-  CoarseView C;   // Linv, LinvT as tagged LDS offsets
+  uint32_t linv_off, linvt_off;  // inverse factor and its transpose (LDS)
+  int nL;                        // coarsest size
 };
 
-// Runs a recorded op program in one workgroup; every op is a data-parallel
-// loop over rows followed by a workgroup barrier.  Reductions are workgroup
-// reductions (no grid synchronization needed).
+template <typename T>
+__device__ __forceinline__ T* lds_at(char* lds, uint32_t off) {
+  return reinterpret_cast<T*>(lds + off);
+}
+
+template <typename MT>
+__device__ __forceinline__ Mat<MT> instr_mat(const TailInstr& I, char* lds) {
+  return Mat<MT>{I.n, 0, 6, 0, lds_at<const int>(lds, I.off), lds_at<const int>(lds, I.width),
+                 lds_at<const int>(lds, I.col), lds_at<const MT>(lds, I.val), lds_at<const MT>(lds, I.D), nullptr};
+}
+
+// Runs a recorded program in one workgroup; every op is a data-parallel loop
+// over rows followed by a workgroup barrier.  Reductions are workgroup
+// reductions (no grid synchronization needed).  The next op's description is
+// loaded while the current one runs.
 template <typename VT, typename MT>
 __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double* red, double* sb, double* sy,
                                          bool copy_constants) {
@@ -472,116 +539,137 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
     for (; i < n16; i += bd) dst[i] = src[i];
   }
   __syncthreads();
-  double* scal = reinterpret_cast<double*>(lds + P.scal_off);
-  const CoarseView C{P.C.n, at<const double>(lds, P.C.Linv), at<const double>(lds, P.C.LinvT)};
-  const TailOp* ops = reinterpret_cast<const TailOp*>(lds + P.ops_off);
-  const Mat<MT>* mats = reinterpret_cast<const Mat<MT>*>(lds + P.mats_off);
-  const Transfer* trs = reinterpret_cast<const Transfer*>(lds + P.trs_off);
+  double* scal = lds_at<double>(lds, P.scal_off);
+  const CoarseView C{P.nL, lds_at<const double>(lds, P.linv_off), lds_at<const double>(lds, P.linvt_off)};
+  const ConstCode* ops = (const ConstCode*)(P.ops);
+  TailCode next;
+  if (P.nops > 0) code_fetch(ops, next);
   for (int o = 0; o < P.nops; ++o) {
-    const TailOp& op = ops[o];
-    switch (op.type) {
+    const TailInstr I = code_unpack(next);
+    if (o + 1 < P.nops) code_fetch(ops + o + 1, next);
+    switch (I.type) {
       case OP_CHEB_FIRST: {
-        const Mat<MT> A = lds_mat(mats[op.level], lds);
-        const VT* w0 = at<const VT>(lds, op.a);
-        VT* w1 = at<VT>(lds, op.c);
-        VT* y = at<VT>(lds, op.d);
-        const VT* e = op.i2 ? at<const VT>(lds, op.w.p[0]) : nullptr;
-        const int* agg = op.i2 ? lds_tr(trs[op.level], lds).agg : nullptr;
+        const Mat<MT> A = instr_mat<MT>(I, lds);
+        const VT* w0 = lds_at<const VT>(lds, I.a);
+        VT* w1 = lds_at<VT>(lds, I.c);
+        VT* y = lds_at<VT>(lds, I.d);
+        const VT* e = I.i2 ? lds_at<const VT>(lds, I.e) : nullptr;
+        const int* agg = I.i2 ? lds_at<const int>(lds, I.agg) : nullptr;
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_first<VT, MT, VT, false>(A, r, 0, w0, w1, y, op.f0, op.f1, op.f2, op.f3, op.i0, op.i1, e, agg);
+          row_cheb_first<VT, MT, VT, false>(A, r, 0, w0, w1, y, I.f0, I.f1, I.f2, I.f3, I.i0, I.i1, e, agg);
         break;
       }
       case OP_CHEB_NEXT: {
-        const Mat<MT> A = lds_mat(mats[op.level], lds);
-        const VT* wk = at<const VT>(lds, op.a);
-        const VT* wp = at<const VT>(lds, op.b);
-        VT* wn = at<VT>(lds, op.c);
-        VT* y = at<VT>(lds, op.d);
+        const Mat<MT> A = instr_mat<MT>(I, lds);
+        const VT* wk = lds_at<const VT>(lds, I.a);
+        const VT* wp = lds_at<const VT>(lds, I.b);
+        VT* wn = lds_at<VT>(lds, I.c);
+        VT* y = lds_at<VT>(lds, I.d);
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_next<VT, MT, VT, false>(A, r, 0, wk, wp, wn, y, op.f0, op.f1, op.f2, op.i0);
+          row_cheb_next<VT, MT, VT, false>(A, r, 0, wk, wp, wn, y, I.f0, I.f1, I.f2, I.i0);
         break;
       }
       case OP_SCALE_ADD: {
-        const VT* w0 = at<const VT>(lds, op.a);
-        VT* y = at<VT>(lds, op.d);
-        for (int i = tid; i < op.n; i += bd) {
-          VT v = (VT)op.f0 * w0[i];
-          if (op.i0) v += y[i];
+        const VT* w0 = lds_at<const VT>(lds, I.a);
+        VT* y = lds_at<VT>(lds, I.d);
+        for (int i = tid; i < I.n; i += bd) {
+          VT v = (VT)I.f0 * w0[i];
+          if (I.i0) v += y[i];
           y[i] = v;
         }
         break;
       }
       case OP_RESIDUAL: {
-        const Mat<MT> A = lds_mat(mats[op.level], lds);
-        const VT* f = at<const VT>(lds, op.a);
-        const VT* x = at<const VT>(lds, op.b);
-        VT* sv = at<VT>(lds, op.c);
+        const Mat<MT> A = instr_mat<MT>(I, lds);
+        const VT* f = lds_at<const VT>(lds, I.a);
+        const VT* x = lds_at<const VT>(lds, I.b);
+        VT* sv = lds_at<VT>(lds, I.c);
         for (int r = tid; r < A.n; r += bd) (void)row_residual<VT, MT, VT, false>(A, r, 0, f, x, sv);
         break;
       }
       case OP_RESIDUAL_P: {
-        const Mat<MT> A = lds_mat(mats[op.level], lds);
-        const VT* f = at<const VT>(lds, op.a);
-        const VT* x = at<const VT>(lds, op.b);
-        const VT* e = at<const VT>(lds, op.w.p[0]);
-        const int* agg = lds_tr(trs[op.level], lds).agg;
-        VT* sv = at<VT>(lds, op.c);
+        const Mat<MT> A = instr_mat<MT>(I, lds);
+        const VT* f = lds_at<const VT>(lds, I.a);
+        const VT* x = lds_at<const VT>(lds, I.b);
+        const VT* e = lds_at<const VT>(lds, I.e);
+        const int* agg = lds_at<const int>(lds, I.agg);
+        VT* sv = lds_at<VT>(lds, I.c);
         for (int r = tid; r < A.n; r += bd) (void)row_residual_p<VT, MT, VT, false>(A, r, 0, f, x, e, agg, sv);
         break;
       }
       case OP_RESTRICT: {
-        const Transfer T = lds_tr(trs[op.level], lds);
-        const VT* sv = at<const VT>(lds, op.a);
-        VT* b = at<VT>(lds, op.c);
-        for (int I = tid; I < T.nc; I += bd) row_restrict<VT>(T, I, sv, b);
+        const int* members = lds_at<const int>(lds, I.members);
+        const int* moff = lds_at<const int>(lds, I.member_off);
+        const VT* sv = lds_at<const VT>(lds, I.a);
+        VT* b = lds_at<VT>(lds, I.c);
+        for (int J = tid; J < I.n; J += bd) {
+          VT acc = 0;
+          for (int k = moff[J]; k < moff[J + 1]; ++k) acc += sv[members[k]];
+          b[J] = acc;
+        }
         break;
       }
       case OP_PROLONG: {
-        const Transfer T = lds_tr(trs[op.level], lds);
-        const VT* e = at<const VT>(lds, op.a);
-        VT* x = at<VT>(lds, op.c);
-        for (int i = tid; i < T.n; i += bd) row_prolong<VT>(T, i, e, x);
+        const int* agg = lds_at<const int>(lds, I.agg);
+        const VT* e = lds_at<const VT>(lds, I.a);
+        VT* x = lds_at<VT>(lds, I.c);
+        for (int i = tid; i < I.n; i += bd) x[i] += e[agg[i]];
         break;
       }
       case OP_COARSE:
-        coarse_apply<VT, VT>(C, at<const VT>(lds, op.a), at<VT>(lds, op.c), sb, sy);
+        coarse_apply<VT, VT>(C, lds_at<const VT>(lds, I.a), lds_at<VT>(lds, I.c), sb, sy);
         break;
       case OP_MULTIDOT: {
+        const uint32_t* vo = lds_at<const uint32_t>(lds, I.aux);
+        const int* so = lds_at<const int>(lds, I.aux + 4 * I.k);
+        uint32_t qo[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) qo[i] = i < I.k ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vo[i]) : 0u;
         double v[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = 0.0;
-        const VT* z = at<const VT>(lds, op.a);
-        for (int j = tid; j < op.n; j += bd) {
+        const VT* z = lds_at<const VT>(lds, I.a);
+        for (int j = tid; j < I.n; j += bd) {
           const double zj = (double)z[j];
 #pragma unroll
           for (int i = 0; i < 8; ++i)
-            if (i < op.k) v[i] += zj * (double)at<const VT>(lds, op.w.p[i])[j];
+            if (i < I.k) v[i] += zj * (double)lds_at<const VT>(lds, qo[i])[j];
         }
-        block_sum_k<8>(v, op.k, red);
-        if (tid == 0)
-          for (int i = 0; i < op.k; ++i) scal[op.s0.s[i]] = v[i];
+        block_sum_k<8>(v, I.k, red);
+        if (tid == 0) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (i < I.k) scal[so[i]] = v[i];
+        }
         break;
       }
       case OP_FCG_P: {
+        const uint32_t* vo = lds_at<const uint32_t>(lds, I.aux);
+        const int* sd = lds_at<const int>(lds, I.aux + 4 * I.k);
+        const int* sr = lds_at<const int>(lds, I.aux + 8 * I.k);
         double beta[8];
+        uint32_t po[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) beta[i] = i < op.k ? fcg_beta(scal, op.s0.s[i], op.s1.s[i]) : 0.0;
-        const VT* z = at<const VT>(lds, op.a);
-        VT* p = at<VT>(lds, op.c);
-        for (int j = tid; j < op.n; j += bd) {
+        for (int i = 0; i < 8; ++i) {
+          beta[i] = i < I.k ? fcg_beta(scal, sd[i], sr[i]) : 0.0;
+          po[i] = i < I.k ? (uint32_t)__builtin_amdgcn_readfirstlane((int)vo[i]) : 0u;
+        }
+        const VT* z = lds_at<const VT>(lds, I.a);
+        VT* p = lds_at<VT>(lds, I.c);
+        for (int j = tid; j < I.n; j += bd) {
           double v = (double)z[j];
 #pragma unroll
           for (int i = 0; i < 8; ++i)
-            if (i < op.k) v -= beta[i] * (double)at<const VT>(lds, op.w.p[i])[j];
+            if (i < I.k) v -= beta[i] * (double)lds_at<const VT>(lds, po[i])[j];
           p[j] = (VT)v;
         }
         break;
       }
       case OP_SPMV_DOTS: {
-        const Mat<MT> A = lds_mat(mats[op.level], lds);
-        const VT* p = at<const VT>(lds, op.a);
-        const VT* rv = at<const VT>(lds, op.b);
-        VT* q = at<VT>(lds, op.c);
+        const Mat<MT> A = instr_mat<MT>(I, lds);
+        const VT* p = lds_at<const VT>(lds, I.a);
+        const VT* rv = lds_at<const VT>(lds, I.b);
+        VT* q = lds_at<VT>(lds, I.c);
         double v[2] = {0.0, 0.0};
         for (int r = tid; r < A.n; r += bd) {
           double w[2];
@@ -591,21 +679,21 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         }
         block_sum<2>(v, red);
         if (tid == 0) {
-          scal[op.s0.s[0]] = v[0];
-          scal[op.s0.s[1]] = v[1];
+          scal[I.i0] = v[0];
+          scal[I.i1] = v[1];
         }
         break;
       }
       case OP_FCG_XR: {
-        const double alpha = fcg_alpha(scal, op.i0, op.i1);
-        const VT* p = at<const VT>(lds, op.a);
-        const VT* q = at<const VT>(lds, op.b);
-        VT* x = at<VT>(lds, op.c);
-        VT* r = at<VT>(lds, op.d);
-        for (int j = tid; j < op.n; j += bd) {
+        const double alpha = fcg_alpha(scal, I.i0, I.i1);
+        const VT* p = lds_at<const VT>(lds, I.a);
+        const VT* q = lds_at<const VT>(lds, I.b);
+        VT* x = lds_at<VT>(lds, I.c);
+        VT* r = lds_at<VT>(lds, I.d);
+        for (int j = tid; j < I.n; j += bd) {
           const double pj = (double)p[j];
-          x[j] = (VT)(op.i2 ? alpha * pj : (double)x[j] + alpha * pj);
-          if (op.i3) r[j] = (VT)((double)r[j] - alpha * (double)q[j]);
+          x[j] = (VT)(I.i2 ? alpha * pj : (double)x[j] + alpha * pj);
+          if (I.i3) r[j] = (VT)((double)r[j] - alpha * (double)q[j]);
         }
         break;
       }

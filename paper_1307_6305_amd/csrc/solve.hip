@@ -807,6 +807,51 @@ void tail_buffers(const amg_hier* h, int t, std::vector<LdsBuf>& bufs) {
   bufs.push_back({h->scal, sizeof(double) * SCAL_SIZE, false});
 }
 
+// Words of the auxiliary area an op needs (operand lists of inner products
+// and direction updates).
+inline size_t aux_words(const TailOp& o) {
+  if (o.type == OP_MULTIDOT) return 2 * (size_t)o.k;
+  if (o.type == OP_FCG_P) return 3 * (size_t)o.k;
+  return 0;
+}
+
+// Auxiliary words of all ops, each op's list starting on 16 bytes.
+inline size_t aux_total(const std::vector<TailOp>& ops) {
+  size_t aux = 0;
+  for (const auto& o : ops) aux += (aux_words(o) + 3) & ~size_t(3);
+  return aux;
+}
+
+// Instructions are kept in device memory; the LDS image starts with the
+// auxiliary operand lists.
+inline size_t header_bytes(const std::vector<TailOp>& ops) { return round16(aux_total(ops) * sizeof(int32_t)); }
+
+// The kernel's packed form of an instruction (offsets in 16-byte units).
+inline bool pack_instr(const TailInstr& I, TailCode& c) {
+  std::memset(&c, 0, sizeof(c));
+  auto u = [](uint32_t off, bool& ok) -> uint32_t {
+    if ((off & 15) || (off >> 4) > 0xFFFF) ok = false;
+    return off >> 4;
+  };
+  bool ok = I.type >= 0 && I.type < 256 && I.k >= 0 && I.k < 256 && (I.i2 & ~1) == 0 && (I.i3 & ~1) == 0;
+  c.w[0] = (uint32_t)I.type | ((uint32_t)I.k << 8) | ((uint32_t)I.i2 << 16) | ((uint32_t)I.i3 << 17);
+  c.w[1] = (uint32_t)I.n;
+  c.w[2] = (uint32_t)I.i0;
+  c.w[3] = (uint32_t)I.i1;
+  c.w[4] = u(I.a, ok) | (u(I.b, ok) << 16);
+  c.w[5] = u(I.c, ok) | (u(I.d, ok) << 16);
+  c.w[6] = u(I.off, ok) | (u(I.width, ok) << 16);
+  c.w[7] = u(I.col, ok) | (u(I.val, ok) << 16);
+  c.w[8] = u(I.D, ok) | (u(I.agg, ok) << 16);
+  c.w[9] = u(I.members, ok) | (u(I.member_off, ok) << 16);
+  c.w[10] = u(I.e, ok) | (u(I.aux, ok) << 16);
+  c.f[0] = I.f0;
+  c.f[1] = I.f1;
+  c.f[2] = I.f2;
+  c.f[3] = I.f3;
+  return ok;
+}
+
 template <typename VT, typename MT>
 int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   h->tail_level = 0;
@@ -816,23 +861,18 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   const size_t static_lds = sizeof(double) * (16 * 8 + 2 * 1024) + 1024;  // red, sb, sy + margin
   if ((size_t)max_lds <= static_lds) return AMG_OK;
   const size_t budget = (size_t)max_lds - static_lds;
-  // LDS image: [op list][Mat descriptors][Transfer descriptors][level data ...]
-  auto program_bytes = [&](int t, size_t* nops_out) -> size_t {
-    std::vector<TailOp> ops;
-    Engine<VT, MT> E{h, s, &ops};
-    if (E.inner(t) != AMG_OK) return SIZE_MAX;
-    *nops_out = ops.size();
-    return round16(ops.size() * sizeof(TailOp)) + round16((h->L + 1) * sizeof(Mat<MT>)) +
-           round16((h->L + 1) * sizeof(Transfer));
-  };
+  // LDS image: [instructions][auxiliary operand lists][level data ...]
   int t = 0;
   for (int cand = h->L - 1; cand >= 1; --cand) {
     if (h->lv[cand].n > h->p.tail_rows || h->lv[cand].n > kTailMaxRows || !h->lv[cand].plain_off) break;
     std::vector<LdsBuf> bufs;
     tail_buffers<VT, MT>(h, cand, bufs);
-    size_t nops = 0;
-    size_t tot = program_bytes(cand, &nops);
-    if (tot == SIZE_MAX) break;
+    std::vector<TailOp> ops;
+    {
+      Engine<VT, MT> E{h, s, &ops};
+      if (E.inner(cand) != AMG_OK) break;
+    }
+    size_t tot = header_bytes(ops);
     for (const auto& b : bufs) tot += round16(b.bytes);
     if (tot > budget) break;
     t = cand;
@@ -843,10 +883,8 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
     Engine<VT, MT> E{h, s, &ops};
     AMG_TRY(E.inner(t));
   }
-  const uint32_t ops_off = 0;
-  const uint32_t mats_off = ops_off + (uint32_t)round16(ops.size() * sizeof(TailOp));
-  const uint32_t trs_off = mats_off + (uint32_t)round16((h->L + 1) * sizeof(Mat<MT>));
-  uint64_t off = trs_off + round16((h->L + 1) * sizeof(Transfer));
+  const uint32_t aux_off = 0;
+  uint64_t off = header_bytes(ops);
   std::vector<LdsBuf> bufs;
   tail_buffers<VT, MT>(h, t, bufs);
   // image order: the header, then every constant buffer (one contiguous
@@ -872,57 +910,90 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   const size_t need = off;
   // every operand of the program must be one of the placed buffers
   bool ok = true;
-  auto tr = [&](const void* p) -> const void* {
-    if (!p) return p;
+  auto lo = [&](const void* p) -> uint32_t {
+    if (!p) return 0;
     for (const auto& m : map)
-      if (m.first == p) return (const void*)(kLdsTag | m.second);
+      if (m.first == p) return (uint32_t)m.second;
     ok = false;
-    return p;
+    return 0;
   };
-  for (auto& o : ops) {
-    o.a = tr(o.a);
-    o.b = tr(o.b);
-    o.c = const_cast<void*>(tr(o.c));
-    o.d = const_cast<void*>(tr(o.d));
-    for (int i = 0; i < 8; ++i) o.w.p[i] = i < o.k ? tr(o.w.p[i]) : nullptr;
+  std::vector<TailInstr> ins(ops.size());
+  std::vector<int32_t> aux;
+  for (size_t i = 0; i < ops.size(); ++i) {
+    const TailOp& o = ops[i];
+    TailInstr& I = ins[i];
+    std::memset(&I, 0, sizeof(I));
+    I.type = o.type;
+    I.n = o.n;
+    I.k = o.k;
+    I.i0 = o.i0;
+    I.i1 = o.i1;
+    I.i2 = o.i2;
+    I.i3 = o.i3;
+    I.f0 = o.f0;
+    I.f1 = o.f1;
+    I.f2 = o.f2;
+    I.f3 = o.f3;
+    I.a = lo(o.a);
+    I.b = lo(o.b);
+    I.c = lo(o.c);
+    I.d = lo(o.d);
+    if (o.level >= t && o.level < h->L) {
+      const Mat<MT> A = plain_mat_of<MT>(h->lv[o.level]);
+      const Transfer T = transfer_of(h, o.level);
+      switch (o.type) {
+        case OP_CHEB_FIRST: case OP_CHEB_NEXT: case OP_RESIDUAL: case OP_RESIDUAL_P: case OP_SPMV_DOTS:
+          I.off = lo(A.off);
+          I.width = lo(A.width);
+          I.col = lo(A.col);
+          I.val = lo(A.val);
+          I.D = lo(A.D);
+          break;
+        default:
+          break;
+      }
+      if (o.type == OP_RESTRICT) {
+        I.members = lo(T.members);
+        I.member_off = lo(T.member_off);
+      }
+      if (o.type == OP_PROLONG || o.type == OP_RESIDUAL_P || (o.type == OP_CHEB_FIRST && o.i2)) I.agg = lo(T.agg);
+    }
+    if (o.type == OP_RESIDUAL_P || (o.type == OP_CHEB_FIRST && o.i2)) I.e = lo(o.w.p[0]);
+    if (o.type == OP_SPMV_DOTS) {
+      I.i0 = o.s0.s[0];
+      I.i1 = o.s0.s[1];
+    }
+    if (aux_words(o)) {
+      I.aux = aux_off + (uint32_t)(aux.size() * sizeof(int32_t));
+      for (int j = 0; j < o.k; ++j) aux.push_back((int32_t)lo(o.w.p[j]));
+      for (int j = 0; j < o.k; ++j) aux.push_back(o.s0.s[j]);
+      if (o.type == OP_FCG_P)
+        for (int j = 0; j < o.k; ++j) aux.push_back(o.s1.s[j]);
+      while (aux.size() & 3) aux.push_back(0);
+    }
   }
-  std::vector<Mat<MT>> mats(h->L + 1);
-  std::vector<Transfer> trs(h->L + 1);
-  std::memset(mats.data(), 0, mats.size() * sizeof(Mat<MT>));
-  std::memset(trs.data(), 0, trs.size() * sizeof(Transfer));
-  for (int l = t; l < h->L; ++l) {
-    Mat<MT> A = plain_mat_of<MT>(h->lv[l]);
-    A.off = (const int*)tr(A.off);
-    A.width = (const int*)tr(A.width);
-    A.col = (const int*)tr(A.col);
-    A.val = (const MT*)tr(A.val);
-    A.D = (const MT*)tr(A.D);
-    mats[l] = A;
-    Transfer T = transfer_of(h, l);
-    T.agg = (const int*)tr(T.agg);
-    T.members = (const int*)tr(T.members);
-    T.member_off = (const int*)tr(T.member_off);
-    trs[l] = T;
-  }
-  const void* Linv = tr(h->chol_inv);
-  const void* LinvT = tr(h->chol_invT);
-  const void* scal_t = tr(h->scal);
-  const void* sol_t = tr(h->ws[t].sol);
+  std::vector<TailCode> code(ins.size());
+  for (size_t i = 0; i < ins.size(); ++i) ok = pack_instr(ins[i], code[i]) && ok;
+  const uint32_t linv = lo(h->chol_inv);
+  const uint32_t linvt = lo(h->chol_invT);
+  const uint32_t scal_t = lo(h->scal);
+  const uint32_t sol_t = lo(h->ws[t].sol);
   if (!ok || need > budget) {
     set_last_error("tail program refers to data outside its LDS image");
     return AMG_ERR_DEVICE;
   }
-  // the header (ops, descriptors) and the constant buffers packed into one
-  // device blob laid out as the start of the LDS image
-  std::vector<char> head(trs_off + round16((h->L + 1) * sizeof(Transfer)), 0);
-  std::memcpy(head.data() + ops_off, ops.data(), ops.size() * sizeof(TailOp));
-  std::memcpy(head.data() + mats_off, mats.data(), mats.size() * sizeof(Mat<MT>));
-  std::memcpy(head.data() + trs_off, trs.data(), trs.size() * sizeof(Transfer));
+  // the header (operand lists) and the constant buffers packed into one
+  // device blob laid out as the start of the LDS image; the instructions
+  // follow it in device memory (read from there, not copied into LDS)
+  std::vector<char> head(header_bytes(ops), 0);
+  if (!aux.empty()) std::memcpy(head.data() + aux_off, aux.data(), aux.size() * sizeof(int32_t));
   const size_t blob_bytes = std::max<size_t>(head.size(), const_end);
+  const size_t code_at = round16(blob_bytes) + 256;
   char* d_blob = nullptr;
   void* d_cin = nullptr;
-  AMG_TRY(dalloc(h, (void**)&d_blob, blob_bytes + 16));
-  AMG_HIP(hipMemcpyAsync(d_blob, head.data(), head.size(), hipMemcpyHostToDevice, s));
+  AMG_TRY(dalloc(h, (void**)&d_blob, code_at + code.size() * sizeof(TailCode) + 16));
+  if (!head.empty()) AMG_HIP(hipMemcpyAsync(d_blob, head.data(), head.size(), hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(d_blob + code_at, code.data(), code.size() * sizeof(TailCode), hipMemcpyHostToDevice, s));
   for (const auto& c : consts)
     if (c.first->bytes > 0)
       AMG_HIP(hipMemcpyAsync(d_blob + c.second, c.first->g, c.first->bytes, hipMemcpyDeviceToDevice, s));
@@ -936,13 +1007,13 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   std::memset(&P, 0, sizeof(P));
   P.nops = (int)ops.size();
   P.ncin = (int)cin.size();
-  P.ops_off = ops_off;
-  P.mats_off = mats_off;
-  P.trs_off = trs_off;
-  P.scal_off = (uint32_t)(uint64_t)scal_t;
+  P.ops = reinterpret_cast<const TailCode*>(d_blob + code_at);
+  P.scal_off = scal_t;
   P.cin = (const TailCopy*)d_cin;
-  P.cout = TailCopy{h->ws[t].sol, (uint32_t)(uint64_t)sol_t, (int)round16(sizeof(VT) * h->lv[t].n)};
-  P.C = CoarseView{h->nL, (const double*)Linv, (const double*)LinvT};
+  P.cout = TailCopy{h->ws[t].sol, sol_t, (int)round16(sizeof(VT) * h->lv[t].n)};
+  P.linv_off = linv;
+  P.linvt_off = linvt;
+  P.nL = h->nL;
   h->tail_prog_storage.resize(sizeof(TailProgram));
   std::memcpy(h->tail_prog_storage.data(), &P, sizeof(P));
   h->tail_prog = h->tail_prog_storage.data();
