@@ -44,6 +44,10 @@ struct amg_hier {
     void* sol = nullptr;
     void* Z[8] = {};
     void* Q[8] = {};
+    // launch-bound levels with two inner steps: the right-hand side after
+    // step 0 and the direction of step 1 (updates folded into later kernels)
+    void* rhs2 = nullptr;
+    void* P1 = nullptr;
   };
   std::vector<Work> ws;
   // outer flexible CG (always FP64, finest level)

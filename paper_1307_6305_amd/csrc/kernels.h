@@ -108,6 +108,50 @@ struct XProlong {
   __device__ __forceinline__ VT operator()(int j) const { return x[j] + e[agg[j]]; }
 };
 
+// Flexible-CG vector updates read where they are used instead of in a pass
+// of their own.  Each computes exactly what the update step stores (FP64
+// fused multiply-add, rounded to the vector type), so folding changes no bit.
+//   XAxpy:  r_j - alpha q_j        (right-hand side after a step)
+//   XDir:   z_j - beta p_j         (new direction against one earlier one)
+//   CUpd:   x_a + alpha p_a        (inner solution after its last step)
+template <typename VT>
+__device__ __forceinline__ VT fcg_axpy(double a, double x, double y) {
+  return (VT)__builtin_fma(a, x, y);
+}
+
+template <typename VT>
+struct XAxpy {
+  const VT* __restrict__ r;
+  const VT* __restrict__ q;
+  double alpha;
+  __device__ __forceinline__ VT operator()(int j) const { return fcg_axpy<VT>(-alpha, (double)q[j], (double)r[j]); }
+};
+
+template <typename VT>
+struct XDir {
+  const VT* __restrict__ z;
+  const VT* __restrict__ p;
+  double beta;
+  __device__ __forceinline__ VT operator()(int j) const { return fcg_axpy<VT>(-beta, (double)p[j], (double)z[j]); }
+};
+
+template <typename VT>
+struct CUpd {
+  const VT* __restrict__ x;
+  const VT* __restrict__ p;
+  double alpha;
+  __device__ __forceinline__ VT operator()(int a) const { return fcg_axpy<VT>(alpha, (double)p[a], (double)x[a]); }
+};
+
+// x_j + e_{agg(j)} with the coarse correction e given by an accessor.
+template <typename VT, typename CE>
+struct XProlongC {
+  const VT* __restrict__ x;
+  CE e;
+  const int* __restrict__ agg;
+  __device__ __forceinline__ VT operator()(int j) const { return x[j] + e(agg[j]); }
+};
+
 // sum_j W_rj x_j over the stored entries of the row in `slot`, computed by
 // the K lanes j = 0..K-1 of the slot together (every lane gets the sum).
 // Entry k of the row goes to class k mod 8; each class is summed in order
@@ -224,6 +268,44 @@ __device__ __forceinline__ void row_cheb_first(const Mat<MT>& A, int slot, int j
   y[r] = (VT)yy;
 }
 
+// The same step with w0 and the accumulated start value of y given by
+// accessors (W0(j): w0 at row j; Y0(r): the value y is accumulated onto).
+// Returns the row in the writing lane (-1 in the others) and its w0 value.
+template <typename VT, typename MT, typename W0, typename Y0>
+__device__ __forceinline__ int row_cheb_first_a(const Mat<MT>& A, int slot, int j, const W0& w0, VT* w1, VT* y,
+                                                const Y0& yin, double theta, double inv_eta, double c0, double c1,
+                                                int accum, int store, VT* w0_out) {
+  using AT = VT;
+  const int r = row_at(A, slot);
+  const AT x0 = (AT)w0(r);
+  const AT d = (AT)A.D[r];
+  const AT y0 = accum ? (AT)yin(r) : (AT)0;
+  const AT off = offdiag_a<AT, true>(A, slot, j, w0);
+  if (j) return -1;
+  const AT ax = d * x0 - off;
+  const AT t = (ax - (AT)theta * x0) * (AT)inv_eta;
+  if (store) w1[r] = (VT)t;
+  AT yy = (AT)c0 * x0 + (AT)c1 * t;
+  if (accum) yy += y0;
+  y[r] = (VT)yy;
+  *w0_out = (VT)x0;
+  return r;
+}
+
+template <typename VT>
+struct YPlain {
+  const VT* __restrict__ y;
+  __device__ __forceinline__ VT operator()(int r) const { return y[r]; }
+};
+
+template <typename VT, typename CE>
+struct YFold {
+  const VT* __restrict__ y;
+  CE e;
+  const int* __restrict__ agg;
+  __device__ __forceinline__ VT operator()(int r) const { return (VT)(y[r] + e(agg[r])); }
+};
+
 // w_{k+1} = 2 (A w_k - theta w_k) / eta - w_{k-1};  y += c_{k+1} w_{k+1}.
 // wnext may alias wprev (each element is read before it is overwritten).
 template <typename VT, typename MT, typename PT, bool G = true>
@@ -279,6 +361,23 @@ __device__ __forceinline__ int row_residual_p(const Mat<MT>& A, int slot, int j,
   return r;
 }
 
+// s = f - A X with the operand given by an accessor (X(j): x_j, e.g.
+// x_j + e_{agg(j)}).
+template <typename VT, typename MT, typename RT, typename XA>
+__device__ __forceinline__ int row_residual_a(const Mat<MT>& A, int slot, int j, const RT* __restrict__ f,
+                                              const XA& X, VT* s) {
+  using AT = VT;
+  const int r = row_at(A, slot);
+  const AT xr = (AT)X(r);
+  const AT d = (AT)A.D[r];
+  const AT fr = (AT)f[r];
+  const AT off = offdiag_a<AT, true>(A, slot, j, X);
+  if (j) return -1;
+  const AT ax = d * xr - off;
+  s[r] = (VT)(fr - ax);
+  return r;
+}
+
 template <typename VT>
 __device__ __forceinline__ void row_restrict(const Transfer& T, int I, const VT* __restrict__ s, VT* b) {
   VT acc = 0;
@@ -307,6 +406,25 @@ __device__ __forceinline__ int row_spmv_dots(const Mat<MT>& A, int slot, int j, 
   q[r] = (VT)ap;
   v[0] = (double)pr * (double)ap;
   v[1] = (double)pr * rr;
+  return r;
+}
+
+// q = A P with the operand given by an accessor; also returns P_r in pr.
+template <typename VT, typename MT, typename RT, typename PA>
+__device__ __forceinline__ int row_spmv_dots_a(const Mat<MT>& A, int slot, int j, const PA& P, VT* q,
+                                               const RT* __restrict__ rv, double (&v)[2], VT* pr_out) {
+  using AT = VT;
+  const int r = row_at(A, slot);
+  const AT pr = (AT)P(r);
+  const AT d = (AT)A.D[r];
+  const double rr = (double)rv[r];
+  const AT off = offdiag_a<AT, true>(A, slot, j, P);
+  if (j) return -1;
+  const AT ap = d * pr - off;
+  q[r] = (VT)ap;
+  v[0] = (double)pr * (double)ap;
+  v[1] = (double)pr * rr;
+  *pr_out = (VT)pr;
   return r;
 }
 

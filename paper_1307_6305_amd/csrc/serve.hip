@@ -160,7 +160,7 @@ struct Server {
     const size_t data = 2 * level0;
     // outer FCG vectors, the finest level's cycle vectors, coarse-level vectors
     const size_t work = (16 + 16 * (size_t)cfg.params.restart + 4 * vt) * n +
-                        (5 + 2 * (size_t)cfg.params.inner_steps) * vt * n;
+                        (7 + 2 * (size_t)cfg.params.inner_steps) * vt * n;
     return data + work + (64 << 10);
   }
 

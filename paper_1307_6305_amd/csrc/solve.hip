@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(TPB) k_fcg_p(int n, PT* p, const ZT* z, VecPtr
   double v = (double)z[j];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
-    if (i < k) v -= beta[i] * (double)static_cast<const PT*>(ps.p[i])[j];
+    if (i < k) v = __builtin_fma(-beta[i], (double)static_cast<const PT*>(ps.p[i])[j], v);
   p[j] = (PT)v;
 }
 
@@ -212,14 +212,98 @@ __global__ void __launch_bounds__(TPB) k_fcg_xr(int n, const PT* __restrict__ p,
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) {
     const double pj = (double)p[j];
-    x[j] = (VT)(x_init ? alpha * pj : (double)x[j] + alpha * pj);
+    x[j] = x_init ? (VT)(alpha * pj) : fcg_axpy<VT>(alpha, pj, (double)x[j]);
     if (upd_r) {
-      const double rj = (double)r[j] - alpha * (double)q[j];
+      const double rj = __builtin_fma(-alpha, (double)q[j], (double)r[j]);
       r[j] = (VT)rj;
       if (RR) v[0] = rj * rj;
     }
   }
   if (RR) grid_sum_finish<1>(v, red);
+}
+
+// ---- flexible-CG updates folded into the kernels that read their results
+// (inner solves of the launch-bound levels, two steps).
+
+// First smoothing step of inner step 1 with step 0's update applied on the
+// fly: w0 = rhs - alpha q (stored into rhs2 for the steps that follow) and
+// sol = alpha p (x_init) or sol + alpha p.
+template <typename VT, typename MT>
+__global__ void __launch_bounds__(kMaxRowThreads) k_cheb_first_upd(Mat<MT> A, const VT* __restrict__ rhs,
+                                                                   const VT* __restrict__ q, VT* rhs2,
+                                                                   const VT* __restrict__ p, VT* sol, int x_init,
+                                                                   VT* w1, VT* y, double theta, double inv_eta,
+                                                                   double c0, double c1, int store,
+                                                                   const double* scal, int s_rho, int s_gam) {
+  const double alpha = fcg_alpha(scal, s_rho, s_gam);
+  const SlotLane sl = slot_of(A);
+  if (sl.slot < 0) return;
+  VT w0v;
+  const int r = row_cheb_first_a<VT, MT>(A, sl.slot, sl.lane, XAxpy<VT>{rhs, q, alpha}, w1, y, YPlain<VT>{y}, theta,
+                                         inv_eta, c0, c1, 0, store, &w0v);
+  if (r >= 0) {
+    rhs2[r] = w0v;
+    const double pr = (double)p[r];
+    sol[r] = x_init ? (VT)(alpha * pr) : fcg_axpy<VT>(alpha, pr, (double)sol[r]);
+  }
+}
+
+// q = A p with p = z - beta z0 formed on the fly (beta = dot / rho) and
+// stored into pout; (p, q) and (p, r) as in k_spmv_dots.
+template <typename VT, typename MT>
+__global__ void __launch_bounds__(kMaxRowThreads) k_spmv_dots_dir(Mat<MT> A, const VT* __restrict__ z,
+                                                                  const VT* __restrict__ z0, VT* pout, VT* q,
+                                                                  const VT* __restrict__ rv, const double* scal,
+                                                                  int s_dot, int s_rho, Red red) {
+  __shared__ double stage[2 * TPB];
+  const double beta = fcg_beta(scal, s_dot, s_rho);
+  const SlotLane sl = slot_of(A);
+  double v[2] = {0.0, 0.0};
+  int r = -1;
+  if (sl.slot >= 0) {
+    VT pr;
+    r = row_spmv_dots_a<VT, MT, VT>(A, sl.slot, sl.lane, XDir<VT>{z, z0, beta}, q, rv, v, &pr);
+    if (r >= 0) pout[r] = pr;
+  }
+  if (needs_stage(A)) tile_stage<2>(v, r >= 0 ? r - sl.tile * TPB : -1, stage);
+  grid_sum_finish<2>(v, red);
+}
+
+// The prolongation consumers with the coarse correction e = esol + alpha ep
+// (the inner solve's last update, never stored).
+template <typename VT, typename MT, typename RT>
+__global__ void __launch_bounds__(kMaxRowThreads) k_residual_pu(Mat<MT> A, const RT* __restrict__ f,
+                                                                const VT* __restrict__ x, const VT* __restrict__ esol,
+                                                                const VT* __restrict__ ep, const int* __restrict__ agg,
+                                                                VT* s, const double* scal, int s_rho, int s_gam) {
+  const double alpha = fcg_alpha(scal, s_rho, s_gam);
+  const SlotLane q = slot_of(A);
+  if (q.slot >= 0)
+    (void)row_residual_a<VT, MT, RT>(A, q.slot, q.lane, f,
+                                     XProlongC<VT, CUpd<VT>>{x, CUpd<VT>{esol, ep, alpha}, agg}, s);
+}
+
+template <typename VT, typename MT, typename RT>
+__global__ void __launch_bounds__(kMaxRowThreads) k_cheb_first_fu(Mat<MT> A, const RT* __restrict__ w0, VT* w1, VT* y,
+                                                                  double theta, double inv_eta, double c0, double c1,
+                                                                  int store, const VT* __restrict__ esol,
+                                                                  const VT* __restrict__ ep, const int* __restrict__ agg,
+                                                                  const double* scal, int s_rho, int s_gam) {
+  const double alpha = fcg_alpha(scal, s_rho, s_gam);
+  const SlotLane q = slot_of(A);
+  if (q.slot < 0) return;
+  VT w0v;
+  (void)row_cheb_first_a<VT, MT>(A, q.slot, q.lane, XPlain<RT>{w0}, w1, y,
+                                 YFold<VT, CUpd<VT>>{y, CUpd<VT>{esol, ep, alpha}, agg}, theta, inv_eta, c0, c1, 1,
+                                 store, &w0v);
+}
+
+template <typename VT>
+__global__ void k_prolong_u(Transfer T, const VT* __restrict__ esol, const VT* __restrict__ ep, VT* x,
+                            const double* scal, int s_rho, int s_gam) {
+  const double alpha = fcg_alpha(scal, s_rho, s_gam);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T.n) x[i] += CUpd<VT>{esol, ep, alpha}(T.agg[i]);
 }
 
 template <int K>
@@ -277,6 +361,25 @@ struct Engine {
   hipStream_t s;
   std::vector<TailOp>* rec = nullptr;
 
+  // An inner solve's last update x += alpha p, left to the kernels that read
+  // the coarse correction (alpha from the step's scalar slots).
+  struct Deferred {
+    bool on = false;
+    const VT* sol = nullptr;
+    const VT* p = nullptr;
+    int s_rho = 0, s_gam = 0;
+  };
+  // The previous inner step's update, applied by the first smoothing step of
+  // the next one: rhs2 = rhs - alpha q, sol = [sol +] alpha p.
+  struct StepUpd {
+    const VT* rhs;
+    const VT* q;
+    const VT* p;
+    VT* sol;
+    int x_init;
+    int s_rho, s_gam;
+  };
+
   Mat<MT> A(int l) const { return mat_of<MT>(h->lv[l]); }
   static VT* wsv(void* p) { return static_cast<VT*>(p); }
 
@@ -302,10 +405,31 @@ struct Engine {
   }
 
   // fold_e: y holds x before the prolongation of the coarse correction fold_e
+  // (fold_d.on: the correction is fold_d.sol + alpha fold_d.p).  upd: w0 is
+  // rhs2 of the update, formed on the fly and stored (accum false).
   template <typename RT>
   int32_t cheb_first(int l, const RT* w0, VT* w1, VT* y, double c0, double c1, bool accum, bool store,
-                     const VT* fold_e = nullptr) {
+                     const VT* fold_e = nullptr, const Deferred* fold_d = nullptr, const StepUpd* upd = nullptr) {
     const Level& lv = h->lv[l];
+    if (!rec && upd) {
+      if constexpr (std::is_same<RT, VT>::value) {
+        const auto Am = A(l);
+        hipLaunchKernelGGL((k_cheb_first_upd<VT, MT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, upd->rhs, upd->q,
+                           const_cast<VT*>(w0), upd->p, upd->sol, upd->x_init, w1, y, lv.theta, 1.0 / lv.eta, c0, c1,
+                           (int)store, (const double*)h->scal, upd->s_rho, upd->s_gam);
+        AMG_HIP(hipGetLastError());
+        return AMG_OK;
+      }
+      return AMG_ERR_DEVICE;
+    }
+    if (!rec && fold_d && fold_d->on) {
+      const auto Am = A(l);
+      hipLaunchKernelGGL((k_cheb_first_fu<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, w0, w1, y, lv.theta,
+                         1.0 / lv.eta, c0, c1, (int)store, fold_d->sol, fold_d->p, transfer_of(h, l).agg,
+                         (const double*)h->scal, fold_d->s_rho, fold_d->s_gam);
+      AMG_HIP(hipGetLastError());
+      return AMG_OK;
+    }
     if (rec) {
       if constexpr (std::is_same<RT, VT>::value) {
         TailOp o = op(OP_CHEB_FIRST, l, lv.n);
@@ -404,14 +528,15 @@ struct Engine {
   // w_k and w_{k-1} (w_{k+1} overwrites w_{k-1} in place).  fold_e (m >= 1,
   // accumulating): y is x before the prolongation x += P fold_e.
   template <typename RT>
-  int32_t smooth(int l, const RT* r, VT* y, bool accum, const VT* fold_e = nullptr) {
+  int32_t smooth(int l, const RT* r, VT* y, bool accum, const VT* fold_e = nullptr, const Deferred* fold_d = nullptr,
+                 const StepUpd* upd = nullptr) {
     const Level& lv = h->lv[l];
     const int m = h->p.degree;
     const double* c = lv.coef.data();
     if (m == 0) return scale_add(l, r, y, c[0], accum);
     VT* bufA = wsv(h->ws[l].A);
     VT* bufB = wsv(h->ws[l].B);
-    AMG_TRY(cheb_first(l, r, bufA, y, c[0], c[1], accum, m > 1, fold_e));
+    AMG_TRY(cheb_first(l, r, bufA, y, c[0], c[1], accum, m > 1, fold_e, fold_d, upd));
     VT* cur = bufA;
     VT* prevbuf = nullptr;
     for (int k = 1; k < m; ++k) {
@@ -449,7 +574,14 @@ struct Engine {
 
   // out = f - A (x + P e), x itself unchanged
   template <typename RT>
-  int32_t residual_p(int l, const RT* f, const VT* x, const VT* e, VT* out) {
+  int32_t residual_p(int l, const RT* f, const VT* x, const VT* e, VT* out, const Deferred* d = nullptr) {
+    if (!rec && d && d->on) {
+      const auto Am = A(l);
+      hipLaunchKernelGGL((k_residual_pu<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, f, x, d->sol, d->p,
+                         transfer_of(h, l).agg, out, (const double*)h->scal, d->s_rho, d->s_gam);
+      AMG_HIP(hipGetLastError());
+      return AMG_OK;
+    }
     if (rec) {
       if constexpr (std::is_same<RT, VT>::value) {
         TailOp o = op(OP_RESIDUAL_P, l, h->lv[l].n);
@@ -481,8 +613,14 @@ struct Engine {
     return AMG_OK;
   }
 
-  int32_t prolong(int l, const VT* e, VT* x) {
+  int32_t prolong(int l, const VT* e, VT* x, const Deferred* d = nullptr) {
     const Transfer T = transfer_of(h, l);
+    if (!rec && d && d->on) {
+      hipLaunchKernelGGL((k_prolong_u<VT>), dim3(nblk(T.n)), dim3(TPB), 0, s, T, d->sol, d->p, x,
+                         (const double*)h->scal, d->s_rho, d->s_gam);
+      AMG_HIP(hipGetLastError());
+      return AMG_OK;
+    }
     if (rec) {
       TailOp o = op(OP_PROLONG, l, T.n);
       o.a = e; o.c = x;
@@ -588,38 +726,83 @@ struct Engine {
 
   // x = Kcycle(l, r)
   template <typename RT>
-  int32_t kcycle(int l, const RT* r, VT* x) {
+  // upd: the first smoothing step also applies the previous inner step's
+  // update (r is then the rhs2 it writes).
+  int32_t kcycle(int l, const RT* r, VT* x, const StepUpd* upd = nullptr) {
     if (l == h->L) return coarse(r, x);
     VT* S = wsv(h->ws[l].S);
     VT* b = wsv(h->ws[l + 1].rhs);
     VT* e = wsv(h->ws[l + 1].sol);
-    AMG_TRY(smooth(l, r, x, false));
+    AMG_TRY(smooth(l, r, x, false, nullptr, nullptr, upd));
     AMG_TRY(residual(l, r, x, S));
     AMG_TRY(restrict_(l, S, b));
+    Deferred d;
     if (l + 1 == h->L) {
       AMG_TRY(coarse(static_cast<const VT*>(b), e));
     } else if (!rec && h->tail_level == l + 1) {
       AMG_TRY(tail());
     } else {
-      AMG_TRY(inner(l + 1));
+      AMG_TRY(inner(l + 1, &d));
     }
     // on launch-bound levels (and in recorded programs) the prolongation
     // x += P e is folded into the residual and the first smoothing step that
     // follow it: the same roundings, one pass fewer
     if (h->p.degree > 0 && (rec || h->lv[l].n < kFoldProlongRows)) {
-      AMG_TRY(residual_p(l, r, x, e, S));
-      AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true, e));
+      AMG_TRY(residual_p(l, r, x, e, S, &d));
+      AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true, e, &d));
       return AMG_OK;
     }
-    AMG_TRY(prolong(l, e, x));
+    AMG_TRY(prolong(l, e, x, &d));
     AMG_TRY(residual(l, r, x, S));
     AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true));
     return AMG_OK;
   }
 
+  // Two flexible-CG steps on a launch-bound level with the vector updates
+  // folded into the kernels that read them: step 0's update goes into step
+  // 1's first smoothing step, step 1's direction into its product, and step
+  // 1's update of the solution into the caller's prolongation (*out).
+  int32_t inner_folded(int l, Deferred* out) {
+    const int n = h->lv[l].n;
+    auto& W = h->ws[l];
+    VT* rhs = wsv(W.rhs);
+    VT* rhs2 = wsv(W.rhs2);
+    VT* sol = wsv(W.sol);
+    VT* Z0 = wsv(W.Z[0]);
+    VT* Z1 = wsv(W.Z[1]);
+    VT* Q0 = wsv(W.Q[0]);
+    VT* Q1 = wsv(W.Q[1]);
+    VT* P1 = wsv(W.P1);
+    const int base = lbase(l);
+    AMG_TRY(kcycle(l, static_cast<const VT*>(rhs), Z0));
+    AMG_TRY(spmv_dots(l, Z0, Q0, rhs, slots2(base, base + 8)));
+    const StepUpd u{rhs, Q0, Z0, sol, 1, base, base + 8};
+    AMG_TRY(kcycle(l, static_cast<const VT*>(rhs2), Z1, &u));
+    VecPtrs qs{};
+    qs.p[0] = W.Q[0];
+    AMG_TRY(multidot(l, n, Z1, qs, 1, slots_range(base + 16, 1), false));
+    const auto Am = A(l);
+    const Slots pq = slots2(base + 1, base + 9);
+    hipLaunchKernelGGL((k_spmv_dots_dir<VT, MT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, Z1, Z0, P1, Q1, rhs2,
+                       (const double*)h->scal, base + 16, base, red_for(Am.nb, pq));
+    AMG_HIP(hipGetLastError());
+    AMG_TRY(finish<2>(Am.nb, pq));
+    out->on = true;
+    out->sol = sol;
+    out->p = P1;
+    out->s_rho = base + 1;
+    out->s_gam = base + 9;
+    return AMG_OK;
+  }
+
   // exactly nu flexible-CG steps from zero on level l (1 <= l < L): rhs -> sol
-  int32_t inner(int l) {
+  // (with `out` given, the launch-bound two-step case may leave the last
+  // update of sol to the caller, see inner_folded)
+  int32_t inner(int l, Deferred* out = nullptr) {
     const int nu = h->p.inner_steps;
+    if (out && !rec && nu == 2 && h->p.degree > 0 && h->lv[l].n < kFoldProlongRows && h->ws[l].rhs2 &&
+        h->ws[l].P1)
+      return inner_folded(l, out);
     const int n = h->lv[l].n;
     auto& W = h->ws[l];
     VT* rhs = wsv(W.rhs);
@@ -1071,6 +1254,10 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
       for (int k = 0; k < h->p.inner_steps; ++k) {
         AMG_TRY(dalloc(h, &W.Z[k], n * vt + 16));
         AMG_TRY(dalloc(h, &W.Q[k], n * vt + 16));
+      }
+      if (h->p.inner_steps == 2 && h->p.degree > 0 && n < (size_t)kFoldProlongRows) {
+        AMG_TRY(dalloc(h, &W.rhs2, n * vt + 16));
+        AMG_TRY(dalloc(h, &W.P1, n * vt + 16));
       }
     }
   }
