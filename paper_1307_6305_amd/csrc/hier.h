@@ -48,6 +48,11 @@ struct amg_hier {
     // step 0 and the direction of step 1 (updates folded into later kernels)
     void* rhs2 = nullptr;
     void* P1 = nullptr;
+    // launch-bound levels: aggregate-to-block map of the fused residual +
+    // restriction, and the row-to-slot map of a sorted layout
+    void* agg_blk = nullptr;
+    int n_agg_blk = 0;
+    void* slot_of_row = nullptr;
   };
   std::vector<Work> ws;
   // outer flexible CG (always FP64, finest level)

@@ -378,6 +378,20 @@ __device__ __forceinline__ int row_residual_a(const Mat<MT>& A, int slot, int j,
   return r;
 }
 
+// The value f_r - (A x)_r of the row in `slot` (every lane gets it; the
+// same arithmetic as row_residual).
+template <typename VT, typename MT, typename RT>
+__device__ __forceinline__ VT row_residual_value(const Mat<MT>& A, int slot, int j, const RT* __restrict__ f,
+                                                 const VT* __restrict__ x, int r) {
+  using AT = VT;
+  const AT xr = (AT)x[r];
+  const AT d = (AT)A.D[r];
+  const AT fr = (AT)f[r];
+  const AT off = offdiag<AT, true>(A, slot, j, x);
+  const AT ax = d * xr - off;
+  return (VT)(fr - ax);
+}
+
 template <typename VT>
 __device__ __forceinline__ void row_restrict(const Transfer& T, int I, const VT* __restrict__ s, VT* b) {
   VT acc = 0;

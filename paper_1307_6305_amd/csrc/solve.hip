@@ -121,6 +121,36 @@ __global__ void k_restrict(Transfer T, const VT* __restrict__ s, VT* b) {
   if (I < T.nc) row_restrict<VT>(T, I, s, b);
 }
 
+// b = P^T (f - A x) in one pass on launch-bound levels: block k takes the
+// aggregates agg_blk[k] .. agg_blk[k + 1] - 1 (at most TPB member rows, their
+// member lists contiguous), K lanes compute each member row's residual (the
+// value k_residual stores), the rows are staged in member order and each
+// aggregate adds its members in order, as k_restrict does.  slot_of_row maps
+// a row to its slot in sorted layouts (null otherwise).
+template <typename VT, typename MT, typename RT>
+__global__ void __launch_bounds__(kMaxRowThreads) k_restrict_residual(Mat<MT> A, Transfer T,
+                                                                      const int* __restrict__ agg_blk,
+                                                                      const int* __restrict__ slot_of_row,
+                                                                      const RT* __restrict__ f,
+                                                                      const VT* __restrict__ x, VT* b) {
+  __shared__ VT stage[TPB];
+  const int J0 = agg_blk[blockIdx.x], J1 = agg_blk[blockIdx.x + 1];
+  const int m0 = T.member_off[J0], m1 = T.member_off[J1];
+  const int m = threadIdx.x >> A.lk, lane = threadIdx.x & ((1 << A.lk) - 1);
+  if (m0 + m < m1) {
+    const int r = T.members[m0 + m];
+    const int slot = slot_of_row ? slot_of_row[r] : r;
+    const VT v = row_residual_value<VT, MT, RT>(A, slot, lane, f, x, r);
+    if (lane == 0) stage[m] = v;
+  }
+  __syncthreads();
+  for (int J = J0 + (int)threadIdx.x; J < J1; J += blockDim.x) {
+    VT acc = 0;
+    for (int k = T.member_off[J]; k < T.member_off[J + 1]; ++k) acc += stage[k - m0];
+    b[J] = acc;
+  }
+}
+
 template <typename VT>
 __global__ void k_prolong(Transfer T, const VT* __restrict__ e, VT* x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -600,6 +630,21 @@ struct Engine {
     return AMG_OK;
   }
 
+  // b = P^T (f - A x) without storing the residual (levels with an
+  // aggregate-to-block map); false when the level has none.
+  template <typename RT>
+  bool restrict_residual(int l, const RT* f, const VT* x, VT* b, int32_t* st) {
+    const auto& W = h->ws[l];
+    if (rec || !W.agg_blk) return false;
+    const auto Am = A(l);
+    hipLaunchKernelGGL((k_restrict_residual<VT, MT, RT>), dim3(W.n_agg_blk), dim3(TPB << Am.lk), 0, s, Am,
+                       transfer_of(h, l), (const int*)W.agg_blk, (const int*)W.slot_of_row, f, x, b);
+    const hipError_t e = hipGetLastError();
+    *st = e == hipSuccess ? AMG_OK : AMG_ERR_DEVICE;
+    if (e != hipSuccess) set_last_error(std::string("k_restrict_residual: ") + hipGetErrorString(e));
+    return true;
+  }
+
   int32_t restrict_(int l, const VT* sv, VT* b) {
     const Transfer T = transfer_of(h, l);
     if (rec) {
@@ -734,8 +779,13 @@ struct Engine {
     VT* b = wsv(h->ws[l + 1].rhs);
     VT* e = wsv(h->ws[l + 1].sol);
     AMG_TRY(smooth(l, r, x, false, nullptr, nullptr, upd));
-    AMG_TRY(residual(l, r, x, S));
-    AMG_TRY(restrict_(l, S, b));
+    int32_t rst = AMG_OK;
+    if (restrict_residual(l, r, x, b, &rst)) {
+      AMG_TRY(rst);
+    } else {
+      AMG_TRY(residual(l, r, x, S));
+      AMG_TRY(restrict_(l, S, b));
+    }
     Deferred d;
     if (l + 1 == h->L) {
       AMG_TRY(coarse(static_cast<const VT*>(b), e));
@@ -1220,6 +1270,49 @@ void destroy_graphs(amg_hier* h) {
 
 int32_t prepare_solve_impl(amg_hier* h, hipStream_t s);
 
+// The aggregate-to-block map of the fused residual + restriction on level l:
+// aggregates in order, packed greedily into blocks of at most TPB member
+// rows; members must be listed aggregate by aggregate.  Sorted layouts also
+// get the row-to-slot map.  Levels where a single aggregate exceeds a block
+// keep the two separate steps.
+int32_t prepare_restrict_residual(amg_hier* h, int l, hipStream_t s) {
+  const Level& lv = h->lv[l];
+  const int n = lv.n, nc = h->lv[l + 1].n;
+  std::vector<int> moff(nc + 1);
+  AMG_HIP(hipMemcpyAsync(moff.data(), lv.member_off, sizeof(int) * (nc + 1), hipMemcpyDeviceToHost, s));
+  std::vector<int> perm;
+  if (lv.sell_perm) {
+    perm.resize(n);
+    AMG_HIP(hipMemcpyAsync(perm.data(), lv.sell_perm, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+  if (moff[0] != 0 || moff[nc] != n) return AMG_OK;
+  std::vector<int> blk{0};
+  int rows = 0;
+  for (int J = 0; J < nc; ++J) {
+    const int sz = moff[J + 1] - moff[J];
+    if (sz > TPB) return AMG_OK;
+    if (rows + sz > TPB) {
+      blk.push_back(J);
+      rows = 0;
+    }
+    rows += sz;
+  }
+  blk.push_back(nc);
+  auto& W = h->ws[l];
+  AMG_TRY(dalloc(h, &W.agg_blk, sizeof(int) * blk.size()));
+  AMG_HIP(hipMemcpyAsync(W.agg_blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice, s));
+  W.n_agg_blk = (int)blk.size() - 1;
+  if (lv.sell_perm) {
+    std::vector<int> inv(n);
+    for (int q = 0; q < n; ++q) inv[perm[q]] = q;
+    AMG_TRY(dalloc(h, &W.slot_of_row, sizeof(int) * n));
+    AMG_HIP(hipMemcpyAsync(W.slot_of_row, inv.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+  return AMG_OK;
+}
+
 int32_t prepare_solve(amg_hier* h, hipStream_t s) {
   const size_t before = h->bytes;
   const int32_t st = prepare_solve_impl(h, s);
@@ -1260,6 +1353,7 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
         AMG_TRY(dalloc(h, &W.P1, n * vt + 16));
       }
     }
+    if (l < h->L && n < (size_t)kFoldProlongRows) AMG_TRY(prepare_restrict_residual(h, l, s));
   }
   const size_t n0 = h->lv[0].n;
   AMG_TRY(dalloc(h, &h->r, n0));
