@@ -336,16 +336,30 @@ __global__ void k_prolong_u(Transfer T, const VT* __restrict__ esol, const VT* _
   if (i < T.n) x[i] += CUpd<VT>{esol, ep, alpha}(T.agg[i]);
 }
 
+// Stores the two numbers of the host's stopping test (scal[a], scal[b]) into
+// the pinned host mirror (system-scope stores, visible once the stream has
+// been synchronized).
+__device__ __forceinline__ void publish2(double* host, double va, double vb) {
+  __hip_atomic_store(host + 1, vb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(host, va, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// host: also publish (acc[0], scal[pub]) for the host (K = 1 sums only).
 template <int K>
 __global__ void __launch_bounds__(kFinishThreads) k_finish_sum(int nparts, const double* partials, double* scal,
-                                                               Slots slots) {
+                                                               Slots slots, double* host, int pub) {
   __shared__ double red[16 * 8];
   double acc[K];
   sum_partials<K>(partials, nparts, acc, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) scal[slots.s[k]] = acc[k];
+    if (host) publish2(host, acc[0], scal[pub]);
   }
+}
+
+__global__ void k_publish(const double* scal, int a, int b, double* host) {
+  if (threadIdx.x == 0) publish2(host, scal[a], scal[b]);
 }
 
 template <typename A, typename B>
@@ -426,10 +440,18 @@ struct Engine {
   Red red_for(int blocks, Slots slots) const {
     return Red{h->partials, h->counter, h->scal, slots, blocks <= h->last_block_max ? 1 : 0};
   }
+  // host: publish (the sum, scal[pub]) to the pinned host mirror as well
   template <int K>
-  int32_t finish(int blocks, Slots slots) {
-    if (blocks <= h->last_block_max) return AMG_OK;
-    hipLaunchKernelGGL((k_finish_sum<K>), dim3(1), dim3(kFinishThreads), 0, s, blocks, h->partials, h->scal, slots);
+  int32_t finish(int blocks, Slots slots, double* host = nullptr, int pub = 0) {
+    if (blocks <= h->last_block_max) {
+      if (host) {
+        hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, (const double*)h->scal, slots.s[0], pub, host);
+        AMG_HIP(hipGetLastError());
+      }
+      return AMG_OK;
+    }
+    hipLaunchKernelGGL((k_finish_sum<K>), dim3(1), dim3(kFinishThreads), 0, s, blocks, h->partials, h->scal, slots,
+                       host, pub);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
@@ -899,11 +921,9 @@ struct Engine {
     const Slots rr = slots1(S_RR);
     hipLaunchKernelGGL((k_fcg_xr<double, double, true>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], h->Qo[j], u, h->r,
                        h->scal, S_RHOW + j, S_GAM, 0, 1, red_for(nb, rr));
-    AMG_TRY(finish<1>(nb, rr));
     AMG_HIP(hipGetLastError());
-    // stopping test inputs: (r, r) and rho_j
-    AMG_HIP(hipMemcpyAsync(h->host_scal, h->scal + S_RR, sizeof(double), hipMemcpyDeviceToHost, s));
-    AMG_HIP(hipMemcpyAsync(h->host_scal + 1, h->scal + S_RHOW + j, sizeof(double), hipMemcpyDeviceToHost, s));
+    // with the stopping test's inputs, (r, r) and rho_j, published to the host
+    AMG_TRY(finish<1>(nb, rr, h->host_scal, S_RHOW + j));
     return AMG_OK;
   }
 
@@ -1373,7 +1393,7 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
   AMG_TRY(dalloc(h, &h->counter, 1));
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, h->counter);
   AMG_HIP(hipGetLastError());
-  AMG_HIP(hipHostMalloc((void**)&h->host_scal, 64 * sizeof(double), hipHostMallocDefault));
+  AMG_HIP(hipHostMalloc((void**)&h->host_scal, 64 * sizeof(double), hipHostMallocCoherent));
   AMG_HIP(hipStreamSynchronize(s));
   if (h->mixed) {
     AMG_TRY(prepare_tail<float, float>(h, s));
