@@ -476,29 +476,56 @@ __device__ __forceinline__ double fcg_beta(const double* scal, int s_dot, int s_
 }
 
 // Coarsest solve x = L^-T (L^-1 b) with the inverted factor: two triangular
-// products, thread i owning rows i, i + blockDim, ... (n <= 1024).  For small
-// n every thread runs the full range of j -- the factor's other triangle
-// holds exact zeros, so the sums are unchanged -- which keeps the loop
-// uniform across the wavefront and lets its loads be issued ahead.
+// products.  For n <= 256 every product row is split into G = 4 partial sums
+// (column classes j mod 4, each added in order over the full range of j --
+// the factor's other triangle holds exact zeros, so the sums are unchanged),
+// which are then added as (p0 + p1) + (p2 + p3): four times shorter chains.
+// Larger n use one sum per row over its triangle.  The association depends
+// only on n, not on the block size.  sb and sy hold 1024 doubles each.
 template <typename VT, typename RT>
 __device__ __forceinline__ void coarse_apply(const CoarseView& C, const RT* __restrict__ b, VT* x, double* sb,
                                              double* sy) {
   const int n = C.n;
-  const bool full = n <= 256;
   for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = (double)b[i];
   __syncthreads();
+  if (n <= 256) {
+    constexpr int G = 4;
+    // y = L^-1 b: partials into sy, then y into sb
+    for (int t = threadIdx.x; t < G * n; t += blockDim.x) {
+      const int i = t / G, g = t % G;
+      double acc = 0.0;
+#pragma unroll 4
+      for (int j = g; j < n; j += G) acc += C.LinvT[(size_t)j * n + i] * sb[j];
+      sy[t] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      sb[i] = (sy[G * i] + sy[G * i + 1]) + (sy[G * i + 2] + sy[G * i + 3]);
+    __syncthreads();
+    // x = L^-T y
+    for (int t = threadIdx.x; t < G * n; t += blockDim.x) {
+      const int i = t / G, g = t % G;
+      double acc = 0.0;
+#pragma unroll 4
+      for (int j = g; j < n; j += G) acc += C.Linv[(size_t)j * n + i] * sb[j];
+      sy[t] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      x[i] = (VT)((sy[G * i] + sy[G * i + 1]) + (sy[G * i + 2] + sy[G * i + 3]));
+    return;
+  }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double acc = 0.0;
-    const int j1 = full ? n : i + 1;
 #pragma unroll 8
-    for (int j = 0; j < j1; ++j) acc += C.LinvT[(size_t)j * n + i] * sb[j];
+    for (int j = 0; j <= i; ++j) acc += C.LinvT[(size_t)j * n + i] * sb[j];
     sy[i] = acc;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double acc = 0.0;
 #pragma unroll 8
-    for (int j = full ? 0 : i; j < n; ++j) acc += C.Linv[(size_t)j * n + i] * sy[j];
+    for (int j = i; j < n; ++j) acc += C.Linv[(size_t)j * n + i] * sy[j];
     x[i] = (VT)acc;
   }
 }
@@ -634,6 +661,10 @@ struct TailProgram {
   TailCopy cout;  // solution of the tail level, LDS -> device
   uint32_t linv_off, linvt_off;  // inverse factor and its transpose (LDS)
   int nL;                        // coarsest size
+  // When the program's last step (sol += alpha p) is folded into the copy-out:
+  // LDS offset of p (0: plain copy), the step's scalar slots, row count.
+  uint32_t fin_p;
+  int fin_rho, fin_gam, fin_n;
 };
 
 template <typename T>
@@ -834,7 +865,13 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
     }
     __syncthreads();
   }
-  {
+  if (P.fin_p) {
+    const double alpha = fcg_alpha(scal, P.fin_rho, P.fin_gam);
+    const VT* x = lds_at<const VT>(lds, P.cout.dst);
+    const VT* p = lds_at<const VT>(lds, P.fin_p);
+    VT* dst = static_cast<VT*>(const_cast<void*>(P.cout.src));
+    for (int i = tid; i < P.fin_n; i += bd) dst[i] = fcg_axpy<VT>(alpha, (double)p[i], (double)x[i]);
+  } else {
     const int4* src = reinterpret_cast<const int4*>(lds + P.cout.dst);
     int4* dst = static_cast<int4*>(const_cast<void*>(P.cout.src));
     for (int i = tid; i < (P.cout.bytes >> 4); i += bd) dst[i] = src[i];

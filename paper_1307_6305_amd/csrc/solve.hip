@@ -1136,6 +1136,14 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
     Engine<VT, MT> E{h, s, &ops};
     AMG_TRY(E.inner(t));
   }
+  // the last step, sol += alpha p on the tail level, goes into the copy-out
+  TailOp fin{};
+  const bool fold_fin = !ops.empty() && ops.back().type == OP_FCG_XR && ops.back().i2 == 0 && ops.back().i3 == 0 &&
+                        ops.back().c == h->ws[t].sol;
+  if (fold_fin) {
+    fin = ops.back();
+    ops.pop_back();
+  }
   const uint32_t aux_off = 0;
   uint64_t off = header_bytes(ops);
   std::vector<LdsBuf> bufs;
@@ -1267,6 +1275,16 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   P.linv_off = linv;
   P.linvt_off = linvt;
   P.nL = h->nL;
+  if (fold_fin) {
+    P.fin_p = lo(fin.a);
+    P.fin_rho = fin.i0;
+    P.fin_gam = fin.i1;
+    P.fin_n = h->lv[t].n;
+    if (!ok || P.fin_p == 0) {
+      set_last_error("tail program: the folded last step refers to data outside its LDS image");
+      return AMG_ERR_DEVICE;
+    }
+  }
   h->tail_prog_storage.resize(sizeof(TailProgram));
   std::memcpy(h->tail_prog_storage.data(), &P, sizeof(P));
   h->tail_prog = h->tail_prog_storage.data();
