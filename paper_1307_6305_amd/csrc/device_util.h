@@ -140,17 +140,20 @@ constexpr int kFinishThreads = 256;
 
 // Sum of partials[b*K + k] over b < nparts in a fixed order, by one block of
 // kFinishThreads threads: thread t adds b = t, t + 256, ...; then the block tree.
+// kn: only the first kn of the K values are summed (the rest are left 0).
 template <int K>
-__device__ __forceinline__ void sum_partials(const double* partials, int nparts, double (&acc)[K], double* red) {
+__device__ __forceinline__ void sum_partials(const double* partials, int nparts, double (&acc)[K], double* red,
+                                             int kn = K) {
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
   if (threadIdx.x < kFinishThreads) {
     for (int b = threadIdx.x; b < nparts; b += kFinishThreads) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc[k] += partials[b * K + k];
+      for (int k = 0; k < K; ++k)
+        if (k < kn) acc[k] += partials[b * K + k];
     }
   }
-  block_sum<K>(acc, red);
+  block_sum_k<K>(acc, kn, red);
 }
 
 // kn: only the first kn values are summed (the rest are written as given).

@@ -347,13 +347,14 @@ __device__ __forceinline__ void publish2(double* host, double va, double vb) {
 // host: also publish (acc[0], scal[pub]) for the host (K = 1 sums only).
 template <int K>
 __global__ void __launch_bounds__(kFinishThreads) k_finish_sum(int nparts, const double* partials, double* scal,
-                                                               Slots slots, double* host, int pub) {
+                                                               Slots slots, int kn, double* host, int pub) {
   __shared__ double red[16 * 8];
   double acc[K];
-  sum_partials<K>(partials, nparts, acc, red);
+  sum_partials<K>(partials, nparts, acc, red, kn);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) scal[slots.s[k]] = acc[k];
+    for (int k = 0; k < K; ++k)
+      if (k < kn) scal[slots.s[k]] = acc[k];
     if (host) publish2(host, acc[0], scal[pub]);
   }
 }
@@ -442,7 +443,7 @@ struct Engine {
   }
   // host: publish (the sum, scal[pub]) to the pinned host mirror as well
   template <int K>
-  int32_t finish(int blocks, Slots slots, double* host = nullptr, int pub = 0) {
+  int32_t finish(int blocks, Slots slots, double* host = nullptr, int pub = 0, int kn = K) {
     if (blocks <= h->last_block_max) {
       if (host) {
         hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, (const double*)h->scal, slots.s[0], pub, host);
@@ -451,7 +452,7 @@ struct Engine {
       return AMG_OK;
     }
     hipLaunchKernelGGL((k_finish_sum<K>), dim3(1), dim3(kFinishThreads), 0, s, blocks, h->partials, h->scal, slots,
-                       host, pub);
+                       kn, host, pub);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
@@ -738,7 +739,7 @@ struct Engine {
       hipLaunchKernelGGL((k_multidot<VT, VT>), dim3(nb), dim3(TPB), 0, s, n, (const VT*)z, qs, k, rd);
     }
     AMG_HIP(hipGetLastError());
-    return finish<8>(nb, out);
+    return finish<8>(nb, out, nullptr, 0, k);
   }
 
   // -------- flexible CG steps on a coarse level (cycle vector type)
