@@ -96,6 +96,10 @@ enum { AMG_TIE_INDEX = 0, AMG_TIE_HASH = 1 };
  *                 32-bit finalizer of (i * 2654435761 + j) mod 2^32 -- on
  *                 structured meshes this breaks the long index chains, so the
  *                 handshake needs far fewer rounds (a different hierarchy).
+ *   fuse          1 (default): on levels below 2^18 rows, fold the inner
+ *                 flexible-CG vector updates into the kernels that read them
+ *                 and form the restriction of the residual in one pass; 0: one
+ *                 launch per step.  Both give the same bits.
  */
 typedef struct {
   int32_t degree;
@@ -117,6 +121,7 @@ typedef struct {
   int32_t lanes_per_row;
   int32_t sort_rows;
   int32_t tie_break;
+  int32_t fuse;
 } amg_params;
 
 typedef struct amg_hier amg_hier;

@@ -65,6 +65,7 @@ class amg_params(ctypes.Structure):
         ("lanes_per_row", ctypes.c_int32),
         ("sort_rows", ctypes.c_int32),
         ("tie_break", ctypes.c_int32),
+        ("fuse", ctypes.c_int32),
     ]
 
 

@@ -124,6 +124,7 @@ void amg_params_default(amg_params* p) {
   p->lanes_per_row = 1;
   p->sort_rows = 0;
   p->tie_break = AMG_TIE_INDEX;
+  p->fuse = 1;
 }
 
 const char* amg_strerror(int32_t s) {

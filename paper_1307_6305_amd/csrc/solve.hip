@@ -658,7 +658,7 @@ struct Engine {
   template <typename RT>
   bool restrict_residual(int l, const RT* f, const VT* x, VT* b, int32_t* st) {
     const auto& W = h->ws[l];
-    if (rec || !W.agg_blk) return false;
+    if (rec || !h->p.fuse || !W.agg_blk) return false;
     const auto Am = A(l);
     hipLaunchKernelGGL((k_restrict_residual<VT, MT, RT>), dim3(W.n_agg_blk), dim3(TPB << Am.lk), 0, s, Am,
                        transfer_of(h, l), (const int*)W.agg_blk, (const int*)W.slot_of_row, f, x, b);
@@ -873,7 +873,7 @@ struct Engine {
   // update of sol to the caller, see inner_folded)
   int32_t inner(int l, Deferred* out = nullptr) {
     const int nu = h->p.inner_steps;
-    if (out && !rec && nu == 2 && h->p.degree > 0 && h->lv[l].n < kFoldProlongRows && h->ws[l].rhs2 &&
+    if (out && !rec && h->p.fuse && nu == 2 && h->p.degree > 0 && h->lv[l].n < kFoldProlongRows && h->ws[l].rhs2 &&
         h->ws[l].P1)
       return inner_folded(l, out);
     const int n = h->lv[l].n;
@@ -1387,12 +1387,12 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
         AMG_TRY(dalloc(h, &W.Z[k], n * vt + 16));
         AMG_TRY(dalloc(h, &W.Q[k], n * vt + 16));
       }
-      if (h->p.inner_steps == 2 && h->p.degree > 0 && n < (size_t)kFoldProlongRows) {
+      if (h->p.fuse && h->p.inner_steps == 2 && h->p.degree > 0 && n < (size_t)kFoldProlongRows) {
         AMG_TRY(dalloc(h, &W.rhs2, n * vt + 16));
         AMG_TRY(dalloc(h, &W.P1, n * vt + 16));
       }
     }
-    if (l < h->L && n < (size_t)kFoldProlongRows) AMG_TRY(prepare_restrict_residual(h, l, s));
+    if (h->p.fuse && l < h->L && n < (size_t)kFoldProlongRows) AMG_TRY(prepare_restrict_residual(h, l, s));
   }
   const size_t n0 = h->lv[0].n;
   AMG_TRY(dalloc(h, &h->r, n0));
