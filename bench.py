@@ -45,6 +45,11 @@ WORKLOADS = {
     "grid2d-64": (lambda: inputs.grid2d(64), "uniform", 1, dict(degree=3, agg_size=4)),
     "tet3d-128": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16)),
     "tet3d-128-mixed": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16, precision=1)),
+    # unstructured: jittered 64^3 grid, Delaunay tetrahedralization (Section 4's general graphs)
+    "delaunay3d-64": (lambda: inputs.delaunay3d(64, inputs.seed_for(6, 64)), "normal", 6,
+                      dict(degree=4, agg_size=16)),
+    "delaunay3d-64-mixed": (lambda: inputs.delaunay3d(64, inputs.seed_for(6, 64)), "normal", 6,
+                            dict(degree=4, agg_size=16, precision=1)),
     # one random geometric graph of the batched form's kind, at 2M points
     "rgg-2m-mixed": (lambda: inputs.rgg(2_000_000, inputs.seed_for(4, 999)), "uniform", 4,
                      dict(degree=4, agg_size=8, precision=1)),

@@ -58,7 +58,11 @@ enum { AMG_TIE_INDEX = 0, AMG_TIE_HASH = 1 };
 /*
  * Solver parameters (plain struct, passed by pointer, copied by amg_setup).
  *   degree        m of the smoother q_m (Section 3; Section 4 uses 4).  Must give
- *                 E_m = delta^m (kappa-1)/2 < 1, else AMG_ERR_DEGREE.
+ *                 E_m = delta^m (kappa-1)/2 < 1, else AMG_ERR_DEGREE.  -1: the
+ *                 smallest m with E_m <= smoother_rho and E_m < 1 (the bound on
+ *                 m of Section 3, read with the consistent units of E_m < 1).
+ *   smoother_rho  damping factor rho for degree = -1, in (0, 1] (default 0.33:
+ *                 m = 4 at lambda0_ratio 10, the choice of Section 4).
  *   agg_size      target aggregate size; log2(agg_size) rounded = number of
  *                 matching passes per level (4 -> 2 passes, 16 -> 4).
  *   coarse_max    stop coarsening once a level has at most this many rows.
@@ -122,6 +126,7 @@ typedef struct {
   int32_t sort_rows;
   int32_t tie_break;
   int32_t fuse;
+  double smoother_rho;
 } amg_params;
 
 typedef struct amg_hier amg_hier;
@@ -156,6 +161,7 @@ typedef struct {
   int32_t lanes_per_row[AMG_MAX_LEVELS];
   int32_t sorted_rows[AMG_MAX_LEVELS];
   int64_t sell_entries[AMG_MAX_LEVELS];  /* stored entries including padding    */
+  int32_t degree;                     /* smoother degree in use                 */
 } amg_hier_desc;
 
 /* Fill *p with the defaults: degree 4, agg_size 4, coarse_max 64,

@@ -119,6 +119,35 @@ def tet3d(N: int) -> Graph:
     return Graph(n, row_ptr, col, w, d, name=f"tet3d-{N}")
 
 
+def delaunay3d(N: int, seed: int) -> Graph:
+    """Unstructured mesh of the unit cube in the manner of Section 4's general
+    graphs: the N^3 vertices of the structured grid (spacing h = 1/(N-1), id
+    (z*N+y)*N+x) each moved by a random vector of length h/2 (direction uniform
+    on the sphere), then the Delaunay tetrahedralization of the moved points
+    (SciPy / Qhull); its edges with w_e = 1.  d_i = 1 on the vertices that lay
+    on the cube's boundary before the move."""
+    from scipy.spatial import Delaunay
+
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    grid = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(np.float64)
+    v = rng.standard_normal(grid.shape)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    h = 1.0 / (N - 1)
+    pts = (grid + 0.5 * v) * h
+    tet = Delaunay(pts).simplices.astype(np.int64)
+    pairs = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    ei = np.concatenate([tet[:, a] for a, _ in pairs])
+    ej = np.concatenate([tet[:, b] for _, b in pairs])
+    n = N ** 3
+    row_ptr, col, w = csr_from_edges(n, ei, ej)
+    if np.any(np.diff(row_ptr) == 0):
+        raise ValueError("a vertex is in no tetrahedron")
+    bnd = (x == 0) | (x == N - 1) | (y == 0) | (y == N - 1) | (z == 0) | (z == N - 1)
+    d = bnd.ravel().astype(np.float64)
+    return Graph(n, row_ptr, col, w, d, name=f"delaunay3d-{N}-s{seed}")
+
+
 def _morton16(px: np.ndarray, py: np.ndarray) -> np.ndarray:
     """Interleave two 16-bit integer coordinates into a 32-bit Morton key."""
 

@@ -48,7 +48,7 @@ from .aggregation import (
     quotient,
     aggregate_level,
 )
-from .poly import SmootherPoly, lambda_max_bound, best_poly, error_Em, q_eval, residual_poly_eval
+from .poly import SmootherPoly, lambda_max_bound, best_poly, error_Em, degree_for, q_eval, residual_poly_eval
 from .cycle import (
     Params,
     Hierarchy,
@@ -66,7 +66,7 @@ from .cycle import (
 __all__ = [
     "Level", "assemble", "apply_A", "bilinear_form", "row_abs_sums",
     "edge_strengths", "greedy_matching", "coarse_ids", "quotient", "aggregate_level",
-    "SmootherPoly", "lambda_max_bound", "best_poly", "error_Em", "q_eval", "residual_poly_eval",
+    "SmootherPoly", "lambda_max_bound", "best_poly", "error_Em", "degree_for", "q_eval", "residual_poly_eval",
     "Params", "Hierarchy", "build_hierarchy", "smooth", "residual", "restrict", "prolong",
     "coarse_solve", "kcycle", "fcg", "FCGResult",
 ]

@@ -85,6 +85,18 @@ def error_Em(m: int, kappa: float) -> float:
     return _delta(kappa) ** m * (kappa - 1.0) / 2.0
 
 
+def degree_for(rho: float, kappa: float, max_degree: int = 64) -> int:
+    """Smallest degree m meeting the bound on m of Section 3: a damping factor
+    E_m <= rho on [lambda0, lambda1] and E_m < 1 (the positivity condition read
+    with consistent units, see the module docstring).  E_m decreases in m, so
+    this is the first m that passes both tests."""
+    for m in range(max_degree + 1):
+        e = error_Em(m, kappa)
+        if e <= rho and e < 1.0:
+            return m
+    return max_degree
+
+
 def q_eval(poly: SmootherPoly, x: np.ndarray) -> np.ndarray:
     """q_m(x) evaluated through the Chebyshev series (numpy's chebval)."""
     t = (np.asarray(x, dtype=np.float64) - poly.theta) / poly.eta

@@ -66,6 +66,7 @@ class amg_params(ctypes.Structure):
         ("sort_rows", ctypes.c_int32),
         ("tie_break", ctypes.c_int32),
         ("fuse", ctypes.c_int32),
+        ("smoother_rho", ctypes.c_double),
     ]
 
 
@@ -98,6 +99,7 @@ class amg_hier_desc(ctypes.Structure):
         ("lanes_per_row", ctypes.c_int32 * AMG_MAX_LEVELS),
         ("sorted_rows", ctypes.c_int32 * AMG_MAX_LEVELS),
         ("sell_entries", ctypes.c_int64 * AMG_MAX_LEVELS),
+        ("degree", ctypes.c_int32),
     ]
 
 
@@ -325,6 +327,7 @@ def amg_describe(h: Hierarchy) -> dict:
         "precision": ds.precision,
         "device_bytes": ds.device_bytes,
         "layout_ms": ds.layout_ms,
+        "degree": ds.degree,
         # sliced-ELL layout of every smoothed level (the finest at least)
         "layouts": [{"slice_height": ds.slice_height[l], "lanes_per_row": ds.lanes_per_row[l],
                      "sorted_rows": ds.sorted_rows[l], "entries": ds.sell_entries[l]}

@@ -125,6 +125,7 @@ void amg_params_default(amg_params* p) {
   p->sort_rows = 0;
   p->tie_break = AMG_TIE_INDEX;
   p->fuse = 1;
+  p->smoother_rho = 0.33;
 }
 
 const char* amg_strerror(int32_t s) {
@@ -156,6 +157,7 @@ int32_t amg_setup(int32_t n, const int32_t* row_ptr, const int32_t* col, const d
   std::string msg;
   int32_t st = amg::validate_params(p, msg);
   if (st != AMG_OK) { amg::set_last_error(msg); return st; }
+  p.degree = amg::resolved_degree(p);
   st = amg::validate_graph(n, row_ptr, col, w, d, msg);
   if (st != AMG_OK) { amg::set_last_error(msg); return st; }
   AMG_TRY(check_device());

@@ -84,6 +84,9 @@ struct amg_hier {
 namespace amg {
 
 int32_t validate_params(const amg_params& p, std::string& msg);
+// The smoother degree in use: p.degree, or for -1 the smallest m with
+// E_m <= p.smoother_rho and E_m < 1 (valid parameters only).
+int32_t resolved_degree(const amg_params& p);
 int32_t validate_graph(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
                        const double* d, std::string& msg);
 

@@ -1229,6 +1229,7 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
   amg_hier_desc& ds = h->desc;
   std::memset(&ds, 0, sizeof(ds));
   ds.levels = (int)h->lv.size();
+  ds.degree = h->p.degree;
   double gsum = 0.0, osum = 0.0;
   for (int l = 0; l <= h->L; ++l) {
     ds.n[l] = h->lv[l].n;

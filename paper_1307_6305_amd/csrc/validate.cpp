@@ -10,8 +10,32 @@
 
 namespace amg {
 
+namespace {
+
+double smoother_error(int m, double kappa) {
+  const double sk = std::sqrt(kappa);
+  const double delta = (sk - 1.0) / (sk + 1.0);
+  return std::pow(delta, m) * (kappa - 1.0) / 2.0;
+}
+
+}  // namespace
+
+// Section 3: E_m = delta^m (kappa - 1) / 2 decreases in m; the smallest m
+// meeting both the damping requirement (E_m <= rho) and E_m < 1.
+int32_t resolved_degree(const amg_params& p) {
+  if (p.degree >= 0) return p.degree;
+  int m = 0;
+  while (m < 64 && !(smoother_error(m, p.lambda0_ratio) <= p.smoother_rho && smoother_error(m, p.lambda0_ratio) < 1.0))
+    ++m;
+  return m;
+}
+
 int32_t validate_params(const amg_params& p, std::string& msg) {
-  if (p.degree < 0 || p.degree > 64) { msg = "degree out of range [0, 64]"; return AMG_ERR_ARG; }
+  if (p.degree < -1 || p.degree > 64) { msg = "degree out of range [-1, 64]"; return AMG_ERR_ARG; }
+  if (p.degree == -1 && !(p.smoother_rho > 0.0 && p.smoother_rho <= 1.0)) {
+    msg = "smoother_rho must lie in (0, 1] for degree -1";
+    return AMG_ERR_ARG;
+  }
   if (p.agg_size < 2 || p.agg_size > (1 << 12)) { msg = "agg_size out of range [2, 4096]"; return AMG_ERR_ARG; }
   if (p.coarse_max < 1) { msg = "coarse_max must be >= 1"; return AMG_ERR_ARG; }
   if (!(p.lambda0_ratio > 1.0) || !std::isfinite(p.lambda0_ratio)) { msg = "lambda0_ratio must be > 1"; return AMG_ERR_ARG; }
@@ -43,7 +67,7 @@ int32_t validate_params(const amg_params& p, std::string& msg) {
   const double kappa = p.lambda0_ratio;
   const double sk = std::sqrt(kappa);
   const double delta = (sk - 1.0) / (sk + 1.0);
-  const double Em = std::pow(delta, p.degree) * (kappa - 1.0) / 2.0;
+  const double Em = std::pow(delta, resolved_degree(p)) * (kappa - 1.0) / 2.0;
   if (!(Em < 1.0)) { msg = "smoother degree too low for lambda0_ratio: E_m >= 1"; return AMG_ERR_DEGREE; }
   return AMG_OK;
 }

@@ -39,6 +39,7 @@ CASES = {
     "grid100x37_agg16_m5": (lambda: inputs.grid2d(100, 37), dict(degree=5, agg_size=16)),
     "grid64_raw_agg4": (lambda: inputs.grid2d(64), dict(degree=3, agg_size=4, match_key=1)),
     "tet3d_12_agg8_m4": (lambda: inputs.tet3d(12), dict(degree=4, agg_size=8)),
+    "delaunay11_agg16_m4": (lambda: inputs.delaunay3d(11, seed=inputs.seed_for(6, 11)), dict(degree=4, agg_size=16)),
     "rgg_6000_agg8_m4": (lambda: inputs.rgg(6000, seed=inputs.seed_for(4, 1)), dict(degree=4, agg_size=8)),
     "random_weighted_agg4": (lambda: inputs.random_graph(700, 0.006, seed=5, weighted=True),
                              dict(degree=4, agg_size=4, coarse_max=40)),

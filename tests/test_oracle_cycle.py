@@ -30,7 +30,7 @@ def test_smoother_equals_spectral_definition(m):
 
 
 def test_lambda1_bounds_spectrum():
-    for g in (inputs.grid2d(10), inputs.tet3d(4), inputs.random_graph(30, 0.2, 1, True)):
+    for g in (inputs.grid2d(10), inputs.tet3d(4), inputs.random_graph(30, 0.2, 1, True), inputs.delaunay3d(6, 3)):
         lvl = _level(g)
         lam = np.linalg.eigvalsh(lvl.dense())
         assert lam.max() <= oracle.lambda_max_bound(lvl) + 1e-12

@@ -13,6 +13,7 @@ CASES = [
     (lambda: inputs.tet3d(6), 3),
     (lambda: inputs.random_graph(80, 0.05, seed=11, weighted=True), 2),
     (lambda: inputs.rgg(1500, seed=2), 3),
+    (lambda: inputs.delaunay3d(8, seed=9), 3),
 ]
 
 

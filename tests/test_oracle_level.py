@@ -10,6 +10,7 @@ from oracle.level import bilinear_form
 GRAPHS = [
     lambda: inputs.grid2d(9, 7),
     lambda: inputs.tet3d(5),
+    lambda: inputs.delaunay3d(6, seed=7),
     lambda: inputs.random_graph(30, 0.15, seed=3, weighted=True),
     lambda: inputs.random_graph(25, 0.2, seed=4, weighted=False),
 ]
@@ -63,3 +64,38 @@ def test_generators_shapes():
     assert deg.max() == 14
     inner = (2 * 6 + 2) * 6 + 2
     assert deg[inner] == 14
+
+
+def test_delaunay_mesh():
+    """Jittered-grid Delaunay mesh of the cube: valid symmetric CSR, every
+    vertex in the mesh, connected, the boundary set of the structured grid, a
+    reproducible draw, and the Euler characteristic of a tetrahedralized ball
+    (V - E + F - T = 1) for the triangulation it came from."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    from scipy.spatial import Delaunay
+
+    N = 9
+    g = inputs.delaunay3d(N, seed=11)
+    assert g.n == N ** 3
+    A = csr_matrix((g.w, g.col, g.row_ptr), shape=(g.n, g.n))
+    assert (A != A.T).nnz == 0 and np.all(A.diagonal() == 0)
+    for i in range(g.n):
+        c = g.col[g.row_ptr[i]:g.row_ptr[i + 1]]
+        assert np.all(np.diff(c) > 0)
+    assert connected_components(A, directed=False)[0] == 1
+    assert int(g.d.sum()) == N ** 3 - (N - 2) ** 3
+    g2 = inputs.delaunay3d(N, seed=11)
+    assert np.array_equal(g.col, g2.col) and np.array_equal(g.row_ptr, g2.row_ptr)
+    assert not np.array_equal(inputs.delaunay3d(N, seed=12).col[:50], g.col[:50]) or \
+        inputs.delaunay3d(N, seed=12).nnz != g.nnz
+    # the same triangulation, rebuilt from the same draw, gives the Euler characteristic
+    rng = np.random.default_rng(11)
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    grid = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1).astype(np.float64)
+    v = rng.standard_normal(grid.shape)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    tet = Delaunay((grid + 0.5 * v) / (N - 1)).simplices
+    faces = {tuple(sorted(f)) for t in tet for f in
+             ((t[0], t[1], t[2]), (t[0], t[1], t[3]), (t[0], t[2], t[3]), (t[1], t[2], t[3]))}
+    assert g.n - g.n_edges + len(faces) - len(tet) == 1

@@ -75,7 +75,7 @@ def test_greedy_equals_handshake(seed, key):
 
 
 def test_greedy_equals_handshake_on_grid_ties():
-    for g in (inputs.grid2d(11, 8), inputs.tet3d(4)):
+    for g in (inputs.grid2d(11, 8), inputs.tet3d(4), inputs.delaunay3d(6, 4)):
         lvl = _level(g)
         for key in ("normalized", "raw"):
             for tie in ("index", "hash"):

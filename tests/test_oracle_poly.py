@@ -119,3 +119,22 @@ def test_degree_two_diverges():
     g = __import__("inputs").grid2d(8)
     with pytest.raises(ValueError):
         oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(degree=2))
+
+
+def test_degree_for_matches_the_bound_on_m():
+    """Automatic degree: the smallest m with E_m <= rho and E_m < 1.  Pinned
+    against the closed form of Section 3's bound on m, with the positivity
+    term read in consistent units (lambda1 -> 1):
+    m = ceil(max(|ln(2 rho/(kappa-1))|, |ln(2/(kappa-1))|) / |ln delta|)."""
+    for kappa in (10.0, 30.0, 100.0):
+        delta = (math.sqrt(kappa) - 1) / (math.sqrt(kappa) + 1)
+        for rho in (0.9, 0.6, 0.33, 0.2, 0.1, 0.05, 0.01, 1e-3):
+            bound = max(abs(math.log(2 * rho / (kappa - 1))), abs(math.log(2 / (kappa - 1)))) / abs(math.log(delta))
+            assert oracle.degree_for(rho, kappa) == math.ceil(bound), (kappa, rho)
+    # Section 4: kappa = 10 and m = 4; the damping factors of the neighbouring degrees
+    assert oracle.degree_for(0.33, 10.0) == 4
+    assert oracle.degree_for(0.64, 10.0) == 3
+    assert oracle.degree_for(0.2, 10.0) == 5
+    assert oracle.degree_for(0.05, 10.0) == 7
+    # rho = 1: only E_m < 1 binds, and m = 2 diverges at kappa = 10
+    assert oracle.degree_for(1.0, 10.0) == 3
