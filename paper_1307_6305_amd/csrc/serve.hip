@@ -257,227 +257,243 @@ struct Server {
     size_t next = 0;                 // next request (submission order) not yet fully admitted
     int next_rhs = 0;                // first right-hand side of it not yet admitted
     std::vector<Slot> active;
+    std::vector<Slot> fresh;         // admitted in this round, not yet started
     ItemState* d_states = nullptr;   // pool of item states, one per slot position
     int* d_nactive = nullptr;
     const int max_slots = std::max(1, cfg.max_slots);
-    AMG_HIP(hipMalloc(&d_states, sizeof(ItemState) * max_slots));
-    AMG_HIP(hipMalloc(&d_nactive, sizeof(int)));
     std::vector<int> free_state(max_slots);
     for (int i = 0; i < max_slots; ++i) free_state[i] = max_slots - 1 - i;
     std::map<const void*, int> state_index;
     Schedule sched_iter, sched_aux;
     bool membership_changed = true;
-    const BatchCtl ctl{cfg.params.tol, cfg.params.max_iter, 0, d_nactive};
     int32_t result = AMG_OK;
 
     auto cleanup = [&]() {
       (void)hipStreamSynchronize(s);
       schedule_free(&sched_iter);
       schedule_free(&sched_aux);
-      for (Slot& sl : active) {
-        (void)hipFree(sl.f);
-        (void)hipFree(sl.u);
-      }
-      (void)hipFree(d_states);
-      (void)hipFree(d_nactive);
+      for (std::vector<Slot>* v : {&active, &fresh})
+        for (Slot& sl : *v) {
+          if (sl.f) (void)hipFree(sl.f);
+          if (sl.u) (void)hipFree(sl.u);
+        }
+      if (d_states) (void)hipFree(d_states);
+      if (d_nactive) (void)hipFree(d_nactive);
     };
 
-    while (true) {
-      const double t = now();
-      // --- queue setups for arrived requests whose graph is not resident,
-      //     reserving a conservative size estimate against the budget.  Only
-      //     the head-of-line request's setup may evict idle hierarchies; later
-      //     ones start early only in free room (otherwise they could evict the
-      //     hierarchy the head needs, and the two would evict each other).
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        for (size_t k = next; k < reqs.size(); ++k) {
-          Req* rq = reqs[k].get();
-          const amg_request& q = rq->q;
-          if (resident.count(q.graph_id) || setup_pending.count(q.graph_id)) continue;
-          if (!q.row_ptr) continue;  // no data to set up: fails at admission
-          const size_t est = setup_estimate(q);
-          if (k > next) {
-            if ((double)(bytes + est) > cfg.hbm_budget_bytes) break;
-          } else if (!make_room(est)) {
-            if (active.empty() && resident_busy() == 0 && setup_pending.empty()) {
-              // larger than the whole budget: nothing can ever make room
-              setup_pending[q.graph_id] = 0;
-              Resident* R = new Resident();
-              R->failed = true;
-              R->status = AMG_ERR_BUDGET;
-              resident[q.graph_id] = R;
-              setup_pending.erase(q.graph_id);
+    // The admission and iteration loop; a device error ends it early.
+    auto loop = [&]() -> int32_t {
+      AMG_HIP(hipMalloc(&d_states, sizeof(ItemState) * max_slots));
+      AMG_HIP(hipMalloc(&d_nactive, sizeof(int)));
+      // built after the allocation: the kernels take the counter's address from it
+      const BatchCtl ctl{cfg.params.tol, cfg.params.max_iter, 0, d_nactive};
+      while (true) {
+        const double t = now();
+        // --- queue setups for arrived requests whose graph is not resident,
+        //     reserving a conservative size estimate against the budget.  Only
+        //     the head-of-line request's setup may evict idle hierarchies; later
+        //     ones start early only in free room (otherwise they could evict the
+        //     hierarchy the head needs, and the two would evict each other).
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          for (size_t k = next; k < reqs.size(); ++k) {
+            Req* rq = reqs[k].get();
+            const amg_request& q = rq->q;
+            if (resident.count(q.graph_id) || setup_pending.count(q.graph_id)) continue;
+            if (!q.row_ptr) continue;  // no data to set up: fails at admission
+            const size_t est = setup_estimate(q);
+            if (k > next) {
+              if ((double)(bytes + est) > cfg.hbm_budget_bytes) break;
+            } else if (!make_room(est)) {
+              if (active.empty() && resident_busy() == 0 && setup_pending.empty()) {
+                // larger than the whole budget: nothing can ever make room
+                setup_pending[q.graph_id] = 0;
+                Resident* R = new Resident();
+                R->failed = true;
+                R->status = AMG_ERR_BUDGET;
+                resident[q.graph_id] = R;
+                setup_pending.erase(q.graph_id);
+              }
+              break;  // keep arrival order: later graphs wait for room too
             }
-            break;  // keep arrival order: later graphs wait for room too
+            bytes += est;
+            note_bytes();
+            setup_pending[q.graph_id] = est;
+            setup_queue.push_back(rq);
           }
-          bytes += est;
-          note_bytes();
-          setup_pending[q.graph_id] = est;
-          setup_queue.push_back(rq);
         }
-      }
-      cv.notify_all();
-      // --- admit submitted right-hand sides (in order) while slots and memory allow
-      std::vector<Slot> fresh;
-      for (;;) {
-        bool no_more = false;
-        Req* rq = request_at(next, &no_more);
-        if (!rq) break;
-        const amg_request& q = rq->q;
-        if ((int)(active.size() + fresh.size()) >= max_slots) break;
-        std::unique_lock<std::mutex> lk(mu);
-        auto it = resident.find(q.graph_id);
-        if (it == resident.end()) {
-          if (!q.row_ptr && !setup_pending.count(q.graph_id)) {  // evicted and no data: fail
-            fail_request(rq, AMG_ERR_ARG, next_rhs);
+        cv.notify_all();
+        // --- admit submitted right-hand sides (in order) while slots and memory allow
+        fresh.clear();
+        for (;;) {
+          bool no_more = false;
+          Req* rq = request_at(next, &no_more);
+          if (!rq) break;
+          const amg_request& q = rq->q;
+          if ((int)(active.size() + fresh.size()) >= max_slots) break;
+          std::unique_lock<std::mutex> lk(mu);
+          auto it = resident.find(q.graph_id);
+          if (it == resident.end()) {
+            if (!q.row_ptr && !setup_pending.count(q.graph_id)) {  // evicted and no data: fail
+              fail_request(rq, AMG_ERR_ARG, next_rhs);
+              lk.unlock();
+              ++next;
+              next_rhs = 0;
+              continue;
+            }
+            break;  // setup still running: keep submission order
+          }
+          Resident* R = it->second;
+          if (R->failed) {
+            fail_request(rq, R->status, next_rhs);
             lk.unlock();
             ++next;
             next_rhs = 0;
             continue;
           }
-          break;  // setup still running: keep submission order
-        }
-        Resident* R = it->second;
-        if (R->failed) {
-          fail_request(rq, R->status, next_rhs);
+          // one slot: workspace (spare clone, the hierarchy's own, or a new clone) + f, u
+          const size_t n = (size_t)q.n;
+          amg_hier* ws = nullptr;
+          bool own = false;
+          size_t extra = 2 * n * sizeof(double) + 64;
+          if (!R->spare.empty()) {
+            ws = R->spare.back();
+          } else if (!R->own_lent) {
+            own = true;  // the hierarchy's own workspace is free
+          } else {
+            extra += R->h->ws_bytes;
+          }
+          if (!make_room(extra, R)) {
+            if (active.empty() && fresh.empty()) {  // nothing will ever free memory: give up on it
+              fail_request(rq, AMG_ERR_BUDGET, next_rhs);
+              lk.unlock();
+              ++next;
+              next_rhs = 0;
+              continue;
+            }
+            break;
+          }
+          if (!R->spare.empty()) {
+            R->spare.pop_back();
+          } else if (!own) {
+            const int32_t st = make_clone(R->h, &ws, s);
+            if (st != AMG_OK) return st;
+            R->clone_bytes += ws->bytes;
+            bytes += ws->bytes;
+          }
+          if (own) {
+            ws = R->h;
+            R->own_lent = true;
+          }
+          bytes += 2 * n * sizeof(double);
+          note_bytes();
+          Slot sl;
+          sl.rq = rq;
+          sl.rhs = next_rhs;
+          sl.res = R;
+          sl.ws = ws;
+          sl.own_ws = own;
+          sl.admit_s = std::max(t, q.arrival_s);  // submitted after this round began
+          R->in_flight++;
+          R->last_use = t;
           lk.unlock();
-          ++next;
-          next_rhs = 0;
+          const int si = free_state.back();
+          free_state.pop_back();
+          sl.st = d_states + si;
+          state_index[sl.st] = si;
+          const size_t rhs_k = (size_t)next_rhs;
+          // the slot is accounted for from here on (an error fails it with the rest)
+          fresh.push_back(sl);
+          if (++next_rhs >= q.nrhs) {
+            ++next;
+            next_rhs = 0;
+          }
+          Slot& fs = fresh.back();
+          AMG_HIP(hipMalloc(&fs.f, n * sizeof(double)));
+          AMG_HIP(hipMalloc(&fs.u, n * sizeof(double)));
+          AMG_HIP(hipMemcpyAsync(fs.f, q.f + rhs_k * n, n * sizeof(double), hipMemcpyHostToDevice, s));
+          AMG_HIP(hipMemsetAsync(fs.u, 0, n * sizeof(double), s));
+        }
+        // --- start the new slots: r = f - A u, activation
+        if (!fresh.empty()) {
+          std::vector<BatchItem> items;
+          for (const Slot& sl : fresh) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+          AMG_TRY(schedule_build(&sched_aux, SCHED_INIT, items, s));
+          hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, d_nactive);
+          AMG_TRY(schedule_run(&sched_aux, ctl, s));
+          for (const Slot& sl : fresh) active.push_back(sl);
+          fresh.clear();
+          membership_changed = true;
+        }
+        if (active.empty()) {
+          bool no_more = false;
+          if (!request_at(next, &no_more) && no_more) break;  // closing and everything done
+          // wait for a submission, a setup or the close
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait_for(lk, std::chrono::milliseconds(2));
           continue;
         }
-        // one slot: workspace (spare clone, the hierarchy's own, or a new clone) + f, u
-        const size_t n = (size_t)q.n;
-        amg_hier* ws = nullptr;
-        bool own = false;
-        size_t extra = 2 * n * sizeof(double) + 64;
-        if (!R->spare.empty()) {
-          ws = R->spare.back();
-        } else if (!R->own_lent) {
-          own = true;  // the hierarchy's own workspace is free
-        } else {
-          extra += R->h->ws_bytes;
+        // --- one round of outer iterations over every in-flight slot
+        if (membership_changed) {
+          std::vector<BatchItem> items;
+          for (const Slot& sl : active) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+          AMG_TRY(schedule_build(&sched_iter, SCHED_ITER, items, s));
+          membership_changed = false;
         }
-        if (!make_room(extra, R)) {
-          if (active.empty() && fresh.empty()) {  // nothing will ever free memory: give up on it
-            fail_request(rq, AMG_ERR_BUDGET, next_rhs);
-            lk.unlock();
-            ++next;
-            next_rhs = 0;
-            continue;
-          }
-          break;
-        }
-        if (!R->spare.empty()) {
-          R->spare.pop_back();
-        } else if (!own) {
-          const int32_t st = make_clone(R->h, &ws, s);
-          if (st != AMG_OK) {
-            lk.unlock();
-            result = st;
-            cleanup();
-            return st;
-          }
-          R->clone_bytes += ws->bytes;
-          bytes += ws->bytes;
-        }
-        if (own) {
-          ws = R->h;
-          R->own_lent = true;
-        }
-        bytes += 2 * n * sizeof(double);
-        note_bytes();
-        Slot sl;
-        sl.rq = rq;
-        sl.rhs = next_rhs;
-        sl.res = R;
-        sl.ws = ws;
-        sl.own_ws = own;
-        sl.admit_s = std::max(t, q.arrival_s);  // submitted after this round began
-        R->in_flight++;
-        R->last_use = t;
-        lk.unlock();
-        AMG_HIP(hipMalloc(&sl.f, n * sizeof(double)));
-        AMG_HIP(hipMalloc(&sl.u, n * sizeof(double)));
-        AMG_HIP(hipMemcpyAsync(sl.f, q.f + (size_t)next_rhs * n, n * sizeof(double), hipMemcpyHostToDevice, s));
-        AMG_HIP(hipMemsetAsync(sl.u, 0, n * sizeof(double), s));
-        const int si = free_state.back();
-        free_state.pop_back();
-        sl.st = d_states + si;
-        state_index[sl.st] = si;
-        fresh.push_back(sl);
-        if (++next_rhs >= q.nrhs) {
-          ++next;
-          next_rhs = 0;
-        }
-      }
-      // --- start the new slots: r = f - A u, activation
-      if (!fresh.empty()) {
-        std::vector<BatchItem> items;
-        for (const Slot& sl : fresh) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
-        AMG_TRY(schedule_build(&sched_aux, SCHED_INIT, items, s));
-        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, d_nactive);
-        AMG_TRY(schedule_run(&sched_aux, ctl, s));
-        for (const Slot& sl : fresh) active.push_back(sl);
-        membership_changed = true;
-      }
-      if (active.empty()) {
-        bool no_more = false;
-        if (!request_at(next, &no_more) && no_more) break;  // closing and everything done
-        // wait for a submission, a setup or the close
-        std::unique_lock<std::mutex> lk(mu);
-        cv.wait_for(lk, std::chrono::milliseconds(2));
-        continue;
-      }
-      // --- one round of outer iterations over every in-flight slot
-      if (membership_changed) {
-        std::vector<BatchItem> items;
-        for (const Slot& sl : active) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
-        AMG_TRY(schedule_build(&sched_iter, SCHED_ITER, items, s));
-        membership_changed = false;
-      }
-      for (int k = 0; k < std::max(1, cfg.iters_per_step); ++k) AMG_TRY(schedule_run(&sched_iter, ctl, s));
-      ++steps;
-      // --- retire converged slots
-      std::vector<ItemState> hst(active.size());
-      for (size_t i = 0; i < active.size(); ++i)
-        AMG_HIP(hipMemcpyAsync(&hst[i], active[i].st, sizeof(ItemState), hipMemcpyDeviceToHost, s));
-      AMG_HIP(hipStreamSynchronize(s));
-      std::vector<Slot> done, keep;
-      for (size_t i = 0; i < active.size(); ++i) (hst[i].active ? keep : done).push_back(active[i]);
-      if (!done.empty()) {
-        std::vector<BatchItem> items;
-        for (const Slot& sl : done) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
-        AMG_TRY(schedule_build(&sched_aux, SCHED_FINAL, items, s));
-        AMG_TRY(schedule_run(&sched_aux, ctl, s));
-        std::vector<ItemState> fst(done.size());
-        for (size_t i = 0; i < done.size(); ++i)
-          AMG_HIP(hipMemcpyAsync(&fst[i], done[i].st, sizeof(ItemState), hipMemcpyDeviceToHost, s));
-        for (const Slot& sl : done) {
-          const amg_request& q = sl.rq->q;
-          if (q.u)
-            AMG_HIP(hipMemcpyAsync(q.u + (size_t)sl.rhs * q.n, sl.u, sizeof(double) * q.n, hipMemcpyDeviceToHost,
-                                   s));
-        }
+        for (int k = 0; k < std::max(1, cfg.iters_per_step); ++k) AMG_TRY(schedule_run(&sched_iter, ctl, s));
+        ++steps;
+        // --- retire converged slots
+        std::vector<ItemState> hst(active.size());
+        for (size_t i = 0; i < active.size(); ++i)
+          AMG_HIP(hipMemcpyAsync(&hst[i], active[i].st, sizeof(ItemState), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
-        std::lock_guard<std::mutex> lk(mu);
-        for (size_t i = 0; i < done.size(); ++i) {
-          const Slot& sl = done[i];
-          const double rho0 = std::sqrt(fst[i].rr0);
-          complete(sl, fst[i].status, fst[i].iter, rho0 > 0 ? std::sqrt(fst[i].rrt) / rho0 : 0.0);
-          (void)hipFree(sl.f);
-          (void)hipFree(sl.u);
-          bytes -= 2 * (size_t)sl.rq->q.n * sizeof(double);
-          sl.res->in_flight--;
-          sl.res->last_use = now();
-          if (sl.own_ws) sl.res->own_lent = false;
-          else sl.res->spare.push_back(sl.ws);
-          free_state.push_back(state_index[sl.st]);
-          state_index.erase(sl.st);
+        std::vector<Slot> done, keep;
+        for (size_t i = 0; i < active.size(); ++i) (hst[i].active ? keep : done).push_back(active[i]);
+        if (!done.empty()) {
+          std::vector<BatchItem> items;
+          for (const Slot& sl : done) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+          AMG_TRY(schedule_build(&sched_aux, SCHED_FINAL, items, s));
+          AMG_TRY(schedule_run(&sched_aux, ctl, s));
+          std::vector<ItemState> fst(done.size());
+          for (size_t i = 0; i < done.size(); ++i)
+            AMG_HIP(hipMemcpyAsync(&fst[i], done[i].st, sizeof(ItemState), hipMemcpyDeviceToHost, s));
+          for (const Slot& sl : done) {
+            const amg_request& q = sl.rq->q;
+            if (q.u)
+              AMG_HIP(hipMemcpyAsync(q.u + (size_t)sl.rhs * q.n, sl.u, sizeof(double) * q.n, hipMemcpyDeviceToHost,
+                                     s));
+          }
+          AMG_HIP(hipStreamSynchronize(s));
+          std::lock_guard<std::mutex> lk(mu);
+          for (size_t i = 0; i < done.size(); ++i) {
+            const Slot& sl = done[i];
+            const double rho0 = std::sqrt(fst[i].rr0);
+            complete(sl, fst[i].status, fst[i].iter, rho0 > 0 ? std::sqrt(fst[i].rrt) / rho0 : 0.0);
+            (void)hipFree(sl.f);
+            (void)hipFree(sl.u);
+            bytes -= 2 * (size_t)sl.rq->q.n * sizeof(double);
+            sl.res->in_flight--;
+            sl.res->last_use = now();
+            if (sl.own_ws) sl.res->own_lent = false;
+            else sl.res->spare.push_back(sl.ws);
+            free_state.push_back(state_index[sl.st]);
+            state_index.erase(sl.st);
+          }
+          active.swap(keep);
+          membership_changed = true;
         }
-        active.swap(keep);
-        membership_changed = true;
       }
+      return AMG_OK;
+    };
+    result = loop();
+    if (result != AMG_OK) {
+      // complete every admitted slot and every right-hand side not yet
+      // admitted with the error; no further submissions are taken
+      std::lock_guard<std::mutex> lk(mu);
+      closing = true;
+      for (std::vector<Slot>* v : {&active, &fresh})
+        for (const Slot& sl : *v) complete(sl, result, 0, 0.0);
+      for (size_t k = next; k < reqs.size(); ++k) fail_request(reqs[k].get(), result, k == next ? next_rhs : 0);
     }
     cleanup();
     return result;
@@ -488,71 +504,85 @@ struct Server {
     double* f = nullptr;
     double* u = nullptr;
     size_t cap = 0;
-    for (size_t next = 0;; ++next) {
-      Req* rq = nullptr;
-      for (;;) {  // the next submission, or the end
-        bool no_more = false;
-        rq = request_at(next, &no_more);
-        if (rq || no_more) break;
-        std::unique_lock<std::mutex> lk(mu);
-        cv.wait_for(lk, std::chrono::milliseconds(2));
-      }
-      if (!rq) break;
-      const amg_request& q = rq->q;
-      Resident* R = nullptr;
-      auto it = resident.find(q.graph_id);
-      if (it != resident.end()) {
-        R = it->second;
-      } else if (q.row_ptr) {
-        R = new Resident();
-        R->status = amg_setup(q.n, q.row_ptr, q.col, q.w, q.d, &cfg.params, s, &R->h);
-        R->failed = R->status != AMG_OK;
-        R->bytes = R->h ? hier_bytes(R->h) : 0;
-        ++setups;
-        if (!R->failed && !make_room(R->bytes)) {
-          amg_free(R->h);
-          R->h = nullptr;
-          R->failed = true;
-          R->status = AMG_ERR_BUDGET;
+    size_t next = 0;  // the request being served
+    int cur_rhs = 0;  // its first right-hand side not yet completed
+    auto loop = [&]() -> int32_t {
+      for (;; ++next) {
+        cur_rhs = 0;
+        Req* rq = nullptr;
+        for (;;) {  // the next submission, or the end
+          bool no_more = false;
+          rq = request_at(next, &no_more);
+          if (rq || no_more) break;
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait_for(lk, std::chrono::milliseconds(2));
         }
-        if (!R->failed) bytes += R->bytes;
-        note_bytes();
-        resident[q.graph_id] = R;
+        if (!rq) break;
+        const amg_request& q = rq->q;
+        Resident* R = nullptr;
+        auto it = resident.find(q.graph_id);
+        if (it != resident.end()) {
+          R = it->second;
+        } else if (q.row_ptr) {
+          R = new Resident();
+          R->status = amg_setup(q.n, q.row_ptr, q.col, q.w, q.d, &cfg.params, s, &R->h);
+          R->failed = R->status != AMG_OK;
+          R->bytes = R->h ? hier_bytes(R->h) : 0;
+          ++setups;
+          if (!R->failed && !make_room(R->bytes)) {
+            amg_free(R->h);
+            R->h = nullptr;
+            R->failed = true;
+            R->status = AMG_ERR_BUDGET;
+          }
+          if (!R->failed) bytes += R->bytes;
+          note_bytes();
+          resident[q.graph_id] = R;
+        }
+        if (!R || R->failed) {
+          std::lock_guard<std::mutex> lk(mu);
+          fail_request(rq, R ? R->status : AMG_ERR_ARG);
+          continue;
+        }
+        R->last_use = now();
+        const double admit = now();
+        if ((size_t)q.n > cap) {
+          if (f) (void)hipFree(f);
+          if (u) (void)hipFree(u);
+          cap = q.n;
+          AMG_HIP(hipMalloc(&f, cap * sizeof(double)));
+          AMG_HIP(hipMalloc(&u, cap * sizeof(double)));
+        }
+        for (int k = 0; k < q.nrhs; ++k) {
+          AMG_HIP(hipMemcpyAsync(f, q.f + (size_t)k * q.n, q.n * sizeof(double), hipMemcpyHostToDevice, s));
+          AMG_HIP(hipMemsetAsync(u, 0, q.n * sizeof(double), s));
+          amg_info info{};
+          const int32_t st = solve(R->h, f, u, s, &info);
+          if (q.u) AMG_HIP(hipMemcpyAsync(q.u + (size_t)k * q.n, u, q.n * sizeof(double), hipMemcpyDeviceToHost, s));
+          AMG_HIP(hipStreamSynchronize(s));
+          Slot sl;
+          sl.rq = rq;
+          sl.rhs = k;
+          sl.admit_s = admit;
+          std::lock_guard<std::mutex> lk(mu);
+          complete(sl, st == AMG_OK || st == AMG_ERR_MAXIT || st == AMG_ERR_BREAKDOWN ? info.status : st, info.iters,
+                   info.rel_res_true);
+          cur_rhs = k + 1;
+          ++steps;
+        }
       }
-      if (!R || R->failed) {
-        std::lock_guard<std::mutex> lk(mu);
-        fail_request(rq, R ? R->status : AMG_ERR_ARG);
-        continue;
-      }
-      R->last_use = now();
-      const double admit = now();
-      if ((size_t)q.n > cap) {
-        if (f) (void)hipFree(f);
-        if (u) (void)hipFree(u);
-        cap = q.n;
-        AMG_HIP(hipMalloc(&f, cap * sizeof(double)));
-        AMG_HIP(hipMalloc(&u, cap * sizeof(double)));
-      }
-      for (int k = 0; k < q.nrhs; ++k) {
-        AMG_HIP(hipMemcpyAsync(f, q.f + (size_t)k * q.n, q.n * sizeof(double), hipMemcpyHostToDevice, s));
-        AMG_HIP(hipMemsetAsync(u, 0, q.n * sizeof(double), s));
-        amg_info info{};
-        const int32_t st = solve(R->h, f, u, s, &info);
-        if (q.u) AMG_HIP(hipMemcpyAsync(q.u + (size_t)k * q.n, u, q.n * sizeof(double), hipMemcpyDeviceToHost, s));
-        AMG_HIP(hipStreamSynchronize(s));
-        Slot sl;
-        sl.rq = rq;
-        sl.rhs = k;
-        sl.admit_s = admit;
-        std::lock_guard<std::mutex> lk(mu);
-        complete(sl, st == AMG_OK || st == AMG_ERR_MAXIT || st == AMG_ERR_BREAKDOWN ? info.status : st, info.iters,
-                 info.rel_res_true);
-        ++steps;
-      }
+      return AMG_OK;
+    };
+    const int32_t result = loop();
+    if (result != AMG_OK) {
+      std::lock_guard<std::mutex> lk(mu);
+      closing = true;
+      for (size_t k = next; k < reqs.size(); ++k) fail_request(reqs[k].get(), result, k == next ? cur_rhs : 0);
     }
+    (void)hipStreamSynchronize(s);
     if (f) (void)hipFree(f);
     if (u) (void)hipFree(u);
-    return AMG_OK;
+    return result;
   }
 
   ~Server() {
