@@ -109,7 +109,19 @@ def run_cpu_baseline(g, f, params: dict, sample: str):
         "solve_s": round(t_solve, 3),
         "iters": res.iters,
         "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
     }, res
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def layout_kw(args) -> dict:
@@ -453,6 +465,26 @@ def main():
     }
     print(f"[bench] cheb step: {kt['launches']} launches, avg {kt['avg_ms'] * 1e3:.2f} us -> {achieved:.0f} GB/s",
           file=sys.stderr, flush=True)
+    # the same step one launch at a time, after reading 1 GiB that displaces
+    # the level from the 256 MB Infinity Cache (cold HBM; clean lines, so no
+    # write-backs fall into the timed launch) and after reading 4 MiB (warm;
+    # the same single-launch event overhead)
+    single = {}
+    for name, mib in (("warm", 4), ("cold", 1024)):
+        buf = torch.ones(mib * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+        sink = torch.zeros(1, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        tot = 0.0
+        for _ in range(30):
+            torch.sum(buf, dim=0, out=sink[0])
+            tot += amg.amg_time_step(h, reps=1)["avg_ms"]
+        del buf, sink
+        single[name] = tot / 30
+    torch.cuda.synchronize()
+    roofline["single_launch_us"] = {k: round(v * 1e3, 2) for k, v in single.items()}
+    roofline["achieved_cold"] = round(bytes_launch / (single["cold"] * 1e-3) / 1e9, 1)
+    print(f"[bench] cheb step one launch at a time: warm {single['warm'] * 1e3:.2f} us, cold HBM "
+          f"{single['cold'] * 1e3:.2f} us -> {roofline['achieved_cold']:.0f} GB/s", file=sys.stderr, flush=True)
 
     if args.copy_probe:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)  # 256 MiB
