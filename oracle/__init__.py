@@ -62,6 +62,7 @@ from .cycle import (
     fcg,
     FCGResult,
 )
+from .amli import amli_cycle, amli_setup, estimate_lambda_min, poly_coefficients, splitmix64, start_vector
 
 __all__ = [
     "Level", "assemble", "apply_A", "bilinear_form", "row_abs_sums",
@@ -69,4 +70,5 @@ __all__ = [
     "SmootherPoly", "lambda_max_bound", "best_poly", "error_Em", "degree_for", "q_eval", "residual_poly_eval",
     "Params", "Hierarchy", "build_hierarchy", "smooth", "residual", "restrict", "prolong",
     "coarse_solve", "kcycle", "fcg", "FCGResult",
+    "amli_cycle", "amli_setup", "estimate_lambda_min", "poly_coefficients", "splitmix64", "start_vector",
 ]
