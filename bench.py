@@ -43,6 +43,9 @@ WORKLOADS = {
     "grid2d-1024-agg4": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=3, agg_size=4)),
     "grid2d-1024-hash": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=3, agg_size=16, tie_break=1)),
     "grid2d-64": (lambda: inputs.grid2d(64), "uniform", 1, dict(degree=3, agg_size=4)),
+    # the stationary AMLI W-cycle (Section 4's other column) on the default workload
+    "grid2d-1024-amli": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=3, agg_size=16, cycle=1)),
+    "tet3d-128-amli": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16, cycle=1)),
     "tet3d-128": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16)),
     "tet3d-128-mixed": (lambda: inputs.tet3d(128), "normal", 3, dict(degree=5, agg_size=16, precision=1)),
     # unstructured: jittered 64^3 grid, Delaunay tetrahedralization (Section 4's general graphs)
@@ -525,7 +528,8 @@ def main():
         "config": {
             "workload": f"{args.workload}: {g.name}, n={g.n}, stored off-diagonals={g.nnz}, "
                         f"{'mixed FP32 cycle / FP64 FCG' if mixed else 'FP64'}, agg {params.agg_size}, "
-                        f"degree {params.degree}, W(1,1) k-cycle, FCG restart {params.restart}, tol {params.tol}",
+                        f"degree {params.degree}, W(1,1) {'AMLI cycle' if params.cycle == 1 else 'k-cycle'}, "
+                        f"FCG restart {params.restart}, tol {params.tol}",
             "levels": desc["n"],
             "iters": info["iters"],
             "rel_res_true": info["rel_res_true"],
@@ -541,6 +545,8 @@ def main():
             "tail_rows": params.tail_rows,
             "layouts": desc["layouts"],
             "layout_ms": round(desc["layout_ms"], 2),
+            "cycle": "stationary AMLI W-cycle" if params.cycle == 1 else "nonlinear AMLI (k-cycle)",
+            "amli_lambda_min": [round(x, 4) for x in desc["amli_lambda_min"][1:-1]] if params.cycle == 1 else None,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -52,6 +52,7 @@ typedef enum {
 enum { AMG_FP64 = 0, AMG_MIXED = 1 };
 enum { AMG_KEY_NORMALIZED = 0, AMG_KEY_RAW = 1 };
 enum { AMG_TIE_INDEX = 0, AMG_TIE_HASH = 1 };
+enum { AMG_CYCLE_K = 0, AMG_CYCLE_AMLI = 1 };
 
 #define AMG_MAX_LEVELS 32
 
@@ -100,6 +101,13 @@ enum { AMG_TIE_INDEX = 0, AMG_TIE_HASH = 1 };
  *                 32-bit finalizer of (i * 2654435761 + j) mod 2^32 -- on
  *                 structured meshes this breaks the long index chains, so the
  *                 handshake needs far fewer rounds (a different hierarchy).
+ *   cycle         AMG_CYCLE_K (default): the nonlinear AMLI cycle (k-cycle) of
+ *                 Section 4 inside flexible CG; AMG_CYCLE_AMLI: the stationary
+ *                 AMLI W-cycle, whose coarse correction is the degree-1 best
+ *                 uniform approximation to 1/t on [a, 1] applied to the
+ *                 preconditioned coarse operator (a estimated at setup by 20
+ *                 power iterations on I - B A per level); needs inner_steps = 2;
+ *                 not available in the batched and served forms.
  *   fuse          1 (default): on levels below 2^18 rows, fold the inner
  *                 flexible-CG vector updates into the kernels that read them
  *                 and form the restriction of the residual in one pass; 0: one
@@ -127,6 +135,7 @@ typedef struct {
   int32_t tie_break;
   int32_t fuse;
   double smoother_rho;
+  int32_t cycle;
 } amg_params;
 
 typedef struct amg_hier amg_hier;
@@ -162,6 +171,7 @@ typedef struct {
   int32_t sorted_rows[AMG_MAX_LEVELS];
   int64_t sell_entries[AMG_MAX_LEVELS];  /* stored entries including padding    */
   int32_t degree;                     /* smoother degree in use                 */
+  double amli_lambda_min[AMG_MAX_LEVELS];  /* AMLI: estimated lambda_min(B_l A_l), 0 elsewhere */
 } amg_hier_desc;
 
 /* Fill *p with the defaults: degree 4, agg_size 4, coarse_max 64,

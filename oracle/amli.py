@@ -92,7 +92,10 @@ def estimate_lambda_min(h: Hierarchy, l: int, coef: dict, iters: int = AMLI_POWE
         w = v - amli_cycle(h, l, Av, coef)
         Aw = apply_A(lvl, w)
         mu = float(np.dot(w, Av)) / float(np.dot(v, Av))
-        v = w / math.sqrt(float(np.dot(w, Aw)))
+        ww = float(np.dot(w, Aw))
+        if not (ww > 0.0 and math.isfinite(ww)):
+            break
+        v = w / math.sqrt(ww)
     return 1.0 - mu
 
 

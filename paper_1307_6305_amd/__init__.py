@@ -41,6 +41,8 @@ AMG_KEY_NORMALIZED = 0
 AMG_KEY_RAW = 1
 AMG_TIE_INDEX = 0
 AMG_TIE_HASH = 1
+AMG_CYCLE_K = 0
+AMG_CYCLE_AMLI = 1
 AMG_MAX_LEVELS = 32
 
 
@@ -67,6 +69,7 @@ class amg_params(ctypes.Structure):
         ("tie_break", ctypes.c_int32),
         ("fuse", ctypes.c_int32),
         ("smoother_rho", ctypes.c_double),
+        ("cycle", ctypes.c_int32),
     ]
 
 
@@ -100,6 +103,7 @@ class amg_hier_desc(ctypes.Structure):
         ("sorted_rows", ctypes.c_int32 * AMG_MAX_LEVELS),
         ("sell_entries", ctypes.c_int64 * AMG_MAX_LEVELS),
         ("degree", ctypes.c_int32),
+        ("amli_lambda_min", ctypes.c_double * AMG_MAX_LEVELS),
     ]
 
 
@@ -265,6 +269,8 @@ def amg_params_default(**overrides) -> amg_params:
             v = {"normalized": AMG_KEY_NORMALIZED, "raw": AMG_KEY_RAW}[v]
         if k == "tie_break" and isinstance(v, str):
             v = {"index": AMG_TIE_INDEX, "hash": AMG_TIE_HASH}[v]
+        if k == "cycle" and isinstance(v, str):
+            v = {"k": AMG_CYCLE_K, "amli": AMG_CYCLE_AMLI}[v]
         setattr(p, k, v)
     return p
 
@@ -328,6 +334,7 @@ def amg_describe(h: Hierarchy) -> dict:
         "device_bytes": ds.device_bytes,
         "layout_ms": ds.layout_ms,
         "degree": ds.degree,
+        "amli_lambda_min": list(ds.amli_lambda_min[:L]),
         # sliced-ELL layout of every smoothed level (the finest at least)
         "layouts": [{"slice_height": ds.slice_height[l], "lanes_per_row": ds.lanes_per_row[l],
                      "sorted_rows": ds.sorted_rows[l], "entries": ds.sell_entries[l]}

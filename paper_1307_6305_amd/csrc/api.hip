@@ -39,6 +39,9 @@ int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s) {
   c->chol_invT = h->chol_invT;
   c->nL = h->nL;
   c->desc = h->desc;
+  c->amli_a = h->amli_a;
+  c->amli_g0 = h->amli_g0;
+  c->amli_g1 = h->amli_g1;
   c->parent = h;
   const int32_t st = prepare_solve(c, s);
   if (st != AMG_OK) {
@@ -126,6 +129,7 @@ void amg_params_default(amg_params* p) {
   p->tie_break = AMG_TIE_INDEX;
   p->fuse = 1;
   p->smoother_rho = 0.33;
+  p->cycle = AMG_CYCLE_K;
 }
 
 const char* amg_strerror(int32_t s) {
@@ -235,6 +239,10 @@ int32_t check_serve_cfg(const amg_serve_cfg* cfg) {
   if (pst != AMG_OK) {
     amg::set_last_error(msg);
     return pst;
+  }
+  if (cfg->params.cycle != AMG_CYCLE_K) {
+    amg::set_last_error("the served form runs the nonlinear cycle (AMG_CYCLE_K) only");
+    return AMG_ERR_ARG;
   }
   return AMG_OK;
 }

@@ -919,6 +919,10 @@ int32_t batch_compatible(const std::vector<amg_hier*>& hs) {
   const amg_params& p0 = hs[0]->p;
   for (size_t i = 0; i < hs.size(); ++i) {
     const amg_hier* h = hs[i];
+    if (h->p.cycle != AMG_CYCLE_K) {
+      set_last_error("the batched form runs the nonlinear cycle (AMG_CYCLE_K) only");
+      return AMG_ERR_ARG;
+    }
     if (h->mixed != hs[0]->mixed || h->p.degree != p0.degree || h->p.inner_steps != p0.inner_steps ||
         h->p.restart != p0.restart) {
       set_last_error("batched items must share precision, degree, inner steps and restart");

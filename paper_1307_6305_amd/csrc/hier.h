@@ -75,6 +75,10 @@ struct amg_hier {
   hipStream_t graph_stream = nullptr;  // stream the graphs were captured on
   const void* graph_u = nullptr;       // solution pointer baked into the graphs
 
+  // stationary AMLI cycle: per level, the estimated lambda_min(B_l A_l) and
+  // the coarse-correction polynomial g0 + g1 t (levels 1 .. L-1)
+  std::vector<double> amli_a, amli_g0, amli_g1;
+
   amg_hier_desc desc{};
   std::vector<void*> allocs;
   size_t bytes = 0;     // device bytes owned (allocs)

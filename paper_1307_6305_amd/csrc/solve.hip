@@ -151,6 +151,13 @@ __global__ void __launch_bounds__(kMaxRowThreads) k_restrict_residual(Mat<MT> A,
   }
 }
 
+// out = a x + b y in FP64 (out may alias x or y).
+template <typename VT>
+__global__ void k_axpby(int n, double a, const VT* x, double b, const VT* y, VT* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (VT)(a * (double)x[i] + b * (double)y[i]);
+}
+
 template <typename VT>
 __global__ void k_prolong(Transfer T, const VT* __restrict__ e, VT* x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -814,6 +821,8 @@ struct Engine {
       AMG_TRY(coarse(static_cast<const VT*>(b), e));
     } else if (!rec && h->tail_level == l + 1) {
       AMG_TRY(tail());
+    } else if (h->p.cycle == AMG_CYCLE_AMLI) {
+      AMG_TRY(amli_correction(l + 1));
     } else {
       AMG_TRY(inner(l + 1, &d));
     }
@@ -828,6 +837,33 @@ struct Engine {
     AMG_TRY(prolong(l, e, x, &d));
     AMG_TRY(residual(l, r, x, S));
     AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true));
+    return AMG_OK;
+  }
+
+  // The coarse correction of the cycle on level l (1 <= l < L): rhs -> sol.
+  int32_t coarse_correction(int l) {
+    if (h->p.cycle == AMG_CYCLE_AMLI) return amli_correction(l);
+    return inner(l);
+  }
+
+  // Stationary AMLI: sol = g0 y0 + g1 B(A y0), y0 = B rhs, with B the cycle on
+  // level l and g0 + g1 t the degree-1 best approximation to 1/t on [a_l, 1].
+  int32_t amli_correction(int l) {
+    auto& W = h->ws[l];
+    VT* rhs = wsv(W.rhs);
+    VT* sol = wsv(W.sol);
+    VT* y0 = wsv(W.Z[0]);
+    VT* y1 = wsv(W.Z[1]);
+    VT* ay = wsv(W.Q[0]);
+    if ((int)h->amli_g0.size() <= l) {
+      set_last_error("AMLI coefficients missing for level " + std::to_string(l));
+      return AMG_ERR_DEVICE;
+    }
+    AMG_TRY(kcycle(l, static_cast<const VT*>(rhs), y0));
+    AMG_TRY(spmv_dots(l, y0, ay, y0, slots2(S_DUMMY, S_DUMMY)));
+    AMG_TRY(kcycle(l, static_cast<const VT*>(ay), y1));
+    AMG_TRY(scale_add(l, static_cast<const VT*>(y0), sol, h->amli_g0[l], false));
+    AMG_TRY(scale_add(l, static_cast<const VT*>(y1), sol, h->amli_g1[l], true));
     return AMG_OK;
   }
 
@@ -1124,7 +1160,7 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
     std::vector<TailOp> ops;
     {
       Engine<VT, MT> E{h, s, &ops};
-      if (E.inner(cand) != AMG_OK) break;
+      if (E.coarse_correction(cand) != AMG_OK) break;
     }
     size_t tot = header_bytes(ops);
     for (const auto& b : bufs) tot += round16(b.bytes);
@@ -1135,7 +1171,7 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   std::vector<TailOp> ops;
   {
     Engine<VT, MT> E{h, s, &ops};
-    AMG_TRY(E.inner(t));
+    AMG_TRY(E.coarse_correction(t));
   }
   // the last step, sol += alpha p on the tail level, goes into the copy-out
   TailOp fin{};
@@ -1309,6 +1345,88 @@ void destroy_graphs(amg_hier* h) {
 
 int32_t prepare_solve_impl(amg_hier* h, hipStream_t s);
 
+// ---- stationary AMLI: the coarse-correction polynomials
+constexpr int kAmliPowerIters = 20;
+constexpr double kAmliMinA = 1e-3, kAmliMaxA = 0.99;
+
+// splitmix64 (Steele, Lea and Flood): one output of the generator whose state
+// is x.
+inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// g0 + g1 t: the degree-1 best uniform approximation to 1/t on [a, 1] (the
+// smoother's closed form with lambda1 = 1, lambda0 = a).
+void amli_poly(double a, double* g0, double* g1) {
+  const double theta = 0.5 * (1.0 + a), eta = 0.5 * (1.0 - a);
+  const double sk = std::sqrt(1.0 / a);
+  const double dl = (sk - 1.0) / (sk + 1.0);
+  const double om = 1.0 - dl * dl;
+  const double c0 = 2.0 * dl / om;
+  const double c1 = -4.0 * dl * dl / (om * om);
+  *g1 = c1 / (eta * eta);
+  *g0 = (c0 - c1 * theta / eta) / eta;
+}
+
+// lambda_min(B_l A_l) for l = L-1 .. 1 (each B_l uses the polynomials of the
+// levels below it): power iteration on I - B_l A_l in the A_l inner product
+// from a counter-based start vector, Rayleigh quotients mu, a_l = 1 - mu.
+template <typename VT, typename MT>
+int32_t estimate_amli(amg_hier* h, hipStream_t s) {
+  const auto t0 = clk::now();
+  const int L = h->L;
+  h->amli_a.assign(L + 1, 0.0);
+  h->amli_g0.assign(L + 1, 0.0);
+  h->amli_g1.assign(L + 1, 0.0);
+  Engine<VT, MT> E{h, s};
+  std::vector<VT> v0;
+  double sc[4];
+  constexpr int S_VAV = S_DOTS, S_VV = S_DOTS + 1, S_WAW = S_DOTS + 2, S_WAV = S_DOTS + 3;
+  for (int l = L - 1; l >= 1; --l) {
+    const int n = h->lv[l].n;
+    auto& W = h->ws[l];
+    VT* V = static_cast<VT*>(W.Q[1]);
+    VT* AV = static_cast<VT*>(W.Q[0]);
+    VT* Y = static_cast<VT*>(W.Z[0]);
+    VT* AW = static_cast<VT*>(W.Z[1]);
+    if (!V || !AV || !Y || !AW) {
+      set_last_error("AMLI needs the two-step workspace on every coarse level");
+      return AMG_ERR_ARG;
+    }
+    v0.resize(n);
+    const uint64_t base = (uint64_t)l << 40;
+    for (int i = 0; i < n; ++i)
+      v0[i] = (VT)(2.0 * ((double)(splitmix64(base + (uint64_t)i) >> 11) * 0x1.0p-53) - 1.0);
+    AMG_HIP(hipMemcpyAsync(V, v0.data(), sizeof(VT) * n, hipMemcpyHostToDevice, s));
+    double mu = 0.0;
+    for (int it = 0; it < kAmliPowerIters; ++it) {
+      AMG_TRY(E.spmv_dots(l, V, AV, V, slots2(S_VAV, S_VV)));
+      AMG_TRY(E.kcycle(l, static_cast<const VT*>(AV), Y));
+      hipLaunchKernelGGL((k_axpby<VT>), dim3(nblk(n)), dim3(TPB), 0, s, n, 1.0, (const VT*)V, -1.0, (const VT*)Y, Y);
+      AMG_HIP(hipGetLastError());
+      AMG_TRY(E.spmv_dots(l, Y, AW, AV, slots2(S_WAW, S_WAV)));
+      AMG_HIP(hipMemcpyAsync(sc, h->scal + S_DOTS, sizeof(sc), hipMemcpyDeviceToHost, s));
+      AMG_HIP(hipStreamSynchronize(s));
+      mu = sc[3] / sc[0];
+      const double ww = sc[2];
+      if (!(ww > 0.0) || !std::isfinite(ww)) break;
+      hipLaunchKernelGGL((k_axpby<VT>), dim3(nblk(n)), dim3(TPB), 0, s, n, 1.0 / std::sqrt(ww), (const VT*)Y, 0.0,
+                         (const VT*)V, V);
+      AMG_HIP(hipGetLastError());
+    }
+    const double a = std::min(std::max(1.0 - mu, kAmliMinA), kAmliMaxA);
+    h->amli_a[l] = a;
+    amli_poly(a, &h->amli_g0[l], &h->amli_g1[l]);
+    h->desc.amli_lambda_min[l] = a;
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+  h->desc.setup_ms += std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  return AMG_OK;
+}
+
 // The aggregate-to-block map of the fused residual + restriction on level l:
 // aggregates in order, packed greedily into blocks of at most TPB member
 // rows; members must be listed aggregate by aggregate.  Sorted layouts also
@@ -1414,6 +1532,15 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
   AMG_HIP(hipGetLastError());
   AMG_HIP(hipHostMalloc((void**)&h->host_scal, 64 * sizeof(double), hipHostMallocCoherent));
   AMG_HIP(hipStreamSynchronize(s));
+  if (h->p.cycle == AMG_CYCLE_AMLI && h->amli_g0.empty()) {
+    // the cycle on each level runs through device-wide kernels here: the tail
+    // program (which records these polynomials) is prepared afterwards
+    if (h->mixed) {
+      AMG_TRY(estimate_amli<float, float>(h, s));
+    } else {
+      AMG_TRY(estimate_amli<double, double>(h, s));
+    }
+  }
   if (h->mixed) {
     AMG_TRY(prepare_tail<float, float>(h, s));
   } else {

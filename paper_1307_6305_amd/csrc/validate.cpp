@@ -59,6 +59,14 @@ int32_t validate_params(const amg_params& p, std::string& msg) {
   }
   if (p.sort_rows != 0 && p.sort_rows != 1) { msg = "sort_rows must be 0 or 1"; return AMG_ERR_ARG; }
   if (p.fuse != 0 && p.fuse != 1) { msg = "fuse must be 0 or 1"; return AMG_ERR_ARG; }
+  if (p.cycle != AMG_CYCLE_K && p.cycle != AMG_CYCLE_AMLI) {
+    msg = "cycle must be AMG_CYCLE_K or AMG_CYCLE_AMLI";
+    return AMG_ERR_ARG;
+  }
+  if (p.cycle == AMG_CYCLE_AMLI && p.inner_steps != 2) {
+    msg = "the AMLI cycle is a W-cycle: inner_steps must be 2";
+    return AMG_ERR_ARG;
+  }
   if (p.tie_break != AMG_TIE_INDEX && p.tie_break != AMG_TIE_HASH) {
     msg = "tie_break must be AMG_TIE_INDEX or AMG_TIE_HASH";
     return AMG_ERR_ARG;

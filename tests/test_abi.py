@@ -50,7 +50,7 @@ def test_params_default(amg):
     assert p.lambda0_ratio == 10.0 and p.tol == 1e-8 and p.precision == amg.AMG_FP64
     assert (p.autotune, p.slice_height, p.lanes_per_row, p.sort_rows) == (1, 64, 1, 0)
     assert p.tie_break == amg.AMG_TIE_INDEX and amg.amg_params_default(tie_break="hash").tie_break == amg.AMG_TIE_HASH
-    assert p.fuse == 1 and p.smoother_rho == 0.33
+    assert p.fuse == 1 and p.smoother_rho == 0.33 and p.cycle == amg.AMG_CYCLE_K
     with pytest.raises(TypeError):
         amg.amg_params_default(no_such_field=1)
 
@@ -108,7 +108,8 @@ def test_validation_errors_before_device(amg):
     assert _setup_code(amg, 0, g.row_ptr, g.col, g.w, g.d)[0] == amg.AMG_ERR_ARG
     for bad in (dict(slice_height=4), dict(slice_height=48), dict(lanes_per_row=3), dict(lanes_per_row=8),
                 dict(sort_rows=2), dict(autotune=-1), dict(tie_break=2), dict(fuse=2),
-                dict(degree=-2), dict(degree=-1, smoother_rho=0.0), dict(degree=-1, smoother_rho=1.5)):
+                dict(degree=-2), dict(degree=-1, smoother_rho=0.0), dict(degree=-1, smoother_rho=1.5),
+                dict(cycle=2), dict(cycle=1, inner_steps=3)):
         code = _setup_code(amg, g.n, g.row_ptr, g.col, g.w, g.d, amg.amg_params_default(**bad))[0]
         assert code == amg.AMG_ERR_ARG, bad
     # unsorted columns
@@ -137,6 +138,8 @@ def test_server_argument_errors_before_device(amg):
         assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG, bad
         assert not hnd.value
     cfg = amg.amg_serve_cfg_default(amg.amg_params_default(restart=0))
+    assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
+    cfg = amg.amg_serve_cfg_default(amg.amg_params_default(cycle="amli"))
     assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
     assert lib.amg_server_create(ctypes.byref(amg.amg_serve_cfg_default()), None, None) == amg.AMG_ERR_ARG
     cnt = ctypes.c_int32()
