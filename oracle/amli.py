@@ -18,7 +18,10 @@ interval it approximates on; readings taken here:
   k-cycle.
 * a_l estimates the smallest eigenvalue of B_l A_l: power iteration on
   I - B_l A_l in the A_l inner product, `AMLI_POWER_ITERS` steps, a = 1 - the
-  last Rayleigh quotient, clamped to [1e-3, 0.99].  Levels are treated from the
+  last Rayleigh quotient, clamped to [0.18, 0.99]: the degree-1 best
+  approximation is positive on (0, 1] only for a > 3 - 2 sqrt(2) = 0.1716, and
+  CG needs the cycle to stay positive definite (for t < a the polynomial is
+  larger still, so a clamped interval keeps it positive on the whole spectrum).  Levels are treated from the
   coarsest up (B_l needs a_{l+1}).  The start vector is counter-based:
   v_i = 2 u(splitmix64(2^40 l + i)) - 1 with u(z) = (z >> 11) 2^-53, splitmix64
   as published by Steele, Lea and Flood (one output of the generator whose
@@ -38,7 +41,7 @@ from .level import apply_A
 from .poly import best_poly
 
 AMLI_POWER_ITERS = 20
-A_MIN, A_MAX = 1e-3, 0.99
+A_MIN, A_MAX = 0.18, 0.99
 _MASK = (1 << 64) - 1
 
 

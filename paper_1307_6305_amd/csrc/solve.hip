@@ -1347,7 +1347,8 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s);
 
 // ---- stationary AMLI: the coarse-correction polynomials
 constexpr int kAmliPowerIters = 20;
-constexpr double kAmliMinA = 1e-3, kAmliMaxA = 0.99;
+// a below 3 - 2 sqrt(2) would make the degree-1 polynomial negative near t = 1
+constexpr double kAmliMinA = 0.18, kAmliMaxA = 0.99;
 
 // splitmix64 (Steele, Lea and Flood): one output of the generator whose state
 // is x.

@@ -89,3 +89,14 @@ def test_amli_cg_converges(N, agg):
         e = res.x - u
         lvl = h.levels[0]
         assert np.sqrt(e @ oracle.apply_A(lvl, e)) <= 1e-7 * np.sqrt(u @ oracle.apply_A(lvl, u))
+
+
+def test_positivity_threshold():
+    """The degree-1 best approximation to 1/t on [a, 1] is positive at t = 1
+    exactly when a > 3 - 2 sqrt(2); the interval is clamped above it."""
+    thr = 3 - 2 * np.sqrt(2)
+    for a in (thr - 1e-3, thr + 1e-3):
+        g0, g1 = oracle.poly_coefficients(a)
+        assert (g0 + g1 > 0) == (a > thr)
+    from oracle.amli import A_MIN
+    assert A_MIN > thr
