@@ -119,6 +119,44 @@ def tet3d(N: int) -> Graph:
     return Graph(n, row_ptr, col, w, d, name=f"tet3d-{N}")
 
 
+def poisson2d(N: int, neumann: bool = True) -> Graph:
+    """Linear finite elements for the Laplacian on the unit square with the
+    structured right-triangle mesh of Section 4 (n = N^2): the stiffness matrix
+    is the 5-point graph Laplacian (the diagonal edges of the triangles carry
+    zero weight and are not stored), w_e = 1.  Neumann (d = 0) as in the
+    paper's experiments, else d = 1 on the boundary."""
+    r, c = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    vid = r * N + c
+    ei = np.concatenate([vid[:, :-1].ravel(), vid[:-1, :].ravel()])
+    ej = np.concatenate([vid[:, 1:].ravel(), vid[1:, :].ravel()])
+    row_ptr, col, w = csr_from_edges(N * N, ei, ej)
+    bnd = (r == 0) | (r == N - 1) | (c == 0) | (c == N - 1)
+    d = np.zeros(N * N) if neumann else bnd.ravel().astype(np.float64)
+    return Graph(N * N, row_ptr, col, w, d, name=f"poisson2d-{N}{'-neumann' if neumann else ''}")
+
+
+def poisson3d(N: int, neumann: bool = True) -> Graph:
+    """The same on the unit cube with the Kuhn 6-tetrahedra mesh (n = N^3): the
+    stiffness matrix is the 7-point graph Laplacian (the face and body
+    diagonals carry zero weight), w_e = 1, vertex id (z*N+y)*N+x."""
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    vid = ((z * N + y) * N + x).astype(np.int64)
+    ei = np.concatenate([vid[:, :, :-1].ravel(), vid[:, :-1, :].ravel(), vid[:-1, :, :].ravel()])
+    ej = np.concatenate([vid[:, :, 1:].ravel(), vid[:, 1:, :].ravel(), vid[1:, :, :].ravel()])
+    n = N ** 3
+    row_ptr, col, w = csr_from_edges(n, ei, ej)
+    bnd = (x == 0) | (x == N - 1) | (y == 0) | (y == N - 1) | (z == 0) | (z == N - 1)
+    d = np.zeros(n) if neumann else bnd.ravel().astype(np.float64)
+    return Graph(n, row_ptr, col, w, d, name=f"poisson3d-{N}{'-neumann' if neumann else ''}")
+
+
+def project_range(f: np.ndarray) -> np.ndarray:
+    """f minus its mean: the right-hand side of a pure Neumann problem must be
+    orthogonal to the constants (the kernel of A)."""
+    f = np.asarray(f, dtype=np.float64)
+    return f - f.mean()
+
+
 def delaunay3d(N: int, seed: int) -> Graph:
     """Unstructured mesh of the unit cube in the manner of Section 4's general
     graphs: the N^3 vertices of the structured grid (spacing h = 1/(N-1), id

@@ -47,6 +47,10 @@ from .aggregation import (
     coarse_ids,
     quotient,
     aggregate_level,
+    mis_keys,
+    distance_k_mis,
+    nearest_owner,
+    mis_aggregate,
 )
 from .poly import SmootherPoly, lambda_max_bound, best_poly, error_Em, degree_for, q_eval, residual_poly_eval
 from .cycle import (
@@ -67,6 +71,7 @@ from .amli import amli_cycle, amli_setup, estimate_lambda_min, poly_coefficients
 __all__ = [
     "Level", "assemble", "apply_A", "bilinear_form", "row_abs_sums",
     "edge_strengths", "greedy_matching", "coarse_ids", "quotient", "aggregate_level",
+    "mis_keys", "distance_k_mis", "nearest_owner", "mis_aggregate",
     "SmootherPoly", "lambda_max_bound", "best_poly", "error_Em", "degree_for", "q_eval", "residual_poly_eval",
     "Params", "Hierarchy", "build_hierarchy", "smooth", "residual", "restrict", "prolong",
     "coarse_solve", "kcycle", "fcg", "FCGResult",

@@ -10,7 +10,8 @@ that this triple product reduces to summations of fine-level entries.
 
 Readings taken where the paper is silent (the paper's own experiments aggregate
 with a maximal independent set on the graph of A^4, Section 4; the workloads
-built here use matching passes instead):
+built here use matching passes by default, and the MIS aggregation of Section 2
+is the option at the end of this module):
 
 * Edge strength.  ``normalized`` (default): s_ij = W_ij^2 / (D_i D_j), evaluated
   as the correctly rounded products W_ij*W_ij and D_i*D_j followed by one
@@ -40,6 +41,7 @@ from __future__ import annotations
 import numpy as np
 
 from .level import Level, assemble
+from .rng import splitmix64
 
 
 def edge_strengths(lvl: Level, key: str = "normalized"):
@@ -148,3 +150,76 @@ def aggregate_level(lvl: Level, passes: int, key: str = "normalized", tie: str =
         g = quotient(g, ids, nc)
         agg = ids[agg]
     return agg, g
+
+
+# ---- the paper's own aggregation: a maximal independent set of the graph of A^k
+
+
+def mis_keys(n: int) -> np.ndarray:
+    """Priority of vertex v: splitmix64(v) (distinct: the generator's output
+    function is a bijection of 64-bit words)."""
+    return np.array([splitmix64(v) for v in range(n)], dtype=np.uint64)
+
+
+def _within(lvl: Level, v: int, k: int) -> np.ndarray:
+    """Vertices at graph distance <= k from v (breadth-first, k hops)."""
+    seen = {v}
+    frontier = [v]
+    for _ in range(k):
+        nxt = []
+        for u in frontier:
+            for w in lvl.col[lvl.row_ptr[u]:lvl.row_ptr[u + 1]]:
+                w = int(w)
+                if w not in seen:
+                    seen.add(w)
+                    nxt.append(w)
+        frontier = nxt
+    return np.fromiter(seen, dtype=np.int64)
+
+
+def distance_k_mis(lvl: Level, k: int) -> np.ndarray:
+    """Step (A) of Section 2's partitioning: a maximal independent set of the
+    graph of A^k (two vertices adjacent when at graph distance <= k).  Reading:
+    the greedy set that takes vertices in decreasing priority (mis_keys) and
+    skips those within distance k of a taken one.  Returned sorted."""
+    keys = mis_keys(lvl.n)
+    blocked = np.zeros(lvl.n, dtype=bool)
+    S = []
+    for v in np.argsort(keys)[::-1]:
+        v = int(v)
+        if blocked[v]:
+            continue
+        S.append(v)
+        blocked[_within(lvl, v, k)] = True
+    return np.array(sorted(S), dtype=np.int64)
+
+
+def nearest_owner(lvl: Level, S: np.ndarray) -> np.ndarray:
+    """Step (B): every vertex joins the set vertex nearest to it in graph
+    distance (breadth-first from all of S at once); a vertex first reached at
+    hop h takes the smallest owner among its neighbours reached at hop h-1."""
+    n = lvl.n
+    owner = -np.ones(n, dtype=np.int64)
+    owner[S] = S
+    frontier = list(S)
+    while frontier:
+        cand = {}
+        for u in frontier:
+            for w in lvl.col[lvl.row_ptr[u]:lvl.row_ptr[u + 1]]:
+                w = int(w)
+                if owner[w] < 0:
+                    cand[w] = min(cand.get(w, n), int(owner[u]))
+        for w, o in cand.items():
+            owner[w] = o
+        frontier = list(cand)
+    return owner
+
+
+def mis_aggregate(lvl: Level, k: int = 4):
+    """(ids, nc): aggregates of steps (A) and (B), coarse ids in increasing
+    order of the set vertex that owns them."""
+    S = distance_k_mis(lvl, k)
+    owner = nearest_owner(lvl, S)
+    if np.any(owner < 0):
+        raise ValueError("graph is not connected")
+    return np.searchsorted(S, owner).astype(np.int64), int(S.shape[0])

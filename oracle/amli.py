@@ -40,16 +40,10 @@ from .cycle import Hierarchy, coarse_solve, prolong, residual, restrict, smooth
 from .level import apply_A
 from .poly import best_poly
 
+from .rng import splitmix64
+
 AMLI_POWER_ITERS = 20
 A_MIN, A_MAX = 0.18, 0.99
-_MASK = (1 << 64) - 1
-
-
-def splitmix64(x: int) -> int:
-    z = (x + 0x9E3779B97F4A7C15) & _MASK
-    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
-    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
-    return z ^ (z >> 31)
 
 
 def start_vector(level: int, n: int) -> np.ndarray:

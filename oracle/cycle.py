@@ -34,7 +34,10 @@ Readings taken where the paper is silent:
   10 % (then that level is the coarsest, which must have at most
   max_coarsest rows).
 * Coarsest solve: dense Cholesky factorization of A_L (SPD because some d_i > 0
-  on a connected graph) and two triangular solves.
+  on a connected graph) and two triangular solves.  Pure Neumann problems
+  (every d_i = 0, Section 4's experiments): A is singular with kernel span{1};
+  the factor is that of A_L + (1/n_L) 1 1^T, whose inverse is the pseudo-inverse
+  on right-hand sides orthogonal to 1 (the caller projects f onto range(A)).
 """
 from __future__ import annotations
 
@@ -44,7 +47,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .aggregation import aggregate_level
+from .aggregation import aggregate_level, mis_aggregate, quotient
 from .level import Level, apply_A, assemble
 from .poly import SmootherPoly, best_poly, error_Em, lambda_max_bound
 
@@ -63,6 +66,8 @@ class Params:
     tie_break: str = "index"
     max_coarsest: int = 2048
     stagnation: float = 0.9
+    aggregation: str = "matching"  # or "mis": Section 2's steps (A), (B) on the graph of A^k
+    mis_distance: int = 4
 
     @property
     def passes(self) -> int:
@@ -102,7 +107,11 @@ def build_hierarchy(n, row_ptr, col, w, d, params: Params | None = None) -> Hier
     aggs = []
     while levels[-1].n > p.coarse_max:
         cur = levels[-1]
-        agg, coarse = aggregate_level(cur, p.passes, p.match_key, p.tie_break)
+        if p.aggregation == "mis":
+            agg, nc = mis_aggregate(cur, p.mis_distance)
+            coarse = quotient(cur, agg, nc)
+        else:
+            agg, coarse = aggregate_level(cur, p.passes, p.match_key, p.tie_break)
         if coarse.n > p.stagnation * cur.n:
             break
         aggs.append(agg)
@@ -110,7 +119,13 @@ def build_hierarchy(n, row_ptr, col, w, d, params: Params | None = None) -> Hier
     if levels[-1].n > p.max_coarsest:
         raise CoarsenError(f"coarsest level has {levels[-1].n} rows")
     polys = [best_poly(lambda_max_bound(l), p.degree, p.lambda0_ratio) for l in levels[:-1]]
-    chol = np.linalg.cholesky(levels[-1].dense())
+    AL = levels[-1].dense()
+    if not np.any(levels[-1].d):
+        # pure Neumann problem (all d_i = 0): A is singular with the constants as
+        # kernel on the connected graph; A_L + (1/n_L) 1 1^T is SPD and its inverse
+        # acts as the pseudo-inverse on right-hand sides orthogonal to 1
+        AL = AL + np.ones_like(AL) / AL.shape[0]
+    chol = np.linalg.cholesky(AL)
     return Hierarchy(levels, aggs, polys, chol, p)
 
 
