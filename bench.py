@@ -53,6 +53,13 @@ WORKLOADS = {
                       dict(degree=4, agg_size=16)),
     "delaunay3d-64-mixed": (lambda: inputs.delaunay3d(64, inputs.seed_for(6, 64)), "normal", 6,
                             dict(degree=4, agg_size=16, precision=1)),
+    # Section 4's model problems as the paper runs them: pure Neumann Laplacians
+    # of the structured FE meshes, aggregates from an independent set of the
+    # graph of A^4 grown to nearest owners
+    "poisson2d-1024-mis": (lambda: inputs.poisson2d(1024), "uniform", 7, dict(degree=3, aggregation="mis",
+                                                                               neumann=1)),
+    "poisson3d-128-mis": (lambda: inputs.poisson3d(128), "uniform", 8, dict(degree=5, aggregation="mis",
+                                                                             neumann=1)),
     # one random geometric graph of the batched form's kind, at 2M points
     "rgg-2m-mixed": (lambda: inputs.rgg(2_000_000, inputs.seed_for(4, 999)), "uniform", 4,
                      dict(degree=4, agg_size=8, precision=1)),
@@ -95,12 +102,20 @@ def cheb_step_bytes(n: int, nnz: int, mixed: bool) -> int:
 def run_cpu_baseline(g, f, params: dict, sample: str):
     import oracle
 
-    op = oracle.Params(degree=params["degree"], agg_size=params["agg_size"])
+    op = oracle.Params(degree=params.get("degree", 4), agg_size=params.get("agg_size", 4),
+                       match_key="raw" if params.get("match_key", 0) == 1 else "normalized",
+                       tie_break="hash" if params.get("tie_break", 0) == 1 else "index",
+                       aggregation=params.get("aggregation", "matching"),
+                       mis_distance=params.get("mis_distance", 4))
     t0 = time.perf_counter()
     h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, op)
+    precond = None
+    if params.get("cycle", 0) == 1:
+        _, coef = oracle.amli_setup(h)
+        precond = lambda r: oracle.amli_cycle(h, 0, r, coef)  # noqa: E731
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
-    res = oracle.fcg(h, f)
+    res = oracle.fcg(h, f, precond=precond)
     t_solve = time.perf_counter() - t0
     return {
         "value": g.n / t_solve,
@@ -114,6 +129,13 @@ def run_cpu_baseline(g, f, params: dict, sample: str):
         "host_cpus": os.cpu_count(),
         "cpu_model": cpu_model(),
     }, res
+
+
+def agg_text(amg, params) -> str:
+    if params.aggregation == amg.AMG_AGG_MIS:
+        return f"aggregates: independent set of the graph of A^{params.mis_distance} + nearest owner" + \
+            (", pure Neumann" if params.neumann else "")
+    return f"agg {params.agg_size} ({int(round(np.log2(params.agg_size)))} matching passes)"
 
 
 def cpu_model() -> str:
@@ -412,6 +434,8 @@ def main():
     make, rhs_kind, cfg, pkw = WORKLOADS[args.workload]
     g = make()
     f_np = inputs.rhs(g.n, inputs.seed_for(cfg), rhs_kind)
+    if not np.any(g.d):  # pure Neumann: f orthogonal to the constants
+        f_np = inputs.project_range(f_np)
     pkw = dict(pkw)
     if args.no_graph:
         pkw["use_graph"] = 0
@@ -527,7 +551,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {g.name}, n={g.n}, stored off-diagonals={g.nnz}, "
-                        f"{'mixed FP32 cycle / FP64 FCG' if mixed else 'FP64'}, agg {params.agg_size}, "
+                        f"{'mixed FP32 cycle / FP64 FCG' if mixed else 'FP64'}, "
+                        f"{agg_text(amg, params)}, "
                         f"degree {params.degree}, W(1,1) {'AMLI cycle' if params.cycle == 1 else 'k-cycle'}, "
                         f"FCG restart {params.restart}, tol {params.tol}",
             "levels": desc["n"],

@@ -53,6 +53,7 @@ enum { AMG_FP64 = 0, AMG_MIXED = 1 };
 enum { AMG_KEY_NORMALIZED = 0, AMG_KEY_RAW = 1 };
 enum { AMG_TIE_INDEX = 0, AMG_TIE_HASH = 1 };
 enum { AMG_CYCLE_K = 0, AMG_CYCLE_AMLI = 1 };
+enum { AMG_AGG_MATCHING = 0, AMG_AGG_MIS = 1 };
 
 #define AMG_MAX_LEVELS 32
 
@@ -108,6 +109,17 @@ enum { AMG_CYCLE_K = 0, AMG_CYCLE_AMLI = 1 };
  *                 preconditioned coarse operator (a estimated at setup by 20
  *                 power iterations on I - B A per level); needs inner_steps = 2;
  *                 not available in the batched and served forms.
+ *   aggregation   AMG_AGG_MATCHING (default): agg_size = 2^P from P heavy-edge
+ *                 matching passes; AMG_AGG_MIS: Section 2's partitioning as the
+ *                 paper's experiments use it -- a maximal independent set of
+ *                 the graph of A^k (k = mis_distance; vertices taken in
+ *                 decreasing splitmix64(index) priority), then every vertex
+ *                 joins its nearest set vertex (ties: the smallest index).
+ *   mis_distance  k of AMG_AGG_MIS, 1..8 (Section 4: 4).
+ *   neumann       1: allow d = 0 everywhere (pure Neumann problem, A singular
+ *                 with the constants as kernel): the coarsest factor is that of
+ *                 A_L + (1/n_L) 1 1^T, a pseudo-inverse on right-hand sides
+ *                 orthogonal to 1; the caller passes f orthogonal to 1.
  *   fuse          1 (default): on levels below 2^18 rows, fold the inner
  *                 flexible-CG vector updates into the kernels that read them
  *                 and form the restriction of the residual in one pass; 0: one
@@ -136,6 +148,9 @@ typedef struct {
   int32_t fuse;
   double smoother_rho;
   int32_t cycle;
+  int32_t aggregation;
+  int32_t mis_distance;
+  int32_t neumann;
 } amg_params;
 
 typedef struct amg_hier amg_hier;

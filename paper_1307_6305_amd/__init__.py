@@ -43,6 +43,8 @@ AMG_TIE_INDEX = 0
 AMG_TIE_HASH = 1
 AMG_CYCLE_K = 0
 AMG_CYCLE_AMLI = 1
+AMG_AGG_MATCHING = 0
+AMG_AGG_MIS = 1
 AMG_MAX_LEVELS = 32
 
 
@@ -70,6 +72,9 @@ class amg_params(ctypes.Structure):
         ("fuse", ctypes.c_int32),
         ("smoother_rho", ctypes.c_double),
         ("cycle", ctypes.c_int32),
+        ("aggregation", ctypes.c_int32),
+        ("mis_distance", ctypes.c_int32),
+        ("neumann", ctypes.c_int32),
     ]
 
 
@@ -271,6 +276,8 @@ def amg_params_default(**overrides) -> amg_params:
             v = {"index": AMG_TIE_INDEX, "hash": AMG_TIE_HASH}[v]
         if k == "cycle" and isinstance(v, str):
             v = {"k": AMG_CYCLE_K, "amli": AMG_CYCLE_AMLI}[v]
+        if k == "aggregation" and isinstance(v, str):
+            v = {"matching": AMG_AGG_MATCHING, "mis": AMG_AGG_MIS}[v]
         setattr(p, k, v)
     return p
 

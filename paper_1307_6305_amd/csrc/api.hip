@@ -130,6 +130,9 @@ void amg_params_default(amg_params* p) {
   p->fuse = 1;
   p->smoother_rho = 0.33;
   p->cycle = AMG_CYCLE_K;
+  p->aggregation = AMG_AGG_MATCHING;
+  p->mis_distance = 4;
+  p->neumann = 0;
 }
 
 const char* amg_strerror(int32_t s) {
@@ -162,7 +165,7 @@ int32_t amg_setup(int32_t n, const int32_t* row_ptr, const int32_t* col, const d
   int32_t st = amg::validate_params(p, msg);
   if (st != AMG_OK) { amg::set_last_error(msg); return st; }
   p.degree = amg::resolved_degree(p);
-  st = amg::validate_graph(n, row_ptr, col, w, d, msg);
+  st = amg::validate_graph(n, row_ptr, col, w, d, msg, p.neumann != 0);
   if (st != AMG_OK) { amg::set_last_error(msg); return st; }
   AMG_TRY(check_device());
   amg_hier* h = new amg_hier();

@@ -91,8 +91,9 @@ int32_t validate_params(const amg_params& p, std::string& msg);
 // The smoother degree in use: p.degree, or for -1 the smallest m with
 // E_m <= p.smoother_rho and E_m < 1 (valid parameters only).
 int32_t resolved_degree(const amg_params& p);
+// allow_singular: d = 0 everywhere is accepted (pure Neumann problem).
 int32_t validate_graph(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
-                       const double* d, std::string& msg);
+                       const double* d, std::string& msg, bool allow_singular = false);
 
 // Device allocation owned by the hierarchy (freed by amg_free).
 int32_t dalloc(amg_hier* h, void** p, size_t bytes);

@@ -16,6 +16,7 @@
 // fused.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -572,6 +573,176 @@ __global__ void k_sort_members(int nc, const int* __restrict__ off, int* __restr
   }
 }
 
+// ------------------------------------------------------------------ MIS aggregation
+// Section 2's partitioning as the paper's experiments use it: (A) a maximal
+// independent set S of the graph of A^k, (B) every vertex joins its nearest
+// vertex of S.  S is the greedy set in decreasing priority key(v) =
+// splitmix64(v), computed in rounds: an undecided vertex joins when no member
+// of S and no undecided vertex of larger key lies within distance k (k hops of
+// max / or propagation), and leaves when a member lies within distance k --
+// the same set as taking the vertices one by one in key order.
+__device__ __forceinline__ unsigned long long mis_key(int v) {
+  unsigned long long z = (unsigned long long)v + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// state: 0 undecided, 1 in S, 2 out
+__global__ void k_mis_seed(int n, const int* __restrict__ state, unsigned long long* __restrict__ mx,
+                           int* __restrict__ near) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  mx[v] = state[v] == 0 ? mis_key(v) : 0ull;
+  near[v] = state[v] == 1 ? 1 : 0;
+}
+
+// one hop over the closed neighbourhood: the largest undecided key and
+// whether a member of S is there
+__global__ void k_mis_hop(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                          const unsigned long long* __restrict__ mx_in, const int* __restrict__ near_in,
+                          unsigned long long* __restrict__ mx_out, int* __restrict__ near_out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  unsigned long long m = mx_in[v];
+  int f = near_in[v];
+  for (int e = rp[v]; e < rp[v + 1]; ++e) {
+    const int u = col[e];
+    const unsigned long long mu = mx_in[u];
+    m = mu > m ? mu : m;
+    f |= near_in[u];
+  }
+  mx_out[v] = m;
+  near_out[v] = f;
+}
+
+__global__ void k_mis_decide(int n, int* __restrict__ state, const unsigned long long* __restrict__ mx,
+                             const int* __restrict__ near, int* undecided) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || state[v] != 0) return;
+  if (near[v]) {
+    state[v] = 2;
+  } else if (mx[v] == mis_key(v)) {
+    state[v] = 1;
+  } else {
+    atomicAdd(undecided, 1);
+  }
+}
+
+__global__ void k_owner_init(int n, const int* __restrict__ state, int* __restrict__ owner, int* __restrict__ flag) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  owner[v] = state[v] == 1 ? v : -1;
+  flag[v] = state[v] == 1 ? 1 : 0;
+}
+
+// one breadth-first hop from all of S: a vertex first reached now takes the
+// smallest owner among its reached neighbours (all reached one hop earlier)
+__global__ void k_owner_hop(int n, const int* __restrict__ rp, const int* __restrict__ col,
+                            const int* __restrict__ own_in, int* __restrict__ own_out, int* changed) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int o = own_in[v];
+  if (o < 0) {
+    int best = INT_MAX;
+    for (int e = rp[v]; e < rp[v + 1]; ++e) {
+      const int ou = own_in[col[e]];
+      if (ou >= 0 && ou < best) best = ou;
+    }
+    if (best != INT_MAX) {
+      o = best;
+      *changed = 1;
+    }
+  }
+  own_out[v] = o;
+}
+
+__global__ void k_owner_ids(int n, const int* __restrict__ owner, const int* __restrict__ pos, int* __restrict__ ids,
+                            int* bad) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int o = owner[v];
+  if (o < 0) {
+    ids[v] = 0;
+    atomicAdd(bad, 1);
+  } else {
+    ids[v] = pos[o];
+  }
+}
+
+// Galerkin over member lists: coarse row I gathers the entries of its member
+// rows (members in increasing order, entries in row order), drops J = I,
+// sorts by J keeping that order among equal J (insertion), and adds runs of
+// equal J left to right -- the sums of the sequential definition.
+__global__ void k_galm_len(int nc, const int* __restrict__ moff, const int* __restrict__ members,
+                           const int* __restrict__ rp, int* __restrict__ len) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int s = 0;
+  for (int k = moff[I]; k < moff[I + 1]; ++k) {
+    const int i = members[k];
+    s += rp[i + 1] - rp[i];
+  }
+  len[I] = s;
+}
+
+__global__ void k_galm_sort(int nc, const int* __restrict__ moff, const int* __restrict__ members,
+                            const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ W,
+                            const int* __restrict__ ids, const int* __restrict__ toff, int* __restrict__ tJ,
+                            double* __restrict__ tW, int* __restrict__ tcnt, int* __restrict__ ucnt) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int o = toff[I];
+  int c = 0;
+  for (int k = moff[I]; k < moff[I + 1]; ++k) {
+    const int i = members[k];
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      const int J = ids[col[e]];
+      if (J == I) continue;
+      const double w = W[e];
+      int p = o + c;
+      while (p > o && tJ[p - 1] > J) {
+        tJ[p] = tJ[p - 1];
+        tW[p] = tW[p - 1];
+        --p;
+      }
+      tJ[p] = J;
+      tW[p] = w;
+      ++c;
+    }
+  }
+  int u = 0;
+  for (int p = 0; p < c; ++p)
+    if (p == 0 || tJ[o + p] != tJ[o + p - 1]) ++u;
+  tcnt[I] = c;
+  ucnt[I] = u;
+}
+
+__global__ void k_galm_reduce(int nc, const int* __restrict__ toff, const int* __restrict__ tcnt,
+                              const int* __restrict__ tJ, const double* __restrict__ tW, const int* __restrict__ crp,
+                              int* __restrict__ ccol, double* __restrict__ cW, const int* __restrict__ moff,
+                              const int* __restrict__ members, const double* __restrict__ d, double* __restrict__ cd) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int o = toff[I], c = tcnt[I];
+  int q = crp[I];
+  int p = 0;
+  while (p < c) {
+    const int J = tJ[o + p];
+    double s = 0.0;
+    while (p < c && tJ[o + p] == J) {
+      s += tW[o + p];
+      ++p;
+    }
+    ccol[q] = J;
+    cW[q] = s;
+    ++q;
+  }
+  double dd = 0.0;
+  for (int k = moff[I]; k < moff[I + 1]; ++k) dd += d[members[k]];
+  cd[I] = dd;
+}
+
 // ------------------------------------------------------------------ sliced ELL
 // Row order of a sorted layout: inside each group of 64 rows (the rows one
 // wavefront covers), rows by decreasing length, ties by index.  A wavefront
@@ -656,6 +827,12 @@ __global__ void k_dense(int n, const int* __restrict__ rp, const int* __restrict
   if (i >= n) return;
   A[(size_t)i * n + i] = D[i];
   for (int k = rp[i]; k < rp[i + 1]; ++k) A[(size_t)i * n + col[k]] = -W[k];
+}
+
+// A + c 1 1^T on the dense n x n coarsest matrix
+__global__ void k_add_const(size_t nn, double* __restrict__ A, double c) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nn) A[i] = A[i] + c;
 }
 
 // Right-looking Cholesky A = L L^T in one workgroup (row-major, lower part);
@@ -854,6 +1031,127 @@ int32_t galerkin_pass(amg_hier* h, Temps& T, const Graph& g, const int* mate, bo
   *t_gal_ms += ms_since(t1);
   *out = c;
   *ids_out = ids;
+  return AMG_OK;
+}
+
+// One MIS aggregation of g (steps A and B): the aggregate map agg_out (n,
+// hierarchy-owned) and the Galerkin coarse graph (hierarchy-owned).
+int32_t mis_level(amg_hier* h, Temps& T, const Graph& g, int k, int** agg_out, Graph* out, int* rounds_out,
+                  double* t_agg_ms, double* t_gal_ms, hipStream_t s) {
+  auto t0 = clk::now();
+  const int n = g.n;
+  int *state, *nearA, *nearB, *counter, *ownA, *ownB, *flag, *pos, *ids;
+  unsigned long long *mxA, *mxB;
+  AMG_TRY(T.get(&state, n));
+  AMG_TRY(T.get(&nearA, n));
+  AMG_TRY(T.get(&nearB, n));
+  AMG_TRY(T.get(&mxA, n));
+  AMG_TRY(T.get(&mxB, n));
+  AMG_TRY(T.get(&counter, 1));
+  hipLaunchKernelGGL(k_fill<int>, dim3(nblk(n)), dim3(TPB), 0, s, (size_t)n, state, 0);
+  AMG_HIP(hipGetLastError());
+  int rounds = 0;
+  for (;;) {
+    if (rounds > n + 1) {
+      set_last_error("independent set rounds did not terminate");
+      return AMG_ERR_DEVICE;
+    }
+    ++rounds;
+    hipLaunchKernelGGL(k_mis_seed, dim3(nblk(n)), dim3(TPB), 0, s, n, state, mxA, nearA);
+    unsigned long long *mi = mxA, *mo = mxB;
+    int *ni = nearA, *no = nearB;
+    for (int hop = 0; hop < k; ++hop) {
+      hipLaunchKernelGGL(k_mis_hop, dim3(nblk(n)), dim3(TPB), 0, s, n, g.rp, g.col, mi, ni, mo, no);
+      std::swap(mi, mo);
+      std::swap(ni, no);
+    }
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (size_t)1, counter, 0);
+    hipLaunchKernelGGL(k_mis_decide, dim3(nblk(n)), dim3(TPB), 0, s, n, state, mi, ni, counter);
+    AMG_HIP(hipGetLastError());
+    int left = 0;
+    AMG_TRY(read_int(counter, &left, s));
+    if (left == 0) break;
+  }
+  // step B: breadth-first from the set
+  AMG_TRY(T.get(&ownA, n));
+  AMG_TRY(T.get(&ownB, n));
+  AMG_TRY(T.get(&flag, n));
+  AMG_TRY(T.get(&pos, n + 1));
+  hipLaunchKernelGGL(k_owner_init, dim3(nblk(n)), dim3(TPB), 0, s, n, state, ownA, flag);
+  AMG_HIP(hipGetLastError());
+  for (int hop = 0;; ++hop) {
+    if (hop > n + 1) {
+      set_last_error("aggregate collection did not terminate");
+      return AMG_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (size_t)1, counter, 0);
+    hipLaunchKernelGGL(k_owner_hop, dim3(nblk(n)), dim3(TPB), 0, s, n, g.rp, g.col, ownA, ownB, counter);
+    AMG_HIP(hipGetLastError());
+    std::swap(ownA, ownB);
+    int changed = 0;
+    AMG_TRY(read_int(counter, &changed, s));
+    if (!changed) break;
+  }
+  AMG_TRY(scan_excl(T, flag, n, pos, s));
+  int nc = 0;
+  AMG_TRY(read_int(pos + n, &nc, s));
+  AMG_TRY(dalloc(h, &ids, n));
+  hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (size_t)1, counter, 0);
+  hipLaunchKernelGGL(k_owner_ids, dim3(nblk(n)), dim3(TPB), 0, s, n, ownA, pos, ids, counter);
+  AMG_HIP(hipGetLastError());
+  int bad = 0;
+  AMG_TRY(read_int(counter, &bad, s));
+  if (bad || nc < 1) {
+    set_last_error("a vertex was not reached from the independent set (disconnected level)");
+    return AMG_ERR_DISCONNECTED;
+  }
+  // member lists (increasing vertex order)
+  int *cnt, *cursor, *moff, *members;
+  AMG_TRY(T.get(&cnt, nc));
+  AMG_TRY(T.get(&cursor, nc));
+  AMG_TRY(T.get(&moff, nc + 1));
+  AMG_TRY(T.get(&members, n));
+  hipLaunchKernelGGL(k_fill<int>, dim3(nblk(nc)), dim3(TPB), 0, s, (size_t)nc, cnt, 0);
+  hipLaunchKernelGGL(k_fill<int>, dim3(nblk(nc)), dim3(TPB), 0, s, (size_t)nc, cursor, 0);
+  hipLaunchKernelGGL(k_count, dim3(nblk(n)), dim3(TPB), 0, s, n, ids, cnt);
+  AMG_TRY(scan_excl(T, cnt, nc, moff, s));
+  hipLaunchKernelGGL(k_scatter_members, dim3(nblk(n)), dim3(TPB), 0, s, n, ids, moff, cursor, members);
+  hipLaunchKernelGGL(k_sort_members, dim3(nblk(nc)), dim3(TPB), 0, s, nc, moff, members);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+  *t_agg_ms += ms_since(t0);
+
+  auto t1 = clk::now();
+  int *len, *toff, *tJ, *tcnt, *ucnt;
+  double* tW;
+  AMG_TRY(T.get(&len, nc));
+  AMG_TRY(T.get(&toff, nc + 1));
+  AMG_TRY(T.get(&tJ, std::max(g.nnz, 1)));
+  AMG_TRY(T.get(&tW, std::max(g.nnz, 1)));
+  AMG_TRY(T.get(&tcnt, nc));
+  AMG_TRY(T.get(&ucnt, nc));
+  hipLaunchKernelGGL(k_galm_len, dim3(nblk(nc)), dim3(TPB), 0, s, nc, moff, members, g.rp, len);
+  AMG_TRY(scan_excl(T, len, nc, toff, s));
+  hipLaunchKernelGGL(k_galm_sort, dim3(nblk(nc)), dim3(TPB), 0, s, nc, moff, members, g.rp, g.col, g.W, ids, toff, tJ,
+                     tW, tcnt, ucnt);
+  Graph c;
+  c.n = nc;
+  AMG_TRY(dalloc(h, &c.rp, nc + 1));
+  AMG_TRY(scan_excl(T, ucnt, nc, c.rp, s));
+  AMG_TRY(read_int(c.rp + nc, &c.nnz, s));
+  AMG_TRY(dalloc(h, &c.col, std::max(c.nnz, 1)));
+  AMG_TRY(dalloc(h, &c.W, std::max(c.nnz, 1)));
+  AMG_TRY(dalloc(h, &c.d, nc));
+  AMG_TRY(dalloc(h, &c.D, nc));
+  hipLaunchKernelGGL(k_galm_reduce, dim3(nblk(nc)), dim3(TPB), 0, s, nc, toff, tcnt, tJ, tW, c.rp, c.col, c.W, moff,
+                     members, g.d, c.d);
+  hipLaunchKernelGGL(k_row_sums, dim3(nblk(nc)), dim3(TPB), 0, s, nc, c.rp, c.W, c.d, c.D);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+  *t_gal_ms += ms_since(t1);
+  *out = c;
+  *agg_out = ids;
+  *rounds_out = rounds;
   return AMG_OK;
 }
 
@@ -1115,6 +1413,8 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
   double t_agg = 0.0, t_gal = 0.0;
   int total_rounds = 0;
   Temps T;
+  bool pure_neumann = true;  // coarse d are sums of fine d (all >= 0)
+  for (int32_t i = 0; i < n && pure_neumann; ++i) pure_neumann = d[i] == 0.0;
 
   Level l0;
   l0.n = n;
@@ -1141,10 +1441,18 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
     Level& cur = h->lv.back();
     Graph g{cur.n, (int)cur.nnz, cur.row_ptr, cur.col, cur.W, cur.d, cur.D};
     int* agg = nullptr;
-    AMG_TRY(dalloc(h, &agg, cur.n));
-    hipLaunchKernelGGL(k_iota, dim3(nblk(cur.n)), dim3(TPB), 0, s, cur.n, agg);
     Temps TL;  // intermediate pass graphs of this level
-    for (int ps = 0; ps < passes; ++ps) {
+    if (p.aggregation == AMG_AGG_MIS) {
+      Graph c;
+      int rounds = 0;
+      AMG_TRY(mis_level(h, TL, g, p.mis_distance, &agg, &c, &rounds, &t_agg, &t_gal, s));
+      total_rounds += rounds;
+      g = c;
+    } else {
+      AMG_TRY(dalloc(h, &agg, cur.n));
+      hipLaunchKernelGGL(k_iota, dim3(nblk(cur.n)), dim3(TPB), 0, s, cur.n, agg);
+    }
+    for (int ps = 0; p.aggregation != AMG_AGG_MIS && ps < passes; ++ps) {
       auto ta = clk::now();
       int* mate = nullptr;
       AMG_TRY(TL.get(&mate, g.n));
@@ -1203,6 +1511,13 @@ int32_t build_hierarchy(amg_hier* h, int32_t n, const int32_t* row_ptr, const in
   hipLaunchKernelGGL(k_fill<double>, dim3(nblk((int64_t)co.n * co.n)), dim3(TPB), 0, s, (size_t)co.n * co.n,
                      h->chol, 0.0);
   hipLaunchKernelGGL(k_dense, dim3(nblk(co.n)), dim3(TPB), 0, s, co.n, co.row_ptr, co.col, co.W, co.D, h->chol);
+  if (pure_neumann) {
+    // d = 0 everywhere: A_L is singular with the constants as kernel (connected
+    // graph); A_L + (1/n_L) 1 1^T is SPD and acts as a pseudo-inverse on
+    // right-hand sides orthogonal to 1
+    hipLaunchKernelGGL(k_add_const, dim3(nblk((int64_t)co.n * co.n)), dim3(TPB), 0, s, (size_t)co.n * co.n,
+                       h->chol, 1.0 / co.n);
+  }
   int* st = nullptr;
   AMG_TRY(T.get(&st, 1));
   hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, s, co.n, h->chol, st);

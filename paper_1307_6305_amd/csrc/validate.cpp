@@ -63,6 +63,12 @@ int32_t validate_params(const amg_params& p, std::string& msg) {
     msg = "cycle must be AMG_CYCLE_K or AMG_CYCLE_AMLI";
     return AMG_ERR_ARG;
   }
+  if (p.aggregation != AMG_AGG_MATCHING && p.aggregation != AMG_AGG_MIS) {
+    msg = "aggregation must be AMG_AGG_MATCHING or AMG_AGG_MIS";
+    return AMG_ERR_ARG;
+  }
+  if (p.mis_distance < 1 || p.mis_distance > 8) { msg = "mis_distance must be in [1, 8]"; return AMG_ERR_ARG; }
+  if (p.neumann != 0 && p.neumann != 1) { msg = "neumann must be 0 or 1"; return AMG_ERR_ARG; }
   if (p.cycle == AMG_CYCLE_AMLI && p.inner_steps != 2) {
     msg = "the AMLI cycle is a W-cycle: inner_steps must be 2";
     return AMG_ERR_ARG;
@@ -82,9 +88,10 @@ int32_t validate_params(const amg_params& p, std::string& msg) {
 
 // CSR checks: sizes, ranges, strictly increasing columns, no self loops,
 // positive finite weights stored symmetrically with identical values,
-// non-negative finite d with at least one positive entry, connectivity.
+// non-negative finite d with at least one positive entry (unless
+// allow_singular), connectivity.
 int32_t validate_graph(int32_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
-                       const double* d, std::string& msg) {
+                       const double* d, std::string& msg, bool allow_singular) {
   if (n < 1) { msg = "n must be >= 1"; return AMG_ERR_ARG; }
   if (!row_ptr || !d) { msg = "null row_ptr or d"; return AMG_ERR_ARG; }
   if (row_ptr[0] != 0) { msg = "row_ptr[0] != 0"; return AMG_ERR_GRAPH; }
@@ -135,7 +142,7 @@ int32_t validate_graph(int32_t n, const int32_t* row_ptr, const int32_t* col, co
     }
   }
   if ((int32_t)queue.size() != n) { msg = "graph is not connected"; return AMG_ERR_DISCONNECTED; }
-  if (!any_d) { msg = "all d_i are zero: A is singular"; return AMG_ERR_SINGULAR; }
+  if (!any_d && !allow_singular) { msg = "all d_i are zero: A is singular (set neumann = 1)"; return AMG_ERR_SINGULAR; }
   return AMG_OK;
 }
 

@@ -51,6 +51,8 @@ def test_params_default(amg):
     assert (p.autotune, p.slice_height, p.lanes_per_row, p.sort_rows) == (1, 64, 1, 0)
     assert p.tie_break == amg.AMG_TIE_INDEX and amg.amg_params_default(tie_break="hash").tie_break == amg.AMG_TIE_HASH
     assert p.fuse == 1 and p.smoother_rho == 0.33 and p.cycle == amg.AMG_CYCLE_K
+    assert (p.aggregation, p.mis_distance, p.neumann) == (amg.AMG_AGG_MATCHING, 4, 0)
+    assert amg.amg_params_default(aggregation="mis").aggregation == amg.AMG_AGG_MIS
     with pytest.raises(TypeError):
         amg.amg_params_default(no_such_field=1)
 
@@ -109,7 +111,8 @@ def test_validation_errors_before_device(amg):
     for bad in (dict(slice_height=4), dict(slice_height=48), dict(lanes_per_row=3), dict(lanes_per_row=8),
                 dict(sort_rows=2), dict(autotune=-1), dict(tie_break=2), dict(fuse=2),
                 dict(degree=-2), dict(degree=-1, smoother_rho=0.0), dict(degree=-1, smoother_rho=1.5),
-                dict(cycle=2), dict(cycle=1, inner_steps=3)):
+                dict(cycle=2), dict(cycle=1, inner_steps=3), dict(aggregation=2), dict(aggregation=-1),
+                dict(aggregation=1, mis_distance=0), dict(aggregation=1, mis_distance=9), dict(neumann=2)):
         code = _setup_code(amg, g.n, g.row_ptr, g.col, g.w, g.d, amg.amg_params_default(**bad))[0]
         assert code == amg.AMG_ERR_ARG, bad
     # unsorted columns
@@ -126,6 +129,10 @@ def test_valid_input_without_gpu_reports_device(amg):
         pytest.skip("a GPU is present")
     g = inputs.grid2d(5)
     code, out = _setup_code(amg, g.n, g.row_ptr, g.col, g.w, g.d)
+    assert code == amg.AMG_ERR_DEVICE and not out.value
+    # a pure Neumann problem (d = 0) passes validation when neumann = 1
+    p = amg.amg_params_default(aggregation="mis", neumann=1)
+    code, out = _setup_code(amg, g.n, g.row_ptr, g.col, g.w, np.zeros(g.n), p)
     assert code == amg.AMG_ERR_DEVICE and not out.value
 
 

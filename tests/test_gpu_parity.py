@@ -25,13 +25,15 @@ def amg():
     return amg
 
 
-def _oracle_params(p):
+def _oracle_params(amg, p):
     return oracle.Params(degree=p.degree, agg_size=p.agg_size, coarse_max=p.coarse_max,
                          lambda0_ratio=p.lambda0_ratio, inner_steps=p.inner_steps, restart=p.restart,
                          tol=p.tol, max_iter=p.max_iter,
                          match_key="raw" if p.match_key == 1 else "normalized",
                          tie_break="hash" if p.tie_break == 1 else "index",
-                         max_coarsest=p.max_coarsest, stagnation=p.stagnation)
+                         max_coarsest=p.max_coarsest, stagnation=p.stagnation,
+                         aggregation="mis" if p.aggregation == amg.AMG_AGG_MIS else "matching",
+                         mis_distance=p.mis_distance)
 
 
 CASES = {
@@ -47,7 +49,20 @@ CASES = {
     "grid120_hash_agg16": (lambda: inputs.grid2d(120), dict(degree=3, agg_size=16, tie_break=1)),
     "rgg_6000_hash_raw_agg8": (lambda: inputs.rgg(6000, seed=inputs.seed_for(4, 2)),
                                dict(degree=4, agg_size=8, tie_break=1, match_key=1)),
+    # Section 2's own partitioning (independent set of the graph of A^k, then
+    # nearest owner), on the pure Neumann model problems of Section 4
+    "poisson2d_72_mis4_neumann": (lambda: inputs.poisson2d(72), dict(degree=3, aggregation="mis", neumann=1)),
+    "poisson3d_20_mis4_neumann": (lambda: inputs.poisson3d(20), dict(degree=4, aggregation="mis", neumann=1)),
+    "delaunay11_mis2": (lambda: inputs.delaunay3d(11, seed=inputs.seed_for(6, 11)),
+                        dict(degree=4, aggregation="mis", mis_distance=2)),
+    "grid100x37_mis1": (lambda: inputs.grid2d(100, 37), dict(degree=3, aggregation="mis", mis_distance=1)),
 }
+
+
+def _rhs(g, seed):
+    """inputs.rhs, projected onto range(A) when d = 0 everywhere (pure Neumann)."""
+    f = inputs.rhs(g.n, seed)
+    return inputs.project_range(f) if not np.any(g.d) else f
 
 _cache = {}
 
@@ -58,7 +73,7 @@ def _case(amg, name):
         g = make()
         p = amg.amg_params_default(**kw)
         h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
-        ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(p))
+        ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(amg, p))
         _cache[name] = (g, p, h, ho)
     return _cache[name]
 
@@ -133,7 +148,7 @@ def test_cycle_application(amg, name):
 @pytest.mark.parametrize("name", list(CASES))
 def test_solve_matches_oracle(amg, name):
     g, p, h, ho = _case(amg, name)
-    f = inputs.rhs(g.n, inputs.seed_for(1))
+    f = _rhs(g, inputs.seed_for(1))
     u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
     info = amg.amg_solve(h, _t(f), u)
     res = oracle.fcg(ho, f)
@@ -171,7 +186,7 @@ def test_nonzero_initial_guess_and_zero_rhs(amg):
     g = inputs.grid2d(50)
     p = amg.amg_params_default(degree=3, agg_size=4)
     h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
-    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(p))
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(amg, p))
     f = inputs.rhs(g.n, 11)
     u0 = inputs.rhs(g.n, 12)
     u = _t(u0)
@@ -206,7 +221,7 @@ def test_stagnating_coarsening_uses_block_cholesky(amg):
     p = amg.amg_params_default(degree=3, agg_size=4, coarse_max=16)
     h = amg.amg_setup(n, rp, col, w, d, p)
     desc = amg.amg_describe(h)
-    ho = oracle.build_hierarchy(n, rp, col, w, d, _oracle_params(p))
+    ho = oracle.build_hierarchy(n, rp, col, w, d, _oracle_params(amg, p))
     assert desc["n"] == [l.n for l in ho.levels] and desc["n"][-1] > 64
     b = np.random.default_rng(0).standard_normal(desc["n"][-1])
     x = torch.zeros(desc["n"][-1], dtype=torch.float64, device="cuda")
@@ -239,7 +254,7 @@ def test_tail_program_matches_oracle(amg, tail_rows):
     g = inputs.grid2d(90, 77)
     p = amg.amg_params_default(degree=4, agg_size=4, tail_rows=tail_rows)
     h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
-    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(p))
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(amg, p))
     r = inputs.rhs(g.n, 21)
     z = torch.zeros(g.n, dtype=torch.float64, device="cuda")
     amg.amg_apply_cycle(h, _t(r), z)
@@ -262,7 +277,7 @@ def test_mixed_precision_solve(amg, make, kw):
     f = inputs.rhs(g.n, 31, "normal")
     p = amg.amg_params_default(precision=amg.AMG_MIXED, **kw)
     h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
-    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(p))
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(amg, p))
     # the hierarchy is the same (FP64 setup), only the cycle runs in FP32
     assert amg.amg_describe(h)["n"] == [l.n for l in ho.levels]
     r = _t(f)
