@@ -157,13 +157,14 @@ def project_range(f: np.ndarray) -> np.ndarray:
     return f - f.mean()
 
 
-def delaunay3d(N: int, seed: int) -> Graph:
+def delaunay3d(N: int, seed: int, neumann: bool = False) -> Graph:
     """Unstructured mesh of the unit cube in the manner of Section 4's general
     graphs: the N^3 vertices of the structured grid (spacing h = 1/(N-1), id
     (z*N+y)*N+x) each moved by a random vector of length h/2 (direction uniform
     on the sphere), then the Delaunay tetrahedralization of the moved points
     (SciPy / Qhull); its edges with w_e = 1.  d_i = 1 on the vertices that lay
-    on the cube's boundary before the move."""
+    on the cube's boundary before the move, or d = 0 (pure Neumann, as in the
+    paper's runs)."""
     from scipy.spatial import Delaunay
 
     rng = np.random.default_rng(seed)
@@ -182,8 +183,8 @@ def delaunay3d(N: int, seed: int) -> Graph:
     if np.any(np.diff(row_ptr) == 0):
         raise ValueError("a vertex is in no tetrahedron")
     bnd = (x == 0) | (x == N - 1) | (y == 0) | (y == N - 1) | (z == 0) | (z == N - 1)
-    d = bnd.ravel().astype(np.float64)
-    return Graph(n, row_ptr, col, w, d, name=f"delaunay3d-{N}-s{seed}")
+    d = np.zeros(n) if neumann else bnd.ravel().astype(np.float64)
+    return Graph(n, row_ptr, col, w, d, name=f"delaunay3d-{N}-s{seed}{'-neumann' if neumann else ''}")
 
 
 def _morton16(px: np.ndarray, py: np.ndarray) -> np.ndarray:

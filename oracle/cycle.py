@@ -68,6 +68,9 @@ class Params:
     stagnation: float = 0.9
     aggregation: str = "matching"  # or "mis": Section 2's steps (A), (B) on the graph of A^k
     mis_distance: int = 4
+    # "residual": ||r_k||_2 <= tol ||r_0||_2; "energy": Section 4's test,
+    # ||x* - x_k||_A <= tol ||x* - x_0||_A
+    stop: str = "residual"
 
     @property
     def passes(self) -> int:
@@ -223,14 +226,34 @@ class FCGResult:
     res_history: list = field(default_factory=list)
 
 
-def fcg(h: Hierarchy, f: np.ndarray, u0: np.ndarray | None = None, precond=None) -> FCGResult:
-    """Outer flexible CG preconditioned by Kcycle(0) (or by ``precond``)."""
+def fcg(h: Hierarchy, f: np.ndarray, u0: np.ndarray | None = None, precond=None,
+        x_exact: np.ndarray | None = None) -> FCGResult:
+    """Outer flexible CG preconditioned by Kcycle(0) (or by ``precond``).
+
+    With ``params.stop == "energy"`` the test is Section 4's: the A-norm of
+    the error x* - x_k, computed from its definition with x* = ``x_exact``, or
+    x* = 0 when f = 0 (the homogeneous problem, whose error is the iterate
+    itself; on a pure Neumann problem any constant vector is a solution and
+    has A-norm 0).  res_history then holds those A-norms."""
     p_ = h.params
     lvl = h.levels[0]
     B = precond if precond is not None else (lambda r: kcycle(h, 0, r))
     x = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
     r = f - apply_A(lvl, x)
-    rho0 = math.sqrt(_dot(r, r))
+    energy = p_.stop == "energy"
+    if energy:
+        if x_exact is None:
+            if np.any(f != 0.0):
+                raise ValueError("the A-norm error test needs x_exact unless f = 0")
+            x_exact = np.zeros_like(f)
+
+        def measure(x, r):
+            e = x_exact - x
+            return math.sqrt(max(_dot(e, apply_A(lvl, e)), 0.0))
+    else:
+        def measure(x, r):
+            return math.sqrt(_dot(r, r))
+    rho0 = measure(x, r)
     hist = [rho0]
     if rho0 == 0.0:
         return FCGResult(x, 0, True, False, hist)
@@ -250,7 +273,7 @@ def fcg(h: Hierarchy, f: np.ndarray, u0: np.ndarray | None = None, precond=None)
         window.append((p, q, rho))
         if len(window) == p_.restart:
             window = []
-        rn = math.sqrt(_dot(r, r))
+        rn = measure(x, r)
         hist.append(rn)
         if rn <= p_.tol * rho0:
             return FCGResult(x, it, True, False, hist)
