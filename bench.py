@@ -35,6 +35,10 @@ import inputs  # noqa: E402
 METRIC = "solve DOF/s to 1e-8 rel. residual + HBM GB/s; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 
+# Section 4's runs: independent set of the graph of A^4, coarsest level below
+# 100 rows, m = 4, lambda0 = lambda1 / 10, the A-norm error test on A u = 0
+TABLE1 = dict(degree=4, aggregation="mis", mis_distance=4, neumann=1, coarse_max=99, stop="energy")
+
 WORKLOADS = {
     # name: (graph builder, rhs kind, seed config, params)
     "grid2d-1024": (lambda: inputs.grid2d(1024), "uniform", 2, dict(degree=3, agg_size=16)),
@@ -56,10 +60,15 @@ WORKLOADS = {
     # Section 4's model problems as the paper runs them: pure Neumann Laplacians
     # of the structured FE meshes, aggregates from an independent set of the
     # graph of A^4 grown to nearest owners
-    "poisson2d-1024-mis": (lambda: inputs.poisson2d(1024), "uniform", 7, dict(degree=3, aggregation="mis",
-                                                                               neumann=1)),
-    "poisson3d-128-mis": (lambda: inputs.poisson3d(128), "uniform", 8, dict(degree=5, aggregation="mis",
-                                                                             neumann=1)),
+    # ("-amli": the stationary AMLI cycle)
+    "poisson2d-1024-mis": (lambda: inputs.poisson2d(1024), "uniform", 7, TABLE1),
+    "poisson2d-1024-mis-amli": (lambda: inputs.poisson2d(1024), "uniform", 7, dict(TABLE1, cycle=1)),
+    "poisson3d-128-mis": (lambda: inputs.poisson3d(128), "uniform", 8, TABLE1),
+    "poisson3d-128-mis-amli": (lambda: inputs.poisson3d(128), "uniform", 8, dict(TABLE1, cycle=1)),
+    "delaunay3d-64-mis": (lambda: inputs.delaunay3d(64, inputs.seed_for(6, 64), neumann=True), "uniform", 9,
+                          TABLE1),
+    "delaunay3d-64-mis-amli": (lambda: inputs.delaunay3d(64, inputs.seed_for(6, 64), neumann=True), "uniform", 9,
+                               dict(TABLE1, cycle=1)),
     # one random geometric graph of the batched form's kind, at 2M points
     "rgg-2m-mixed": (lambda: inputs.rgg(2_000_000, inputs.seed_for(4, 999)), "uniform", 4,
                      dict(degree=4, agg_size=8, precision=1)),
@@ -99,14 +108,15 @@ def cheb_step_bytes(n: int, nnz: int, mixed: bool) -> int:
     return 12 * nnz + 8 * n + 8 * n + 8 * n + 16 * n + 8 * n
 
 
-def run_cpu_baseline(g, f, params: dict, sample: str):
+def run_cpu_baseline(g, f, params: dict, sample: str, u0=None):
     import oracle
 
     op = oracle.Params(degree=params.get("degree", 4), agg_size=params.get("agg_size", 4),
+                       coarse_max=params.get("coarse_max", 64),
                        match_key="raw" if params.get("match_key", 0) == 1 else "normalized",
                        tie_break="hash" if params.get("tie_break", 0) == 1 else "index",
                        aggregation=params.get("aggregation", "matching"),
-                       mis_distance=params.get("mis_distance", 4))
+                       mis_distance=params.get("mis_distance", 4), stop=params.get("stop", "residual"))
     t0 = time.perf_counter()
     h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, op)
     precond = None
@@ -115,7 +125,7 @@ def run_cpu_baseline(g, f, params: dict, sample: str):
         precond = lambda r: oracle.amli_cycle(h, 0, r, coef)  # noqa: E731
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
-    res = oracle.fcg(h, f, precond=precond)
+    res = oracle.fcg(h, f, u0, precond=precond)
     t_solve = time.perf_counter() - t0
     return {
         "value": g.n / t_solve,
@@ -303,6 +313,84 @@ def serve_stream(nreq: int, seed: int, new_frac: float = 0.3, max_rhs: int = 32)
     return graphs, reqs
 
 
+# Table 1's outer iteration counts (stationary AMLI, nonlinear AMLI), as printed
+PAPER_TABLE1 = {
+    ("2d", 512): (20, 19), ("2d", 1024): (22, 20), ("2d", 2048): (23, 21), ("2d", 4096): (24, 21),
+    ("3d", 32): (22, 20), ("3d", 64): (23, 22), ("3d", 128): (23, 22), ("3d", 256): (25, 22),
+    ("unstruct", 32): (24, 21), ("unstruct", 64): (25, 23), ("unstruct", 128): (27, 24), ("unstruct", 256): (28, 24),
+}
+
+
+def table1_graph(family: str, N: int):
+    if family == "2d":
+        return inputs.poisson2d(N)
+    if family == "3d":
+        return inputs.poisson3d(N)
+    if family == "unstruct":
+        return inputs.delaunay3d(N, inputs.seed_for(9, N), neumann=True)
+    raise ValueError(f"unknown Table 1 family {family!r}")
+
+
+def run_table1(args, amg, torch):
+    """Section 4's experiment: pure Neumann FE Laplacians, aggregates from an
+    independent set of the graph of A^4, m = 4, W(1,1) stationary AMLI and
+    nonlinear AMLI cycles, iterations to a 1e-8 reduction of the A-norm of the
+    error (A u = 0 from a random initial guess orthogonal to 1)."""
+    dev = torch.device("cuda:0")
+    for item in args.table1.split(","):
+        family, N = item.split(":")
+        N = int(N)
+        t_gen = time.perf_counter()
+        g = table1_graph(family, N)
+        t_gen = time.perf_counter() - t_gen
+        u0_np = inputs.project_range(inputs.rhs(g.n, inputs.seed_for(9, 1000 + N), "uniform"))
+        print(f"[table1] {family} N={N}: n={g.n} nnz={g.nnz} (generated in {t_gen:.1f} s)", file=sys.stderr,
+              flush=True)
+        f = torch.zeros(g.n, dtype=torch.float64, device=dev)
+        u0 = torch.tensor(u0_np, dtype=torch.float64, device=dev)
+        u = torch.empty_like(u0)
+        row = {"table1": family, "N": N, "n": g.n, "nnz": g.nnz, "graph": g.name}
+        for cyc, key in (("amli", "amli"), ("k", "n_amli")):
+            p = amg.amg_params_default(cycle=cyc, **{k: v for k, v in TABLE1.items()})
+            h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+            desc = amg.amg_describe(h)
+            times = []
+            for _ in range(max(args.steps, 1) + 1):
+                u.copy_(u0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = amg.amg_solve(h, f, u)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            levels = desc["n"]
+            row["levels"] = levels
+            row["coarsening"] = [round(levels[i] / levels[i + 1], 1) for i in range(len(levels) - 1)]
+            row["grid_complexity"] = round(desc["grid_complexity"], 4)
+            row["operator_complexity"] = round(desc["operator_complexity"], 4)
+            row["setup_ms"] = round(desc["setup_ms"], 1)
+            row[key] = {"iters": info["iters"], "status": info["status"], "rel_A_err": info["rel_res"],
+                        "solve_ms": round(1e3 * min(times[1:]), 2),
+                        "amli_lambda_min": [round(x, 4) for x in desc["amli_lambda_min"][1:-1]]
+                        if cyc == "amli" else None}
+            print(f"[table1]   {key}: {info['iters']} iterations, {1e3 * min(times[1:]):.1f} ms, levels {levels}",
+                  file=sys.stderr, flush=True)
+            h.close()
+        paper = PAPER_TABLE1.get((family, N))
+        row["paper"] = {"amli": paper[0], "n_amli": paper[1]} if paper else None
+        if g.n <= args.table1_oracle:
+            import oracle
+
+            op = oracle.Params(degree=4, aggregation="mis", mis_distance=4, coarse_max=99, stop="energy")
+            ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, op)
+            _, coef = oracle.amli_setup(ho)
+            ra = oracle.fcg(ho, np.zeros(g.n), u0_np, precond=lambda r: oracle.amli_cycle(ho, 0, r, coef))
+            rk = oracle.fcg(ho, np.zeros(g.n), u0_np)
+            row["oracle"] = {"amli": ra.iters, "n_amli": rk.iters, "levels": [lv.n for lv in ho.levels]}
+            print(f"[table1]   oracle: amli {ra.iters}, n_amli {rk.iters}", file=sys.stderr, flush=True)
+        print(json.dumps(row), flush=True)
+        del f, u0, u
+
+
 def run_serve(args, amg, torch):
     """Served form: an open-loop Poisson stream replayed twice at the same
     arrival times -- continuous batching (mixed precision) and one-at-a-time
@@ -411,6 +499,11 @@ def main():
                          "instead of the autotuner")
     ap.add_argument("--layout-sweep", action="store_true",
                     help="also time the dominant kernel in every fixed layout (reported under layout_sweep)")
+    ap.add_argument("--table1", default=None, metavar="SIZES",
+                    help="Section 4's iteration-count runs: comma list of FAMILY:N (2d:N for N^2, 3d:N for N^3, "
+                         "unstruct:N for the Delaunay mesh of N^3 points), both cycles; one JSON line each")
+    ap.add_argument("--table1-oracle", type=int, default=0,
+                    help="also run the oracle on problems of at most this many rows")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -430,12 +523,19 @@ def main():
     if args.serve:
         run_serve(args, amg, torch)
         return
+    if args.table1:
+        run_table1(args, amg, torch)
+        return
     dev = torch.device("cuda:0")
     make, rhs_kind, cfg, pkw = WORKLOADS[args.workload]
     g = make()
     f_np = inputs.rhs(g.n, inputs.seed_for(cfg), rhs_kind)
     if not np.any(g.d):  # pure Neumann: f orthogonal to the constants
         f_np = inputs.project_range(f_np)
+    u0_np = None
+    if pkw.get("stop") == "energy":
+        # the A-norm error test runs on A u = 0 from a random initial guess
+        u0_np, f_np = f_np, np.zeros(g.n)
     pkw = dict(pkw)
     if args.no_graph:
         pkw["use_graph"] = 0
@@ -457,13 +557,21 @@ def main():
           file=sys.stderr, flush=True)
     f = torch.tensor(f_np, dtype=torch.float64, device=dev)
     u = torch.zeros_like(f)
+    u0 = None if u0_np is None else torch.tensor(u0_np, dtype=torch.float64, device=dev)
+
+    def start():
+        if u0 is None:
+            u.zero_()
+        else:
+            u.copy_(u0)
+
     for _ in range(args.warmup):
-        u.zero_()
+        start()
         info = amg.amg_solve(h, f, u)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        u.zero_()
+        start()
         info = amg.amg_solve(h, f, u)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -527,12 +635,14 @@ def main():
     if not args.no_cpu_baseline:
         cpu, res = run_cpu_baseline(
             g, f_np, pkw, sample=f"the oracle's full setup and FP64 solve of the same workload "
-                                 f"(n={g.n}), single thread; value = n / solve seconds")
+                                 f"(n={g.n}), single thread; value = n / solve seconds", u0=u0_np)
         e = u_gpu - res.x
         import oracle as _o
 
         lvl0 = _o.assemble(g.n, g.row_ptr, g.col, g.w, g.d)
-        err_vs_oracle = float(np.sqrt(e @ _o.apply_A(lvl0, e)) / np.sqrt(res.x @ _o.apply_A(lvl0, res.x)))
+        # relative to the solution, or to the initial error on A u = 0
+        ref = res.x if u0_np is None else u0_np
+        err_vs_oracle = float(np.sqrt(e @ _o.apply_A(lvl0, e)) / np.sqrt(ref @ _o.apply_A(lvl0, ref)))
         print(f"[bench] oracle solve {cpu['solve_s']:.2f} s, iters {cpu['iters']}, A-norm err vs oracle "
               f"{err_vs_oracle:.2e}", file=sys.stderr, flush=True)
 
@@ -571,6 +681,8 @@ def main():
             "layouts": desc["layouts"],
             "layout_ms": round(desc["layout_ms"], 2),
             "cycle": "stationary AMLI W-cycle" if params.cycle == 1 else "nonlinear AMLI (k-cycle)",
+            "stop": "A-norm of the error <= tol x initial (A u = 0 from a random u0)"
+                    if params.stop == amg.AMG_STOP_ENERGY else "||r||_2 <= tol ||r0||_2",
             "amli_lambda_min": [round(x, 4) for x in desc["amli_lambda_min"][1:-1]] if params.cycle == 1 else None,
         },
         "roofline": roofline,

@@ -54,6 +54,7 @@ enum { AMG_KEY_NORMALIZED = 0, AMG_KEY_RAW = 1 };
 enum { AMG_TIE_INDEX = 0, AMG_TIE_HASH = 1 };
 enum { AMG_CYCLE_K = 0, AMG_CYCLE_AMLI = 1 };
 enum { AMG_AGG_MATCHING = 0, AMG_AGG_MIS = 1 };
+enum { AMG_STOP_RESIDUAL = 0, AMG_STOP_ENERGY = 1 };
 
 #define AMG_MAX_LEVELS 32
 
@@ -120,6 +121,16 @@ enum { AMG_AGG_MATCHING = 0, AMG_AGG_MIS = 1 };
  *                 with the constants as kernel): the coarsest factor is that of
  *                 A_L + (1/n_L) 1 1^T, a pseudo-inverse on right-hand sides
  *                 orthogonal to 1; the caller passes f orthogonal to 1.
+ *   stop          AMG_STOP_RESIDUAL (default): ||r_k||_2 <= tol ||r_0||_2 on the
+ *                 recursively updated residual.  AMG_STOP_ENERGY: Section 4's
+ *                 test, the A-norm of the error reduced by tol, for the
+ *                 homogeneous problem A u = 0 from the caller's initial guess
+ *                 (f must be zero: amg_solve returns AMG_ERR_ARG otherwise);
+ *                 the error is then the iterate itself, and (u_k, A u_k) is
+ *                 formed from a fresh product each iteration (one extra
+ *                 finest-level product).  On a pure Neumann problem
+ *                 constants have A-norm 0.  Single
+ *                 solves only (the batched and served forms reject it).
  *   fuse          1 (default): on levels below 2^18 rows, fold the inner
  *                 flexible-CG vector updates into the kernels that read them
  *                 and form the restriction of the residual in one pass; 0: one
@@ -151,13 +162,14 @@ typedef struct {
   int32_t aggregation;
   int32_t mis_distance;
   int32_t neumann;
+  int32_t stop;
 } amg_params;
 
 typedef struct amg_hier amg_hier;
 
-/* Per-solve report.  rel_res is the recursively updated residual norm ratio the
- * stopping test uses; rel_res_true = ||f - A u||_2 / ||f - A u0||_2 recomputed in
- * FP64 at the end. */
+/* Per-solve report.  rel_res is the ratio the stopping test uses (recursively
+ * updated residual norms, or A-norms of the error under AMG_STOP_ENERGY);
+ * rel_res_true = ||f - A u||_2 / ||f - A u0||_2 recomputed in FP64 at the end. */
 typedef struct {
   int32_t status;
   int32_t iters;

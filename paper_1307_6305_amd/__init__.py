@@ -45,6 +45,8 @@ AMG_CYCLE_K = 0
 AMG_CYCLE_AMLI = 1
 AMG_AGG_MATCHING = 0
 AMG_AGG_MIS = 1
+AMG_STOP_RESIDUAL = 0
+AMG_STOP_ENERGY = 1
 AMG_MAX_LEVELS = 32
 
 
@@ -75,6 +77,7 @@ class amg_params(ctypes.Structure):
         ("aggregation", ctypes.c_int32),
         ("mis_distance", ctypes.c_int32),
         ("neumann", ctypes.c_int32),
+        ("stop", ctypes.c_int32),
     ]
 
 
@@ -278,6 +281,8 @@ def amg_params_default(**overrides) -> amg_params:
             v = {"k": AMG_CYCLE_K, "amli": AMG_CYCLE_AMLI}[v]
         if k == "aggregation" and isinstance(v, str):
             v = {"matching": AMG_AGG_MATCHING, "mis": AMG_AGG_MIS}[v]
+        if k == "stop" and isinstance(v, str):
+            v = {"residual": AMG_STOP_RESIDUAL, "energy": AMG_STOP_ENERGY}[v]
         setattr(p, k, v)
     return p
 

@@ -133,6 +133,7 @@ void amg_params_default(amg_params* p) {
   p->aggregation = AMG_AGG_MATCHING;
   p->mis_distance = 4;
   p->neumann = 0;
+  p->stop = AMG_STOP_RESIDUAL;
 }
 
 const char* amg_strerror(int32_t s) {
@@ -243,8 +244,8 @@ int32_t check_serve_cfg(const amg_serve_cfg* cfg) {
     amg::set_last_error(msg);
     return pst;
   }
-  if (cfg->params.cycle != AMG_CYCLE_K) {
-    amg::set_last_error("the served form runs the nonlinear cycle (AMG_CYCLE_K) only");
+  if (cfg->params.cycle != AMG_CYCLE_K || cfg->params.stop != AMG_STOP_RESIDUAL) {
+    amg::set_last_error("the served form runs the nonlinear cycle (AMG_CYCLE_K) with the residual test only");
     return AMG_ERR_ARG;
   }
   return AMG_OK;

@@ -923,6 +923,10 @@ int32_t batch_compatible(const std::vector<amg_hier*>& hs) {
       set_last_error("the batched form runs the nonlinear cycle (AMG_CYCLE_K) only");
       return AMG_ERR_ARG;
     }
+    if (h->p.stop != AMG_STOP_RESIDUAL) {
+      set_last_error("the batched form uses the residual stopping test (AMG_STOP_RESIDUAL) only");
+      return AMG_ERR_ARG;
+    }
     if (h->mixed != hs[0]->mixed || h->p.degree != p0.degree || h->p.inner_steps != p0.inner_steps ||
         h->p.restart != p0.restart) {
       set_last_error("batched items must share precision, degree, inner steps and restart");

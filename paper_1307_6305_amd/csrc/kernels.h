@@ -17,7 +17,7 @@ constexpr int TAIL_THREADS = 1024;
 
 // Scalar area.  Outer iteration: rr, (p,r), window dots, window rho.
 // Inner solve on level l: base(l) + [0,8) rho_k, [8,16) gamma_k, [16,24) dots.
-constexpr int S_RR = 0, S_GAM = 2, S_RR0 = 3, S_RRT = 4, S_DUMMY = 7, S_DOTS = 8, S_RHOW = 16;
+constexpr int S_RR = 0, S_XR = 1, S_GAM = 2, S_RR0 = 3, S_RRT = 4, S_FF = 5, S_DUMMY = 7, S_DOTS = 8, S_RHOW = 16;
 inline int lbase(int l) { return 64 + 32 * l; }
 constexpr int SCAL_SIZE = 64 + 32 * (AMG_MAX_LEVELS + 1);
 

@@ -959,9 +959,37 @@ struct Engine {
     hipLaunchKernelGGL((k_fcg_xr<double, double, true>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], h->Qo[j], u, h->r,
                        h->scal, S_RHOW + j, S_GAM, 0, 1, red_for(nb, rr));
     AMG_HIP(hipGetLastError());
+    if (h->p.stop == AMG_STOP_ENERGY) {
+      // f = 0: the error is u itself; (u, A u) from a fresh product (the
+      // recursive residual drifts along the constants of a Neumann problem,
+      // which the iterates pick up), published with rho_j
+      AMG_TRY(finish<1>(nb, rr));
+      return energy64(u, h->host_scal, S_RHOW + j);
+    }
     // with the stopping test's inputs, (r, r) and rho_j, published to the host
     AMG_TRY(finish<1>(nb, rr, h->host_scal, S_RHOW + j));
     return AMG_OK;
+  }
+
+  // (u, A u) into scal[S_XR] (A u into tmp); host: publish it with scal[pub]
+  int32_t energy64(const double* u, double* host = nullptr, int pub = 0) {
+    const auto A64 = mat_of<double>(h->lv[0]);
+    const Slots sl = slots2(S_XR, S_DUMMY);
+    hipLaunchKernelGGL((k_spmv_dots<double, double, double>), dim3(A64.nb), dim3(TPB << A64.lk), 0, s, A64, u,
+                       h->tmp, u, red_for(A64.nb, sl));
+    AMG_HIP(hipGetLastError());
+    return finish<2>(A64.nb, sl, host, pub);
+  }
+
+  // (a, b) in FP64 into scal[slot] (finest-level vectors)
+  int32_t dot64(const double* a, const double* b, int slot) {
+    const int n = h->lv[0].n, nb = nblk(n);
+    VecPtrs qs{};
+    qs.p[0] = b;
+    const Slots sl = slots1(slot);
+    hipLaunchKernelGGL((k_multidot<double, double>), dim3(nb), dim3(TPB), 0, s, n, a, qs, 1, red_for(nb, sl));
+    AMG_HIP(hipGetLastError());
+    return finish<1>(nb, sl);
   }
 
   // out = f - A u (FP64) and its squared norm into scal[slot]
@@ -1001,14 +1029,28 @@ template <typename VT, typename MT>
 int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
   auto t0 = clk::now();
   Engine<VT, MT> E{h, s};
+  const bool energy = h->p.stop == AMG_STOP_ENERGY;
   AMG_TRY(E.residual64(f, u, h->r, S_RR0));
+  if (energy) {
+    AMG_TRY(E.dot64(f, f, S_FF));
+    AMG_TRY(E.energy64(u));
+    AMG_HIP(hipMemcpyAsync(h->host_scal + 3, h->scal + S_FF, sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(h->host_scal + 4, h->scal + S_XR, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
   AMG_HIP(hipMemcpyAsync(h->host_scal, h->scal + S_RR0, sizeof(double), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   const double rho0 = std::sqrt(h->host_scal[0]);
+  // energy test: ||u_k||_A = sqrt((u_k, A u_k)) against ||u_0||_A
+  const double en0 = energy ? std::sqrt(std::max(h->host_scal[4], 0.0)) : 0.0;
+  if (energy && h->host_scal[3] != 0.0) {
+    set_last_error("the A-norm error test solves A u = 0: f must be zero");
+    return AMG_ERR_ARG;
+  }
+  const double ref0 = energy ? en0 : rho0;
   int32_t status = AMG_OK;
   int it = 0;
-  double rel = rho0 > 0.0 ? 1.0 : 0.0;
-  if (rho0 > 0.0) {
+  double rel = ref0 > 0.0 ? 1.0 : 0.0;
+  if (ref0 > 0.0) {
     const bool use_graph = h->p.use_graph != 0;
     if (use_graph && (!h->graphs_ready || h->graph_u != u)) {
       AMG_TRY(capture_graphs<VT, MT>(h, u));
@@ -1028,7 +1070,7 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
         status = AMG_ERR_BREAKDOWN;
         break;
       }
-      rel = std::sqrt(rr) / rho0;
+      rel = energy ? std::sqrt(std::max(rr, 0.0)) / en0 : std::sqrt(rr) / rho0;
       if (rel <= h->p.tol) {
         status = AMG_OK;
         break;

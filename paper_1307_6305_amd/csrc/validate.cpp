@@ -69,6 +69,10 @@ int32_t validate_params(const amg_params& p, std::string& msg) {
   }
   if (p.mis_distance < 1 || p.mis_distance > 8) { msg = "mis_distance must be in [1, 8]"; return AMG_ERR_ARG; }
   if (p.neumann != 0 && p.neumann != 1) { msg = "neumann must be 0 or 1"; return AMG_ERR_ARG; }
+  if (p.stop != AMG_STOP_RESIDUAL && p.stop != AMG_STOP_ENERGY) {
+    msg = "stop must be AMG_STOP_RESIDUAL or AMG_STOP_ENERGY";
+    return AMG_ERR_ARG;
+  }
   if (p.cycle == AMG_CYCLE_AMLI && p.inner_steps != 2) {
     msg = "the AMLI cycle is a W-cycle: inner_steps must be 2";
     return AMG_ERR_ARG;

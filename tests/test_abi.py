@@ -52,6 +52,7 @@ def test_params_default(amg):
     assert p.tie_break == amg.AMG_TIE_INDEX and amg.amg_params_default(tie_break="hash").tie_break == amg.AMG_TIE_HASH
     assert p.fuse == 1 and p.smoother_rho == 0.33 and p.cycle == amg.AMG_CYCLE_K
     assert (p.aggregation, p.mis_distance, p.neumann) == (amg.AMG_AGG_MATCHING, 4, 0)
+    assert p.stop == amg.AMG_STOP_RESIDUAL and amg.amg_params_default(stop="energy").stop == amg.AMG_STOP_ENERGY
     assert amg.amg_params_default(aggregation="mis").aggregation == amg.AMG_AGG_MIS
     with pytest.raises(TypeError):
         amg.amg_params_default(no_such_field=1)
@@ -112,7 +113,8 @@ def test_validation_errors_before_device(amg):
                 dict(sort_rows=2), dict(autotune=-1), dict(tie_break=2), dict(fuse=2),
                 dict(degree=-2), dict(degree=-1, smoother_rho=0.0), dict(degree=-1, smoother_rho=1.5),
                 dict(cycle=2), dict(cycle=1, inner_steps=3), dict(aggregation=2), dict(aggregation=-1),
-                dict(aggregation=1, mis_distance=0), dict(aggregation=1, mis_distance=9), dict(neumann=2)):
+                dict(aggregation=1, mis_distance=0), dict(aggregation=1, mis_distance=9), dict(neumann=2),
+                dict(stop=2), dict(stop=-1)):
         code = _setup_code(amg, g.n, g.row_ptr, g.col, g.w, g.d, amg.amg_params_default(**bad))[0]
         assert code == amg.AMG_ERR_ARG, bad
     # unsorted columns
@@ -147,6 +149,8 @@ def test_server_argument_errors_before_device(amg):
     cfg = amg.amg_serve_cfg_default(amg.amg_params_default(restart=0))
     assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
     cfg = amg.amg_serve_cfg_default(amg.amg_params_default(cycle="amli"))
+    assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
+    cfg = amg.amg_serve_cfg_default(amg.amg_params_default(stop="energy"))
     assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
     assert lib.amg_server_create(ctypes.byref(amg.amg_serve_cfg_default()), None, None) == amg.AMG_ERR_ARG
     cnt = ctypes.c_int32()
