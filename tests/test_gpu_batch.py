@@ -130,3 +130,31 @@ def test_batch_maxit_status(amg):
     u = torch.zeros_like(f)
     infos = amg.amg_solve_batch([h], [f], [u])
     assert infos[0]["status"] == amg.AMG_ERR_MAXIT and infos[0]["iters"] == 2
+
+
+def test_batch_mis_neumann_items(amg):
+    """Hierarchies from Section 2's partitioning, pure Neumann ones included,
+    batched with a matching hierarchy: each item against the oracle."""
+    specs = [(inputs.poisson2d(60), dict(aggregation="mis", neumann=1)),
+             (inputs.poisson3d(14), dict(aggregation="mis", neumann=1)),
+             (inputs.delaunay3d(9, seed=inputs.seed_for(6, 9)), dict(aggregation="mis", mis_distance=2)),
+             (inputs.grid2d(50, 41), dict(agg_size=8))]
+    hs, fs, hos = [], [], []
+    for i, (g, kw) in enumerate(specs):
+        p = amg.amg_params_default(degree=4, **kw)
+        hs.append(amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p))
+        f = inputs.rhs(g.n, 80 + i)
+        fs.append(inputs.project_range(f) if not np.any(g.d) else f)
+        hos.append(oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(
+            degree=4, agg_size=p.agg_size, aggregation="mis" if p.aggregation == amg.AMG_AGG_MIS else "matching",
+            mis_distance=p.mis_distance)))
+    us = [torch.zeros(g.n, dtype=torch.float64, device="cuda") for g, _ in specs]
+    infos = amg.amg_solve_batch(hs, [_t(f) for f in fs], us)
+    for i, ((g, _), info, ho) in enumerate(zip(specs, infos, hos)):
+        res = oracle.fcg(ho, fs[i])
+        assert info["status"] == 0 and res.converged, (i, info)
+        assert abs(info["iters"] - res.iters) <= 1, (i, info["iters"], res.iters)
+        lo = ho.levels[0]
+        e = us[i].cpu().numpy() - res.x
+        errA = np.sqrt(e @ oracle.apply_A(lo, e)) / np.sqrt(res.x @ oracle.apply_A(lo, res.x))
+        assert errA <= 1e-6, (i, errA)
