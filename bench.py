@@ -338,8 +338,9 @@ def run_table1(args, amg, torch):
     error (A u = 0 from a random initial guess orthogonal to 1)."""
     dev = torch.device("cuda:0")
     for item in args.table1.split(","):
-        family, N = item.split(":")
+        family, N, *rest = item.split(":")
         N = int(N)
+        k = int(rest[0]) if rest else 4
         t_gen = time.perf_counter()
         g = table1_graph(family, N)
         t_gen = time.perf_counter() - t_gen
@@ -349,9 +350,9 @@ def run_table1(args, amg, torch):
         f = torch.zeros(g.n, dtype=torch.float64, device=dev)
         u0 = torch.tensor(u0_np, dtype=torch.float64, device=dev)
         u = torch.empty_like(u0)
-        row = {"table1": family, "N": N, "n": g.n, "nnz": g.nnz, "graph": g.name}
+        row = {"table1": family, "N": N, "n": g.n, "nnz": g.nnz, "graph": g.name, "mis_distance": k}
         for cyc, key in (("amli", "amli"), ("k", "n_amli")):
-            p = amg.amg_params_default(cycle=cyc, **{k: v for k, v in TABLE1.items()})
+            p = amg.amg_params_default(cycle=cyc, **dict(TABLE1, mis_distance=k))
             h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
             desc = amg.amg_describe(h)
             times = []
@@ -380,7 +381,7 @@ def run_table1(args, amg, torch):
         if g.n <= args.table1_oracle:
             import oracle
 
-            op = oracle.Params(degree=4, aggregation="mis", mis_distance=4, coarse_max=99, stop="energy")
+            op = oracle.Params(degree=4, aggregation="mis", mis_distance=k, coarse_max=99, stop="energy")
             ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, op)
             _, coef = oracle.amli_setup(ho)
             ra = oracle.fcg(ho, np.zeros(g.n), u0_np, precond=lambda r: oracle.amli_cycle(ho, 0, r, coef))
@@ -500,8 +501,9 @@ def main():
     ap.add_argument("--layout-sweep", action="store_true",
                     help="also time the dominant kernel in every fixed layout (reported under layout_sweep)")
     ap.add_argument("--table1", default=None, metavar="SIZES",
-                    help="Section 4's iteration-count runs: comma list of FAMILY:N (2d:N for N^2, 3d:N for N^3, "
-                         "unstruct:N for the Delaunay mesh of N^3 points), both cycles; one JSON line each")
+                    help="Section 4's iteration-count runs: comma list of FAMILY:N[:K] (2d:N for N^2, 3d:N for N^3, "
+                         "unstruct:N for the Delaunay mesh of N^3 points; K = the distance of the independent set, "
+                         "default 4), both cycles; one JSON line each")
     ap.add_argument("--table1-oracle", type=int, default=0,
                     help="also run the oracle on problems of at most this many rows")
     ap.add_argument("--copy-probe", action="store_true",
