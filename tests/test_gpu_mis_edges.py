@@ -1,0 +1,79 @@
+"""Degenerate cases of Section 2's partitioning on the device, against the
+oracle: a path, a star (the whole graph within distance k of one vertex), a
+two-vertex graph, k at least the diameter, a random weighted graph with k = 1,
+and pure Neumann versions.  Bars: every level and aggregate map bit-exact;
+solves within one iteration of the oracle with the true residual at most the
+tolerance."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def amg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1307_6305_amd as amg
+
+    amg.load_library()
+    return amg
+
+
+def _graph(n, ei, ej, d):
+    rp, col, w = inputs.csr_from_edges(n, np.asarray(ei), np.asarray(ej))
+    return inputs.Graph(n, rp, col, w, np.asarray(d, dtype=np.float64), name="edge-case")
+
+
+def _path(n, neumann):
+    d = np.zeros(n) if neumann else np.r_[1.0, np.zeros(n - 2), 1.0]
+    return _graph(n, np.arange(n - 1), np.arange(1, n), d)
+
+
+def _star(n, neumann):
+    d = np.zeros(n) if neumann else np.r_[np.zeros(n - 1), 1.0]
+    return _graph(n, np.zeros(n - 1, dtype=np.int64), np.arange(1, n), d)
+
+
+CASES = {
+    "path_300_k4": (lambda: _path(300, False), dict(mis_distance=4, coarse_max=8)),
+    "path_300_k1_neumann": (lambda: _path(300, True), dict(mis_distance=1, coarse_max=8, neumann=1)),
+    "star_200_k2": (lambda: _star(200, False), dict(mis_distance=2, coarse_max=8)),
+    "star_200_k1_neumann": (lambda: _star(200, True), dict(mis_distance=1, coarse_max=8, neumann=1)),
+    "two_vertices": (lambda: _graph(2, [0], [1], [1.0, 0.0]), dict(mis_distance=1, coarse_max=1)),
+    "grid_30_k8_beyond_diameter": (lambda: inputs.grid2d(30, 5), dict(mis_distance=8, coarse_max=4)),
+    "random_weighted_k1": (lambda: inputs.random_graph(600, 0.01, seed=11, weighted=True),
+                           dict(mis_distance=1, coarse_max=20)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mis_edge_case(amg, name):
+    make, kw = CASES[name]
+    g = make()
+    p = amg.amg_params_default(degree=4, aggregation="mis", **kw)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(
+        degree=4, aggregation="mis", mis_distance=p.mis_distance, coarse_max=p.coarse_max))
+    desc = amg.amg_describe(h)
+    assert desc["n"] == [lv.n for lv in ho.levels]
+    for l, lo in enumerate(ho.levels):
+        ex = amg.amg_level_export(h, l)
+        for key, ref in (("row_ptr", lo.row_ptr), ("col", lo.col), ("W", lo.W), ("d", lo.d), ("D", lo.D)):
+            assert np.array_equal(ex[key], ref), (l, key)
+        if l < ho.L:
+            assert np.array_equal(ex["agg"], ho.aggs[l]), l
+    f = inputs.rhs(g.n, 21)
+    if not np.any(g.d):
+        f = inputs.project_range(f)
+    u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, torch.tensor(f, device="cuda"), u)
+    res = oracle.fcg(ho, f)
+    assert info["status"] == 0 and res.converged, info
+    assert abs(info["iters"] - res.iters) <= 1, (info["iters"], res.iters)
+    assert info["rel_res_true"] <= p.tol * 1.05
