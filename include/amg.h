@@ -187,9 +187,11 @@ typedef struct {
   double grid_complexity;             /* sum n_l / n_0 (Section 4)              */
   double operator_complexity;         /* sum (nnz_l + n_l) / (nnz_0 + n_0)      */
   double setup_ms;                    /* whole amg_setup, device time           */
-  double aggregation_ms;              /* matching passes + coarse numbering     */
+  double aggregation_ms;              /* matching passes (or independent set and
+                                         nearest owners) + coarse numbering     */
   double galerkin_ms;                 /* coarse operators (sort and reduce)     */
-  int32_t match_rounds;               /* handshake rounds summed over passes    */
+  int32_t match_rounds;               /* handshake rounds summed over passes (or
+                                         independent-set rounds over levels)    */
   int32_t precision;
   double device_bytes;                /* device memory held by the hierarchy    */
   double layout_ms;                   /* sliced-ELL layouts incl. autotuning    */
