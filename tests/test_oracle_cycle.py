@@ -180,3 +180,27 @@ def test_iteration_counts_near_constant_in_n():
         its.append(oracle.fcg(h, inputs.rhs(g.n, 1)).iters)
     assert max(its) - min(its) <= 5
     assert max(its) <= 25
+
+
+def test_table1_reading_trend():
+    """Section 4's experiment as read here (Section 2's partitioning at k = 4,
+    pure Neumann FE Laplacians, m = 4, coarsest below 100 rows, the A-norm
+    error reduced 1e-8 on A u = 0): as in Table 1, the counts barely grow with
+    n and the nonlinear cycle needs no more iterations than the stationary one
+    (at most one more, rounding)."""
+    with open(os.path.join(GOLDEN, "table1_iterations.json")) as fh:
+        t1 = json.load(fh)
+    assert all(a >= b for a, b in t1["2d_structured"].values())
+    counts = []
+    for g in (inputs.poisson2d(64), inputs.poisson2d(128), inputs.poisson2d(256), inputs.poisson3d(32)):
+        p = oracle.Params(degree=4, aggregation="mis", mis_distance=4, coarse_max=99, stop="energy")
+        h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, p)
+        u0 = inputs.project_range(inputs.rhs(g.n, 5))
+        nk = oracle.fcg(h, np.zeros(g.n), u0)
+        _, coef = oracle.amli_setup(h)
+        na = oracle.fcg(h, np.zeros(g.n), u0, precond=lambda r, h=h, coef=coef: oracle.amli_cycle(h, 0, r, coef))
+        assert nk.converged and na.converged
+        assert nk.iters <= na.iters + 1, (g.name, nk.iters, na.iters)
+        counts.append(nk.iters)
+    assert max(counts[:3]) - min(counts[:3]) <= 3, counts
+    assert max(counts) <= 30, counts
