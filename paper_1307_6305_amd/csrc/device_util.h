@@ -8,6 +8,16 @@
 
 namespace amg {
 
+// splitmix64 (Steele, Lea and Flood): one output of the generator whose state
+// is x.  The method's counter-based draws (independent-set priorities, power
+// iteration start vectors) all come from it.
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // Sum over the 64 lanes of a wavefront; the result is valid in every lane.
 // The shuffle tree is fixed, so the result is deterministic.
 template <typename T>

@@ -581,12 +581,7 @@ __global__ void k_sort_members(int nc, const int* __restrict__ off, int* __restr
 // of S and no undecided vertex of larger key lies within distance k (k hops of
 // max / or propagation), and leaves when a member lies within distance k --
 // the same set as taking the vertices one by one in key order.
-__device__ __forceinline__ unsigned long long mis_key(int v) {
-  unsigned long long z = (unsigned long long)v + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
+__device__ __forceinline__ unsigned long long mis_key(int v) { return splitmix64((uint64_t)v); }
 
 // state: 0 undecided, 1 in S, 2 out
 __global__ void k_mis_seed(int n, const int* __restrict__ state, unsigned long long* __restrict__ mx,

@@ -1392,15 +1392,6 @@ constexpr int kAmliPowerIters = 20;
 // a below 3 - 2 sqrt(2) would make the degree-1 polynomial negative near t = 1
 constexpr double kAmliMinA = 0.18, kAmliMaxA = 0.99;
 
-// splitmix64 (Steele, Lea and Flood): one output of the generator whose state
-// is x.
-inline uint64_t splitmix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 // g0 + g1 t: the degree-1 best uniform approximation to 1/t on [a, 1] (the
 // smoother's closed form with lambda1 = 1, lambda0 = a).
 void amli_poly(double a, double* g0, double* g1) {
