@@ -108,8 +108,8 @@ enum { AMG_STOP_RESIDUAL = 0, AMG_STOP_ENERGY = 1 };
  *                 AMLI W-cycle, whose coarse correction is the degree-1 best
  *                 uniform approximation to 1/t on [a, 1] applied to the
  *                 preconditioned coarse operator (a estimated at setup by 20
- *                 power iterations on I - B A per level); needs inner_steps = 2;
- *                 not available in the batched and served forms.
+ *                 power iterations on I - B A per level); needs inner_steps = 2.
+ *                 The items of one batch share the cycle.
  *   aggregation   AMG_AGG_MATCHING (default): agg_size = 2^P from P heavy-edge
  *                 matching passes; AMG_AGG_MIS: Section 2's partitioning as the
  *                 paper's experiments use it -- a maximal independent set of

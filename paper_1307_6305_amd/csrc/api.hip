@@ -244,8 +244,8 @@ int32_t check_serve_cfg(const amg_serve_cfg* cfg) {
     amg::set_last_error(msg);
     return pst;
   }
-  if (cfg->params.cycle != AMG_CYCLE_K || cfg->params.stop != AMG_STOP_RESIDUAL) {
-    amg::set_last_error("the served form runs the nonlinear cycle (AMG_CYCLE_K) with the residual test only");
+  if (cfg->params.stop != AMG_STOP_RESIDUAL) {
+    amg::set_last_error("the served form uses the residual stopping test (AMG_STOP_RESIDUAL) only");
     return AMG_ERR_ARG;
   }
   return AMG_OK;

@@ -524,12 +524,13 @@ struct Builder {
 
   // Vectors are named per item: the level's rhs, sol, Z[k], S, A, B buffers,
   // or the outer r / z.
-  enum Src { SRC_OUTER_R, SRC_RHS, SRC_S };
+  enum Src { SRC_OUTER_R, SRC_RHS, SRC_S, SRC_Q0 };
   enum Dst { DST_OUTER_Z, DST_Z };
 
   const void* src_ptr(int i, int l, Src s) const {
     if (s == SRC_OUTER_R) return H(i)->r;
     if (s == SRC_RHS) return H(i)->ws[l].rhs;
+    if (s == SRC_Q0) return H(i)->ws[l].Q[0];
     return H(i)->ws[l].S;
   }
   void* dst_ptr(int i, int l, Dst d, int k) const {
@@ -711,7 +712,12 @@ struct Builder {
     }
     coarse(C);
     tail(T);
-    if (!R.empty()) inner(l + 1, R);
+    if (!R.empty()) {
+      if (H(I[0])->p.cycle == AMG_CYCLE_AMLI)
+        amli(l + 1, R);
+      else
+        inner(l + 1, R);
+    }
     if (H(I[0])->p.degree > 0) {
       // the prolongation folded into the residual and the first smoothing step
       residual(l, I, src, dst, k, true);
@@ -721,6 +727,44 @@ struct Builder {
     prolong(l, I, dst, k);
     residual(l, I, src, dst, k);
     smooth(l, I, SRC_S, dst, k, true);
+  }
+
+  // The stationary AMLI correction on level l for the items I: sol = g0 y0 +
+  // g1 y1 with y0 = B rhs, y1 = B (A y0), the same steps as the single-system
+  // solve (the product's inner products go to a dummy slot).
+  void amli(int l, const std::vector<int>& I) {
+    kcycle(l, I, SRC_RHS, DST_Z, 0);
+    {
+      std::vector<BatchOp> v;
+      for (int i : I) {
+        const auto& W = H(i)->ws[l];
+        BatchOp o = blank(B_SPMV_DOTS, i);
+        fill_mats(o, i, l);
+        o.n = H(i)->lv[l].n;
+        o.a = W.Z[0];
+        o.b = W.Z[0];
+        o.c = W.Q[0];
+        o.scal = H(i)->scal;
+        for (int q = 0; q < 8; ++q) o.s0.s[q] = S_DUMMY;
+        v.push_back(o);
+      }
+      step(v, true);
+    }
+    kcycle(l, I, SRC_Q0, DST_Z, 1);
+    for (int t = 0; t < 2; ++t) {
+      std::vector<BatchOp> v;
+      for (int i : I) {
+        const auto& W = H(i)->ws[l];
+        BatchOp o = blank(B_SCALE_ADD, i);
+        o.n = H(i)->lv[l].n;
+        o.a = W.Z[t];
+        o.d = W.sol;
+        o.f0 = t == 0 ? H(i)->amli_g0[l] : H(i)->amli_g1[l];
+        o.i0 = t;
+        v.push_back(o);
+      }
+      step(v, false);
+    }
   }
 
   // nu flexible-CG steps from zero on level l for the items I
@@ -919,8 +963,8 @@ int32_t batch_compatible(const std::vector<amg_hier*>& hs) {
   const amg_params& p0 = hs[0]->p;
   for (size_t i = 0; i < hs.size(); ++i) {
     const amg_hier* h = hs[i];
-    if (h->p.cycle != AMG_CYCLE_K) {
-      set_last_error("the batched form runs the nonlinear cycle (AMG_CYCLE_K) only");
+    if (h->p.cycle == AMG_CYCLE_AMLI && (int)h->amli_g0.size() < h->L) {
+      set_last_error("AMLI coefficients missing");
       return AMG_ERR_ARG;
     }
     if (h->p.stop != AMG_STOP_RESIDUAL) {
@@ -928,8 +972,8 @@ int32_t batch_compatible(const std::vector<amg_hier*>& hs) {
       return AMG_ERR_ARG;
     }
     if (h->mixed != hs[0]->mixed || h->p.degree != p0.degree || h->p.inner_steps != p0.inner_steps ||
-        h->p.restart != p0.restart) {
-      set_last_error("batched items must share precision, degree, inner steps and restart");
+        h->p.restart != p0.restart || h->p.cycle != p0.cycle) {
+      set_last_error("batched items must share precision, degree, inner steps, restart and cycle");
       return AMG_ERR_ARG;
     }
     if (!h->chol_inv) {

@@ -148,8 +148,6 @@ def test_server_argument_errors_before_device(amg):
         assert not hnd.value
     cfg = amg.amg_serve_cfg_default(amg.amg_params_default(restart=0))
     assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
-    cfg = amg.amg_serve_cfg_default(amg.amg_params_default(cycle="amli"))
-    assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
     cfg = amg.amg_serve_cfg_default(amg.amg_params_default(stop="energy"))
     assert lib.amg_server_create(ctypes.byref(cfg), None, ctypes.byref(hnd)) == amg.AMG_ERR_ARG
     assert lib.amg_server_create(ctypes.byref(amg.amg_serve_cfg_default()), None, None) == amg.AMG_ERR_ARG
