@@ -684,10 +684,12 @@ __global__ void k_galm_len(int nc, const int* __restrict__ moff, const int* __re
 __global__ void k_galm_sort(int nc, const int* __restrict__ moff, const int* __restrict__ members,
                             const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ W,
                             const int* __restrict__ ids, const int* __restrict__ toff, int* __restrict__ tJ,
-                            double* __restrict__ tW, int* __restrict__ tcnt, int* __restrict__ ucnt) {
+                            double* __restrict__ tW, int* __restrict__ tcnt, int* __restrict__ ucnt,
+                            int max_len) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   const int o = toff[I];
+  if (toff[I + 1] - o > max_len) return;  // a long row: the hash kernel's
   int c = 0;
   for (int k = moff[I]; k < moff[I + 1]; ++k) {
     const int i = members[k];
@@ -736,6 +738,102 @@ __global__ void k_galm_reduce(int nc, const int* __restrict__ toff, const int* _
   double dd = 0.0;
   for (int k = moff[I]; k < moff[I + 1]; ++k) dd += d[members[k]];
   cd[I] = dd;
+}
+
+// The same coarse rows for long rows (more than kGalHashLen gathered entries;
+// the insertion sort above is quadratic in the row), in time linear in the
+// row: one wavefront per coarse row visits its entries in the sequential order
+// (members in increasing index, entries in row order), 64 at a time; lane 0
+// adds each weight to its coarse column's slot of an LDS hash table (a slot
+// starts at 0 and adds in that order: the sums of the sequential definition);
+// the distinct columns are then written in increasing order with their sums,
+// one entry per column, which k_galm_reduce copies unchanged.  A row with more
+// than kGalFill distinct columns sets *overflow, and the caller then sorts
+// every row instead.
+constexpr int kGalHashLen = 384, kGalTable = 1024, kGalFill = 768;
+
+__global__ void __launch_bounds__(64) k_galm_hash(int nc, const int* __restrict__ moff,
+                                                  const int* __restrict__ members, const int* __restrict__ rp,
+                                                  const int* __restrict__ col, const double* __restrict__ W,
+                                                  const int* __restrict__ ids, const int* __restrict__ toff,
+                                                  int* __restrict__ tJ, double* __restrict__ tW,
+                                                  int* __restrict__ tcnt, int* __restrict__ ucnt, int* overflow) {
+  __shared__ int key[kGalTable];
+  __shared__ double sum[kGalTable];
+  __shared__ int dk[kGalFill];
+  __shared__ double dsum[kGalFill];
+  __shared__ int cj[64];
+  __shared__ double cw[64];
+  __shared__ int nd_s, ovf_s, nk_s;
+  const int I = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (I >= nc || toff[I + 1] - toff[I] <= kGalHashLen) return;
+  for (int s = lane; s < kGalTable; s += 64) key[s] = -1;
+  if (lane == 0) {
+    nd_s = 0;
+    ovf_s = 0;
+    nk_s = 0;
+  }
+  __syncthreads();
+  const int m1 = moff[I + 1];
+  for (int m = moff[I]; m < m1; ++m) {
+    const int i = members[m];
+    const int e1 = rp[i + 1];
+    for (int e0 = rp[i]; e0 < e1; e0 += 64) {
+      const int cnt = min(64, e1 - e0);
+      if (lane < cnt) {
+        cj[lane] = ids[col[e0 + lane]];
+        cw[lane] = W[e0 + lane];
+      }
+      __syncthreads();
+      if (lane == 0) {
+        for (int t = 0; t < cnt; ++t) {
+          const int J = cj[t];
+          if (J == I) continue;
+          int s = (int)(((unsigned)J * 2654435761u) & (unsigned)(kGalTable - 1));
+          while (key[s] != -1 && key[s] != J) s = (s + 1) & (kGalTable - 1);
+          if (key[s] == -1) {
+            if (nd_s == kGalFill) {
+              ovf_s = 1;
+              break;
+            }
+            key[s] = J;
+            sum[s] = 0.0;
+            ++nd_s;
+          }
+          sum[s] += cw[t];
+        }
+      }
+      __syncthreads();
+      if (ovf_s) break;
+    }
+    if (ovf_s) break;
+  }
+  if (ovf_s) {
+    if (lane == 0) atomicOr(overflow, 1);
+    return;
+  }
+  for (int s = lane; s < kGalTable; s += 64) {
+    const int J = key[s];
+    if (J >= 0) {
+      const int q = atomicAdd(&nk_s, 1);
+      dk[q] = J;
+      dsum[q] = sum[s];
+    }
+  }
+  __syncthreads();
+  const int nd = nd_s, o = toff[I];
+  for (int q = lane; q < nd; q += 64) {
+    const int J = dk[q];
+    int rank = 0;
+    for (int t = 0; t < nd; ++t) rank += dk[t] < J;
+    tJ[o + rank] = J;
+    tW[o + rank] = dsum[q];
+  }
+  if (lane == 0) {
+    tcnt[I] = nd;
+    ucnt[I] = nd;
+  }
 }
 
 // ------------------------------------------------------------------ sliced ELL
@@ -1127,8 +1225,22 @@ int32_t mis_level(amg_hier* h, Temps& T, const Graph& g, int k, int** agg_out, G
   AMG_TRY(T.get(&ucnt, nc));
   hipLaunchKernelGGL(k_galm_len, dim3(nblk(nc)), dim3(TPB), 0, s, nc, moff, members, g.rp, len);
   AMG_TRY(scan_excl(T, len, nc, toff, s));
+  int* overflow = nullptr;
+  AMG_TRY(T.get(&overflow, 1));
+  hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, (size_t)1, overflow, 0);
+  // rows up to kGalHashLen entries: insertion sort, one thread per row; longer
+  // rows: the hash kernel (all rows sorted if one has too many columns)
   hipLaunchKernelGGL(k_galm_sort, dim3(nblk(nc)), dim3(TPB), 0, s, nc, moff, members, g.rp, g.col, g.W, ids, toff, tJ,
-                     tW, tcnt, ucnt);
+                     tW, tcnt, ucnt, kGalHashLen);
+  hipLaunchKernelGGL(k_galm_hash, dim3(nc), dim3(64), 0, s, nc, moff, members, g.rp, g.col, g.W, ids, toff, tJ, tW,
+                     tcnt, ucnt, overflow);
+  AMG_HIP(hipGetLastError());
+  int overflowed = 0;
+  AMG_TRY(read_int(overflow, &overflowed, s));
+  if (overflowed) {
+    hipLaunchKernelGGL(k_galm_sort, dim3(nblk(nc)), dim3(TPB), 0, s, nc, moff, members, g.rp, g.col, g.W, ids, toff,
+                       tJ, tW, tcnt, ucnt, INT_MAX);
+  }
   Graph c;
   c.n = nc;
   AMG_TRY(dalloc(h, &c.rp, nc + 1));
