@@ -557,11 +557,38 @@ __global__ void k_scatter_members(int n, const int* __restrict__ agg, const int*
   members[off[a] + atomicAdd(&cursor[a], 1)] = i;
 }
 
-// Members of each aggregate in increasing vertex order (deterministic).
+// Members of each aggregate in increasing vertex order (deterministic; the
+// keys are distinct).  Insertion sort for the small aggregates of matching,
+// heapsort for the large ones an independent set of the graph of A^k can make.
+__device__ void sift_down(int* a, int root, int m) {
+  const int v = a[root];
+  int r = root;
+  for (;;) {
+    int c = 2 * r + 1;
+    if (c >= m) break;
+    if (c + 1 < m && a[c + 1] > a[c]) ++c;
+    if (a[c] <= v) break;
+    a[r] = a[c];
+    r = c;
+  }
+  a[r] = v;
+}
+
 __global__ void k_sort_members(int nc, const int* __restrict__ off, int* __restrict__ members) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
-  const int o = off[I], e = off[I + 1];
+  const int o = off[I], e = off[I + 1], m = e - o;
+  if (m > 32) {
+    int* a = members + o;
+    for (int r = m / 2 - 1; r >= 0; --r) sift_down(a, r, m);
+    for (int k = m - 1; k > 0; --k) {
+      const int t = a[0];
+      a[0] = a[k];
+      a[k] = t;
+      sift_down(a, 0, k);
+    }
+    return;
+  }
   for (int k = o + 1; k < e; ++k) {
     const int v = members[k];
     int p = k;
