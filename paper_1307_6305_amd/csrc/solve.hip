@@ -121,6 +121,29 @@ __global__ void k_restrict(Transfer T, const VT* __restrict__ s, VT* b) {
   if (I < T.nc) row_restrict<VT>(T, I, s, b);
 }
 
+// The same sums for large aggregates (an independent set of A^k makes
+// aggregates of tens to hundreds of rows): one wavefront per aggregate loads
+// 64 members' values at once, so that members lying side by side share cache
+// lines and the loads are not one thread's serial chain; every lane then adds
+// the values in member order (broadcast by shuffles), as row_restrict does.
+constexpr int kRestrictWaveMembers = 24;  // mean aggregate size from which it is used
+
+template <typename VT>
+__global__ void __launch_bounds__(256) k_restrict_wave(Transfer T, const VT* __restrict__ s, VT* b) {
+  const int I = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  const int lane = (int)threadIdx.x & 63;
+  if (I >= T.nc) return;  // uniform per wavefront
+  const int k0 = T.member_off[I], k1 = T.member_off[I + 1];
+  VT acc = 0;
+  for (int c = k0; c < k1; c += 64) {
+    const int k = c + lane;
+    const VT v = k < k1 ? s[T.members[k]] : (VT)0;
+    const int cnt = min(64, k1 - c);
+    for (int t = 0; t < cnt; ++t) acc += __shfl(v, t, 64);
+  }
+  if (lane == 0) b[I] = acc;
+}
+
 // b = P^T (f - A x) in one pass on launch-bound levels: block k takes the
 // aggregates agg_blk[k] .. agg_blk[k + 1] - 1 (at most TPB member rows, their
 // member lists contiguous), K lanes compute each member row's residual (the
@@ -683,7 +706,10 @@ struct Engine {
       rec->push_back(o);
       return AMG_OK;
     }
-    hipLaunchKernelGGL((k_restrict<VT>), dim3(nblk(T.nc)), dim3(TPB), 0, s, T, sv, b);
+    if (T.n >= kRestrictWaveMembers * (int64_t)T.nc)
+      hipLaunchKernelGGL((k_restrict_wave<VT>), dim3((T.nc + 3) / 4), dim3(256), 0, s, T, sv, b);
+    else
+      hipLaunchKernelGGL((k_restrict<VT>), dim3(nblk(T.nc)), dim3(TPB), 0, s, T, sv, b);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
