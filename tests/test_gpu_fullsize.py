@@ -1,6 +1,7 @@
 """Parity at the benchmark's full size, in the launch configuration bench.py
 times: the 1024 x 1024 grid (1,048,576 unknowns), aggregates of 16, degree 3,
-FP64; and the 128^3 tetrahedral cube in mixed precision (properties only)."""
+FP64; Section 4's 1024^2 Neumann square with its own partitioning; and the
+128^3 tetrahedral cube in mixed precision (properties only)."""
 import numpy as np
 import pytest
 
@@ -92,3 +93,35 @@ def test_fullsize_tet3d_mixed_properties(amg):
     e = (um - u64).cpu().numpy()
     x = u64.cpu().numpy()
     assert np.sqrt(e @ oracle.apply_A(lvl0, e)) <= 1e-6 * np.sqrt(x @ oracle.apply_A(lvl0, x))
+
+
+def test_fullsize_section4_square(amg):
+    """Section 4's 2D model problem at the bench size (1024^2 pure Neumann FE
+    square, independent set of A^4, m = 4, coarsest below 100 rows, the A-norm
+    test on A u = 0), in the bench's launch configuration: every level and
+    aggregate map bit-exact, one cycle within 1e-10, iterations within one of
+    the oracle's and the A-norm ratio of the result at most the tolerance."""
+    g = inputs.poisson2d(1024)
+    p = amg.amg_params_default(degree=4, aggregation="mis", mis_distance=4, neumann=1, coarse_max=99,
+                               stop="energy")
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(
+        degree=4, aggregation="mis", mis_distance=4, coarse_max=99, stop="energy"))
+    assert amg.amg_describe(h)["n"] == [l.n for l in ho.levels]
+    for l, lo in enumerate(ho.levels):
+        ex = amg.amg_level_export(h, l)
+        assert np.array_equal(ex["col"], lo.col) and np.array_equal(ex["W"], lo.W), l
+        if l < ho.L:
+            assert np.array_equal(ex["agg"], ho.aggs[l]), l
+    u0 = inputs.project_range(inputs.rhs(g.n, inputs.seed_for(9, 2024), "uniform"))
+    z = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    amg.amg_apply_cycle(h, torch.tensor(u0, device="cuda"), z)
+    zo = oracle.kcycle(ho, 0, u0)
+    assert np.linalg.norm(z.cpu().numpy() - zo) <= 1e-10 * np.linalg.norm(zo)
+    u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, torch.zeros_like(u), u)
+    res = oracle.fcg(ho, np.zeros(g.n), u0)
+    assert info["status"] == 0 and res.converged and abs(info["iters"] - res.iters) <= 1, (info, res.iters)
+    lo = ho.levels[0]
+    uh = u.cpu().numpy()
+    assert np.sqrt(uh @ oracle.apply_A(lo, uh)) <= p.tol * np.sqrt(u0 @ oracle.apply_A(lo, u0))
