@@ -403,6 +403,8 @@ def run_serve(args, amg, torch):
           file=sys.stderr, flush=True)
     p64 = amg.amg_params_default(degree=4, agg_size=8)
     pmx = amg.amg_params_default(degree=4, agg_size=8, precision="mixed")
+    # the same with hashed matching ties: fewer handshake rounds per new graph
+    pmh = amg.amg_params_default(degree=4, agg_size=8, precision="mixed", tie_break="hash")
     # capacity of the one-at-a-time FP64 server (all requests at once)
     cfg = amg.amg_serve_cfg_default(p64, mode="sequential", realtime=0, hbm_budget_bytes=200e9)
     comps, st, _ = amg.amg_serve(cfg, reqs, want_u=False)
@@ -422,7 +424,8 @@ def run_serve(args, amg, torch):
         r["arrival_s"] = t
         t += rng.exponential(1.0 / rate)
     results = {}
-    for name, mode, params in (("batched_mixed", "batched", pmx), ("sequential_fp64", "sequential", p64)):
+    for name, mode, params in (("batched_mixed", "batched", pmx), ("sequential_fp64", "sequential", p64),
+                               ("batched_mixed_hash_ties", "batched", pmh)):
         cfg = amg.amg_serve_cfg_default(params, mode=mode, realtime=1, hbm_budget_bytes=200e9,
                                         iters_per_step=args.serve_iters_per_step, max_slots=args.serve_slots)
         comps, st, _ = amg.amg_serve(cfg, reqs, want_u=False)
@@ -470,6 +473,7 @@ def run_serve(args, amg, torch):
             "capacity_dof_per_s": {"sequential_fp64": dof / st["wall_s"], "batched_mixed": dof / stb["wall_s"]},
             "batched_mixed": results["batched_mixed"],
             "sequential_fp64": results["sequential_fp64"],
+            "batched_mixed_hash_ties": results["batched_mixed_hash_ties"],
         },
     }
     print(json.dumps(out), flush=True)
