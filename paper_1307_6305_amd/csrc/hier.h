@@ -74,6 +74,7 @@ struct amg_hier {
   hipGraphExec_t iter_exec[8] = {};
   hipStream_t graph_stream = nullptr;  // stream the graphs were captured on
   const void* graph_u = nullptr;       // solution pointer baked into the graphs
+  hipEvent_t iter_ev[2] = {};          // completion of the outer iterations in flight
 
   // stationary AMLI cycle: per level, the estimated lambda_min(B_l A_l) and
   // the coarse-correction polynomial g0 + g1 t (levels 1 .. L-1)

@@ -42,6 +42,13 @@ constexpr int kMaxRowThreads = TPB * 4;
 // Levels below this many rows fold the prolongation into the next steps.
 constexpr int kFoldProlongRows = 1 << 18;
 
+// Outer iterations: the pinned host slots of the stopping test (a pair per
+// restart-window position from this index on), and the margin above the
+// tolerance of the predicted ratio from which the next iteration is queued
+// before the test is read.
+constexpr int kPubBase = 8;
+constexpr double kAheadFactor = 4.0;
+
 struct SlotLane {
   int tile, slot, lane;
 };
@@ -962,6 +969,10 @@ struct Engine {
     return AMG_OK;
   }
 
+  // Pinned host slots of the stopping test's two numbers, one pair per
+  // window position, so that two iterations in flight never share one.
+  double* pub_slot(int j) const { return h->host_scal + kPubBase + 2 * j; }
+
   // one outer iteration at window position j; u, r FP64 (finest level)
   int32_t outer_iter(int j, double* u) {
     const int n = h->lv[0].n;
@@ -990,10 +1001,10 @@ struct Engine {
       // recursive residual drifts along the constants of a Neumann problem,
       // which the iterates pick up), published with rho_j
       AMG_TRY(finish<1>(nb, rr));
-      return energy64(u, h->host_scal, S_RHOW + j);
+      return energy64(u, pub_slot(j), S_RHOW + j);
     }
     // with the stopping test's inputs, (r, r) and rho_j, published to the host
-    AMG_TRY(finish<1>(nb, rr, h->host_scal, S_RHOW + j));
+    AMG_TRY(finish<1>(nb, rr, pub_slot(j), S_RHOW + j));
     return AMG_OK;
   }
 
@@ -1082,27 +1093,63 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
       AMG_TRY(capture_graphs<VT, MT>(h, u));
       h->graph_u = u;
     }
-    status = AMG_ERR_MAXIT;
-    for (it = 1; it <= h->p.max_iter; ++it) {
-      const int j = (it - 1) % h->p.restart;
+    for (hipEvent_t& e : h->iter_ev)
+      if (!e) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const int R = h->p.restart;
+    auto launch = [&](int k) -> int32_t {
       if (use_graph) {
-        AMG_HIP(hipGraphLaunch(h->iter_exec[j], s));
+        AMG_HIP(hipGraphLaunch(h->iter_exec[(k - 1) % R], s));
       } else {
-        AMG_TRY(E.outer_iter(j, u));
+        AMG_TRY(E.outer_iter((k - 1) % R, u));
       }
-      AMG_HIP(hipStreamSynchronize(s));
-      const double rr = h->host_scal[0], rho = h->host_scal[1];
+      AMG_HIP(hipEventRecord(h->iter_ev[k & 1], s));
+      return AMG_OK;
+    };
+    auto ratio = [&](int k) {
+      const double rr = h->host_scal[kPubBase + 2 * ((k - 1) % R)];
+      return energy ? std::sqrt(std::max(rr, 0.0)) / en0 : std::sqrt(rr) / rho0;
+    };
+    // Iteration k + 1 is queued before the test of iteration k is read when
+    // the ratio predicted for k (the last one times the last reduction) is
+    // above kAheadFactor x tol, so that the device does not idle while the
+    // host reads; if the test passes at k after all, the queued iteration
+    // still runs and is counted.  (With a window of one position both would
+    // publish into the same slot.)
+    status = AMG_ERR_MAXIT;
+    AMG_TRY(launch(1));
+    int queued = 1;
+    double last = 1.0, before = 1.0;  // ratios of iterations k - 1 and k - 2
+    for (it = 1; it <= h->p.max_iter; ++it) {
+      const double predicted = last * std::min(1.0, last / before);
+      if (R >= 2 && it >= 2 && queued == it && it < h->p.max_iter && predicted > kAheadFactor * h->p.tol) {
+        AMG_TRY(launch(it + 1));
+        queued = it + 1;
+      }
+      AMG_HIP(hipEventSynchronize(h->iter_ev[it & 1]));
+      const double rho = h->host_scal[kPubBase + 2 * ((it - 1) % R) + 1];
       if (!(rho > 0.0) || !std::isfinite(rho)) {
         status = AMG_ERR_BREAKDOWN;
         break;
       }
-      rel = energy ? std::sqrt(std::max(rr, 0.0)) / en0 : std::sqrt(rr) / rho0;
+      rel = ratio(it);
       if (rel <= h->p.tol) {
         status = AMG_OK;
         break;
       }
+      before = last;
+      last = rel;
+      if (queued == it && it < h->p.max_iter) {
+        AMG_TRY(launch(it + 1));
+        queued = it + 1;
+      }
     }
     if (it > h->p.max_iter) it = h->p.max_iter;
+    if (queued > it) {
+      // the iteration queued ahead ran too: report it
+      AMG_HIP(hipEventSynchronize(h->iter_ev[queued & 1]));
+      it = queued;
+      if (status == AMG_OK) rel = ratio(it);
+    }
   }
   // true FP64 residual of the returned u
   AMG_TRY(E.residual64(f, u, h->tmp, S_RRT));
@@ -1407,6 +1454,10 @@ void destroy_graphs(amg_hier* h) {
   for (int j = 0; j < 8; ++j) {
     if (h->iter_exec[j]) (void)hipGraphExecDestroy(h->iter_exec[j]);
     h->iter_exec[j] = nullptr;
+  }
+  for (hipEvent_t& e : h->iter_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
   }
   h->graphs_ready = false;
 }

@@ -309,3 +309,30 @@ def test_hash_ties_fewer_rounds(amg):
         assert info["status"] == 0 and info["rel_res_true"] <= 1.05e-8
         h.close()
     assert rounds["hash"] * 4 < rounds["index"], rounds
+
+
+@pytest.mark.parametrize("restart,use_graph", [(1, 1), (2, 0), (5, 1)])
+def test_iteration_limit_and_window(amg, restart, use_graph):
+    """The outer loop queues the next iteration before reading the test of the
+    current one: an iteration limit still stops at exactly max_iter iterations
+    with the oracle's iterate, and windows of one and two positions (one shared
+    pinned slot, or alternating ones) solve as the oracle does."""
+    g = inputs.grid2d(80, 53)
+    kw = dict(degree=3, agg_size=4, restart=restart, use_graph=use_graph)
+    p3 = amg.amg_params_default(max_iter=3, **kw)
+    h3 = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p3)
+    ho3 = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(amg, p3))
+    f = inputs.rhs(g.n, 31)
+    u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h3, _t(f), u)
+    res = oracle.fcg(ho3, f)
+    assert info["status"] == amg.AMG_ERR_MAXIT and info["iters"] == 3 and not res.converged
+    assert _rel(u, res.x) <= 1e-9
+    p = amg.amg_params_default(**kw)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(amg, p))
+    u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, _t(f), u)
+    res = oracle.fcg(ho, f)
+    assert info["status"] == 0 and abs(info["iters"] - res.iters) <= 1
+    assert info["rel_res_true"] <= p.tol * 1.05
