@@ -63,3 +63,21 @@ def test_multipass_equals_direct_galerkin():
     assert np.array_equal(direct.col, chained.col)
     assert np.array_equal(direct.W, chained.W)
     assert np.array_equal(direct.D, chained.D)
+
+
+@pytest.mark.parametrize("aggregation", ["matching", "mis"])
+def test_transfers_are_the_piecewise_constant_prolongator(aggregation):
+    """Restriction and prolongation equal P^T v and P e for the 0/1 matrix with
+    P[i, agg(i)] = 1 (built here from its definition), and A_H = P^T A P."""
+    g = inputs.poisson2d(30) if aggregation == "mis" else inputs.grid2d(30, 17)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d,
+                               oracle.Params(agg_size=4, aggregation=aggregation, coarse_max=8))
+    rng = np.random.default_rng(4)
+    for l in range(h.L):
+        agg, n, nc = h.aggs[l], h.levels[l].n, h.levels[l + 1].n
+        P = np.zeros((n, nc))
+        P[np.arange(n), agg] = 1.0
+        v, e = rng.standard_normal(n), rng.standard_normal(nc)
+        np.testing.assert_allclose(oracle.restrict(agg, nc, v), P.T @ v, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(oracle.prolong(agg, e), P @ e, rtol=0, atol=0)
+        np.testing.assert_allclose(h.levels[l + 1].dense(), P.T @ h.levels[l].dense() @ P, rtol=0, atol=1e-12)
