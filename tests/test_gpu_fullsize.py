@@ -1,7 +1,8 @@
 """Parity at the benchmark's full size, in the launch configuration bench.py
 times: the 1024 x 1024 grid (1,048,576 unknowns), aggregates of 16, degree 3,
-FP64; Section 4's 1024^2 Neumann square with its own partitioning; and the
-128^3 tetrahedral cube in mixed precision (properties only)."""
+FP64; Section 4's 1024^2 Neumann square with its own partitioning; the
+128^3 tetrahedral cube in mixed precision (properties only); and the batch of
+256 random geometric graphs (properties, sampled items)."""
 import numpy as np
 import pytest
 
@@ -125,3 +126,31 @@ def test_fullsize_section4_square(amg):
     lo = ho.levels[0]
     uh = u.cpu().numpy()
     assert np.sqrt(uh @ oracle.apply_A(lo, uh)) <= p.tol * np.sqrt(u0 @ oracle.apply_A(lo, u0))
+
+
+def test_fullsize_batch_rgg256(amg):
+    """The batched form at the bench's full size and launch configuration (256
+    random geometric graphs, 9.8 M unknowns, mixed precision, agg 8, m 4, one
+    amg_solve_batch): every item converges with its true FP64 residual at most
+    the tolerance (a property at any size), and sampled items (the smallest
+    and two others) match the oracle to the mixed-precision bar."""
+    sizes = inputs.rgg_batch_sizes(256, inputs.seed_for(4))
+    graphs = [inputs.rgg(int(n), inputs.seed_for(4, i)) for i, n in enumerate(sizes)]
+    p = amg.amg_params_default(degree=4, agg_size=8, precision="mixed")
+    hs = [amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p) for g in graphs]
+    fs = [torch.tensor(inputs.rhs(g.n, inputs.seed_for(4, 1000 + i)), dtype=torch.float64, device="cuda")
+          for i, g in enumerate(graphs)]
+    us = [torch.zeros_like(f) for f in fs]
+    infos = amg.amg_solve_batch(hs, fs, us)
+    assert all(i["status"] == 0 and i["rel_res_true"] <= 1.05e-8 for i in infos)
+    order = np.argsort([g.n for g in graphs])
+    for k in (int(order[0]), int(order[len(order) // 3]), 17):
+        g = graphs[k]
+        ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, oracle.Params(degree=4, agg_size=8))
+        res = oracle.fcg(ho, fs[k].cpu().numpy())
+        assert infos[k]["iters"] <= res.iters + 3, (k, infos[k]["iters"], res.iters)
+        e = us[k].cpu().numpy() - res.x
+        lo = ho.levels[0]
+        assert np.sqrt(e @ oracle.apply_A(lo, e)) <= 1e-6 * np.sqrt(res.x @ oracle.apply_A(lo, res.x)), k
+    for h in hs:
+        h.close()
