@@ -72,7 +72,7 @@ enum { AMG_STOP_RESIDUAL = 0, AMG_STOP_ENERGY = 1 };
  *   lambda0_ratio lambda1 / lambda0 of the smoothing interval (Section 4: 10).
  *   inner_steps   flexible-CG steps per coarse level in the k-cycle (W-cycle: 2).
  *   restart       outer FCG keeps at most this many directions (Section 4: 5).
- *   tol           stop when ||r_k||_2 <= tol * ||r_0||_2.
+ *   tol           the stopping test's reduction factor (see stop).
  *   max_iter      outer iteration cap.
  *   precision     AMG_FP64, or AMG_MIXED: cycle, smoother and coarse-level
  *                 vectors and matrices in FP32 with FP32 accumulation; outer FCG,
@@ -88,7 +88,7 @@ enum { AMG_STOP_RESIDUAL = 0, AMG_STOP_ENERGY = 1 };
  *                 workgroup's LDS runs as one workgroup-resident kernel
  *                 (0 disables).
  *   autotune      1: choose every level's sliced-ELL layout at setup -- levels
- *                 of at least 32768 rows by timing the Chebyshev step on each
+ *                 of at least 262144 rows by timing the Chebyshev step on each
  *                 candidate layout, smaller ones by the bytes a pass moves;
  *                 0: use slice_height / lanes_per_row / sort_rows everywhere.
  *                 The layout never changes results: row sums are added in a
@@ -129,8 +129,8 @@ enum { AMG_STOP_RESIDUAL = 0, AMG_STOP_ENERGY = 1 };
  *                 the error is then the iterate itself, and (u_k, A u_k) is
  *                 formed from a fresh product each iteration (one extra
  *                 finest-level product).  On a pure Neumann problem
- *                 constants have A-norm 0.  Single
- *                 solves only (the batched and served forms reject it).
+ *                 constants have A-norm 0.  Single solves only (the batched
+ *                 and served forms reject it).
  *   fuse          1 (default): on levels below 2^18 rows, fold the inner
  *                 flexible-CG vector updates into the kernels that read them
  *                 and form the restriction of the residual in one pass; 0: one
