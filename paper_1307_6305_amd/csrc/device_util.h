@@ -157,7 +157,23 @@ __device__ __forceinline__ void sum_partials(const double* partials, int nparts,
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
   if (threadIdx.x < kFinishThreads) {
-    for (int b = threadIdx.x; b < nparts; b += kFinishThreads) {
+    // B partials' loads in flight at once, then added in the same order as
+    // one at a time (b, b + kFinishThreads, ...): the same sums
+    constexpr int B = K <= 2 ? 8 : 4;
+    int b = threadIdx.x;
+    for (; b + (B - 1) * kFinishThreads < nparts; b += B * kFinishThreads) {
+      double t[B][K];
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+#pragma unroll
+        for (int k = 0; k < K; ++k) t[i][k] = k < kn ? partials[(b + i * kFinishThreads) * K + k] : 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          if (k < kn) acc[k] += t[i][k];
+    }
+    for (; b < nparts; b += kFinishThreads) {
 #pragma unroll
       for (int k = 0; k < K; ++k)
         if (k < kn) acc[k] += partials[b * K + k];
