@@ -392,10 +392,26 @@ __device__ __forceinline__ VT row_residual_value(const Mat<MT>& A, int slot, int
   return (VT)(fr - ax);
 }
 
+// b_I = sum of s over the members of aggregate I in member order; the
+// members' indices and values are loaded eight at a time, then added in
+// order (the same sums as one at a time, without a serial chain of loads).
 template <typename VT>
 __device__ __forceinline__ void row_restrict(const Transfer& T, int I, const VT* __restrict__ s, VT* b) {
+  constexpr int B = 8;
   VT acc = 0;
-  for (int k = T.member_off[I]; k < T.member_off[I + 1]; ++k) acc += s[T.members[k]];
+  int k = T.member_off[I];
+  const int k1 = T.member_off[I + 1];
+  for (; k + B <= k1; k += B) {
+    int m[B];
+    VT v[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) m[i] = T.members[k + i];
+#pragma unroll
+    for (int i = 0; i < B; ++i) v[i] = s[m[i]];
+#pragma unroll
+    for (int i = 0; i < B; ++i) acc += v[i];
+  }
+  for (; k < k1; ++k) acc += s[T.members[k]];
   b[I] = acc;
 }
 
