@@ -213,8 +213,20 @@ __device__ __forceinline__ AT offdiag_seq(const Mat<MT>& A, int r, const XA& x) 
   const MT* __restrict__ v = A.val + A.off[s] + p;
   const int wd = A.width[s];
   AT acc = (AT)0;
-#pragma unroll 4
-  for (int t = 0; t < wd; ++t) acc += (AT)v[t * 64] * (AT)x(c[t * 64]);
+  int t = 0;
+  for (; t + 8 <= wd; t += 8) {  // eight entries' loads in flight, added in order
+    int cc[8];
+    AT vv[8], xx[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cc[i] = c[(t + i) * 64];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) vv[i] = (AT)v[(t + i) * 64];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) xx[i] = (AT)x(cc[i]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc += vv[i] * xx[i];
+  }
+  for (; t < wd; ++t) acc += (AT)v[t * 64] * (AT)x(c[t * 64]);
   return acc;
 }
 
