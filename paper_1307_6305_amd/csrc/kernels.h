@@ -510,6 +510,26 @@ __device__ __forceinline__ double fcg_beta(const double* scal, int s_dot, int s_
 // which are then added as (p0 + p1) + (p2 + p3): four times shorter chains.
 // Larger n use one sum per row over its triangle.  The association depends
 // only on n, not on the block size.  sb and sy hold 1024 doubles each.
+// sum over j = j0, j0 + G, ... < n of M[j n + i] v[j], in that order, with
+// eight products' loads in flight at a time
+template <int G>
+__device__ __forceinline__ double column_dot(const double* __restrict__ M, const double* v, int n, int i, int j0) {
+  double acc = 0.0;
+  int j = j0;
+  for (; j + 7 * G < n; j += 8 * G) {
+    double m[8], w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      m[q] = M[(size_t)(j + q * G) * n + i];
+      w[q] = v[j + q * G];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += m[q] * w[q];
+  }
+  for (; j < n; j += G) acc += M[(size_t)j * n + i] * v[j];
+  return acc;
+}
+
 template <typename VT, typename RT>
 __device__ __forceinline__ void coarse_apply(const CoarseView& C, const RT* __restrict__ b, VT* x, double* sb,
                                              double* sy) {
@@ -521,10 +541,7 @@ __device__ __forceinline__ void coarse_apply(const CoarseView& C, const RT* __re
     // y = L^-1 b: partials into sy, then y into sb
     for (int t = threadIdx.x; t < G * n; t += blockDim.x) {
       const int i = t / G, g = t % G;
-      double acc = 0.0;
-#pragma unroll 4
-      for (int j = g; j < n; j += G) acc += C.LinvT[(size_t)j * n + i] * sb[j];
-      sy[t] = acc;
+      sy[t] = column_dot<G>(C.LinvT, sb, n, i, g);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -533,10 +550,7 @@ __device__ __forceinline__ void coarse_apply(const CoarseView& C, const RT* __re
     // x = L^-T y
     for (int t = threadIdx.x; t < G * n; t += blockDim.x) {
       const int i = t / G, g = t % G;
-      double acc = 0.0;
-#pragma unroll 4
-      for (int j = g; j < n; j += G) acc += C.Linv[(size_t)j * n + i] * sb[j];
-      sy[t] = acc;
+      sy[t] = column_dot<G>(C.Linv, sb, n, i, g);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -795,7 +809,16 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         VT* b = lds_at<VT>(lds, I.c);
         for (int J = tid; J < I.n; J += bd) {
           VT acc = 0;
-          for (int k = moff[J]; k < moff[J + 1]; ++k) acc += sv[members[k]];
+          int k = moff[J];
+          const int k1 = moff[J + 1];
+          for (; k + 8 <= k1; k += 8) {  // eight members' loads in flight, added in order
+            VT v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = sv[members[k + q]];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += v[q];
+          }
+          for (; k < k1; ++k) acc += sv[members[k]];
           b[J] = acc;
         }
         break;
