@@ -22,7 +22,9 @@ interval it approximates on; readings taken here:
   approximation is positive on (0, 1] only for a > 3 - 2 sqrt(2) = 0.1716, and
   CG needs the cycle to stay positive definite (for t < a the polynomial is
   larger still, so a clamped interval keeps it positive on the whole spectrum).  Levels are treated from the
-  coarsest up (B_l needs a_{l+1}).  The start vector is counter-based:
+  coarsest up (B_l needs a_{l+1}).  If the iterate w = (I - B_l A_l) v has no
+  positive A-norm (it vanishes when the cycle solves v's equation exactly) the
+  iteration stops with the quotient it has: there is nothing left to power.  The start vector is counter-based:
   v_i = 2 u(splitmix64(2^40 l + i)) - 1 with u(z) = (z >> 11) 2^-53, splitmix64
   as published by Steele, Lea and Flood (one output of the generator whose
   state is the argument).

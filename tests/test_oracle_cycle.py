@@ -5,11 +5,13 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 import inputs
 import oracle
 from oracle import spectral
+from oracle.cycle import fcg_fixed
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -132,6 +134,99 @@ def test_fcg_with_fixed_preconditioner_is_pcg():
     assert info == 0 and res.converged
     assert abs(res.iters - count[0]) <= 1
     np.testing.assert_allclose(res.x, x, rtol=1e-6, atol=1e-9)
+
+
+def test_fcg_restart_window_is_restarted_pcg():
+    """Section 4 restarts the outer iteration every five iterations.  With a
+    fixed SPD preconditioner, flexible CG whose stored directions are cleared
+    once five are held is preconditioned CG restarted from its current iterate
+    every five iterations: scipy's cg run five iterations at a time from the
+    previous iterate gives the same iterates, one by one, and the same count.
+    (Without the restart the sixth iterate already differs by ~20 %.)"""
+    g = inputs.grid2d(24)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d,
+                               oracle.Params(degree=3, restart=5, max_iter=2000))
+    A = sp.csr_matrix(h.levels[0].dense())
+    Dinv = 1.0 / A.diagonal()
+    f = inputs.rhs(g.n, 3)
+    mine = []
+    res = oracle.fcg(h, f, precond=lambda r: Dinv * r, callback=lambda x: mine.append(x.copy()))
+    assert res.converged and res.iters == len(mine) > 100
+    M = spla.LinearOperator(A.shape, matvec=lambda r: Dinv * r)
+    ref, x = [], np.zeros(g.n)
+    while len(ref) < len(mine):
+        x, _ = spla.cg(A, f, x0=x, rtol=0.0, atol=0.0, maxiter=5, M=M, callback=lambda xk: ref.append(xk.copy()))
+    for k, (a, b) in enumerate(zip(mine, ref)):
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b), k
+    r0 = np.linalg.norm(f)
+    first = next(k + 1 for k, xk in enumerate(ref) if np.linalg.norm(f - A @ xk) <= 1e-8 * r0)
+    assert first == res.iters
+
+
+def _three_level(N=8):
+    g = inputs.grid2d(N)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d,
+                               oracle.Params(degree=3, agg_size=4, coarse_max=5))
+    assert h.L == 2
+    return g, h
+
+
+def _dense_two_level(h, l):
+    A = h.levels[l].dense()
+    P = spectral.prolongator(h.aggs[l], h.levels[l + 1].n)
+    R = spectral.smoother_matrix(A, h.polys[l])
+    return A, P, R, spectral.two_level(A, P, R)[1]
+
+
+def test_inner_fcg_two_steps_is_krylov_minimiser():
+    """Section 4 applies flexible CG recursively to the coarse equations, two
+    steps per level (W-cycle).  On a three-level hierarchy Kcycle(1) is the
+    linear two-level B_1 of Section 3 (exact coarsest solve), so two steps from
+    zero give the A_1-norm minimiser of the error over span{B_1 b, B_1 A_1 B_1 b},
+    computed densely; and Kcycle(0) is smoothing, that minimiser on the
+    restricted residual, prolongation and smoothing again, composed densely."""
+    g, h = _three_level()
+    A1, _, _, B1 = _dense_two_level(h, 1)
+    rng = np.random.default_rng(7)
+
+    def minimiser(b):
+        V = np.stack([B1 @ b, B1 @ A1 @ B1 @ b], axis=1)
+        return V @ np.linalg.solve(V.T @ A1 @ V, V.T @ b)
+
+    for _ in range(3):
+        b = rng.standard_normal(h.levels[1].n)
+        np.testing.assert_allclose(oracle.kcycle(h, 1, b), B1 @ b, rtol=1e-12, atol=1e-13)
+        x = fcg_fixed(h, 1, b, 2)
+        xs = minimiser(b)
+        assert np.abs(x - xs).max() <= 1e-11 * np.abs(xs).max()
+    A0, P0, R0, _ = _dense_two_level(h, 0)
+    r = rng.standard_normal(g.n)
+    x = R0 @ r
+    x = x + P0 @ minimiser(P0.T @ (r - A0 @ x))
+    x = x + R0 @ (r - A0 @ x)
+    z = oracle.kcycle(h, 0, r)
+    assert np.abs(z - x).max() <= 1e-11 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("N,agg,tol", [(32, 4, 1e-15), (48, 16, 3e-15), (32, 4, 1e-10), (48, 16, 1e-13)])
+def test_true_residual_confirms_the_stopping_test(N, agg, tol):
+    """A pass of the recursive residual is confirmed on the true residual: every
+    converged solve has ||f - A x|| <= tol ||f|| (dense product here), and at
+    tolerances near the rounding floor, where the recursive residual runs ahead
+    of the true one, the true residual replaces it and the iteration still
+    converges."""
+    g = inputs.grid2d(N)
+    h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d,
+                               oracle.Params(degree=3, agg_size=agg, tol=tol, max_iter=80))
+    f = inputs.rhs(g.n, 9)
+    res = oracle.fcg(h, f)
+    A = h.levels[0].dense()
+    assert res.converged
+    assert np.linalg.norm(f - A @ res.x) <= tol * np.linalg.norm(f)
+    if tol < 1e-14:
+        assert res.replacements >= 1
+    else:
+        assert res.replacements == 0
 
 
 @pytest.mark.parametrize("N,m,agg", [(32, 3, 4), (40, 4, 8), (24, 5, 16)])

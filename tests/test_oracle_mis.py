@@ -83,6 +83,16 @@ def test_nearest_owner_and_connected_aggregates(make):
     D = _hops(lvl)
     dmin = D[:, S].min(axis=1)
     assert np.all(D[np.arange(lvl.n), owner] == dmin)             # a nearest set vertex
+    # ties between set vertices at the same distance go to the smallest index
+    # (brute force over the all-pairs hop distances)
+    Sa = np.asarray(S)
+    ties = 0
+    for v in range(lvl.n):
+        cand = Sa[D[v, Sa] == dmin[v]]
+        ties += len(cand) > 1
+        assert owner[v] == cand.min()
+    if not g.name.startswith("random"):  # meshes and geometric graphs have equidistant set vertices
+        assert ties > 0
     ids, nc = mis_aggregate(lvl, 4)
     assert nc == len(S) and set(np.unique(ids)) == set(range(nc))
     A = csr_matrix((np.ones(lvl.nnz), lvl.col, lvl.row_ptr), shape=(lvl.n, lvl.n))
