@@ -169,13 +169,22 @@ typedef struct amg_hier amg_hier;
 
 /* Per-solve report.  rel_res is the ratio the stopping test uses (recursively
  * updated residual norms, or A-norms of the error under AMG_STOP_ENERGY);
- * rel_res_true = ||f - A u||_2 / ||f - A u0||_2 recomputed in FP64 at the end. */
+ * rel_res_true = ||f - A u||_2 / ||f - A u0||_2 recomputed in FP64 at the end.
+ * Under AMG_STOP_RESIDUAL a pass of the recursive test is confirmed on the
+ * true FP64 residual, which then replaces the recursive one: AMG_OK means
+ * rel_res_true <= tol; if it is above tol the outer iteration restarts from
+ * it (counted in `replacements`) and goes on.
+ * iters counts the outer iterations applied to u; test_iter is the iteration
+ * whose stopping test passed (iters - 1 when the single solve had already
+ * queued the next iteration before reading the test; = iters otherwise). */
 typedef struct {
   int32_t status;
   int32_t iters;
   double rel_res;
   double rel_res_true;
   double solve_ms;
+  int32_t test_iter;
+  int32_t replacements;
 } amg_info;
 
 /* Hierarchy description (sizes, complexities and setup timings). */

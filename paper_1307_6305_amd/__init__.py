@@ -88,7 +88,14 @@ class amg_info(ctypes.Structure):
         ("rel_res", ctypes.c_double),
         ("rel_res_true", ctypes.c_double),
         ("solve_ms", ctypes.c_double),
+        ("test_iter", ctypes.c_int32),
+        ("replacements", ctypes.c_int32),
     ]
+
+
+def _info_dict(i: amg_info) -> dict:
+    return {"status": i.status, "iters": i.iters, "rel_res": i.rel_res, "rel_res_true": i.rel_res_true,
+            "solve_ms": i.solve_ms, "test_iter": i.test_iter, "replacements": i.replacements}
 
 
 class amg_hier_desc(ctypes.Structure):
@@ -362,8 +369,7 @@ def amg_solve(h: Hierarchy, f, u, stream=None, check: bool = False) -> dict:
                                     ctypes.byref(info))
     if code in (AMG_ERR_ARG, AMG_ERR_DEVICE, AMG_ERR_NOMEM) or (check and code != AMG_OK):
         _check(code, "amg_solve")
-    return {"status": info.status, "iters": info.iters, "rel_res": info.rel_res,
-            "rel_res_true": info.rel_res_true, "solve_ms": info.solve_ms}
+    return _info_dict(info)
 
 
 def amg_solve_batch(hs, fs, us, stream=None, check: bool = False) -> list:
@@ -379,8 +385,7 @@ def amg_solve_batch(hs, fs, us, stream=None, check: bool = False) -> list:
     code = load_library().amg_solve_batch(nb, H, F, U, _stream(stream), infos)
     if code in (AMG_ERR_ARG, AMG_ERR_DEVICE, AMG_ERR_NOMEM) or (check and code != AMG_OK):
         _check(code, "amg_solve_batch")
-    return [{"status": i.status, "iters": i.iters, "rel_res": i.rel_res, "rel_res_true": i.rel_res_true,
-             "solve_ms": i.solve_ms} for i in infos]
+    return [_info_dict(i) for i in infos]
 
 
 def amg_serve_cfg_default(params: amg_params | None = None, **overrides) -> amg_serve_cfg:

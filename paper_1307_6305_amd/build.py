@@ -10,6 +10,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -40,9 +41,9 @@ def _run(cmd):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source and link ``libamg.so``; returns its path."""
+    """Compile every source (in parallel) and link ``libamg.so``; returns its path."""
     os.makedirs(OBJ, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src, tool, extra in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(OBJ, src + ".o")
@@ -52,8 +53,12 @@ def build(verbose: bool = False) -> str:
             cmd = [HIPCC] + HIP_FLAGS + COMMON + extra + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "6"))))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

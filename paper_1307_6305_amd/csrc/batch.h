@@ -15,7 +15,9 @@ struct ItemState {
   int active;  // 1 while the item iterates
   int iter;    // completed outer iterations
   int status;  // AMG_OK, AMG_ERR_MAXIT or AMG_ERR_BREAKDOWN
-  int pad;
+  int pos;     // window position of the next outer iteration
+  int check;   // 1: the recursive residual passed; the true one decides
+  int replaced;  // recursive residuals replaced by the true one
   double rr0, rr, rrt;
 };
 

@@ -45,6 +45,7 @@ enum BatchOpType : int {
   B_O_SPMV,      // q_j = A p_j (FP64), (p_j, q_j), (p_j, r)
   B_O_XR,        // u += alpha p_j, r -= alpha q_j, (r, r); convergence
   B_O_TRUE,      // true residual (f - A u, f - A u)
+  B_O_CONFIRM,   // items whose recursive residual passed: r = f - A u, (r, r)
 };
 
 // Rows per tile (= block) of a batched step: one wavefront, so that many
@@ -165,7 +166,8 @@ __device__ __forceinline__ void batch_mat_tile(const BatchOp& op, int tile, doub
       break;
     }
     case B_O_RESID:
-    case B_O_TRUE: {
+    case B_O_TRUE:
+    case B_O_CONFIRM: {
       double v[1] = {0.0};
       int row = -1;
       if (slive) {
@@ -178,7 +180,7 @@ __device__ __forceinline__ void batch_mat_tile(const BatchOp& op, int tile, doub
       break;
     }
     case B_O_SPMV: {
-      const int j = op.st->iter % op.i0;
+      const int j = op.st->pos;
       double v[2] = {0.0, 0.0};
       int row = -1;
       if (slive)
@@ -249,7 +251,7 @@ __device__ __forceinline__ void batch_vec_tile(const BatchOp& op, int tile, doub
       break;
     }
     case B_O_MULTIDOT: {
-      const int j = op.st->iter % op.i0;
+      const int j = op.st->pos;
       double v[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = 0.0;
@@ -264,7 +266,7 @@ __device__ __forceinline__ void batch_vec_tile(const BatchOp& op, int tile, doub
     }
     case B_O_P: {
       if (!live) break;
-      const int j = op.st->iter % op.i0;
+      const int j = op.st->pos;
       double acc = (double)((const VT*)op.a)[r];
 #pragma unroll
       for (int i = 0; i < 8; ++i)
@@ -273,7 +275,7 @@ __device__ __forceinline__ void batch_vec_tile(const BatchOp& op, int tile, doub
       break;
     }
     case B_O_XR: {
-      const int j = op.st->iter % op.i0;
+      const int j = op.st->pos;
       double v[1] = {0.0};
       if (live) {
         const double alpha = fcg_alpha(op.scal, S_RHOW + j, S_GAM);
@@ -294,7 +296,16 @@ __device__ __forceinline__ void batch_vec_tile(const BatchOp& op, int tile, doub
 
 bool is_matrix_step(int type) {
   return type == B_CHEB_FIRST || type == B_CHEB_NEXT || type == B_RESIDUAL || type == B_SPMV_DOTS ||
-         type == B_O_RESID || type == B_O_TRUE || type == B_O_SPMV;
+         type == B_O_RESID || type == B_O_TRUE || type == B_O_SPMV || type == B_O_CONFIRM;
+}
+
+// Whether an op runs for an item in the state S: the start and the final
+// true residual always; the confirmation only after a pass of the recursive
+// test; every other step while the item iterates.
+__device__ __forceinline__ bool op_runs(int type, const ItemState& S) {
+  if (type == B_O_RESID || type == B_O_TRUE) return true;
+  if (type == B_O_CONFIRM) return S.active && S.check;
+  return S.active;
 }
 
 // One step of the cycle for every item of the launch.  Block b works on tile
@@ -307,7 +318,7 @@ __global__ void __launch_bounds__(kBatchRows * 4) k_batch_mat(const BatchOp* __r
   __shared__ double stage[2 * kBatchRows];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const BatchOp& op = ops[block_op[b]];
-  if (!op.st->active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
+  if (!op_runs(op.type, *op.st)) return;
   batch_mat_tile<VT, MT>(op, b - op.first_block, partials, red, stage);
 }
 
@@ -352,7 +363,7 @@ __global__ void __launch_bounds__(kFinishThreads) k_batch_finish(const BatchOp* 
   __shared__ double red[16 * 8];
   const BatchOp& op = ops[fin[blockIdx.x]];
   ItemState& S = *op.st;
-  if (!S.active && op.type != B_O_RESID && op.type != B_O_TRUE) return;
+  if (!op_runs(op.type, S)) return;
   double acc[8];
   sum_partials<8>(partials + (size_t)op.part * 8, op.blocks, acc, red);
   if (threadIdx.x != 0) return;
@@ -365,12 +376,12 @@ __global__ void __launch_bounds__(kFinishThreads) k_batch_finish(const BatchOp* 
       op.scal[op.s0.s[1]] = acc[1];
       break;
     case B_O_MULTIDOT: {
-      const int j = S.iter % op.i0;
+      const int j = S.pos;
       for (int i = 0; i < j; ++i) op.scal[S_DOTS + i] = acc[i];
       break;
     }
     case B_O_SPMV: {
-      const int j = S.iter % op.i0;
+      const int j = S.pos;
       op.scal[S_RHOW + j] = acc[0];
       op.scal[S_GAM] = acc[1];
       break;
@@ -379,6 +390,9 @@ __global__ void __launch_bounds__(kFinishThreads) k_batch_finish(const BatchOp* 
       S.rr0 = acc[0];
       S.rr = acc[0];
       S.iter = 0;
+      S.pos = 0;
+      S.check = 0;
+      S.replaced = 0;
       S.status = AMG_OK;
       S.active = acc[0] > 0.0 ? 1 : 0;
       if (S.active) atomicAdd(ctl.nactive, 1);
@@ -387,20 +401,44 @@ __global__ void __launch_bounds__(kFinishThreads) k_batch_finish(const BatchOp* 
       S.rrt = acc[0];
       break;
     case B_O_XR: {
-      const int j = S.iter % op.i0;
+      const int j = S.pos;
       const double rho = op.scal[S_RHOW + j];
       S.iter += 1;
+      S.pos = j + 1 == op.i0 ? 0 : j + 1;
       S.rr = acc[0];
       bool stop = false;
       if (!(rho > 0.0) || !isfinite(rho)) {
         S.status = AMG_ERR_BREAKDOWN;
         stop = true;
       } else if (acc[0] <= ctl.tol * ctl.tol * S.rr0) {
-        S.status = AMG_OK;
-        stop = true;
+        S.check = 1;  // the confirmation step decides on the true residual
       } else if (S.iter >= ctl.max_iter) {
         S.status = AMG_ERR_MAXIT;
         stop = true;
+      }
+      if (stop) {
+        S.active = 0;
+        atomicSub(ctl.nactive, 1);
+      }
+      break;
+    }
+    case B_O_CONFIRM: {
+      // r = f - A u has replaced the recursive residual: stop when it passes,
+      // else restart the window from it
+      S.check = 0;
+      S.rr = acc[0];
+      S.rrt = acc[0];
+      bool stop = false;
+      if (acc[0] <= ctl.tol * ctl.tol * S.rr0) {
+        S.status = AMG_OK;
+        stop = true;
+      } else {
+        S.pos = 0;
+        S.replaced += 1;
+        if (S.iter >= ctl.max_iter) {
+          S.status = AMG_ERR_MAXIT;
+          stop = true;
+        }
       }
       if (stop) {
         S.active = 0;
@@ -898,6 +936,7 @@ struct Builder {
     step(pp, false);
     step(sp, true);
     step(xr, true);
+    outer_residual(B_O_CONFIRM, true);
   }
 };
 
@@ -1178,6 +1217,8 @@ int32_t solve_batch(int nb, amg_hier* const* hs, const double* const* f, double*
       infos[i].rel_res = rho0 > 0 ? std::sqrt(S.rr) / rho0 : 0.0;
       infos[i].rel_res_true = rho0 > 0 ? std::sqrt(S.rrt) / rho0 : 0.0;
       infos[i].solve_ms = ms;
+      infos[i].test_iter = S.iter;
+      infos[i].replacements = S.replaced;
     }
     if (S.status != AMG_OK && worst == AMG_OK) worst = S.status;
   }

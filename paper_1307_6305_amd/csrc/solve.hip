@@ -1085,8 +1085,9 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
   }
   const double ref0 = energy ? en0 : rho0;
   int32_t status = AMG_OK;
-  int it = 0;
+  int it = 0, test_it = 0, replaced = 0;
   double rel = ref0 > 0.0 ? 1.0 : 0.0;
+  bool true_known = false;  // scal[S_RRT] holds ||f - A u||^2 of the returned u
   if (ref0 > 0.0) {
     const bool use_graph = h->p.use_graph != 0;
     if (use_graph && (!h->graphs_ready || h->graph_u != u)) {
@@ -1096,25 +1097,38 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
     for (hipEvent_t& e : h->iter_ev)
       if (!e) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     const int R = h->p.restart;
+    int pos_of[2] = {0, 0};  // window position of iteration k at [k & 1]
+    int next_pos = 0;
     auto launch = [&](int k) -> int32_t {
+      const int j = next_pos;
+      pos_of[k & 1] = j;
+      next_pos = j + 1 == R ? 0 : j + 1;
       if (use_graph) {
-        AMG_HIP(hipGraphLaunch(h->iter_exec[(k - 1) % R], s));
+        AMG_HIP(hipGraphLaunch(h->iter_exec[j], s));
       } else {
-        AMG_TRY(E.outer_iter((k - 1) % R, u));
+        AMG_TRY(E.outer_iter(j, u));
       }
       AMG_HIP(hipEventRecord(h->iter_ev[k & 1], s));
       return AMG_OK;
     };
+    auto pub = [&](int k) { return h->host_scal + kPubBase + 2 * pos_of[k & 1]; };
     auto ratio = [&](int k) {
-      const double rr = h->host_scal[kPubBase + 2 * ((k - 1) % R)];
+      const double rr = pub(k)[0];
       return energy ? std::sqrt(std::max(rr, 0.0)) / en0 : std::sqrt(rr) / rho0;
+    };
+    auto broke = [&](int k) {
+      const double rho = pub(k)[1];
+      return !(rho > 0.0) || !std::isfinite(rho);
     };
     // Iteration k + 1 is queued before the test of iteration k is read when
     // the ratio predicted for k (the last one times the last reduction) is
     // above kAheadFactor x tol, so that the device does not idle while the
     // host reads; if the test passes at k after all, the queued iteration
-    // still runs and is counted.  (With a window of one position both would
-    // publish into the same slot.)
+    // still runs and is counted (test_iter keeps k).  (With a window of one
+    // position both would publish into the same slot.)
+    // A pass of the recursive residual test is confirmed on the true residual
+    // r = f - A u, which replaces the recursive one; if it is still above
+    // tol, the window restarts from it.
     status = AMG_ERR_MAXIT;
     AMG_TRY(launch(1));
     int queued = 1;
@@ -1126,15 +1140,47 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
         queued = it + 1;
       }
       AMG_HIP(hipEventSynchronize(h->iter_ev[it & 1]));
-      const double rho = h->host_scal[kPubBase + 2 * ((it - 1) % R) + 1];
-      if (!(rho > 0.0) || !std::isfinite(rho)) {
+      if (broke(it)) {
         status = AMG_ERR_BREAKDOWN;
         break;
       }
       rel = ratio(it);
       if (rel <= h->p.tol) {
-        status = AMG_OK;
-        break;
+        test_it = it;
+        if (queued > it) {
+          // the iteration queued ahead ran too: its update is in u
+          AMG_HIP(hipEventSynchronize(h->iter_ev[queued & 1]));
+          it = queued;
+          if (broke(it)) {
+            status = AMG_ERR_BREAKDOWN;
+            break;
+          }
+          rel = ratio(it);
+        }
+        if (energy) {
+          status = AMG_OK;
+          break;
+        }
+        AMG_TRY(E.residual64(f, u, h->r, S_RRT));
+        AMG_HIP(hipMemcpyAsync(h->host_scal + 2, h->scal + S_RRT, sizeof(double), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        true_known = true;
+        const double rt = std::sqrt(h->host_scal[2]) / rho0;
+        if (rt <= h->p.tol) {
+          status = AMG_OK;
+          break;
+        }
+        // restart from the true residual
+        true_known = false;
+        rel = rt;
+        ++replaced;
+        next_pos = 0;
+        last = before = 1.0;
+        if (it < h->p.max_iter) {
+          AMG_TRY(launch(it + 1));
+          queued = it + 1;
+        }
+        continue;
       }
       before = last;
       last = rel;
@@ -1145,22 +1191,26 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
     }
     if (it > h->p.max_iter) it = h->p.max_iter;
     if (queued > it) {
-      // the iteration queued ahead ran too: report it
+      // an iteration queued ahead of a failing test ran too: report it
       AMG_HIP(hipEventSynchronize(h->iter_ev[queued & 1]));
       it = queued;
-      if (status == AMG_OK) rel = ratio(it);
+      true_known = false;
     }
   }
-  // true FP64 residual of the returned u
-  AMG_TRY(E.residual64(f, u, h->tmp, S_RRT));
-  AMG_HIP(hipMemcpyAsync(h->host_scal + 2, h->scal + S_RRT, sizeof(double), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  if (!true_known) {
+    // true FP64 residual of the returned u
+    AMG_TRY(E.residual64(f, u, h->tmp, S_RRT));
+    AMG_HIP(hipMemcpyAsync(h->host_scal + 2, h->scal + S_RRT, sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+  }
   if (info) {
     info->status = status;
     info->iters = it;
     info->rel_res = rel;
     info->rel_res_true = rho0 > 0.0 ? std::sqrt(h->host_scal[2]) / rho0 : 0.0;
     info->solve_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    info->test_iter = status == AMG_OK ? test_it : it;
+    info->replacements = replaced;
   }
   return status;
 }

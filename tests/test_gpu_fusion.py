@@ -45,7 +45,7 @@ def test_fused_equals_unfused(amg, name, prec, tail_rows):
         h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
         u = torch.zeros_like(f)
         info = amg.amg_solve(h, f, u)
-        assert info["status"] == 0 and info["rel_res_true"] <= 1.05e-8, info
+        assert info["status"] == 0 and info["rel_res_true"] <= 1e-8, info
         z = torch.zeros_like(r)
         amg.amg_apply_cycle(h, r, z)
         torch.cuda.synchronize()

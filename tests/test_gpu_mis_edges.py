@@ -99,7 +99,7 @@ def test_mis_edge_case(amg, name):
     info = amg.amg_solve(h, torch.tensor(f, device="cuda"), u)
     res = oracle.fcg(ho, f)
     assert info["status"] == 0 and res.converged, info
-    assert info["rel_res_true"] <= p.tol * 1.05
+    assert info["rel_res_true"] <= p.tol
     if res.iters <= 60:
         assert abs(info["iters"] - res.iters) <= 1, (info["iters"], res.iters)
     # else: a slowly converging case (the hub), where rounding alone moves the

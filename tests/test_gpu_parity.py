@@ -154,7 +154,7 @@ def test_solve_matches_oracle(amg, name):
     res = oracle.fcg(ho, f)
     assert info["status"] == 0 and res.converged
     assert abs(info["iters"] - res.iters) <= 1, (info, res.iters)
-    assert info["rel_res_true"] <= p.tol * 1.05
+    assert info["rel_res_true"] <= p.tol
     uo = res.x
     lo = ho.levels[0]
     e = u.cpu().numpy() - uo
@@ -192,7 +192,7 @@ def test_nonzero_initial_guess_and_zero_rhs(amg):
     u = _t(u0)
     info = amg.amg_solve(h, _t(f), u)
     res = oracle.fcg(ho, f, u0)
-    assert abs(info["iters"] - res.iters) <= 1 and info["rel_res_true"] <= 1.05e-8
+    assert abs(info["iters"] - res.iters) <= 1 and info["rel_res_true"] <= 1e-8
     z = torch.zeros(g.n, dtype=torch.float64, device="cuda")
     info = amg.amg_solve(h, torch.zeros_like(z), z)
     assert info["iters"] == 0 and info["status"] == 0 and float(z.abs().max()) == 0.0
@@ -287,7 +287,7 @@ def test_mixed_precision_solve(amg, make, kw):
     u = torch.zeros_like(r)
     info = amg.amg_solve(h, r, u)
     res = oracle.fcg(ho, f)
-    assert info["status"] == 0 and info["rel_res_true"] <= 1.05e-8
+    assert info["status"] == 0 and info["rel_res_true"] <= 1e-8
     assert info["iters"] <= res.iters + 3
     lo = ho.levels[0]
     e = u.cpu().numpy() - res.x
@@ -306,7 +306,7 @@ def test_hash_ties_fewer_rounds(amg):
         f = _t(inputs.rhs(g.n, 3))
         u = torch.zeros_like(f)
         info = amg.amg_solve(h, f, u)
-        assert info["status"] == 0 and info["rel_res_true"] <= 1.05e-8
+        assert info["status"] == 0 and info["rel_res_true"] <= 1e-8
         h.close()
     assert rounds["hash"] * 4 < rounds["index"], rounds
 
@@ -335,4 +335,31 @@ def test_iteration_limit_and_window(amg, restart, use_graph):
     info = amg.amg_solve(h, _t(f), u)
     res = oracle.fcg(ho, f)
     assert info["status"] == 0 and abs(info["iters"] - res.iters) <= 1
-    assert info["rel_res_true"] <= p.tol * 1.05
+    assert info["rel_res_true"] <= p.tol
+
+
+@pytest.mark.parametrize("N,agg,tol,use_graph", [(32, 4, 1e-15, 1), (48, 16, 3e-15, 0), (48, 16, 3e-15, 1)])
+def test_true_residual_replaces_recursive(amg, N, agg, tol, use_graph):
+    """Near the rounding floor the recursive residual passes the test before
+    the true one does: the solve confirms on the true FP64 residual, restarts
+    from it, and returns OK only with ||f - A u|| <= tol ||f||, as the oracle
+    does (same number of replacements, iterations within two); the batched
+    form confirms the same way per item."""
+    g = inputs.grid2d(N)
+    p = amg.amg_params_default(degree=3, agg_size=agg, tol=tol, max_iter=80, use_graph=use_graph)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    ho = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, _oracle_params(amg, p))
+    f = inputs.rhs(g.n, 9)
+    res = oracle.fcg(ho, f)
+    assert res.converged and res.replacements >= 1
+    u = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    info = amg.amg_solve(h, _t(f), u)
+    assert info["status"] == 0 and info["rel_res_true"] <= tol, info
+    assert info["replacements"] >= 1 and abs(info["iters"] - res.iters) <= 2, (info, res.iters)
+    A = oracle.apply_A(ho.levels[0], u.cpu().numpy())
+    assert np.linalg.norm(f - A) <= tol * np.linalg.norm(f)
+    ub = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    bi = amg.amg_solve_batch([h], [_t(f)], [ub])[0]
+    assert bi["status"] == 0 and bi["rel_res_true"] <= tol and bi["replacements"] >= 1, bi
+    assert abs(bi["iters"] - res.iters) <= 2, (bi, res.iters)
+    h.close()
