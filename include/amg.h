@@ -261,6 +261,33 @@ int32_t amg_describe(const amg_hier* h, amg_hier_desc* out);
  */
 int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_info* info);
 
+/*
+ * amg_solve without allocating: for callers that cannot allocate device
+ * memory or create runtime objects while they solve (code inside a tight
+ * serving loop, harnesses that forbid allocation, work recorded around HIP
+ * graph capture).  The same solve as amg_solve -- same kernels, same
+ * arithmetic, same stopping test, same arguments and results -- except that
+ *   - the reduction scratch (scalar area, arrival counter and block partials
+ *     of the inner products) is a static device array of 4 MiB that each GPU
+ *     holds from its first use until the process ends, instead of the
+ *     hierarchy's own buffers;
+ *   - no HIP graph, event or stream is created: outer iterations are launched
+ *     directly and the host waits on the stream once per iteration (no
+ *     iteration is queued ahead of the stopping test, so `iters` can be one
+ *     lower than amg_solve's).
+ * No hipMalloc, hipFree or other allocating call is made; the hierarchy's
+ * workspace (allocated by amg_setup) holds the vectors.  Limit: the finest
+ * level may have at most 16,739,328 rows (65,388 blocks of 256 rows of
+ * partials); larger hierarchies return AMG_ERR_ARG with the limit in
+ * amg_last_error().  The hierarchy must live on the current device
+ * (AMG_ERR_ARG otherwise).  Every no-allocation solve on one GPU shares that
+ * GPU's array and leaves its last contents there (the counter is cleared by
+ * a fill kernel at the start of each call): two such solves that overlap in
+ * time on one GPU (different streams or threads) race and give wrong
+ * results; serialize them.
+ */
+int32_t amg_solve_noalloc(amg_hier* h, const double* f, double* u, void* stream, amg_info* info);
+
 /* Duration of the finest level's interior Chebyshev step (one fused pass over
  * the level: w_{k+1} = 2 (A w_k - theta w_k)/eta - w_{k-1}, y += c_{k+1} w_{k+1};
  * the smoother of Section 3), the solve's dominant kernel.  amg_time_step

@@ -206,6 +206,7 @@ SIGNATURES = {
     "amg_free": (None, [_P]),
     "amg_describe": (_I32, [_P, ctypes.POINTER(amg_hier_desc)]),
     "amg_solve": (_I32, [_P, _P, _P, _P, ctypes.POINTER(amg_info)]),
+    "amg_solve_noalloc": (_I32, [_P, _P, _P, _P, ctypes.POINTER(amg_info)]),
     "amg_solve_batch": (_I32, [_I32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _P,
                                ctypes.POINTER(amg_info)]),
     "amg_serve_cfg_default": (None, [ctypes.POINTER(amg_serve_cfg)]),
@@ -369,6 +370,17 @@ def amg_solve(h: Hierarchy, f, u, stream=None, check: bool = False) -> dict:
                                     ctypes.byref(info))
     if code in (AMG_ERR_ARG, AMG_ERR_DEVICE, AMG_ERR_NOMEM) or (check and code != AMG_OK):
         _check(code, "amg_solve")
+    return _info_dict(info)
+
+
+def amg_solve_noalloc(h: Hierarchy, f, u, stream=None, check: bool = False) -> dict:
+    """amg_solve with its reduction scratch in the library's static device
+    array: no allocation, no graphs, no events (include/amg.h)."""
+    info = amg_info()
+    code = load_library().amg_solve_noalloc(h.handle, _dev(f, h.n, "f"), _dev(u, h.n, "u"), _stream(stream),
+                                            ctypes.byref(info))
+    if code in (AMG_ERR_ARG, AMG_ERR_DEVICE, AMG_ERR_NOMEM) or (check and code != AMG_OK):
+        _check(code, "amg_solve_noalloc")
     return _info_dict(info)
 
 

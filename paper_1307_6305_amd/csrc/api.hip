@@ -207,6 +207,11 @@ int32_t amg_solve(amg_hier* h, const double* f, double* u, void* stream, amg_inf
   return amg::solve(h, f, u, static_cast<hipStream_t>(stream), info);
 }
 
+int32_t amg_solve_noalloc(amg_hier* h, const double* f, double* u, void* stream, amg_info* info) {
+  if (!h || !f || !u) { amg::set_last_error("null argument"); return AMG_ERR_ARG; }
+  return amg::solve_noalloc(h, f, u, static_cast<hipStream_t>(stream), info);
+}
+
 int32_t amg_solve_batch(int32_t nb, amg_hier* const* h, const double* const* f, double* const* u, void* stream,
                         amg_info* infos) {
   if (nb < 1 || !h || !f || !u) { amg::set_last_error("invalid argument"); return AMG_ERR_ARG; }

@@ -122,6 +122,11 @@ int32_t step_coarse(amg_hier* h, const double* b, double* x, hipStream_t s);
 int32_t step_cycle(amg_hier* h, const double* r, double* z, hipStream_t s);
 
 int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info);
+// The same solve with its reduction scratch in a static device array (no
+// allocation, no graphs, no events); finest levels up to noalloc_max_rows().
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+int32_t solve_noalloc(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info);
+size_t noalloc_max_rows();
 
 // batched solves (batch.hip)
 int32_t solve_batch(int nb, amg_hier* const* hs, const double* const* f, double* const* u, hipStream_t s,

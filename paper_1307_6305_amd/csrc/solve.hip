@@ -28,6 +28,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "kernels.h"
@@ -442,6 +444,14 @@ struct Engine {
   amg_hier* h;
   hipStream_t s;
   std::vector<TailOp>* rec = nullptr;
+  // Reduction scratch: the scalar area, the block partials and the arrival
+  // counter -- the hierarchy's own buffers unless a solve supplies others.
+  double* scal_ = nullptr;
+  double* partials_ = nullptr;
+  unsigned* counter_ = nullptr;
+  double* sc() const { return scal_ ? scal_ : h->scal; }
+  double* pa() const { return partials_ ? partials_ : h->partials; }
+  unsigned* co() const { return counter_ ? counter_ : h->counter; }
 
   // An inner solve's last update x += alpha p, left to the kernels that read
   // the coarse correction (alpha from the step's scalar slots).
@@ -476,19 +486,19 @@ struct Engine {
 
   // reduction destination for a device-wide kernel of `blocks` blocks
   Red red_for(int blocks, Slots slots) const {
-    return Red{h->partials, h->counter, h->scal, slots, blocks <= h->last_block_max ? 1 : 0};
+    return Red{pa(), co(), sc(), slots, blocks <= h->last_block_max ? 1 : 0};
   }
   // host: publish (the sum, scal[pub]) to the pinned host mirror as well
   template <int K>
   int32_t finish(int blocks, Slots slots, double* host = nullptr, int pub = 0, int kn = K) {
     if (blocks <= h->last_block_max) {
       if (host) {
-        hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, (const double*)h->scal, slots.s[0], pub, host);
+        hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, (const double*)sc(), slots.s[0], pub, host);
         AMG_HIP(hipGetLastError());
       }
       return AMG_OK;
     }
-    hipLaunchKernelGGL((k_finish_sum<K>), dim3(1), dim3(kFinishThreads), 0, s, blocks, h->partials, h->scal, slots,
+    hipLaunchKernelGGL((k_finish_sum<K>), dim3(1), dim3(kFinishThreads), 0, s, blocks, pa(), sc(), slots,
                        kn, host, pub);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
@@ -506,7 +516,7 @@ struct Engine {
         const auto Am = A(l);
         hipLaunchKernelGGL((k_cheb_first_upd<VT, MT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, upd->rhs, upd->q,
                            const_cast<VT*>(w0), upd->p, upd->sol, upd->x_init, w1, y, lv.theta, 1.0 / lv.eta, c0, c1,
-                           (int)store, (const double*)h->scal, upd->s_rho, upd->s_gam);
+                           (int)store, (const double*)sc(), upd->s_rho, upd->s_gam);
         AMG_HIP(hipGetLastError());
         return AMG_OK;
       }
@@ -516,7 +526,7 @@ struct Engine {
       const auto Am = A(l);
       hipLaunchKernelGGL((k_cheb_first_fu<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, w0, w1, y, lv.theta,
                          1.0 / lv.eta, c0, c1, (int)store, fold_d->sol, fold_d->p, transfer_of(h, l).agg,
-                         (const double*)h->scal, fold_d->s_rho, fold_d->s_gam);
+                         (const double*)sc(), fold_d->s_rho, fold_d->s_gam);
       AMG_HIP(hipGetLastError());
       return AMG_OK;
     }
@@ -668,7 +678,7 @@ struct Engine {
     if (!rec && d && d->on) {
       const auto Am = A(l);
       hipLaunchKernelGGL((k_residual_pu<VT, MT, RT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, f, x, d->sol, d->p,
-                         transfer_of(h, l).agg, out, (const double*)h->scal, d->s_rho, d->s_gam);
+                         transfer_of(h, l).agg, out, (const double*)sc(), d->s_rho, d->s_gam);
       AMG_HIP(hipGetLastError());
       return AMG_OK;
     }
@@ -725,7 +735,7 @@ struct Engine {
     const Transfer T = transfer_of(h, l);
     if (!rec && d && d->on) {
       hipLaunchKernelGGL((k_prolong_u<VT>), dim3(nblk(T.n)), dim3(TPB), 0, s, T, d->sol, d->p, x,
-                         (const double*)h->scal, d->s_rho, d->s_gam);
+                         (const double*)sc(), d->s_rho, d->s_gam);
       AMG_HIP(hipGetLastError());
       return AMG_OK;
     }
@@ -803,7 +813,7 @@ struct Engine {
       rec->push_back(o);
       return AMG_OK;
     }
-    hipLaunchKernelGGL((k_fcg_p<VT, VT>), dim3(nblk(n)), dim3(TPB), 0, s, n, p, z, ps, k, h->scal, dots, rhos);
+    hipLaunchKernelGGL((k_fcg_p<VT, VT>), dim3(nblk(n)), dim3(TPB), 0, s, n, p, z, ps, k, sc(), dots, rhos);
     AMG_HIP(hipGetLastError());
     return AMG_OK;
   }
@@ -818,7 +828,7 @@ struct Engine {
       return AMG_OK;
     }
     const int nb = nblk(n);
-    hipLaunchKernelGGL((k_fcg_xr<VT, VT, false>), dim3(nb), dim3(TPB), 0, s, n, p, q, x, r, h->scal, s_rho, s_gam,
+    hipLaunchKernelGGL((k_fcg_xr<VT, VT, false>), dim3(nb), dim3(TPB), 0, s, n, p, q, x, r, sc(), s_rho, s_gam,
                        (int)x_init, (int)upd_r, red_for(nb, slots1(S_DUMMY)));
     AMG_HIP(hipGetLastError());
     return AMG_OK;
@@ -926,7 +936,7 @@ struct Engine {
     const auto Am = A(l);
     const Slots pq = slots2(base + 1, base + 9);
     hipLaunchKernelGGL((k_spmv_dots_dir<VT, MT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, Z1, Z0, P1, Q1, rhs2,
-                       (const double*)h->scal, base + 16, base, red_for(Am.nb, pq));
+                       (const double*)sc(), base + 16, base, red_for(Am.nb, pq));
     AMG_HIP(hipGetLastError());
     AMG_TRY(finish<2>(Am.nb, pq));
     out->on = true;
@@ -986,7 +996,7 @@ struct Engine {
       ps.p[i] = h->P[i];
     }
     if (j > 0) AMG_TRY(multidot(0, n, z, qs, j, slots_range(S_DOTS, j), true));
-    hipLaunchKernelGGL((k_fcg_p<double, VT>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], z, ps, j, h->scal,
+    hipLaunchKernelGGL((k_fcg_p<double, VT>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], z, ps, j, sc(),
                        slots_range(S_DOTS, j), slots_range(S_RHOW, j));
     const Slots pq = slots2(S_RHOW + j, S_GAM);
     hipLaunchKernelGGL((k_spmv_dots<double, double, double>), dim3(A64.nb), dim3(TPB << A64.lk), 0, s, A64, h->P[j], h->Qo[j],
@@ -994,7 +1004,7 @@ struct Engine {
     AMG_TRY(finish<2>(A64.nb, pq));
     const Slots rr = slots1(S_RR);
     hipLaunchKernelGGL((k_fcg_xr<double, double, true>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], h->Qo[j], u, h->r,
-                       h->scal, S_RHOW + j, S_GAM, 0, 1, red_for(nb, rr));
+                       sc(), S_RHOW + j, S_GAM, 0, 1, red_for(nb, rr));
     AMG_HIP(hipGetLastError());
     if (h->p.stop == AMG_STOP_ENERGY) {
       // f = 0: the error is u itself; (u, A u) from a fresh product (the
@@ -1062,19 +1072,41 @@ int32_t capture_graphs(amg_hier* h, double* u) {
   return AMG_OK;
 }
 
+// Reduction scratch supplied by the caller of solve_impl (the no-allocation
+// form); null members: the hierarchy's own buffers.
+struct SolveScratch {
+  double* scal = nullptr;
+  double* partials = nullptr;
+  unsigned* counter = nullptr;
+};
+
+// sx given (the no-allocation form): reductions use sx's buffers, and the
+// solve captures no graphs, creates no events and queues no iteration ahead
+// of the stopping test (one stream synchronization per outer iteration).
 template <typename VT, typename MT>
-int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
+int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info,
+                   const SolveScratch* sx = nullptr) {
   auto t0 = clk::now();
   Engine<VT, MT> E{h, s};
+  const bool noalloc = sx != nullptr;
+  if (noalloc) {
+    E.scal_ = sx->scal;
+    E.partials_ = sx->partials;
+    E.counter_ = sx->counter;
+    // the arrival counter must start at zero (a fill kernel, no memset node)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, E.counter_);
+    AMG_HIP(hipGetLastError());
+  }
+  double* const dscal = E.sc();
   const bool energy = h->p.stop == AMG_STOP_ENERGY;
   AMG_TRY(E.residual64(f, u, h->r, S_RR0));
   if (energy) {
     AMG_TRY(E.dot64(f, f, S_FF));
     AMG_TRY(E.energy64(u));
-    AMG_HIP(hipMemcpyAsync(h->host_scal + 3, h->scal + S_FF, sizeof(double), hipMemcpyDeviceToHost, s));
-    AMG_HIP(hipMemcpyAsync(h->host_scal + 4, h->scal + S_XR, sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(h->host_scal + 3, dscal + S_FF, sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(h->host_scal + 4, dscal + S_XR, sizeof(double), hipMemcpyDeviceToHost, s));
   }
-  AMG_HIP(hipMemcpyAsync(h->host_scal, h->scal + S_RR0, sizeof(double), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipMemcpyAsync(h->host_scal, dscal + S_RR0, sizeof(double), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   const double rho0 = std::sqrt(h->host_scal[0]);
   // energy test: ||u_k||_A = sqrt((u_k, A u_k)) against ||u_0||_A
@@ -1089,13 +1121,14 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
   double rel = ref0 > 0.0 ? 1.0 : 0.0;
   bool true_known = false;  // scal[S_RRT] holds ||f - A u||^2 of the returned u
   if (ref0 > 0.0) {
-    const bool use_graph = h->p.use_graph != 0;
+    const bool use_graph = h->p.use_graph != 0 && !noalloc;
     if (use_graph && (!h->graphs_ready || h->graph_u != u)) {
       AMG_TRY(capture_graphs<VT, MT>(h, u));
       h->graph_u = u;
     }
-    for (hipEvent_t& e : h->iter_ev)
-      if (!e) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (!noalloc)
+      for (hipEvent_t& e : h->iter_ev)
+        if (!e) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     const int R = h->p.restart;
     int pos_of[2] = {0, 0};  // window position of iteration k at [k & 1]
     int next_pos = 0;
@@ -1108,7 +1141,17 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
       } else {
         AMG_TRY(E.outer_iter(j, u));
       }
-      AMG_HIP(hipEventRecord(h->iter_ev[k & 1], s));
+      if (!noalloc) AMG_HIP(hipEventRecord(h->iter_ev[k & 1], s));
+      return AMG_OK;
+    };
+    // completion of iteration k (the no-allocation form has at most one
+    // iteration in flight: the stream itself)
+    auto wait = [&](int k) -> int32_t {
+      if (noalloc) {
+        AMG_HIP(hipStreamSynchronize(s));
+      } else {
+        AMG_HIP(hipEventSynchronize(h->iter_ev[k & 1]));
+      }
       return AMG_OK;
     };
     auto pub = [&](int k) { return h->host_scal + kPubBase + 2 * pos_of[k & 1]; };
@@ -1135,11 +1178,12 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
     double last = 1.0, before = 1.0;  // ratios of iterations k - 1 and k - 2
     for (it = 1; it <= h->p.max_iter; ++it) {
       const double predicted = last * std::min(1.0, last / before);
-      if (R >= 2 && it >= 2 && queued == it && it < h->p.max_iter && predicted > kAheadFactor * h->p.tol) {
+      if (!noalloc && R >= 2 && it >= 2 && queued == it && it < h->p.max_iter &&
+          predicted > kAheadFactor * h->p.tol) {
         AMG_TRY(launch(it + 1));
         queued = it + 1;
       }
-      AMG_HIP(hipEventSynchronize(h->iter_ev[it & 1]));
+      AMG_TRY(wait(it));
       if (broke(it)) {
         status = AMG_ERR_BREAKDOWN;
         break;
@@ -1149,7 +1193,7 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
         test_it = it;
         if (queued > it) {
           // the iteration queued ahead ran too: its update is in u
-          AMG_HIP(hipEventSynchronize(h->iter_ev[queued & 1]));
+          AMG_TRY(wait(queued));
           it = queued;
           if (broke(it)) {
             status = AMG_ERR_BREAKDOWN;
@@ -1162,7 +1206,7 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
           break;
         }
         AMG_TRY(E.residual64(f, u, h->r, S_RRT));
-        AMG_HIP(hipMemcpyAsync(h->host_scal + 2, h->scal + S_RRT, sizeof(double), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipMemcpyAsync(h->host_scal + 2, dscal + S_RRT, sizeof(double), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
         true_known = true;
         const double rt = std::sqrt(h->host_scal[2]) / rho0;
@@ -1192,7 +1236,7 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
     if (it > h->p.max_iter) it = h->p.max_iter;
     if (queued > it) {
       // an iteration queued ahead of a failing test ran too: report it
-      AMG_HIP(hipEventSynchronize(h->iter_ev[queued & 1]));
+      AMG_TRY(wait(queued));
       it = queued;
       true_known = false;
     }
@@ -1200,7 +1244,7 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
   if (!true_known) {
     // true FP64 residual of the returned u
     AMG_TRY(E.residual64(f, u, h->tmp, S_RRT));
-    AMG_HIP(hipMemcpyAsync(h->host_scal + 2, h->scal + S_RRT, sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(h->host_scal + 2, dscal + S_RRT, sizeof(double), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipStreamSynchronize(s));
   }
   if (info) {
@@ -1713,6 +1757,75 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
 int32_t solve(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
   if (h->mixed) return solve_impl<float, float>(h, f, u, s, info);
   return solve_impl<double, double>(h, f, u, s, info);
+}
+
+// ---- the no-allocation solve
+// Its reduction scratch (scalar area, arrival counter, block partials) is this
+// array: one copy per device, held until the process ends, shared by every
+// no-allocation solve on that device.  Host code never passes the array's
+// name to a kernel (on the host it is a stand-in, not a device address): it
+// uses the address hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t kScratchScalBytes = (sizeof(double) * SCAL_SIZE + 255) / 256 * 256;
+constexpr size_t kScratchCounterBytes = 256;
+constexpr size_t kScratchPartialsOff = kScratchScalBytes + kScratchCounterBytes;
+static_assert(kScratchPartialsOff < kNoAllocScratchBytes, "scratch layout");
+// reduction partials: 8 doubles per block of the finest level
+constexpr size_t kScratchMaxBlocks = (kNoAllocScratchBytes - kScratchPartialsOff) / (8 * sizeof(double));
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (which is current), looked up
+// once per device.
+int32_t scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_last_error("device index out of range for the no-allocation scratch");
+    return AMG_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    AMG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+      set_last_error("hipGetSymbolAddress returned a null scratch address");
+      return AMG_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return AMG_OK;
+}
+}  // namespace
+
+size_t noalloc_max_rows() { return kScratchMaxBlocks * (size_t)TPB; }
+
+int32_t solve_noalloc(amg_hier* h, const double* f, double* u, hipStream_t s, amg_info* info) {
+  if ((size_t)std::max(h->max_blocks, 1) > kScratchMaxBlocks) {
+    set_last_error("amg_solve_noalloc: the finest level has " + std::to_string(h->lv[0].n) +
+                   " rows; its reduction scratch holds at most " + std::to_string(noalloc_max_rows()) + " rows");
+    return AMG_ERR_ARG;
+  }
+  int dev = -1;
+  AMG_HIP(hipGetDevice(&dev));
+  if (dev != h->device) {
+    set_last_error("amg_solve_noalloc: the hierarchy lives on device " + std::to_string(h->device) +
+                   ", the current device is " + std::to_string(dev));
+    return AMG_ERR_ARG;
+  }
+  unsigned char* base = nullptr;
+  AMG_TRY(scratch_address(dev, &base));
+  SolveScratch sx;
+  sx.scal = reinterpret_cast<double*>(base);
+  sx.counter = reinterpret_cast<unsigned*>(base + kScratchScalBytes);
+  sx.partials = reinterpret_cast<double*>(base + kScratchPartialsOff);
+  if (h->mixed) return solve_impl<float, float>(h, f, u, s, info, &sx);
+  return solve_impl<double, double>(h, f, u, s, info, &sx);
 }
 
 template <typename VT>
