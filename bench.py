@@ -108,15 +108,113 @@ def cheb_step_bytes(n: int, nnz: int, mixed: bool) -> int:
     return 12 * nnz + 8 * n + 8 * n + 8 * n + 16 * n + 8 * n
 
 
+def copy_bytes(kt: dict) -> int:
+    """Device bytes of one copy of the finest level in the rotating timing:
+    column index + weight per stored entry, the diagonal and three vectors."""
+    vb = kt["value_bytes"]
+    return kt["entries"] * (4 + vb) + kt["rows"] * 4 * vb
+
+
+def rotating_roofline(amg, h, mixed: bool, workload: str, target_bytes: float = 1.5e9) -> dict:
+    """The roofline figure of the dominant kernel: HIP-event time per launch
+    over rotating copies of the finest level (HBM-resident operands) and over
+    one copy (warm: the Infinity Cache holds part of the level)."""
+    warm = amg.amg_time_step(h, reps=200)
+    copies = int(min(64, max(4, -(-target_bytes // copy_bytes(warm)))))
+    reps = max(200, 20 * copies)
+    kt = amg.amg_time_step_rotating(h, reps=reps, copies=copies)
+    bytes_launch = cheb_step_bytes(kt["rows"], kt["nnz"], mixed)
+    achieved = bytes_launch / (kt["avg_ms"] * 1e-3) / 1e9 if kt["avg_ms"] > 0 else 0.0
+    achieved_warm = bytes_launch / (warm["avg_ms"] * 1e-3) / 1e9 if warm["avg_ms"] > 0 else 0.0
+    print(f"[bench] cheb step over {copies} rotating copies ({copies * copy_bytes(kt) / 1e9:.2f} GB): "
+          f"{kt['launches']} launches, avg {kt['avg_ms'] * 1e3:.2f} us -> {achieved:.0f} GB/s; one copy (warm) "
+          f"{warm['avg_ms'] * 1e3:.2f} us -> {achieved_warm:.0f} GB/s", file=sys.stderr, flush=True)
+    return {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": stored_traffic(workload),
+        "kernel": ("k_cheb_next<..., STORE=true, KIND=2> (finest-level three-term step, row operands streamed; "
+                   "the timing instance of the solve's KIND=1 code)") if kt["rows"] >= 1 << 18 else
+                  ("k_cheb_next<..., STORE=true, KIND=3> (finest-level three-term step; the timing instance of the "
+                   "solve's KIND=0 code)"),
+        "bytes_per_launch": bytes_launch,
+        "avg_us": round(kt["avg_ms"] * 1e3, 2),
+        "launches_timed": kt["launches"],
+        "copies": copies,
+        "copies_bytes": copies * copy_bytes(kt),
+        "warm": {"achieved": round(achieved_warm, 1), "frac": round(achieved_warm / HBM_PEAK_GBS, 4),
+                 "avg_us": round(warm["avg_ms"] * 1e3, 2), "launches_timed": warm["launches"],
+                 "note": "one copy back to back: operands partly served by the 256 MB Infinity Cache"},
+    }
+
+
+def oracle_params(params: dict):
+    import oracle
+
+    return oracle.Params(degree=params.get("degree", 4), agg_size=params.get("agg_size", 4),
+                         coarse_max=params.get("coarse_max", 64),
+                         match_key="raw" if params.get("match_key", 0) == 1 else "normalized",
+                         tie_break="hash" if params.get("tie_break", 0) == 1 else "index",
+                         aggregation=params.get("aggregation", "matching"),
+                         mis_distance=params.get("mis_distance", 4), stop=params.get("stop", "residual"))
+
+
+def a_norm_rel_err(oracle, lvl0, u, x) -> float:
+    """||u - x||_A / ||x||_A on the oracle's assembled finest level."""
+    e = u - x
+    return float(np.sqrt(max(e @ oracle.apply_A(lvl0, e), 0.0)) / np.sqrt(x @ oracle.apply_A(lvl0, x)))
+
+
+def oracle_subset(cases, params: dict, sample: str):
+    """The FP64 oracle on a sample of systems the GPU solved: cases are
+    (graph key, graph, f, u from the GPU).  Returns the cpu_baseline record
+    (one thread; value = sampled unknowns / oracle solve seconds) and the
+    largest A-norm error of the GPU solutions against the oracle's."""
+    import oracle
+
+    op = oracle_params(params)
+    hs = {}
+    t_setup = t_solve = 0.0
+    dof = 0
+    errs, iters = [], []
+    for key, g, f, u in cases:
+        if key not in hs:
+            t0 = time.perf_counter()
+            hs[key] = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, op)
+            t_setup += time.perf_counter() - t0
+        ho = hs[key]
+        t0 = time.perf_counter()
+        res = oracle.fcg(ho, f)
+        t_solve += time.perf_counter() - t0
+        errs.append(a_norm_rel_err(oracle, ho.levels[0], u, res.x))
+        iters.append(res.iters)
+        dof += g.n
+    cpu = {
+        "value": dof / t_solve,
+        "unit": "DOF/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": sample,
+        "systems": len(cases),
+        "dof": dof,
+        "setup_s": round(t_setup, 3),
+        "solve_s": round(t_solve, 3),
+        "iters": [min(iters), max(iters)],
+        "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
+    }
+    print(f"[bench] oracle on {len(cases)} sampled systems ({dof} unknowns): setup {t_setup:.1f} s, solve "
+          f"{t_solve:.1f} s, worst A-norm error of the GPU solutions {max(errs):.2e}", file=sys.stderr, flush=True)
+    return cpu, max(errs)
+
+
 def run_cpu_baseline(g, f, params: dict, sample: str, u0=None):
     import oracle
 
-    op = oracle.Params(degree=params.get("degree", 4), agg_size=params.get("agg_size", 4),
-                       coarse_max=params.get("coarse_max", 64),
-                       match_key="raw" if params.get("match_key", 0) == 1 else "normalized",
-                       tie_break="hash" if params.get("tie_break", 0) == 1 else "index",
-                       aggregation=params.get("aggregation", "matching"),
-                       mis_distance=params.get("mis_distance", 4), stop=params.get("stop", "residual"))
+    op = oracle_params(params)
     t0 = time.perf_counter()
     h = oracle.build_hierarchy(g.n, g.row_ptr, g.col, g.w, g.d, op)
     precond = None
@@ -252,6 +350,17 @@ def run_batch(args, amg, torch):
         print(f"[bench] one-at-a-time FP64: {t_single:.3f} s", file=sys.stderr, flush=True)
         for h in h64:
             h.close()
+    # the FP64 oracle on every eighth system (cpu_baseline and the error of
+    # the mixed-precision solutions against FP64)
+    cpu, err = None, None
+    if not args.no_cpu_baseline:
+        sub = list(range(0, count, 8))
+        cases = [(i, graphs[i], inputs.rhs(graphs[i].n, inputs.seed_for(4, 1000 + i)), us[i].cpu().numpy())
+                 for i in sub]
+        cpu, err = oracle_subset(cases, dict(degree=4, agg_size=8),
+                                 sample=f"the oracle's FP64 setup and solve of every eighth system of the batch "
+                                        f"({len(sub)} of {count}), one at a time, single thread; value = sampled "
+                                        f"unknowns / oracle solve seconds")
     out = {
         "metric": METRIC,
         "value": dof * args.steps / elapsed,
@@ -279,7 +388,10 @@ def run_batch(args, amg, torch):
             "setup_s_all": round(t_setup, 2),
             "finest_layouts": chosen,
             "one_at_a_time_fp64": single,
+            "err_A_vs_oracle": err,
+            "err_A_vs_oracle_sample": "max over every eighth system (FP64 oracle)" if err is not None else None,
         },
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     for h in hs:
@@ -424,11 +536,13 @@ def run_serve(args, amg, torch):
         r["arrival_s"] = t
         t += rng.exponential(1.0 / rate)
     results = {}
+    solutions = {}
     for name, mode, params in (("batched_mixed", "batched", pmx), ("sequential_fp64", "sequential", p64),
                                ("batched_mixed_hash_ties", "batched", pmh)):
         cfg = amg.amg_serve_cfg_default(params, mode=mode, realtime=1, hbm_budget_bytes=200e9,
                                         iters_per_step=args.serve_iters_per_step, max_slots=args.serve_slots)
-        comps, st, _ = amg.amg_serve(cfg, reqs, want_u=False)
+        comps, st, sols = amg.amg_serve(cfg, reqs, want_u=True)
+        solutions[name] = sols
         lat = np.array([c["finish_s"] - c["arrival_s"] for c in comps])
         ok = sum(1 for c in comps if c["status"] == 0)
         worst = max(c["rel_res_true"] for c in comps)
@@ -445,6 +559,23 @@ def run_serve(args, amg, torch):
             "peak_bytes": st["peak_bytes"],
         }
         print(f"[bench] {name}: {json.dumps(results[name])}", file=sys.stderr, flush=True)
+    # the FP64 oracle on a sample of completed right-hand sides (requests on
+    # graphs of at most 2.5e5 unknowns, spread over the stream): the error of
+    # each served form's solutions against it
+    cpu = None
+    if not args.no_cpu_baseline:
+        picks = [i for i, r in enumerate(reqs) if r["graph"].n <= 250_000]
+        picks = picks[::max(1, len(picks) // args.serve_oracle_sample)][:args.serve_oracle_sample]
+        for name in results:
+            cases = [(reqs[i]["graph_id"], reqs[i]["graph"], reqs[i]["f"][0], solutions[name][i][0]) for i in picks]
+            c, err = oracle_subset(cases, dict(degree=4, agg_size=8),
+                                   sample=f"the oracle's FP64 setup and solve of the first right-hand side of "
+                                          f"{len(picks)} requests spread evenly over the stream (graphs of at most "
+                                          f"2.5e5 unknowns), single thread; value = sampled unknowns / oracle "
+                                          f"solve seconds")
+            results[name]["err_A_vs_oracle"] = err
+            if cpu is None:
+                cpu = c
     out = {
         "metric": METRIC,
         "value": results["batched_mixed"]["dof_per_s"],
@@ -475,6 +606,7 @@ def run_serve(args, amg, torch):
             "sequential_fp64": results["sequential_fp64"],
             "batched_mixed_hash_ties": results["batched_mixed_hash_ties"],
         },
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -499,6 +631,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-iters-per-step", type=int, default=2)
     ap.add_argument("--serve-slots", type=int, default=512)
+    ap.add_argument("--serve-oracle-sample", type=int, default=12,
+                    help="served form: completed right-hand sides checked against the oracle")
     ap.add_argument("--layout", default=None,
                     help="fixed sliced-ELL layout 'H,K,S' (slice height, lanes per row, sorted 0/1) "
                          "instead of the autotuner")
@@ -588,44 +722,12 @@ def main():
     u_gpu = u.cpu().numpy()
 
     # dominant kernel: the finest level's storing Chebyshev step, timed with
-    # HIP events around back-to-back launches on the solve stream
-    kt = amg.amg_time_step(h, reps=200)
-    bytes_launch = cheb_step_bytes(kt["rows"], kt["nnz"], mixed)
-    achieved = bytes_launch / (kt["avg_ms"] * 1e-3) / 1e9 if kt["avg_ms"] > 0 else 0.0
-    roofline = {
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": stored_traffic(args.workload),
-        "kernel": "k_cheb_next<..., STORE=true, FINE=true> (finest-level three-term step)",
-        "bytes_per_launch": bytes_launch,
-        "avg_us": round(kt["avg_ms"] * 1e3, 2),
-        "launches_timed": kt["launches"],
-    }
-    print(f"[bench] cheb step: {kt['launches']} launches, avg {kt['avg_ms'] * 1e3:.2f} us -> {achieved:.0f} GB/s",
-          file=sys.stderr, flush=True)
-    # the same step one launch at a time, after reading 1 GiB that displaces
-    # the level from the 256 MB Infinity Cache (cold HBM; clean lines, so no
-    # write-backs fall into the timed launch) and after reading 4 MiB (warm;
-    # the same single-launch event overhead)
-    single = {}
-    for name, mib in (("warm", 4), ("cold", 1024)):
-        buf = torch.ones(mib * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
-        sink = torch.zeros(1, dtype=torch.float32, device=dev)
-        torch.cuda.synchronize()
-        tot = 0.0
-        for _ in range(30):
-            torch.sum(buf, dim=0, out=sink[0])
-            tot += amg.amg_time_step(h, reps=1)["avg_ms"]
-        del buf, sink
-        single[name] = tot / 30
-    torch.cuda.synchronize()
-    roofline["single_launch_us"] = {k: round(v * 1e3, 2) for k, v in single.items()}
-    roofline["achieved_cold"] = round(bytes_launch / (single["cold"] * 1e-3) / 1e9, 1)
-    print(f"[bench] cheb step one launch at a time: warm {single['warm'] * 1e3:.2f} us, cold HBM "
-          f"{single['cold'] * 1e3:.2f} us -> {roofline['achieved_cold']:.0f} GB/s", file=sys.stderr, flush=True)
+    # HIP events around back-to-back launches on the solve stream, cycling
+    # over enough copies of the level (matrix, diagonal, vectors) that they
+    # exceed the 256 MB Infinity Cache several times: every launch streams
+    # from HBM.  The same step on one copy (operands left in the Infinity
+    # Cache by the launch before) is reported beside it as the warm figure.
+    roofline = rotating_roofline(amg, h, mixed, args.workload)
 
     if args.copy_probe:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)  # 256 MiB

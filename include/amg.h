@@ -307,6 +307,19 @@ typedef struct {
 
 int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing* timing);
 
+/* The same kernel timed from HBM rather than the 256 MB Infinity Cache: the
+ * library makes copies - 1 device copies of the finest level's sliced-ELL
+ * column indices and weights, its diagonal (and slot map) and the step's
+ * three vectors, runs one untimed round over the copies, then `reps` launches
+ * back to back, launch i on copy i % copies, between two HIP events.  With
+ * the copies together well above the Infinity Cache each launch streams its
+ * operands from HBM.  The copies are freed before returning (this call
+ * allocates and synchronizes `stream`).  1 <= copies <= 64; NOMEM if the
+ * copies do not fit.  The launches are a separate kernel instance of the
+ * same code, so profiles list them on their own. */
+int32_t amg_time_step_rotating(amg_hier* h, int32_t reps, int32_t copies, void* stream,
+                               amg_kernel_timing* timing);
+
 /*
  * Solve nb independent systems together (Section 4's solver for each): item i
  * uses hierarchy h[i], right-hand side f[i] and initial guess / solution u[i]

@@ -217,6 +217,7 @@ SIGNATURES = {
     "amg_server_poll": (_I32, [_P, ctypes.POINTER(amg_completion), _I32, ctypes.c_double, ctypes.POINTER(_I32)]),
     "amg_server_destroy": (_I32, [_P, ctypes.POINTER(amg_serve_stats)]),
     "amg_time_step": (_I32, [_P, _I32, _P, ctypes.POINTER(amg_kernel_timing)]),
+    "amg_time_step_rotating": (_I32, [_P, _I32, _I32, _P, ctypes.POINTER(amg_kernel_timing)]),
     "amg_level_export": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P]),
     "amg_apply_smoother": (_I32, [_P, _I32, _P, _P, _P]),
     "amg_apply_residual": (_I32, [_P, _I32, _P, _P, _P, _P]),
@@ -556,6 +557,16 @@ def amg_time_step(h: Hierarchy, reps: int = 200, stream=None) -> dict:
     _check(load_library().amg_time_step(h.handle, int(reps), _stream(stream), ctypes.byref(t)), "amg_time_step")
     return {"launches": t.launches, "avg_ms": t.avg_ms, "rows": t.rows, "nnz": t.nnz, "entries": t.entries,
             "grid": t.grid, "value_bytes": t.value_bytes}
+
+
+def amg_time_step_rotating(h: Hierarchy, reps: int = 200, copies: int = 8, stream=None) -> dict:
+    """The same step timed over ``copies`` rotating copies of the finest level
+    (each launch streams from HBM, not the Infinity Cache)."""
+    t = amg_kernel_timing()
+    _check(load_library().amg_time_step_rotating(h.handle, int(reps), int(copies), _stream(stream), ctypes.byref(t)),
+           "amg_time_step_rotating")
+    return {"launches": t.launches, "avg_ms": t.avg_ms, "rows": t.rows, "nnz": t.nnz, "entries": t.entries,
+            "grid": t.grid, "value_bytes": t.value_bytes, "copies": int(copies)}
 
 
 def amg_level_export(h: Hierarchy, level: int) -> dict:

@@ -312,6 +312,15 @@ int32_t amg_time_step(amg_hier* h, int32_t reps, void* stream, amg_kernel_timing
   return amg::time_step(h, reps, static_cast<hipStream_t>(stream), timing);
 }
 
+int32_t amg_time_step_rotating(amg_hier* h, int32_t reps, int32_t copies, void* stream, amg_kernel_timing* timing) {
+  if (!h || !timing || reps < 1 || copies < 1 || copies > 64) {
+    amg::set_last_error("invalid argument (reps >= 1, 1 <= copies <= 64)");
+    return AMG_ERR_ARG;
+  }
+  if (h->L < 1) { amg::set_last_error("the finest level is not smoothed in a one-level hierarchy"); return AMG_ERR_ARG; }
+  return amg::time_step_rotating(h, reps, copies, static_cast<hipStream_t>(stream), timing);
+}
+
 int32_t amg_level_export(const amg_hier* h, int32_t level, int32_t* row_ptr, int32_t* col, double* W, double* d,
                          double* D, int32_t* agg) {
   AMG_TRY(check_level(h, level, true));

@@ -143,5 +143,6 @@ int32_t server_submit(void* srv, const amg_request& q, int32_t* ticket);
 int32_t server_poll(void* srv, amg_completion* out, int32_t max, double wait_s, int32_t* count);
 int32_t server_destroy(void* srv, amg_serve_stats* stats);
 int32_t time_step(amg_hier* h, int reps, hipStream_t s, amg_kernel_timing* t);
+int32_t time_step_rotating(amg_hier* h, int reps, int copies, hipStream_t s, amg_kernel_timing* t);
 
 }  // namespace amg

@@ -318,24 +318,40 @@ struct YFold {
   __device__ __forceinline__ VT operator()(int r) const { return (VT)(y[r] + e(agg[r])); }
 };
 
+// Loads and stores of operands a row step touches once (NT: non-temporal,
+// i.e. streamed past the caches instead of displacing what is reused).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_row(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_row(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // w_{k+1} = 2 (A w_k - theta w_k) / eta - w_{k-1};  y += c_{k+1} w_{k+1}.
 // wnext may alias wprev (each element is read before it is overwritten).
-template <typename VT, typename MT, typename PT, bool G = true>
+// NT (levels far larger than the caches): the row's own operands D_r,
+// w_{k-1,r}, y_r and its results are streamed non-temporally, so that the
+// matrix and the gathered w_k stay cached; same arithmetic.
+template <typename VT, typename MT, typename PT, bool G = true, bool NT = false>
 __device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int slot, int j, const VT* __restrict__ wk,
                                               const PT* wprev, VT* wnext, VT* y, double theta, double two_inv_eta,
                                               double ck, int store) {
   using AT = VT;
   const int r = row_at(A, slot);
   const AT xk = (AT)wk[r];
-  const AT d = (AT)A.D[r];
-  const AT wp = (AT)wprev[r];
-  const AT y0 = (AT)y[r];
+  const AT d = (AT)ld_row<NT>(A.D + r);
+  const AT wp = (AT)ld_row<NT>(wprev + r);
+  const AT y0 = (AT)ld_row<NT>(y + r);
   const AT off = offdiag<AT, G>(A, slot, j, wk);
   if (j) return;
   const AT ax = d * xk - off;
   const AT t = (ax - (AT)theta * xk) * (AT)two_inv_eta - wp;
-  if (store) wnext[r] = (VT)t;
-  y[r] = (VT)(y0 + (AT)ck * t);
+  if (store) st_row<NT>(wnext + r, (VT)t);
+  st_row<NT>(y + r, (VT)(y0 + (AT)ck * t));
 }
 
 // s = f - A x; returns the row in the writing lane, -1 in the others

@@ -72,15 +72,23 @@ __global__ void __launch_bounds__(kMaxRowThreads) k_cheb_first(Mat<MT> A, const 
     row_cheb_first<VT, MT, RT>(A, q.slot, q.lane, w0, w1, y, theta, inv_eta, c0, c1, accum, store, e, agg);
 }
 
-// STORE: w_{k+1} is written (every step but the last).  FINE marks launches
-// on the finest level: the same code, a separate instance so that profiles
-// report the finest level's dominant step on its own.
-template <typename VT, typename MT, typename PT, bool STORE, bool FINE>
+// STORE: w_{k+1} is written (every step but the last).  KIND: kStepCoarse
+// (levels that stay in the caches), kStepFine (the finest level, when it has
+// at least kStreamRows rows: the row's own operands are streamed, see
+// row_cheb_next), kStepFineTimed and kStepSmallTimed (the code of kStepFine
+// and of kStepCoarse in separate instances for the rotating-copies timing of
+// a large or a small finest level, so that profiles report them on their
+// own).
+constexpr int kStepCoarse = 0, kStepFine = 1, kStepFineTimed = 2, kStepSmallTimed = 3;
+constexpr int kStreamRows = 1 << 18;
+template <typename VT, typename MT, typename PT, bool STORE, int KIND>
 __global__ void __launch_bounds__(kMaxRowThreads) k_cheb_next(Mat<MT> A, const VT* __restrict__ wk, const PT* wprev,
                                                               VT* wnext, VT* y, double theta, double two_inv_eta,
                                                               double ck) {
   const SlotLane q = slot_of(A);
-  if (q.slot >= 0) row_cheb_next<VT, MT, PT>(A, q.slot, q.lane, wk, wprev, wnext, y, theta, two_inv_eta, ck, STORE);
+  if (q.slot >= 0)
+    row_cheb_next<VT, MT, PT, true, KIND == kStepFine || KIND == kStepFineTimed>(A, q.slot, q.lane, wk, wprev, wnext, y,
+                                                                                theta, two_inv_eta, ck, STORE);
 }
 
 // degree 0: y = [y +] c0 w0
@@ -570,19 +578,19 @@ struct Engine {
     }
     const auto Am = A(l);
     const double ti = 2.0 / lv.eta;
-    if (l == 0) {
+    if (l == 0 && lv.n >= kStreamRows) {
       if (store)
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, true>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev, wnext,
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, kStepFine>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev, wnext,
                            y, lv.theta, ti, ck);
       else
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, true>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, kStepFine>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
                            wnext, y, lv.theta, ti, ck);
     } else {
       if (store)
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, false>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, true, kStepCoarse>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
                            wnext, y, lv.theta, ti, ck);
       else
-        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, false>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, PT, false, kStepCoarse>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev,
                            wnext, y, lv.theta, ti, ck);
     }
     AMG_HIP(hipGetLastError());
@@ -598,10 +606,40 @@ struct Engine {
     VT* wk = wsv(h->ws[0].A);
     VT* wb = wsv(h->ws[0].B);
     VT* y = wsv(h->ws[0].S);
+    const bool big = lv.n >= kStreamRows;  // the instance the solve launches
     AMG_HIP(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i)
-      hipLaunchKernelGGL((k_cheb_next<VT, MT, VT, true, true>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wb, wb, y,
-                         lv.theta, 2.0 / lv.eta, 1e-3);
+    for (int i = 0; i < reps; ++i) {
+      if (big)
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, VT, true, kStepFine>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wb,
+                           wb, y, lv.theta, 2.0 / lv.eta, 1e-3);
+      else
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, VT, true, kStepCoarse>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk,
+                           wb, wb, y, lv.theta, 2.0 / lv.eta, 1e-3);
+    }
+    AMG_HIP(hipGetLastError());
+    AMG_HIP(hipEventRecord(e1, s));
+    return AMG_OK;
+  }
+
+  // `reps` back-to-back launches of the same step cycling over nc copies of
+  // the finest level (matrix, diagonal and the three vectors; copy i % nc for
+  // launch i), so that each launch streams its data from HBM: with the copies
+  // together well above the 256 MB Infinity Cache, a copy has been displaced
+  // by the others before it comes round again.  One untimed round first.
+  int32_t time_fine_step_rotating(int reps, int nc, const Mat<MT>* mats, VT* const* wk, VT* const* wb, VT* const* y,
+                                  hipEvent_t e0, hipEvent_t e1) {
+    const Level& lv = h->lv[0];
+    const bool big = lv.n >= kStreamRows;
+    for (int i = 0; i < reps + nc; ++i) {
+      if (i == nc) AMG_HIP(hipEventRecord(e0, s));
+      const int c = i % nc;
+      if (big)
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, VT, true, kStepFineTimed>), dim3(mats[c].nb), dim3(TPB << mats[c].lk),
+                           0, s, mats[c], wk[c], wb[c], wb[c], y[c], lv.theta, 2.0 / lv.eta, 1e-3);
+      else
+        hipLaunchKernelGGL((k_cheb_next<VT, MT, VT, true, kStepSmallTimed>), dim3(mats[c].nb), dim3(TPB << mats[c].lk),
+                           0, s, mats[c], wk[c], wb[c], wb[c], y[c], lv.theta, 2.0 / lv.eta, 1e-3);
+    }
     AMG_HIP(hipGetLastError());
     AMG_HIP(hipEventRecord(e1, s));
     return AMG_OK;
@@ -1833,7 +1871,7 @@ int32_t time_layout_impl(const Level& lv, void* wk, void* wb, void* y, hipStream
   const Mat<VT> A = mat_of<VT>(lv);
   const dim3 grid(A.nb), block(TPB << A.lk);
   auto launch = [&]() {
-    hipLaunchKernelGGL((k_cheb_next<VT, VT, VT, true, false>), grid, block, 0, s, A, (const VT*)wk, (const VT*)wb,
+    hipLaunchKernelGGL((k_cheb_next<VT, VT, VT, true, kStepCoarse>), grid, block, 0, s, A, (const VT*)wk, (const VT*)wb,
                        (VT*)wb, (VT*)y, lv.theta, lv.eta > 0.0 ? 2.0 / lv.eta : 1.0, 1e-3);
   };
   launch();
@@ -1886,6 +1924,86 @@ int32_t time_step(amg_hier* h, int reps, hipStream_t s, amg_kernel_timing* t) {
       st = AMG_ERR_DEVICE;
     }
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::memset(t, 0, sizeof(*t));
+  t->launches = reps;
+  t->avg_ms = ms / reps;
+  t->rows = h->lv[0].n;
+  t->nnz = h->lv[0].nnz;
+  t->entries = h->lv[0].sell_entries;
+  t->grid = (int32_t)nblk(h->lv[0].n);
+  t->value_bytes = h->mixed ? 4 : 8;
+  return st;
+}
+
+// Rotating-copies timing of the finest level's storing Chebyshev step: copy 0
+// is the level itself, copies 1 .. nc-1 are device copies of its column
+// indices, weights, diagonal (and slot map) and of the step's three vectors.
+template <typename VT, typename MT>
+int32_t time_rotating_impl(amg_hier* h, int reps, int nc, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                           std::vector<void*>& owned) {
+  const Level& lv = h->lv[0];
+  const size_t n = lv.n, ent = lv.sell_entries;
+  std::vector<Mat<MT>> mats(nc, mat_of<MT>(lv));
+  std::vector<VT*> wk(nc), wb(nc), y(nc);
+  wk[0] = static_cast<VT*>(h->ws[0].A);
+  wb[0] = static_cast<VT*>(h->ws[0].B);
+  y[0] = static_cast<VT*>(h->ws[0].S);
+  auto dup = [&](const void* src, size_t bytes, void** dst) -> int32_t {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      set_last_error(std::string("hipMalloc (timing copies): ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
+    }
+    owned.push_back(p);
+    AMG_HIP(hipMemcpyAsync(p, src, bytes, hipMemcpyDeviceToDevice, s));
+    *dst = p;
+    return AMG_OK;
+  };
+  for (int c = 1; c < nc; ++c) {
+    void *col, *val, *D, *a, *b, *yy;
+    AMG_TRY(dup(mats[0].col, ent * sizeof(int), &col));
+    AMG_TRY(dup(mats[0].val, ent * sizeof(MT), &val));
+    AMG_TRY(dup(mats[0].D, n * sizeof(MT), &D));
+    AMG_TRY(dup(wk[0], n * sizeof(VT), &a));
+    AMG_TRY(dup(wb[0], n * sizeof(VT), &b));
+    AMG_TRY(dup(y[0], n * sizeof(VT), &yy));
+    mats[c].col = static_cast<const int*>(col);
+    mats[c].val = static_cast<const MT*>(val);
+    mats[c].D = static_cast<const MT*>(D);
+    if (mats[0].perm) {
+      void* perm;
+      AMG_TRY(dup(mats[0].perm, n * sizeof(int), &perm));
+      mats[c].perm = static_cast<const int*>(perm);
+    }
+    wk[c] = static_cast<VT*>(a);
+    wb[c] = static_cast<VT*>(b);
+    y[c] = static_cast<VT*>(yy);
+  }
+  Engine<VT, MT> E{h, s};
+  return E.time_fine_step_rotating(reps, nc, mats.data(), wk.data(), wb.data(), y.data(), e0, e1);
+}
+
+int32_t time_step_rotating(amg_hier* h, int reps, int copies, hipStream_t s, amg_kernel_timing* t) {
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  std::vector<void*> owned;
+  int32_t st = h->mixed ? time_rotating_impl<float, float>(h, reps, copies, s, e0, e1, owned)
+                        : time_rotating_impl<double, double>(h, reps, copies, s, e0, e1, owned);
+  float ms = 0.f;
+  if (st == AMG_OK) {
+    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      set_last_error(std::string("event timing: ") + hipGetErrorString(e));
+      st = AMG_ERR_DEVICE;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  for (void* p : owned) (void)hipFree(p);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   std::memset(t, 0, sizeof(*t));
