@@ -353,6 +353,10 @@ int32_t amg_solve_batch(int32_t nb, amg_hier* const* h, const double* const* f, 
  *   through the batched executor; converged slots retire at the end of a
  *   round; new graphs are set up by a worker thread on its own stream while
  *   solves run; idle hierarchies are evicted least recently used first.
+ *   Right-hand sides are admitted in submission order among requests whose
+ *   graph is resident: a request waiting for its graph's setup does not hold
+ *   back later requests on resident graphs.  Slot vectors come from a reused
+ *   pool, so admission allocates nothing once the pool has grown.
  * AMG_SERVE_SEQUENTIAL: one right-hand side at a time in arrival order with
  *   amg_solve (the comparison mode).
  * realtime = 1: a request becomes visible at its arrival time (seconds from

@@ -52,9 +52,14 @@ int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s) {
   return AMG_OK;
 }
 
+// The caller guarantees that no queued work still uses the clone (the server
+// and the batched solve synchronize their stream before releasing one); the
+// clone's own graphs ran on its graph stream.  (hipFree still waits for the
+// device to drain: a release costs a device-wide wait, which is why the server
+// reuses idle clones rather than freeing them.)
 void free_clone(amg_hier* c) {
   if (!c) return;
-  (void)hipDeviceSynchronize();
+  if (c->graph_stream) (void)hipStreamSynchronize(c->graph_stream);
   destroy_graphs(c);
   if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
   for (void* p : c->allocs) (void)hipFree(p);

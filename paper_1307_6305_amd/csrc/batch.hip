@@ -465,6 +465,10 @@ struct Launch {
   int threads;
 };
 
+// The schedule's device arrays, packed into one buffer that later builds of
+// the same Schedule reuse (it only grows), so that rebuilding a schedule --
+// the server does so whenever slots join -- costs no allocation and no free
+// (a free synchronizes the whole device).
 struct ScheduleDev {
   BatchOp* ops = nullptr;
   int* map = nullptr;
@@ -472,7 +476,9 @@ struct ScheduleDev {
   TailProgram* tails = nullptr;
   ItemState** tail_states = nullptr;
   double* partials = nullptr;
-  std::vector<void*> allocs;
+  char* buf = nullptr;
+  size_t cap = 0;
+  std::vector<char> staging;  // host image of the uploaded arrays
 };
 
 namespace {
@@ -970,27 +976,8 @@ int32_t run_impl(const Schedule* S, const BatchCtl& ctl, hipStream_t s) {
   return AMG_OK;
 }
 
-int32_t sdalloc(ScheduleDev* D, Schedule* S, void** p, size_t bytes) {
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, bytes + 16);
-  if (e != hipSuccess) {
-    set_last_error(std::string("hipMalloc (batch schedule): ") + hipGetErrorString(e));
-    return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
-  }
-  D->allocs.push_back(q);
-  S->bytes += bytes + 16;
-  *p = q;
-  return AMG_OK;
-}
-
-template <typename T>
-int32_t upload(ScheduleDev* D, Schedule* S, T** dst, const std::vector<T>& v, hipStream_t s) {
-  void* p = nullptr;
-  AMG_TRY(sdalloc(D, S, &p, std::max<size_t>(1, v.size()) * sizeof(T)));
-  *dst = static_cast<T*>(p);
-  if (!v.empty()) AMG_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  return AMG_OK;
-}
+// Byte offset of the next array in the packed buffer (256-byte aligned).
+inline size_t pack_next(size_t off) { return (off + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -1024,25 +1011,69 @@ int32_t batch_compatible(const std::vector<amg_hier*>& hs) {
 }
 
 int32_t schedule_build(Schedule* S, SchedKind kind, const std::vector<BatchItem>& items, hipStream_t s) {
-  schedule_free(S);
   S->kind = kind;
   S->mixed = items.empty() ? false : items[0].h->mixed;
+  delete S->launches;
   S->launches = new std::vector<Launch>();
-  S->dev = new ScheduleDev();
+  if (!S->dev) S->dev = new ScheduleDev();
   if (items.empty()) return AMG_OK;
   Builder bd(items, S->mixed, S->launches);
   if (kind == SCHED_INIT) bd.outer_residual(B_O_RESID, true);
   else if (kind == SCHED_FINAL) bd.outer_residual(B_O_TRUE, false);
   else bd.outer_iteration();
   ScheduleDev* D = S->dev;
-  AMG_TRY(upload(D, S, &D->ops, bd.ops, s));
-  AMG_TRY(upload(D, S, &D->map, bd.map, s));
-  AMG_TRY(upload(D, S, &D->fin, bd.fin, s));
-  AMG_TRY(upload(D, S, &D->tails, bd.tails, s));
-  AMG_TRY(upload(D, S, &D->tail_states, bd.tail_states, s));
-  void* p = nullptr;
-  AMG_TRY(sdalloc(D, S, &p, (size_t)std::max(1, bd.max_parts) * 8 * sizeof(double)));
-  D->partials = static_cast<double*>(p);
+  // layout of the packed buffer: ops, map, fin, tails, tail states, partials
+  size_t off = 0;
+  const size_t o_ops = off;
+  off = pack_next(off + sizeof(BatchOp) * bd.ops.size());
+  const size_t o_map = off;
+  off = pack_next(off + sizeof(int) * bd.map.size());
+  const size_t o_fin = off;
+  off = pack_next(off + sizeof(int) * bd.fin.size());
+  const size_t o_tails = off;
+  off = pack_next(off + sizeof(TailProgram) * bd.tails.size());
+  const size_t o_ts = off;
+  off = pack_next(off + sizeof(ItemState*) * bd.tail_states.size());
+  const size_t upload_bytes = off;
+  const size_t o_part = off;
+  off = pack_next(off + (size_t)std::max(1, bd.max_parts) * 8 * sizeof(double));
+  if (off > D->cap) {
+    // grow (with room for later, larger batches); the old buffer may still
+    // be read by work queued on the stream
+    if (D->buf) {
+      AMG_HIP(hipStreamSynchronize(s));
+      (void)hipFree(D->buf);
+      D->buf = nullptr;
+      D->cap = 0;
+    }
+    const size_t want = off + off / 2;
+    hipError_t e = hipMalloc(&D->buf, want);
+    if (e != hipSuccess) {
+      D->buf = nullptr;
+      set_last_error(std::string("hipMalloc (batch schedule): ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;
+    }
+    D->cap = want;
+    S->bytes = want;
+  }
+  D->ops = reinterpret_cast<BatchOp*>(D->buf + o_ops);
+  D->map = reinterpret_cast<int*>(D->buf + o_map);
+  D->fin = reinterpret_cast<int*>(D->buf + o_fin);
+  D->tails = reinterpret_cast<TailProgram*>(D->buf + o_tails);
+  D->tail_states = reinterpret_cast<ItemState**>(D->buf + o_ts);
+  D->partials = reinterpret_cast<double*>(D->buf + o_part);
+  // the previous upload may still be in flight from the staging image
+  AMG_HIP(hipStreamSynchronize(s));
+  D->staging.assign(upload_bytes, 0);
+  auto put = [&](size_t o, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(D->staging.data() + o, src, bytes);
+  };
+  put(o_ops, bd.ops.data(), sizeof(BatchOp) * bd.ops.size());
+  put(o_map, bd.map.data(), sizeof(int) * bd.map.size());
+  put(o_fin, bd.fin.data(), sizeof(int) * bd.fin.size());
+  put(o_tails, bd.tails.data(), sizeof(TailProgram) * bd.tails.size());
+  put(o_ts, bd.tail_states.data(), sizeof(ItemState*) * bd.tail_states.size());
+  AMG_HIP(hipMemcpyAsync(D->buf, D->staging.data(), upload_bytes, hipMemcpyHostToDevice, s));
   size_t max_lds = 0;
   for (const auto& L : *S->launches)
     if (L.kind == 2) max_lds = std::max(max_lds, L.lds);
@@ -1050,7 +1081,6 @@ int32_t schedule_build(Schedule* S, SchedKind kind, const std::vector<BatchItem>
     const void* fn = S->mixed ? (const void*)k_batch_tail<float, float> : (const void*)k_batch_tail<double, double>;
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
   }
-  AMG_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
   return AMG_OK;
 }
 
@@ -1061,7 +1091,7 @@ int32_t schedule_run(const Schedule* S, const BatchCtl& ctl, hipStream_t s) {
 
 void schedule_free(Schedule* S) {
   if (S->dev) {
-    for (void* p : S->dev->allocs) (void)hipFree(p);
+    if (S->dev->buf) (void)hipFree(S->dev->buf);
     delete S->dev;
     S->dev = nullptr;
   }

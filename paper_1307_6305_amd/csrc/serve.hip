@@ -38,6 +38,12 @@ using clk = std::chrono::steady_clock;
 
 __global__ void k_zero_count(int* c) { *c = 0; }
 
+// u = 0 (a fill kernel rather than a memset node)
+__global__ void k_zero_vec(double* u, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) u[i] = 0.0;
+}
+
 struct Resident {
   amg_hier* h = nullptr;
   size_t bytes = 0;
@@ -66,6 +72,48 @@ struct Slot {
 
 size_t hier_bytes(const amg_hier* h) { return h->bytes; }
 
+// Device vectors of the slots (right-hand side and solution), kept in size
+// classes (powers of two, at least 4096 doubles) and reused, so that admitting
+// and retiring right-hand sides allocates nothing once the pool holds enough
+// buffers (a free would also synchronize the whole device).
+struct VecPool {
+  std::map<size_t, std::vector<double*>> idle;  // class (doubles) -> idle buffers
+  size_t held = 0;                               // device bytes of every buffer
+  static size_t cls(size_t n) {
+    size_t c = 4096;
+    while (c < n) c <<= 1;
+    return c;
+  }
+  // bytes a get(n) would have to allocate
+  size_t need(size_t n) const {
+    auto it = idle.find(cls(n));
+    return it != idle.end() && !it->second.empty() ? 0 : cls(n) * sizeof(double);
+  }
+  int32_t get(size_t n, double** out) {
+    auto& v = idle[cls(n)];
+    if (!v.empty()) {
+      *out = v.back();
+      v.pop_back();
+      return AMG_OK;
+    }
+    AMG_HIP(hipMalloc(out, cls(n) * sizeof(double)));
+    held += cls(n) * sizeof(double);
+    return AMG_OK;
+  }
+  void put(double* p, size_t n) { idle[cls(n)].push_back(p); }
+  // frees the idle buffers (under memory pressure); returns the bytes freed
+  size_t release_idle() {
+    size_t b = 0;
+    for (auto& kv : idle) {
+      for (double* p : kv.second) (void)hipFree(p);
+      b += kv.first * sizeof(double) * kv.second.size();
+      kv.second.clear();
+    }
+    held -= b;
+    return b;
+  }
+};
+
 // One submitted request: the caller's record, with the right-hand sides and
 // (when given) the graph copied in; u stays the caller's.
 struct Req {
@@ -86,6 +134,7 @@ struct Server {
   int evictions = 0, setups = 0, steps = 0;
 
   std::map<int, Resident*> resident;
+  VecPool pool;                     // slot vectors (serve loop thread only)
   std::mutex mu;                    // guards the request list, outbox, `resident` setup fields, setup queue
   std::condition_variable cv;       // new request, setup done, closing
   std::condition_variable cv_out;   // new completions
@@ -174,6 +223,7 @@ struct Server {
   // bytes fit the budget; `keep` (the hierarchy the room is for) is never
   // evicted.  Caller holds mu.
   bool make_room(size_t need, const Resident* keep = nullptr) {
+    if ((double)(bytes + need) > cfg.hbm_budget_bytes) bytes -= pool.release_idle();
     while ((double)(bytes + need) > cfg.hbm_budget_bytes) {
       Resident* victim = nullptr;
       int vid = 0;
@@ -239,6 +289,12 @@ struct Server {
   }
 
   // ---------------------------------------------------------------- batched mode
+  // A submitted request with right-hand sides not yet admitted.
+  struct Pending {
+    Req* rq;
+    int next_rhs;
+  };
+
   int32_t run_batched() {
     std::thread th([this] { worker(); });
     struct Joiner {
@@ -254,9 +310,9 @@ struct Server {
       }
     } joiner{this, &th};
 
-    size_t next = 0;                 // next request (submission order) not yet fully admitted
-    int next_rhs = 0;                // first right-hand side of it not yet admitted
-    std::vector<Slot> active;
+    size_t scanned = 0;              // requests moved from the submission list to `pending`
+    std::vector<Pending> pending;    // in submission order
+    std::vector<Slot> active;        // in the iteration schedule, iterating
     std::vector<Slot> fresh;         // admitted in this round, not yet started
     ItemState* d_states = nullptr;   // pool of item states, one per slot position
     int* d_nactive = nullptr;
@@ -266,6 +322,7 @@ struct Server {
     std::map<const void*, int> state_index;
     Schedule sched_iter, sched_aux;
     bool membership_changed = true;
+    size_t sched_items = 0;          // items in sched_iter (active ones and retired ones)
     int32_t result = AMG_OK;
 
     auto cleanup = [&]() {
@@ -274,9 +331,13 @@ struct Server {
       schedule_free(&sched_aux);
       for (std::vector<Slot>* v : {&active, &fresh})
         for (Slot& sl : *v) {
-          if (sl.f) (void)hipFree(sl.f);
-          if (sl.u) (void)hipFree(sl.u);
+          if (sl.f) pool.put(sl.f, (size_t)sl.rq->q.n);
+          if (sl.u) pool.put(sl.u, (size_t)sl.rq->q.n);
         }
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        bytes -= pool.release_idle();
+      }
       if (d_states) (void)hipFree(d_states);
       if (d_nactive) (void)hipFree(d_nactive);
     };
@@ -289,32 +350,37 @@ struct Server {
       const BatchCtl ctl{cfg.params.tol, cfg.params.max_iter, 0, d_nactive};
       while (true) {
         const double t = now();
-        // --- queue setups for arrived requests whose graph is not resident,
-        //     reserving a conservative size estimate against the budget.  Only
-        //     the head-of-line request's setup may evict idle hierarchies; later
-        //     ones start early only in free room (otherwise they could evict the
-        //     hierarchy the head needs, and the two would evict each other).
+        bool no_more = false;
         {
           std::lock_guard<std::mutex> lk(mu);
-          for (size_t k = next; k < reqs.size(); ++k) {
-            Req* rq = reqs[k].get();
+          for (; scanned < reqs.size(); ++scanned) pending.push_back(Pending{reqs[scanned].get(), 0});
+          no_more = closing;
+        }
+        // --- queue setups for pending requests whose graph is not resident,
+        //     reserving a conservative size estimate against the budget.  Only
+        //     the oldest pending request's setup may evict idle hierarchies;
+        //     later ones start early only in free room (otherwise they could
+        //     evict the hierarchy the oldest needs, and the two would evict
+        //     each other).
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          for (size_t k = 0; k < pending.size(); ++k) {
+            Req* rq = pending[k].rq;
             const amg_request& q = rq->q;
             if (resident.count(q.graph_id) || setup_pending.count(q.graph_id)) continue;
             if (!q.row_ptr) continue;  // no data to set up: fails at admission
             const size_t est = setup_estimate(q);
-            if (k > next) {
+            if (k > 0) {
               if ((double)(bytes + est) > cfg.hbm_budget_bytes) break;
             } else if (!make_room(est)) {
               if (active.empty() && resident_busy() == 0 && setup_pending.empty()) {
                 // larger than the whole budget: nothing can ever make room
-                setup_pending[q.graph_id] = 0;
                 Resident* R = new Resident();
                 R->failed = true;
                 R->status = AMG_ERR_BUDGET;
                 resident[q.graph_id] = R;
-                setup_pending.erase(q.graph_id);
               }
-              break;  // keep arrival order: later graphs wait for room too
+              break;  // later graphs wait for room too
             }
             bytes += est;
             note_bytes();
@@ -323,96 +389,108 @@ struct Server {
           }
         }
         cv.notify_all();
-        // --- admit submitted right-hand sides (in order) while slots and memory allow
+        // --- admit pending right-hand sides while slots and memory allow, in
+        //     submission order among requests whose graph is resident; a
+        //     request whose graph is still being set up does not hold back
+        //     later requests on resident graphs
         fresh.clear();
-        for (;;) {
-          bool no_more = false;
-          Req* rq = request_at(next, &no_more);
-          if (!rq) break;
+        bool stop = false;
+        for (size_t k = 0; k < pending.size() && !stop;) {
+          Pending& pd = pending[k];
+          Req* rq = pd.rq;
           const amg_request& q = rq->q;
-          if ((int)(active.size() + fresh.size()) >= max_slots) break;
           std::unique_lock<std::mutex> lk(mu);
           auto it = resident.find(q.graph_id);
           if (it == resident.end()) {
             if (!q.row_ptr && !setup_pending.count(q.graph_id)) {  // evicted and no data: fail
-              fail_request(rq, AMG_ERR_ARG, next_rhs);
-              lk.unlock();
-              ++next;
-              next_rhs = 0;
+              fail_request(rq, AMG_ERR_ARG, pd.next_rhs);
+              pending.erase(pending.begin() + k);
               continue;
             }
-            break;  // setup still running: keep submission order
+            ++k;  // setup still running: later requests may go first
+            continue;
           }
           Resident* R = it->second;
           if (R->failed) {
-            fail_request(rq, R->status, next_rhs);
-            lk.unlock();
-            ++next;
-            next_rhs = 0;
+            fail_request(rq, R->status, pd.next_rhs);
+            pending.erase(pending.begin() + k);
             continue;
           }
-          // one slot: workspace (spare clone, the hierarchy's own, or a new clone) + f, u
-          const size_t n = (size_t)q.n;
-          amg_hier* ws = nullptr;
-          bool own = false;
-          size_t extra = 2 * n * sizeof(double) + 64;
-          if (!R->spare.empty()) {
-            ws = R->spare.back();
-          } else if (!R->own_lent) {
-            own = true;  // the hierarchy's own workspace is free
-          } else {
-            extra += R->h->ws_bytes;
-          }
-          if (!make_room(extra, R)) {
-            if (active.empty() && fresh.empty()) {  // nothing will ever free memory: give up on it
-              fail_request(rq, AMG_ERR_BUDGET, next_rhs);
-              lk.unlock();
-              ++next;
-              next_rhs = 0;
-              continue;
+          bool removed = false;
+          while (pd.next_rhs < q.nrhs) {
+            if ((int)(active.size() + fresh.size()) >= max_slots || free_state.empty()) {
+              stop = true;
+              break;
             }
-            break;
+            // one slot: workspace (spare clone, the hierarchy's own, or a new clone) + f, u
+            const size_t n = (size_t)q.n;
+            amg_hier* ws = nullptr;
+            bool own = false;
+            size_t extra = 2 * pool.need(n) + 64;
+            if (!R->spare.empty()) {
+              ws = R->spare.back();
+            } else if (!R->own_lent) {
+              own = true;  // the hierarchy's own workspace is free
+            } else {
+              extra += R->h->ws_bytes;
+            }
+            if (!make_room(extra, R)) {
+              if (active.empty() && fresh.empty()) {  // nothing will ever free memory: give up on it
+                fail_request(rq, AMG_ERR_BUDGET, pd.next_rhs);
+                pending.erase(pending.begin() + k);
+                removed = true;
+              } else {
+                stop = true;
+              }
+              break;
+            }
+            if (!R->spare.empty()) {
+              R->spare.pop_back();
+            } else if (!own) {
+              const int32_t st = make_clone(R->h, &ws, s);
+              if (st != AMG_OK) return st;
+              R->clone_bytes += ws->bytes;
+              bytes += ws->bytes;
+            }
+            if (own) {
+              ws = R->h;
+              R->own_lent = true;
+            }
+            Slot sl;
+            sl.rq = rq;
+            sl.rhs = pd.next_rhs;
+            sl.res = R;
+            sl.ws = ws;
+            sl.own_ws = own;
+            sl.admit_s = std::max(t, q.arrival_s);  // submitted after this round began
+            R->in_flight++;
+            R->last_use = t;
+            const int si = free_state.back();
+            free_state.pop_back();
+            sl.st = d_states + si;
+            state_index[sl.st] = si;
+            // the slot is accounted for from here on (an error fails it with the rest)
+            fresh.push_back(sl);
+            ++pd.next_rhs;
+            Slot& fs = fresh.back();
+            const size_t before = pool.held;
+            AMG_TRY(pool.get(n, &fs.f));
+            AMG_TRY(pool.get(n, &fs.u));
+            bytes += pool.held - before;
+            note_bytes();
+            // the copy-in without the lock (submissions and polls go on)
+            lk.unlock();
+            AMG_HIP(hipMemcpyAsync(fs.f, q.f + (size_t)sl.rhs * n, n * sizeof(double), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_zero_vec, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fs.u, (int)n);
+            AMG_HIP(hipGetLastError());
+            lk.lock();
           }
-          if (!R->spare.empty()) {
-            R->spare.pop_back();
-          } else if (!own) {
-            const int32_t st = make_clone(R->h, &ws, s);
-            if (st != AMG_OK) return st;
-            R->clone_bytes += ws->bytes;
-            bytes += ws->bytes;
+          if (removed) continue;
+          if (pd.next_rhs >= q.nrhs) {
+            pending.erase(pending.begin() + k);
+            continue;
           }
-          if (own) {
-            ws = R->h;
-            R->own_lent = true;
-          }
-          bytes += 2 * n * sizeof(double);
-          note_bytes();
-          Slot sl;
-          sl.rq = rq;
-          sl.rhs = next_rhs;
-          sl.res = R;
-          sl.ws = ws;
-          sl.own_ws = own;
-          sl.admit_s = std::max(t, q.arrival_s);  // submitted after this round began
-          R->in_flight++;
-          R->last_use = t;
-          lk.unlock();
-          const int si = free_state.back();
-          free_state.pop_back();
-          sl.st = d_states + si;
-          state_index[sl.st] = si;
-          const size_t rhs_k = (size_t)next_rhs;
-          // the slot is accounted for from here on (an error fails it with the rest)
-          fresh.push_back(sl);
-          if (++next_rhs >= q.nrhs) {
-            ++next;
-            next_rhs = 0;
-          }
-          Slot& fs = fresh.back();
-          AMG_HIP(hipMalloc(&fs.f, n * sizeof(double)));
-          AMG_HIP(hipMalloc(&fs.u, n * sizeof(double)));
-          AMG_HIP(hipMemcpyAsync(fs.f, q.f + rhs_k * n, n * sizeof(double), hipMemcpyHostToDevice, s));
-          AMG_HIP(hipMemsetAsync(fs.u, 0, n * sizeof(double), s));
+          ++k;
         }
         // --- start the new slots: r = f - A u, activation
         if (!fresh.empty()) {
@@ -426,18 +504,25 @@ struct Server {
           membership_changed = true;
         }
         if (active.empty()) {
-          bool no_more = false;
-          if (!request_at(next, &no_more) && no_more) break;  // closing and everything done
+          if (pending.empty() && no_more) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (scanned == reqs.size()) break;  // closing and everything done
+            continue;
+          }
           // wait for a submission, a setup or the close
           std::unique_lock<std::mutex> lk(mu);
           cv.wait_for(lk, std::chrono::milliseconds(2));
           continue;
         }
-        // --- one round of outer iterations over every in-flight slot
-        if (membership_changed) {
+        // --- one round of outer iterations over every in-flight slot.  The
+        //     iteration schedule is rebuilt when slots have joined; retired
+        //     slots stay in it as frozen items (their blocks return at once)
+        //     until the next rebuild, or until they outnumber the live ones.
+        if (membership_changed || 2 * active.size() < sched_items) {
           std::vector<BatchItem> items;
           for (const Slot& sl : active) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
           AMG_TRY(schedule_build(&sched_iter, SCHED_ITER, items, s));
+          sched_items = active.size();
           membership_changed = false;
         }
         for (int k = 0; k < std::max(1, cfg.iters_per_step); ++k) AMG_TRY(schedule_run(&sched_iter, ctl, s));
@@ -469,9 +554,11 @@ struct Server {
             const Slot& sl = done[i];
             const double rho0 = std::sqrt(fst[i].rr0);
             complete(sl, fst[i].status, fst[i].iter, rho0 > 0 ? std::sqrt(fst[i].rrt) / rho0 : 0.0);
-            (void)hipFree(sl.f);
-            (void)hipFree(sl.u);
-            bytes -= 2 * (size_t)sl.rq->q.n * sizeof(double);
+            // the slot's buffers, state and workspace go back for reuse: the
+            // iteration schedule still lists the slot, frozen, and is rebuilt
+            // before any of them serves a new slot (new slots always rebuild it)
+            pool.put(sl.f, (size_t)sl.rq->q.n);
+            pool.put(sl.u, (size_t)sl.rq->q.n);
             sl.res->in_flight--;
             sl.res->last_use = now();
             if (sl.own_ws) sl.res->own_lent = false;
@@ -480,7 +567,6 @@ struct Server {
             state_index.erase(sl.st);
           }
           active.swap(keep);
-          membership_changed = true;
         }
       }
       return AMG_OK;
@@ -493,7 +579,8 @@ struct Server {
       closing = true;
       for (std::vector<Slot>* v : {&active, &fresh})
         for (const Slot& sl : *v) complete(sl, result, 0, 0.0);
-      for (size_t k = next; k < reqs.size(); ++k) fail_request(reqs[k].get(), result, k == next ? next_rhs : 0);
+      for (const Pending& pd : pending) fail_request(pd.rq, result, pd.next_rhs);
+      for (size_t k = scanned; k < reqs.size(); ++k) fail_request(reqs[k].get(), result, 0);
     }
     cleanup();
     return result;
@@ -501,9 +588,6 @@ struct Server {
 
   // ---------------------------------------------------------------- sequential mode
   int32_t run_sequential() {
-    double* f = nullptr;
-    double* u = nullptr;
-    size_t cap = 0;
     size_t next = 0;  // the request being served
     int cur_rhs = 0;  // its first right-hand side not yet completed
     auto loop = [&]() -> int32_t {
@@ -546,16 +630,38 @@ struct Server {
         }
         R->last_use = now();
         const double admit = now();
-        if ((size_t)q.n > cap) {
-          if (f) (void)hipFree(f);
-          if (u) (void)hipFree(u);
-          cap = q.n;
-          AMG_HIP(hipMalloc(&f, cap * sizeof(double)));
-          AMG_HIP(hipMalloc(&u, cap * sizeof(double)));
+        double* f = nullptr;
+        double* u = nullptr;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          const size_t before = pool.held;
+          if (!make_room(2 * pool.need((size_t)q.n), R)) {
+            fail_request(rq, AMG_ERR_BUDGET);
+            continue;
+          }
+          AMG_TRY(pool.get((size_t)q.n, &f));
+          const int32_t st = pool.get((size_t)q.n, &u);
+          if (st != AMG_OK) {
+            pool.put(f, (size_t)q.n);
+            return st;
+          }
+          bytes += pool.held - before;
+          note_bytes();
         }
+        struct Give {  // the vectors go back to the pool however the request ends
+          VecPool& p;
+          double* f;
+          double* u;
+          size_t n;
+          ~Give() {
+            p.put(f, n);
+            p.put(u, n);
+          }
+        } give{pool, f, u, (size_t)q.n};
         for (int k = 0; k < q.nrhs; ++k) {
           AMG_HIP(hipMemcpyAsync(f, q.f + (size_t)k * q.n, q.n * sizeof(double), hipMemcpyHostToDevice, s));
-          AMG_HIP(hipMemsetAsync(u, 0, q.n * sizeof(double), s));
+          hipLaunchKernelGGL(k_zero_vec, dim3((unsigned)((q.n + 255) / 256)), dim3(256), 0, s, u, (int)q.n);
+          AMG_HIP(hipGetLastError());
           amg_info info{};
           const int32_t st = solve(R->h, f, u, s, &info);
           if (q.u) AMG_HIP(hipMemcpyAsync(q.u + (size_t)k * q.n, u, q.n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -580,8 +686,10 @@ struct Server {
       for (size_t k = next; k < reqs.size(); ++k) fail_request(reqs[k].get(), result, k == next ? cur_rhs : 0);
     }
     (void)hipStreamSynchronize(s);
-    if (f) (void)hipFree(f);
-    if (u) (void)hipFree(u);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      bytes -= pool.release_idle();
+    }
     return result;
   }
 
