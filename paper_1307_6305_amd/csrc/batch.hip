@@ -61,10 +61,10 @@ struct BatchOp {
   int n;
   int k;
   int i0, i1, i2, i3;
-  int first_block;  // first block (= tile) of this op in its launch
+  int first_block;  // block of this op's tile 0 in its launch
   int blocks;       // tiles of kBatchRows rows
   int part;         // first partial-sum tile of this op (8 doubles per tile)
-  int pad;
+  int stride;       // blocks between two tiles of this op (1, or the size of its shared-matrix group)
   double f0, f1, f2, f3;
   Mat<double> A64;
   Mat<float> A32;
@@ -105,7 +105,10 @@ __device__ __forceinline__ void deposit(double (&v)[K], double* partials, int sl
 // Steps that multiply by a level's matrix: one tile (kBatchRows rows) of one
 // op, with K = 2^lk lanes per row (the launch has kBatchRows << lk threads).
 // Reductions leave one partial sum per tile, added in row order.
-template <typename VT, typename MT>
+// TYPE: 0 for any matrix step (a switch on the op's type), or the one op type
+// of a launch, so that its kernel holds only that step's code (fewer
+// registers, more waves per SIMD).
+template <typename VT, typename MT, int TYPE = 0>
 __device__ __forceinline__ void batch_mat_tile(const BatchOp& op, int tile, double* partials, double* red,
                                                double* stage) {
   const int lk = op.A64.lk;
@@ -113,7 +116,7 @@ __device__ __forceinline__ void batch_mat_tile(const BatchOp& op, int tile, doub
   const int lane = threadIdx.x & ((1 << lk) - 1);
   const bool slive = threadIdx.x < (kBatchRows << lk) && slot < op.n;
   const bool stage_rows = needs_stage(op.A64);
-  switch (op.type) {
+  switch (TYPE ? TYPE : op.type) {
     case B_CHEB_FIRST: {
       if (!slive) break;
       const Mat<MT>& A = op_mat<MT>(op);
@@ -309,9 +312,9 @@ __device__ __forceinline__ bool op_runs(int type, const ItemState& S) {
 }
 
 // One step of the cycle for every item of the launch.  Block b works on tile
-// (b - first_block) of op block_op[b].  Matrix and vector steps are separate
+// (b - first_block) / stride of op block_op[b].  Matrix and vector steps are separate
 // kernels, each with the registers its own code needs.
-template <typename VT, typename MT>
+template <typename VT, typename MT, int TYPE>
 __global__ void __launch_bounds__(kBatchRows * 4) k_batch_mat(const BatchOp* __restrict__ ops,
                                                        const int* __restrict__ block_op, double* partials) {
   __shared__ double red[16 * 8];
@@ -319,7 +322,7 @@ __global__ void __launch_bounds__(kBatchRows * 4) k_batch_mat(const BatchOp* __r
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const BatchOp& op = ops[block_op[b]];
   if (!op_runs(op.type, *op.st)) return;
-  batch_mat_tile<VT, MT>(op, b - op.first_block, partials, red, stage);
+  batch_mat_tile<VT, MT, TYPE>(op, (b - op.first_block) / op.stride, partials, red, stage);
 }
 
 template <typename VT>
@@ -329,7 +332,7 @@ __global__ void __launch_bounds__(kBatchRows) k_batch_vec(const BatchOp* __restr
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const BatchOp& op = ops[block_op[b]];
   if (!op.st->active) return;
-  batch_vec_tile<VT>(op, b - op.first_block, partials, red);
+  batch_vec_tile<VT>(op, (b - op.first_block) / op.stride, partials, red);
 }
 
 // Coarsest solves, one block per item.
@@ -458,6 +461,7 @@ __global__ void k_batch_reset(int* nactive) { *nactive = 0; }
 
 struct Launch {
   int kind;  // 0 vector step, 4 matrix step, 1 coarse, 2 tail, 3 finish
+  int optype;  // the op type of a step launch
   int op0, nops;
   int map0, nblocks;  // block map slice (step) / finish list slice
   int tail0;          // first tail program (tail)
@@ -533,25 +537,59 @@ struct Builder {
     }
   }
 
+  // Matrix steps of items that share a matrix (several right-hand sides on
+  // one hierarchy) are grouped and their blocks interleaved tile by tile:
+  // consecutive blocks -- on the same XCD, see xcd_remap -- take the same
+  // tile for the group's items one after the other, so the tile's matrix
+  // entries come from L2 for all but the first.  Each op's arithmetic and its
+  // partial sums (slot part + tile) do not depend on the block order.
   void step_launch(std::vector<BatchOp> v, bool reduces) {
     Launch L{};
-    L.kind = 0;
+    L.kind = is_matrix_step(v[0].type) ? 4 : 0;
+    L.optype = v[0].type;
+    std::vector<int> group_of(v.size(), 0);  // ops of one group are adjacent after this
+    if (L.kind == 4) {
+      std::vector<BatchOp> sorted;
+      std::vector<char> taken(v.size(), 0);
+      int g = 0;
+      for (size_t q = 0; q < v.size(); ++q) {
+        if (taken[q]) continue;
+        for (size_t r = q; r < v.size(); ++r)
+          if (!taken[r] && v[r].A64.col == v[q].A64.col && v[r].n == v[q].n && v[r].A64.lk == v[q].A64.lk) {
+            taken[r] = 1;
+            sorted.push_back(v[r]);
+            group_of[sorted.size() - 1] = g;
+          }
+        ++g;
+      }
+      v.swap(sorted);
+    } else {
+      for (size_t q = 0; q < v.size(); ++q) group_of[q] = (int)q;
+    }
     L.op0 = (int)ops.size();
     L.nops = (int)v.size();
     L.map0 = (int)map.size();
     int parts = 0, blocks = 0;
-    for (size_t q = 0; q < v.size(); ++q) {
-      BatchOp& o = v[q];
-      o.blocks = nblk(o.n, kBatchRows);
-      o.first_block = blocks;
-      o.part = parts;
-      blocks += o.blocks;
-      if (reduces) parts += o.blocks;
-      for (int t = 0; t < o.blocks; ++t) map.push_back(L.op0 + (int)q);
-      ops.push_back(o);
+    for (size_t q0 = 0; q0 < v.size();) {
+      size_t q1 = q0 + 1;
+      while (q1 < v.size() && group_of[q1] == group_of[q0]) ++q1;
+      const int G = (int)(q1 - q0);
+      const int T = nblk(v[q0].n, kBatchRows);
+      for (size_t q = q0; q < q1; ++q) {
+        BatchOp& o = v[q];
+        o.blocks = T;
+        o.first_block = blocks + (int)(q - q0);
+        o.stride = G;
+        o.part = parts;
+        if (reduces) parts += o.blocks;
+      }
+      for (int t = 0; t < T; ++t)
+        for (size_t q = q0; q < q1; ++q) map.push_back(L.op0 + (int)q);
+      blocks += G * T;
+      q0 = q1;
     }
+    for (const BatchOp& o : v) ops.push_back(o);
     L.nblocks = blocks;
-    L.kind = is_matrix_step(v[0].type) ? 4 : 0;
     L.threads = kBatchRows;
     for (const BatchOp& o : v) L.threads = std::max(L.threads, kBatchRows << o.A64.lk);
     max_parts = std::max(max_parts, parts);
@@ -956,8 +994,20 @@ int32_t run_impl(const Schedule* S, const BatchCtl& ctl, hipStream_t s) {
                            D->partials);
         break;
       case 4:
-        hipLaunchKernelGGL((k_batch_mat<VT, MT>), dim3(L.nblocks), dim3(L.threads), 0, s, D->ops,
-                           D->map + L.map0, D->partials);
+        // the Chebyshev steps and residuals (most of a cycle's matrix passes)
+        // get kernels of their own
+        if (L.optype == B_CHEB_NEXT)
+          hipLaunchKernelGGL((k_batch_mat<VT, MT, B_CHEB_NEXT>), dim3(L.nblocks), dim3(L.threads), 0, s, D->ops,
+                             D->map + L.map0, D->partials);
+        else if (L.optype == B_CHEB_FIRST)
+          hipLaunchKernelGGL((k_batch_mat<VT, MT, B_CHEB_FIRST>), dim3(L.nblocks), dim3(L.threads), 0, s, D->ops,
+                             D->map + L.map0, D->partials);
+        else if (L.optype == B_RESIDUAL)
+          hipLaunchKernelGGL((k_batch_mat<VT, MT, B_RESIDUAL>), dim3(L.nblocks), dim3(L.threads), 0, s, D->ops,
+                             D->map + L.map0, D->partials);
+        else
+          hipLaunchKernelGGL((k_batch_mat<VT, MT, 0>), dim3(L.nblocks), dim3(L.threads), 0, s, D->ops,
+                             D->map + L.map0, D->partials);
         break;
       case 1:
         hipLaunchKernelGGL((k_batch_coarse<VT>), dim3(L.nops), dim3(TPB), 0, s, D->ops + L.op0);
