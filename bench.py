@@ -615,6 +615,145 @@ def run_serve(args, amg, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_serve_stream(args, amg, torch):
+    """A long served stream through the incremental server: requests are made
+    and submitted at their Poisson arrival times by this process (so that the
+    host holds only the graphs and the requests in flight), completions are
+    polled as they come; batched mixed-precision form only.  A sample of
+    completed right-hand sides (graphs of at most 2.5e5 unknowns) is checked
+    against the FP64 oracle."""
+    import threading
+
+    nreq = args.serve_stream
+    rng = np.random.default_rng(inputs.seed_for(5, 7))
+    # the stream's plan (as serve_stream, without the right-hand sides)
+    plan, graphs = [], []
+    t0 = time.perf_counter()
+    for i in range(nreq):
+        if not graphs or rng.random() < 0.3:
+            if rng.random() < 0.5:
+                n = int(np.exp(rng.uniform(np.log(1e3), np.log(2e5))))
+                graphs.append(("rgg", n, int(rng.integers(1 << 30))))
+            else:
+                graphs.append(("grid", int(rng.integers(256, 1025)), 0))
+            plan.append((len(graphs) - 1, 1))
+        else:
+            plan.append((int(rng.integers(len(graphs))), int(rng.integers(1, 33))))
+    built = []
+    for gi, (kind, a, b) in enumerate(graphs):
+        built.append(inputs.rgg(a, b) if kind == "rgg" else inputs.grid2d(a))
+        if gi % 100 == 99:
+            print(f"[bench] stream graphs {gi + 1}/{len(graphs)} ({time.perf_counter() - t0:.0f} s)", file=sys.stderr,
+                  flush=True)
+    nrhs = sum(k for _, k in plan)
+    dof = sum(k * built[g].n for g, k in plan)
+    rate = args.serve_rate
+    arr = np.cumsum(np.concatenate([[0.0], rng.exponential(1.0 / rate, size=nreq - 1)]))
+    picks = [i for i, (g, _) in enumerate(plan) if built[g].n <= 250_000]
+    picks = set(picks[::max(1, len(picks) // args.serve_oracle_sample)][:args.serve_oracle_sample])
+    print(f"[bench] stream: {nreq} requests, {len(graphs)} graphs, {nrhs} right-hand sides, {dof} DOF, "
+          f"Poisson {rate:.2f} req/s", file=sys.stderr, flush=True)
+    pmx = amg.amg_params_default(degree=4, agg_size=8, precision="mixed")
+    cfg = amg.amg_serve_cfg_default(pmx, mode="batched", hbm_budget_bytes=200e9,
+                                    iters_per_step=args.serve_iters_per_step, max_slots=args.serve_slots)
+    srv = amg.Server(cfg)
+    comps, sample = [], {}
+    done = threading.Event()
+    lock = threading.Lock()
+
+    def poller():
+        while not done.is_set() or len(comps) < nrhs:
+            got = srv.poll(256, 0.05)
+            with lock:
+                for c in got:
+                    if c["request"] in picks and c["rhs"] == 0:
+                        sample[c["request"]] = c["u"].copy()
+                    c.pop("u", None)
+                    comps.append(c)
+            if done.is_set() and not got and len(comps) >= nrhs:
+                break
+
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    fs_sample = {}
+    start = time.perf_counter()
+    for i, (g, k) in enumerate(plan):
+        wait = arr[i] - (time.perf_counter() - start)
+        if wait > 0:
+            time.sleep(wait)
+        f = np.random.default_rng(inputs.seed_for(5, 100000 + i)).uniform(-1.0, 1.0, size=(k, built[g].n))
+        if i in picks:
+            fs_sample[i] = f[0].copy()
+        tk = srv.submit(g, f, graph=built[g])
+        assert tk == i
+        if i % 200 == 199:
+            with lock:
+                ndone = len(comps)
+            print(f"[bench] stream: {i + 1}/{nreq} submitted at {time.perf_counter() - start:.0f} s, "
+                  f"{ndone}/{nrhs} right-hand sides done", file=sys.stderr, flush=True)
+    done.set()
+    while True:
+        th.join(timeout=30.0)
+        if not th.is_alive():
+            break
+        with lock:
+            print(f"[bench] stream: draining, {len(comps)}/{nrhs} done", file=sys.stderr, flush=True)
+    span = time.perf_counter() - start
+    stats = srv.close()
+    lat = np.array([c["finish_s"] - c["arrival_s"] for c in comps])
+    ok = sum(1 for c in comps if c["status"] == 0)
+    worst = max(c["rel_res_true"] for c in comps)
+    cpu, err = None, None
+    if not args.no_cpu_baseline and sample:
+        cases = [(plan[i][0], built[plan[i][0]], fs_sample[i], sample[i]) for i in sorted(sample)]
+        cpu, err = oracle_subset(cases, dict(degree=4, agg_size=8),
+                                 sample=f"the oracle's FP64 setup and solve of the first right-hand side of "
+                                        f"{len(cases)} requests spread over the stream (graphs of at most 2.5e5 "
+                                        f"unknowns), single thread; value = sampled unknowns / oracle solve seconds")
+    res = {
+        "solves_per_s": nrhs / span,
+        "dof_per_s": dof / span,
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "span_s": span,
+        "converged": ok,
+        "worst_rel_res_true": worst,
+        "setups": stats["setups"],
+        "evictions": stats["evictions"],
+        "peak_bytes": stats["peak_bytes"],
+        "err_A_vs_oracle": err,
+    }
+    print(f"[bench] stream batched_mixed: {json.dumps(res)}", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC,
+        "value": dof / span,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": 1e3 * span,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"served stream: {nreq} requests (30 % new graphs: random geometric graphs n in [1e3, 2e5] "
+                        f"and 2D grids of side 256..1024; others 1..32 right-hand sides on an earlier graph), Poisson "
+                        f"arrivals at {rate:.2f} req/s, submitted one at a time to the incremental server, 200 GB "
+                        f"budget, batched mixed precision, agg 8, degree 4, tol 1e-8",
+            "requests": nreq,
+            "graphs": len(graphs),
+            "rhs": nrhs,
+            "dof": dof,
+            "rate_req_per_s": rate,
+            "batched_mixed": res,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,6 +776,11 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=512)
     ap.add_argument("--serve-oracle-sample", type=int, default=12,
                     help="served form: completed right-hand sides checked against the oracle")
+    ap.add_argument("--serve-stream", type=int, default=0, metavar="N",
+                    help="served form, long stream: N requests submitted at Poisson arrival times to the "
+                         "incremental server (batched mixed precision only)")
+    ap.add_argument("--serve-rate", type=float, default=3.72,
+                    help="arrival rate (requests/s) of --serve-stream")
     ap.add_argument("--layout", default=None,
                     help="fixed sliced-ELL layout 'H,K,S' (slice height, lanes per row, sorted 0/1) "
                          "instead of the autotuner")
@@ -663,6 +807,9 @@ def main():
     amg.load_library()
     if args.batch:
         run_batch(args, amg, torch)
+        return
+    if args.serve_stream:
+        run_serve_stream(args, amg, torch)
         return
     if args.serve:
         run_serve(args, amg, torch)

@@ -11,6 +11,7 @@ the binding's entry points raises.
 from __future__ import annotations
 
 import ctypes
+import threading
 import os
 
 import numpy as np
@@ -439,6 +440,8 @@ class Server:
         self.handle = hnd
         self._pending = {}  # ticket -> [solution array, completions still to come]
         self._polled = 0
+        self._submitted = 0  # tickets are handed out in submission order
+        self._lock = threading.Lock()  # submit and poll may run on different threads
 
     def submit(self, graph_id: int, f, graph=None, n: int | None = None) -> int:
         """Submit right-hand sides f ((nrhs, n) or (n,)) for graph ``graph_id``;
@@ -464,8 +467,19 @@ class Server:
         u = np.zeros_like(f)
         r.u = u.ctypes.data
         ticket = _I32(-1)
-        _check(self._lib.amg_server_submit(self.handle, ctypes.byref(r), ctypes.byref(ticket)), "amg_server_submit")
-        self._pending[ticket.value] = [u, f.shape[0]]
+        with self._lock:
+            # registered before the call: a poll on another thread may see
+            # the completion as soon as the server has the request
+            expect = self._submitted
+            self._pending[expect] = [u, f.shape[0]]
+            code = self._lib.amg_server_submit(self.handle, ctypes.byref(r), ctypes.byref(ticket))
+            if code != AMG_OK:
+                del self._pending[expect]
+            else:
+                self._submitted += 1
+                if ticket.value != expect:
+                    self._pending[ticket.value] = self._pending.pop(expect)
+        _check(code, "amg_server_submit")
         return ticket.value
 
     def poll(self, max_count: int = 64, wait_s: float = 0.0):
@@ -475,14 +489,15 @@ class Server:
         cnt = _I32(0)
         code = self._lib.amg_server_poll(self.handle, out, max_count, float(wait_s), ctypes.byref(cnt))
         res = []
-        for c in out[:cnt.value]:
-            d = _completion_dict(c)
-            ent = self._pending[c.request]
-            d["u"] = ent[0][c.rhs]
-            ent[1] -= 1
-            if ent[1] == 0:
-                del self._pending[c.request]
-            res.append(d)
+        with self._lock:
+            for c in out[:cnt.value]:
+                d = _completion_dict(c)
+                ent = self._pending[c.request]
+                d["u"] = ent[0][c.rhs]
+                ent[1] -= 1
+                if ent[1] == 0:
+                    del self._pending[c.request]
+                res.append(d)
         _check(code, "amg_server_poll")
         return res
 

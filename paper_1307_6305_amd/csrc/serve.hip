@@ -119,6 +119,7 @@ struct VecPool {
 struct Req {
   amg_request q;
   int ticket = 0;
+  int remaining = 0;  // right-hand sides not yet completed
   std::vector<double> f;
   std::vector<int32_t> rp, col;
   std::vector<double> w, d;
@@ -245,6 +246,25 @@ struct Server {
     return true;
   }
 
+  // One more right-hand side of rq is finished; after the last one the
+  // request's copies of its right-hand sides and graph go (a long stream
+  // would otherwise hold every request's data until the server ends).  The
+  // graph copy stays while a setup of that graph is queued or running (the
+  // setup thread may be reading it).  Caller holds mu.
+  void rhs_done(Req* rq) {
+    if (--rq->remaining > 0) return;
+    std::vector<double>().swap(rq->f);
+    rq->q.f = nullptr;
+    if (!setup_pending.count(rq->q.graph_id)) {
+      std::vector<int32_t>().swap(rq->rp);
+      std::vector<int32_t>().swap(rq->col);
+      std::vector<double>().swap(rq->w);
+      std::vector<double>().swap(rq->d);
+      rq->q.row_ptr = rq->q.col = nullptr;
+      rq->q.w = rq->q.d = nullptr;
+    }
+  }
+
   // Records a finished right-hand side in the outbox.  Caller holds mu.
   void complete(const Slot& sl, int32_t status, int iters, double rel_true) {
     amg_completion c;
@@ -258,6 +278,7 @@ struct Server {
     c.finish_s = now();
     outbox.push_back(c);
     --outstanding;
+    rhs_done(sl.rq);
     cv_out.notify_all();
   }
 
@@ -276,6 +297,7 @@ struct Server {
       c.finish_s = t;
       outbox.push_back(c);
       --outstanding;
+      rhs_done(rq);
     }
     cv_out.notify_all();
   }
@@ -750,6 +772,7 @@ struct Server {
     }
     rq->q.arrival_s = arrival < 0 ? now() : arrival;
     rq->ticket = (int32_t)reqs.size();
+    rq->remaining = in.nrhs;
     if (ticket) *ticket = rq->ticket;
     outstanding += in.nrhs;
     reqs.push_back(std::move(rq));
