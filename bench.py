@@ -703,6 +703,30 @@ def run_serve_stream(args, amg, torch):
     lat = np.array([c["finish_s"] - c["arrival_s"] for c in comps])
     ok = sum(1 for c in comps if c["status"] == 0)
     worst = max(c["rel_res_true"] for c in comps)
+    first = {}
+    for i, (g, _) in enumerate(plan):
+        first.setdefault(g, i)
+    kinds = ["new" if first[g] == i else "repeat" for i, (g, _) in enumerate(plan)]
+    by_kind = {}
+    for k in ("new", "repeat"):
+        lk = np.array([lat[j] for j, c in enumerate(comps) if kinds[c["request"]] == k])
+        if lk.size:
+            by_kind[k] = {"rhs": int(lk.size), "p50_latency_s": float(np.percentile(lk, 50)),
+                          "p99_latency_s": float(np.percentile(lk, 99))}
+    # the slowest requests: time before admission against time in flight
+    slow = sorted(range(len(comps)), key=lambda j: -lat[j])
+    seen_req = set()
+    for j in slow:
+        c = comps[j]
+        if c["request"] in seen_req:
+            continue
+        seen_req.add(c["request"])
+        g, k = plan[c["request"]]
+        print(f"[bench] slow: request {c['request']} ({kinds[c['request']]}, n {built[g].n}, {k} rhs) arrival "
+              f"{c['arrival_s']:.1f} s: latency {lat[j]:.2f} s = wait {c['admit_s'] - c['arrival_s']:.2f} + "
+              f"in flight {c['finish_s'] - c['admit_s']:.2f}", file=sys.stderr, flush=True)
+        if len(seen_req) >= 8:
+            break
     cpu, err = None, None
     if not args.no_cpu_baseline and sample:
         cases = [(plan[i][0], built[plan[i][0]], fs_sample[i], sample[i]) for i in sorted(sample)]
@@ -722,6 +746,7 @@ def run_serve_stream(args, amg, torch):
         "evictions": stats["evictions"],
         "peak_bytes": stats["peak_bytes"],
         "err_A_vs_oracle": err,
+        "by_kind": by_kind,
     }
     print(f"[bench] stream batched_mixed: {json.dumps(res)}", file=sys.stderr, flush=True)
     out = {

@@ -224,8 +224,25 @@ struct Server {
   // bytes fit the budget; `keep` (the hierarchy the room is for) is never
   // evicted.  Caller holds mu.
   bool make_room(size_t need, const Resident* keep = nullptr) {
-    if ((double)(bytes + need) > cfg.hbm_budget_bytes) bytes -= pool.release_idle();
-    while ((double)(bytes + need) > cfg.hbm_budget_bytes) {
+    auto over = [&] { return (double)(bytes + need) > cfg.hbm_budget_bytes; };
+    if (over()) bytes -= pool.release_idle();
+    // then idle workspace clones, those of the least recently used hierarchy
+    // first (a clone is rebuilt in milliseconds, a hierarchy needs a setup)
+    while (over()) {
+      Resident* from = nullptr;
+      for (auto& kv : resident) {
+        Resident* R = kv.second;
+        if (R != keep && !R->spare.empty() && (!from || R->last_use < from->last_use)) from = R;
+      }
+      if (!from) break;
+      amg_hier* c = from->spare.back();
+      from->spare.pop_back();
+      const size_t b = c->bytes;
+      free_clone(c);
+      from->clone_bytes -= b;
+      bytes -= b;
+    }
+    while (over()) {
       Resident* victim = nullptr;
       int vid = 0;
       for (auto& kv : resident) {
