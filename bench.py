@@ -654,7 +654,7 @@ def run_serve_stream(args, amg, torch):
     print(f"[bench] stream: {nreq} requests, {len(graphs)} graphs, {nrhs} right-hand sides, {dof} DOF, "
           f"Poisson {rate:.2f} req/s", file=sys.stderr, flush=True)
     pmx = amg.amg_params_default(degree=4, agg_size=8, precision="mixed")
-    cfg = amg.amg_serve_cfg_default(pmx, mode="batched", hbm_budget_bytes=200e9,
+    cfg = amg.amg_serve_cfg_default(pmx, mode="batched", hbm_budget_bytes=args.serve_budget,
                                     iters_per_step=args.serve_iters_per_step, max_slots=args.serve_slots)
     srv = amg.Server(cfg)
     comps, sample = [], {}
@@ -747,6 +747,8 @@ def run_serve_stream(args, amg, torch):
         "peak_bytes": stats["peak_bytes"],
         "err_A_vs_oracle": err,
         "by_kind": by_kind,
+        "max_in_flight": stats["max_in_flight"],
+        "loop_s": {k: round(stats[k], 2) for k in ("schedule_s", "admit_s", "release_s", "iterate_s")},
     }
     print(f"[bench] stream batched_mixed: {json.dumps(res)}", file=sys.stderr, flush=True)
     out = {
@@ -765,8 +767,8 @@ def run_serve_stream(args, amg, torch):
         "config": {
             "workload": f"served stream: {nreq} requests (30 % new graphs: random geometric graphs n in [1e3, 2e5] "
                         f"and 2D grids of side 256..1024; others 1..32 right-hand sides on an earlier graph), Poisson "
-                        f"arrivals at {rate:.2f} req/s, submitted one at a time to the incremental server, 200 GB "
-                        f"budget, batched mixed precision, agg 8, degree 4, tol 1e-8",
+                        f"arrivals at {rate:.2f} req/s, submitted one at a time to the incremental server, "
+                        f"{args.serve_budget / 1e9:.0f} GB budget, batched mixed precision, agg 8, degree 4, tol 1e-8",
             "requests": nreq,
             "graphs": len(graphs),
             "rhs": nrhs,
@@ -806,6 +808,8 @@ def main():
                          "incremental server (batched mixed precision only)")
     ap.add_argument("--serve-rate", type=float, default=3.72,
                     help="arrival rate (requests/s) of --serve-stream")
+    ap.add_argument("--serve-budget", type=float, default=200e9,
+                    help="device memory budget (bytes) of --serve-stream")
     ap.add_argument("--layout", default=None,
                     help="fixed sliced-ELL layout 'H,K,S' (slice height, lanes per row, sorted 0/1) "
                          "instead of the autotuner")

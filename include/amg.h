@@ -406,6 +406,13 @@ typedef struct {
   int32_t evictions;
   int32_t setups;
   int32_t steps;
+  int32_t max_in_flight;    /* most right-hand sides iterating at once    */
+  double schedule_s;        /* serve loop time building launch schedules  */
+  double admit_s;           /* serve loop time admitting right-hand sides
+                               (workspace clones, copies)                 */
+  double release_s;         /* serve loop time releasing memory           */
+  double iterate_s;         /* serve loop time queueing and waiting for
+                               rounds of outer iterations                 */
 } amg_serve_stats;
 
 /* Defaults: amg_params_default, 200e9 bytes, 256 slots, batched, 2

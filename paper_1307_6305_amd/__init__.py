@@ -185,6 +185,11 @@ class amg_serve_stats(ctypes.Structure):
         ("evictions", ctypes.c_int32),
         ("setups", ctypes.c_int32),
         ("steps", ctypes.c_int32),
+        ("max_in_flight", ctypes.c_int32),
+        ("schedule_s", ctypes.c_double),
+        ("admit_s", ctypes.c_double),
+        ("release_s", ctypes.c_double),
+        ("iterate_s", ctypes.c_double),
     ]
 
 
@@ -422,7 +427,9 @@ def _completion_dict(c) -> dict:
 
 def _stats_dict(stats) -> dict:
     return {"wall_s": stats.wall_s, "peak_bytes": stats.peak_bytes, "evictions": stats.evictions,
-            "setups": stats.setups, "steps": stats.steps}
+            "setups": stats.setups, "steps": stats.steps, "max_in_flight": stats.max_in_flight,
+            "schedule_s": stats.schedule_s, "admit_s": stats.admit_s, "release_s": stats.release_s,
+            "iterate_s": stats.iterate_s}
 
 
 class Server:

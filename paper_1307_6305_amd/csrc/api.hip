@@ -14,6 +14,14 @@ thread_local std::string g_last_error;
 void set_last_error(const std::string& m) { g_last_error = m; }
 
 int32_t dalloc(amg_hier* h, void** p, size_t bytes) {
+  if (h->arena) {
+    const size_t at = (h->arena_used + 255) & ~size_t(255);
+    if (at + bytes <= h->arena_cap) {
+      *p = h->arena + at;
+      h->arena_used = at + bytes;
+      return AMG_OK;
+    }
+  }
   void* q = nullptr;
   hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess) {
@@ -43,6 +51,18 @@ int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s) {
   c->amli_g0 = h->amli_g0;
   c->amli_g1 = h->amli_g1;
   c->parent = h;
+  // the parent's workspace, with room for the 256-byte alignment of each of
+  // its buffers (several per level); a clone that outgrows it falls back to
+  // separate allocations
+  const size_t cap = h->ws_bytes + 256 * (32 * (size_t)h->lv.size() + 64);
+  void* a = nullptr;
+  if (hipMalloc(&a, cap) == hipSuccess) {
+    c->arena = static_cast<char*>(a);
+    c->arena_cap = cap;
+    c->bytes += cap;
+  } else {
+    (void)hipGetLastError();
+  }
   const int32_t st = prepare_solve(c, s);
   if (st != AMG_OK) {
     free_clone(c);
@@ -63,6 +83,7 @@ void free_clone(amg_hier* c) {
   destroy_graphs(c);
   if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
   for (void* p : c->allocs) (void)hipFree(p);
+  if (c->arena) (void)hipFree(c->arena);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   delete c;
 }

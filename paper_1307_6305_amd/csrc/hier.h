@@ -82,7 +82,11 @@ struct amg_hier {
 
   amg_hier_desc desc{};
   std::vector<void*> allocs;
-  size_t bytes = 0;     // device bytes owned (allocs)
+  size_t bytes = 0;     // device bytes owned (allocs and arena)
+  // A workspace clone takes its buffers from one block (one allocation and
+  // one release per clone: each release waits for the device to drain).
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
   size_t ws_bytes = 0;  // of which the solve workspace (what a clone costs)
 };
 

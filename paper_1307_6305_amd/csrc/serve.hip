@@ -125,6 +125,9 @@ struct Req {
   std::vector<double> w, d;
 };
 
+// Fraction of the memory budget that releases bring the server down to.
+constexpr double kLowWater = 0.9;
+
 struct Server {
   amg_serve_cfg cfg;
   hipStream_t s = nullptr;       // solve stream
@@ -132,7 +135,9 @@ struct Server {
   int device = 0;
   clk::time_point t0;
   size_t bytes = 0, peak = 0;
-  int evictions = 0, setups = 0, steps = 0;
+  int evictions = 0, setups = 0, steps = 0, max_in_flight = 0;
+  // where the serve loop's time goes (seconds)
+  double t_schedule = 0.0, t_admit = 0.0, t_release = 0.0, t_iterate = 0.0;
 
   std::map<int, Resident*> resident;
   VecPool pool;                     // slot vectors (serve loop thread only)
@@ -225,10 +230,22 @@ struct Server {
   // evicted.  Caller holds mu.
   bool make_room(size_t need, const Resident* keep = nullptr) {
     auto over = [&] { return (double)(bytes + need) > cfg.hbm_budget_bytes; };
-    if (over()) bytes -= pool.release_idle();
+    if (!over()) return true;
+    // Once the budget binds, release down to a low-water mark (90 % of the
+    // budget) rather than just enough: every release waits for the device to
+    // drain (hipFree), so releasing in bulk pays that wait once for many
+    // admissions instead of once per admission.
+    auto over_low = [&] { return (double)(bytes + need) > kLowWater * cfg.hbm_budget_bytes; };
+    const auto tr0 = clk::now();
+    struct Tally {  // adds the time spent here to t_release however it returns
+      double& t;
+      clk::time_point t0;
+      ~Tally() { t += std::chrono::duration<double>(clk::now() - t0).count(); }
+    } tally{t_release, tr0};
+    bytes -= pool.release_idle();
     // then idle workspace clones, those of the least recently used hierarchy
     // first (a clone is rebuilt in milliseconds, a hierarchy needs a setup)
-    while (over()) {
+    while (over_low()) {
       Resident* from = nullptr;
       for (auto& kv : resident) {
         Resident* R = kv.second;
@@ -434,6 +451,8 @@ struct Server {
         //     later requests on resident graphs
         fresh.clear();
         bool stop = false;
+        const auto ta0 = clk::now();
+        const double rel0 = t_release;
         for (size_t k = 0; k < pending.size() && !stop;) {
           Pending& pd = pending[k];
           Req* rq = pd.rq;
@@ -531,11 +550,15 @@ struct Server {
           }
           ++k;
         }
+        // (releases made for admissions are counted in t_release)
+        t_admit += std::chrono::duration<double>(clk::now() - ta0).count() - (t_release - rel0);
         // --- start the new slots: r = f - A u, activation
         if (!fresh.empty()) {
           std::vector<BatchItem> items;
           for (const Slot& sl : fresh) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+          const auto tb0 = clk::now();
           AMG_TRY(schedule_build(&sched_aux, SCHED_INIT, items, s));
+          t_schedule += std::chrono::duration<double>(clk::now() - tb0).count();
           hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, d_nactive);
           AMG_TRY(schedule_run(&sched_aux, ctl, s));
           for (const Slot& sl : fresh) active.push_back(sl);
@@ -560,10 +583,14 @@ struct Server {
         if (membership_changed || 2 * active.size() < sched_items) {
           std::vector<BatchItem> items;
           for (const Slot& sl : active) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+          const auto tb0 = clk::now();
           AMG_TRY(schedule_build(&sched_iter, SCHED_ITER, items, s));
+          t_schedule += std::chrono::duration<double>(clk::now() - tb0).count();
           sched_items = active.size();
           membership_changed = false;
         }
+        max_in_flight = std::max(max_in_flight, (int)active.size());
+        const auto ti0 = clk::now();
         for (int k = 0; k < std::max(1, cfg.iters_per_step); ++k) AMG_TRY(schedule_run(&sched_iter, ctl, s));
         ++steps;
         // --- retire converged slots
@@ -571,12 +598,15 @@ struct Server {
         for (size_t i = 0; i < active.size(); ++i)
           AMG_HIP(hipMemcpyAsync(&hst[i], active[i].st, sizeof(ItemState), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
+        t_iterate += std::chrono::duration<double>(clk::now() - ti0).count();
         std::vector<Slot> done, keep;
         for (size_t i = 0; i < active.size(); ++i) (hst[i].active ? keep : done).push_back(active[i]);
         if (!done.empty()) {
           std::vector<BatchItem> items;
           for (const Slot& sl : done) items.push_back(BatchItem{sl.ws, sl.f, sl.u, sl.st});
+          const auto tb0 = clk::now();
           AMG_TRY(schedule_build(&sched_aux, SCHED_FINAL, items, s));
+          t_schedule += std::chrono::duration<double>(clk::now() - tb0).count();
           AMG_TRY(schedule_run(&sched_aux, ctl, s));
           std::vector<ItemState> fst(done.size());
           for (size_t i = 0; i < done.size(); ++i)
@@ -830,6 +860,11 @@ struct Server {
     st->evictions = evictions;
     st->setups = setups;
     st->steps = steps;
+    st->max_in_flight = max_in_flight;
+    st->schedule_s = t_schedule;
+    st->admit_s = t_admit;
+    st->release_s = t_release;
+    st->iterate_s = t_iterate;
   }
 };
 

@@ -1773,7 +1773,9 @@ int32_t prepare_solve_impl(amg_hier* h, hipStream_t s) {
   AMG_TRY(dalloc(h, &h->counter, 1));
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, h->counter);
   AMG_HIP(hipGetLastError());
-  AMG_HIP(hipHostMalloc((void**)&h->host_scal, 64 * sizeof(double), hipHostMallocCoherent));
+  // the single-system solve's pinned mirror of its stopping test (workspace
+  // clones serve batches, which keep their state on the device)
+  if (!h->parent) AMG_HIP(hipHostMalloc((void**)&h->host_scal, 64 * sizeof(double), hipHostMallocCoherent));
   AMG_HIP(hipStreamSynchronize(s));
   if (h->p.cycle == AMG_CYCLE_AMLI && h->amli_g0.empty()) {
     // the cycle on each level runs through device-wide kernels here: the tail
