@@ -325,6 +325,87 @@ __global__ void __launch_bounds__(kBatchRows * 4) k_batch_mat(const BatchOp* __r
   batch_mat_tile<VT, MT, TYPE>(op, (b - op.first_block) / op.stride, partials, red, stage);
 }
 
+// One tile of a group of G ops that share a matrix (the right-hand sides of one
+// hierarchy): the lane loads its row's entries once -- when the slice is at
+// most one batch wide -- and applies them to every op of the group in turn,
+// each with the arithmetic of the op's own row step (the same bits as alone).
+// Wider slices take every op through its usual tile.
+template <typename VT, typename MT, int TYPE, int K>
+__device__ __forceinline__ void batch_group_tile(const BatchOp* __restrict__ ops, int g0, int G, int tile,
+                                                 double* partials, double* red, double* stage) {
+  const BatchOp& o0 = ops[g0];
+  const int slot = tile * kBatchRows + (threadIdx.x / K);
+  const int lane = threadIdx.x % K;
+  if (!(threadIdx.x < kBatchRows * K && slot < o0.n)) return;  // these steps do not reduce
+  const Mat<MT>& A = op_mat<MT>(o0);
+  if (A.width[slot >> A.lc] > OffPre<K, MT>::U) {
+    for (int g = 0; g < G; ++g) {
+      const BatchOp& op = ops[g0 + g];
+      if (op_runs(op.type, *op.st)) batch_mat_tile<VT, MT, TYPE>(op, tile, partials, red, stage);
+    }
+    return;
+  }
+  OffPre<K, MT> P;
+  P.load(A, slot, lane);
+  for (int g = 0; g < G; ++g) {
+    const BatchOp& op = ops[g0 + g];
+    if (!op_runs(op.type, *op.st)) continue;
+    if constexpr (TYPE == B_CHEB_NEXT) {
+      if (op.i2)
+        row_cheb_next<VT, MT, double, true, false, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const double*)op.b,
+                                                                   (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.i0, P);
+      else
+        row_cheb_next<VT, MT, VT, true, false, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b,
+                                                               (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.i0, P);
+    } else if constexpr (TYPE == B_CHEB_FIRST) {
+      const VT* e = (const VT*)op.w.p[0];
+      const int* agg = e ? op.T.agg : nullptr;
+      if (op.i2)
+        row_cheb_first<VT, MT, double, true, OffPre<K, MT>>(A, slot, lane, (const double*)op.a, (VT*)op.c, (VT*)op.d,
+                                                            op.f0, op.f1, op.f2, op.f3, op.i0, op.i1, e, agg, P);
+      else
+        row_cheb_first<VT, MT, VT, true, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0,
+                                                        op.f1, op.f2, op.f3, op.i0, op.i1, e, agg, P);
+    } else if constexpr (TYPE == B_RESIDUAL) {
+      const VT* e = (const VT*)op.w.p[0];
+      if (e) {
+        if (op.i2)
+          (void)row_residual_p<VT, MT, double, true, OffPre<K, MT>>(A, slot, lane, (const double*)op.a,
+                                                                    (const VT*)op.b, e, op.T.agg, (VT*)op.c, P);
+        else
+          (void)row_residual_p<VT, MT, VT, true, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b, e,
+                                                                op.T.agg, (VT*)op.c, P);
+      } else if (op.i2) {
+        (void)row_residual<VT, MT, double, true, OffPre<K, MT>>(A, slot, lane, (const double*)op.a, (const VT*)op.b,
+                                                                (VT*)op.c, P);
+      } else {
+        (void)row_residual<VT, MT, VT, true, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b,
+                                                            (VT*)op.c, P);
+      }
+    }
+  }
+}
+
+// Grouped matrix steps: block b takes one tile for the group of ops that
+// starts at block_op[b] (stride = the group's size, first_block its first
+// block).
+template <typename VT, typename MT, int TYPE>
+__global__ void __launch_bounds__(kBatchRows * 4) k_batch_mat_group(const BatchOp* __restrict__ ops,
+                                                             const int* __restrict__ block_op, double* partials) {
+  __shared__ double red[16 * 8];
+  __shared__ double stage[2 * kBatchRows];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int g0 = block_op[b];
+  const BatchOp& o0 = ops[g0];
+  const int tile = b - o0.first_block;
+  if (o0.A64.lk == 0)
+    batch_group_tile<VT, MT, TYPE, 1>(ops, g0, o0.stride, tile, partials, red, stage);
+  else if (o0.A64.lk == 1)
+    batch_group_tile<VT, MT, TYPE, 2>(ops, g0, o0.stride, tile, partials, red, stage);
+  else
+    batch_group_tile<VT, MT, TYPE, 4>(ops, g0, o0.stride, tile, partials, red, stage);
+}
+
 template <typename VT>
 __global__ void __launch_bounds__(kBatchRows) k_batch_vec(const BatchOp* __restrict__ ops, const int* __restrict__ block_op,
                                                    double* partials) {
@@ -459,8 +540,13 @@ __global__ void k_batch_reset(int* nactive) { *nactive = 0; }
 // ------------------------------------------------------------------ schedule
 }  // namespace
 
+// Grouped matrix steps: at most kGroupMax ops per block, on levels of at
+// least kGroupMinTiles tiles.
+constexpr int kGroupMax = 8;
+constexpr int kGroupMinTiles = 1024;
+
 struct Launch {
-  int kind;  // 0 vector step, 4 matrix step, 1 coarse, 2 tail, 3 finish
+  int kind;  // 0 vector step, 4 matrix step, 5 grouped matrix step, 1 coarse, 2 tail, 3 finish
   int optype;  // the op type of a step launch
   int op0, nops;
   int map0, nblocks;  // block map slice (step) / finish list slice
@@ -570,7 +656,43 @@ struct Builder {
     L.nops = (int)v.size();
     L.map0 = (int)map.size();
     int parts = 0, blocks = 0;
-    for (size_t q0 = 0; q0 < v.size();) {
+    // Grouped layout (kind 5): one block per tile and group of at most
+    // kGroupMax ops -- for steps that do not reduce, when some group of at
+    // least two ops spans kGroupMinTiles tiles (smaller levels keep one block
+    // per op and tile: a block's ops run one after the other).
+    bool grouped = false;
+    if (L.kind == 4 && !reduces &&
+        (L.optype == B_CHEB_NEXT || L.optype == B_CHEB_FIRST || L.optype == B_RESIDUAL)) {
+      for (size_t q0 = 0; q0 < v.size();) {
+        size_t q1 = q0 + 1;
+        while (q1 < v.size() && group_of[q1] == group_of[q0]) ++q1;
+        if (q1 - q0 >= 2 && nblk(v[q0].n, kBatchRows) >= kGroupMinTiles) grouped = true;
+        q0 = q1;
+      }
+    }
+    if (grouped) {
+      L.kind = 5;
+      for (size_t q0 = 0; q0 < v.size();) {
+        size_t q1 = q0 + 1;
+        while (q1 < v.size() && group_of[q1] == group_of[q0]) ++q1;
+        const int T = nblk(v[q0].n, kBatchRows);
+        const int gmax = T >= kGroupMinTiles ? kGroupMax : 1;
+        for (size_t a = q0; a < q1; a += gmax) {
+          const size_t e = std::min(q1, a + gmax);
+          for (size_t q = a; q < e; ++q) {
+            BatchOp& o = v[q];
+            o.blocks = T;
+            o.first_block = blocks;
+            o.stride = (int)(e - a);
+            o.part = 0;
+          }
+          for (int t = 0; t < T; ++t) map.push_back(L.op0 + (int)a);
+          blocks += T;
+        }
+        q0 = q1;
+      }
+    }
+    for (size_t q0 = 0; q0 < v.size() && !grouped;) {
       size_t q1 = q0 + 1;
       while (q1 < v.size() && group_of[q1] == group_of[q0]) ++q1;
       const int G = (int)(q1 - q0);
@@ -1008,6 +1130,17 @@ int32_t run_impl(const Schedule* S, const BatchCtl& ctl, hipStream_t s) {
         else
           hipLaunchKernelGGL((k_batch_mat<VT, MT, 0>), dim3(L.nblocks), dim3(L.threads), 0, s, D->ops,
                              D->map + L.map0, D->partials);
+        break;
+      case 5:
+        if (L.optype == B_CHEB_NEXT)
+          hipLaunchKernelGGL((k_batch_mat_group<VT, MT, B_CHEB_NEXT>), dim3(L.nblocks), dim3(L.threads), 0, s,
+                             D->ops, D->map + L.map0, D->partials);
+        else if (L.optype == B_CHEB_FIRST)
+          hipLaunchKernelGGL((k_batch_mat_group<VT, MT, B_CHEB_FIRST>), dim3(L.nblocks), dim3(L.threads), 0, s,
+                             D->ops, D->map + L.map0, D->partials);
+        else
+          hipLaunchKernelGGL((k_batch_mat_group<VT, MT, B_RESIDUAL>), dim3(L.nblocks), dim3(L.threads), 0, s,
+                             D->ops, D->map + L.map0, D->partials);
         break;
       case 1:
         hipLaunchKernelGGL((k_batch_coarse<VT>), dim3(L.nops), dim3(TPB), 0, s, D->ops + L.op0);

@@ -248,6 +248,65 @@ __device__ __forceinline__ AT offdiag(const Mat<MT>& A, int slot, int j, const X
   return offdiag_a<AT, GLOBAL>(A, slot, j, XPlain<XT>{x});
 }
 
+// Where a row step takes its off-diagonal sum from: the matrix in its layout
+// (OffMat), or entries a caller has already loaded for this lane (OffPre:
+// rows whose slice is at most one batch of 8 / K entries per lane wide, the
+// loads offdiag_k issues for its first and only batch, added the same way --
+// the same bits).  The batched executor loads a row's entries once and
+// applies them to every right-hand side that shares the matrix.
+template <bool G>
+struct OffMat {
+  template <typename AT, typename MT, typename XA>
+  __device__ __forceinline__ AT sum(const Mat<MT>& A, int slot, int j, const XA& x) const {
+    return offdiag_a<AT, G>(A, slot, j, x);
+  }
+};
+
+template <int K, typename MT>
+struct OffPre {
+  static constexpr int U = 8 / K;
+  int cv[U];
+  MT vv[U];
+  int wd;  // the slice's width in steps of the lane (<= U)
+  // the entries of the lane of `slot` (its one batch), as offdiag_k loads them
+  __device__ __forceinline__ void load(const Mat<MT>& A, int slot, int j) {
+    const int s = slot >> A.lc, p = slot & ((1 << A.lc) - 1);
+    const int stride = K << A.lc;
+    const int base = A.off[s] + p * K + j;
+    wd = A.width[s];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int tt = min(u, wd - 1) * stride;
+      cv[u] = A.col[base + tt];
+      vv[u] = A.val[base + tt];
+    }
+  }
+  template <typename AT, typename MT2, typename XA>
+  __device__ __forceinline__ AT sum(const Mat<MT2>&, int, int, const XA& x) const {
+    AT acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = (AT)0;
+    AT xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = (AT)x(cv[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < wd) acc[u] = fmadd((AT)vv[u], (AT)xv[u], acc[u]);
+    AT sum;
+    if constexpr (K == 1) {
+      sum = ((acc[0] + acc[4]) + (acc[2] + acc[6])) + ((acc[1] + acc[5]) + (acc[3] + acc[7]));
+    } else if constexpr (K == 2) {
+      sum = (acc[0] + acc[2]) + (acc[1] + acc[3]);
+      sum += __shfl_xor(sum, 1, 64);
+    } else {
+      sum = acc[0] + acc[1];
+      sum += __shfl_xor(sum, 2, 64);
+      sum += __shfl_xor(sum, 1, 64);
+    }
+    return sum;
+  }
+};
+
 template <typename MT>
 __device__ __forceinline__ int row_at(const Mat<MT>& A, int slot) {
   return A.perm ? A.perm[slot] : slot;
@@ -260,17 +319,17 @@ __device__ __forceinline__ int row_at(const Mat<MT>& A, int slot) {
 //
 // With e and agg given (accumulating steps only), y holds x before the
 // prolongation of a coarse correction: y is read as y_r + e_{agg(r)}.
-template <typename VT, typename MT, typename RT, bool G = true>
+template <typename VT, typename MT, typename RT, bool G = true, typename OD = OffMat<G>>
 __device__ __forceinline__ void row_cheb_first(const Mat<MT>& A, int slot, int j, const RT* __restrict__ w0, VT* w1,
                                                VT* y, double theta, double inv_eta, double c0, double c1, int accum,
                                                int store, const VT* __restrict__ e = nullptr,
-                                               const int* __restrict__ agg = nullptr) {
+                                               const int* __restrict__ agg = nullptr, const OD& od = OD()) {
   using AT = VT;
   const int r = row_at(A, slot);
   const AT x0 = (AT)w0[r];
   const AT d = (AT)A.D[r];
   const AT y0 = accum ? (AT)(e ? (VT)(y[r] + e[agg[r]]) : y[r]) : (AT)0;
-  const AT off = offdiag<AT, G>(A, slot, j, w0);
+  const AT off = od.template sum<AT>(A, slot, j, XPlain<RT>{w0});
   if (j) return;
   const AT ax = d * x0 - off;
   const AT t = (ax - (AT)theta * x0) * (AT)inv_eta;
@@ -336,17 +395,17 @@ __device__ __forceinline__ void st_row(T* p, T v) {
 // NT (levels far larger than the caches): the row's own operands D_r,
 // w_{k-1,r}, y_r and its results are streamed non-temporally, so that the
 // matrix and the gathered w_k stay cached; same arithmetic.
-template <typename VT, typename MT, typename PT, bool G = true, bool NT = false>
+template <typename VT, typename MT, typename PT, bool G = true, bool NT = false, typename OD = OffMat<G>>
 __device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int slot, int j, const VT* __restrict__ wk,
                                               const PT* wprev, VT* wnext, VT* y, double theta, double two_inv_eta,
-                                              double ck, int store) {
+                                              double ck, int store, const OD& od = OD()) {
   using AT = VT;
   const int r = row_at(A, slot);
   const AT xk = (AT)wk[r];
   const AT d = (AT)ld_row<NT>(A.D + r);
   const AT wp = (AT)ld_row<NT>(wprev + r);
   const AT y0 = (AT)ld_row<NT>(y + r);
-  const AT off = offdiag<AT, G>(A, slot, j, wk);
+  const AT off = od.template sum<AT>(A, slot, j, XPlain<VT>{wk});
   if (j) return;
   const AT ax = d * xk - off;
   const AT t = (ax - (AT)theta * xk) * (AT)two_inv_eta - wp;
@@ -355,15 +414,15 @@ __device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int slot, int j,
 }
 
 // s = f - A x; returns the row in the writing lane, -1 in the others
-template <typename VT, typename MT, typename RT, bool G = true>
+template <typename VT, typename MT, typename RT, bool G = true, typename OD = OffMat<G>>
 __device__ __forceinline__ int row_residual(const Mat<MT>& A, int slot, int j, const RT* __restrict__ f,
-                                            const VT* __restrict__ x, VT* s) {
+                                            const VT* __restrict__ x, VT* s, const OD& od = OD()) {
   using AT = VT;
   const int r = row_at(A, slot);
   const AT xr = (AT)x[r];
   const AT d = (AT)A.D[r];
   const AT fr = (AT)f[r];
-  const AT off = offdiag<AT, G>(A, slot, j, x);
+  const AT off = od.template sum<AT>(A, slot, j, XPlain<VT>{x});
   if (j) return -1;
   const AT ax = d * xr - off;
   s[r] = (VT)(fr - ax);
@@ -372,17 +431,17 @@ __device__ __forceinline__ int row_residual(const Mat<MT>& A, int slot, int j, c
 
 // s = f - A (x + P e): the residual after the prolongation of the coarse
 // correction e, without writing x + P e (the next smoothing step adds e).
-template <typename VT, typename MT, typename RT, bool G = true>
+template <typename VT, typename MT, typename RT, bool G = true, typename OD = OffMat<G>>
 __device__ __forceinline__ int row_residual_p(const Mat<MT>& A, int slot, int j, const RT* __restrict__ f,
                                               const VT* __restrict__ x, const VT* __restrict__ e,
-                                              const int* __restrict__ agg, VT* s) {
+                                              const int* __restrict__ agg, VT* s, const OD& od = OD()) {
   using AT = VT;
   const XProlong<VT> X{x, e, agg};
   const int r = row_at(A, slot);
   const AT xr = (AT)X(r);
   const AT d = (AT)A.D[r];
   const AT fr = (AT)f[r];
-  const AT off = offdiag_a<AT, G>(A, slot, j, X);
+  const AT off = od.template sum<AT>(A, slot, j, X);
   if (j) return -1;
   const AT ax = d * xr - off;
   s[r] = (VT)(fr - ax);

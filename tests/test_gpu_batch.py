@@ -158,3 +158,45 @@ def test_batch_mis_neumann_items(amg):
         e = us[i].cpu().numpy() - res.x
         errA = np.sqrt(e @ oracle.apply_A(lo, e)) / np.sqrt(res.x @ oracle.apply_A(lo, res.x))
         assert errA <= 1e-6, (i, errA)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_grouped_rhs_on_a_large_level(amg, prec):
+    # several right-hand sides on one hierarchy whose finest level spans more
+    # than 1024 tiles of 64 rows: the batched executor loads each row's
+    # entries once for the group and applies them to every right-hand side;
+    # every item must give the bits it gives alone (where it is not grouped),
+    # in any mix, and converge like the one-at-a-time solve
+    g = inputs.grid2d(300)
+    g2 = inputs.rgg(4000, seed=inputs.seed_for(4, 5))
+    p = amg.amg_params_default(degree=4, agg_size=8, precision=prec)
+    h = amg.amg_setup(g.n, g.row_ptr, g.col, g.w, g.d, p)
+    h2 = amg.amg_setup(g2.n, g2.row_ptr, g2.col, g2.w, g2.d, p)
+    assert g.n >= 1024 * 64
+    fs = [_t(inputs.rhs(g.n, 90 + k)) for k in range(5)]
+    f2 = _t(inputs.rhs(g2.n, 99))
+    us = [torch.zeros_like(f) for f in fs]
+    u2 = torch.zeros_like(f2)
+    infos = amg.amg_solve_batch([h, h2, h, h, h, h], [fs[0], f2] + fs[1:], [us[0], u2] + us[1:])
+    for k in range(5):
+        info = infos[0] if k == 0 else infos[k + 1]
+        assert info["status"] == 0 and info["rel_res_true"] <= 1e-8, info
+        alone = torch.zeros_like(fs[k])
+        inf1 = amg.amg_solve_batch([h], [fs[k]], [alone])
+        assert inf1[0]["iters"] == info["iters"]
+        assert torch.equal(alone, us[k]), k
+    alone2 = torch.zeros_like(f2)
+    amg.amg_solve_batch([h2], [f2], [alone2])
+    assert torch.equal(alone2, u2)
+    # three of them in another mix (a group of three, reversed)
+    sub = [torch.zeros_like(fs[k]) for k in (4, 2, 0)]
+    amg.amg_solve_batch([h] * 3, [fs[4], fs[2], fs[0]], sub)
+    for j, k in enumerate((4, 2, 0)):
+        assert torch.equal(sub[j], us[k]), k
+    # against the one-at-a-time solve of the same system
+    u1 = torch.zeros_like(fs[1])
+    ref = amg.amg_solve(h, fs[1], u1)
+    assert abs(ref["iters"] - infos[2]["iters"]) <= 1
+    assert (torch.linalg.norm(u1 - us[1]) / torch.linalg.norm(u1)).item() <= 1e-6
+    h.close()
+    h2.close()
