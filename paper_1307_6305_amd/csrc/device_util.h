@@ -77,6 +77,20 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
+// red[0*K + k] + red[1*K + k] + ... + red[(nw-1)*K + k], added in that
+// order: all sixteen slots are loaded at once (one LDS round trip instead of
+// nw dependent ones) and the sums past nw are discarded, not added.
+template <int K>
+__device__ __forceinline__ double wave_partials_sum(const double* red, int k, int nw) {
+  double r[16];
+#pragma unroll
+  for (int w = 0; w < 16; ++w) r[w] = red[w * K + k];
+  double s = r[0];
+#pragma unroll
+  for (int w = 1; w < 16; ++w) s = w < nw ? s + r[w] : s;
+  return s;
+}
+
 // Block-wide sum of K values per thread (blockDim.x a multiple of 64, at most
 // 1024).  Returns the totals in thread 0; `red` is LDS scratch of 16*K doubles.
 template <int K>
@@ -91,11 +105,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double s = red[k];
-      for (int w = 1; w < nw; ++w) s += red[w * K + k];
-      v[k] = s;
-    }
+    for (int k = 0; k < K; ++k) v[k] = wave_partials_sum<K>(red, k, nw);
   }
 }
 
@@ -115,13 +125,8 @@ __device__ __forceinline__ void block_sum_k(double (&v)[K], int kn, double* red)
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k < kn) {
-        double s = red[k];
-        for (int w = 1; w < nw; ++w) s += red[w * K + k];
-        v[k] = s;
-      }
-    }
+    for (int k = 0; k < K; ++k)
+      if (k < kn) v[k] = wave_partials_sum<K>(red, k, nw);
   }
 }
 

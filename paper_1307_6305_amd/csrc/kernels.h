@@ -676,10 +676,9 @@ struct TailOp {
   Slots s0, s1;
 };
 
-// One op as the tail interpreter reads it from LDS: every operand is a byte
-// offset into the workgroup's LDS image, with the op's matrix (plain layout)
-// and transfer map resolved when the program is laid out, so that an op costs
-// a few scalar loads for its description.  Fields by op:
+// One op as the tail interpreter reads it: every operand is a byte offset
+// into the workgroup's LDS image, with the op's matrix (plain layout) and
+// transfer map resolved when the program is laid out.  Fields by op:
 //   CHEB_FIRST  a w0, c w1, d y, f0 theta, f1 1/eta, f2 c0, f3 c1, i0 accum,
 //               i1 store, i2 fold (e = coarse correction, agg)
 //   CHEB_NEXT   a w_k, b w_k-1, c w_k+1, d y, f0 theta, f1 2/eta, f2 c, i0 store
@@ -704,58 +703,22 @@ struct TailInstr {
 };
 static_assert(sizeof(TailInstr) == 128, "tail instructions are 128 bytes");
 
-// The packed form the kernel reads: LDS offsets (multiples of 16 below 1 MiB)
-// in 16-byte units, two to a word; flags and k beside the op type.
-//   w0 type | k << 8 | i2 << 16 | i3 << 17    w1 n    w2 i0    w3 i1
-//   w4 a | b     w5 c | d     w6 off | width     w7 col | val
-//   w8 D | agg   w9 members | member_off     w10 e | aux     w11 unused
-struct TailCode {
-  uint32_t w[12];
-  double f[4];
-};
-static_assert(sizeof(TailCode) == 80, "packed tail instructions are 80 bytes");
+// Instructions stay in device memory, in this form (nothing to decode), and
+// each op reads its own with scalar loads (constant address space: uniform,
+// read-only) into scalar registers: neither LDS bandwidth nor vector
+// registers, and every wave's per-op work on the scalar unit -- which the
+// compute unit's waves share -- is a handful of instructions.  The kernel
+// touches every line of the list once at start, so those reads hit the
+// scalar cache.
+typedef __attribute__((address_space(4))) const TailInstr ConstInstr;
+typedef __attribute__((address_space(4))) const uint32_t ConstWord;
 
-// Instructions are read with scalar loads from the program's device copy
-// (constant address space: uniform, read-only), so an op's description costs
-// neither LDS bandwidth nor vector registers; the next op's is loaded while
-// the current one runs.
-typedef __attribute__((address_space(4))) const TailCode ConstCode;
-
-__device__ __forceinline__ void code_fetch(const ConstCode* p, TailCode& c) {
-#pragma unroll
-  for (int i = 0; i < 12; ++i) c.w[i] = p->w[i];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) c.f[i] = p->f[i];
-}
-
-__device__ __forceinline__ TailInstr code_unpack(const TailCode& c) {
+__device__ __forceinline__ TailInstr instr_load(const ConstInstr* p) {
   TailInstr I;
-  I.type = (int)(c.w[0] & 0xFF);
-  I.k = (int)((c.w[0] >> 8) & 0xFF);
-  I.i2 = (int)((c.w[0] >> 16) & 1);
-  I.i3 = (int)((c.w[0] >> 17) & 1);
-  I.n = (int)c.w[1];
-  I.i0 = (int)c.w[2];
-  I.i1 = (int)c.w[3];
-  I.a = (c.w[4] & 0xFFFF) << 4;
-  I.b = (c.w[4] >> 16) << 4;
-  I.c = (c.w[5] & 0xFFFF) << 4;
-  I.d = (c.w[5] >> 16) << 4;
-  I.off = (c.w[6] & 0xFFFF) << 4;
-  I.width = (c.w[6] >> 16) << 4;
-  I.col = (c.w[7] & 0xFFFF) << 4;
-  I.val = (c.w[7] >> 16) << 4;
-  I.D = (c.w[8] & 0xFFFF) << 4;
-  I.agg = (c.w[8] >> 16) << 4;
-  I.members = (c.w[9] & 0xFFFF) << 4;
-  I.member_off = (c.w[9] >> 16) << 4;
-  I.e = (c.w[10] & 0xFFFF) << 4;
-  I.aux = (c.w[10] >> 16) << 4;
-  I.pad0 = I.pad1 = I.pad2 = 0;
-  I.f0 = c.f[0];
-  I.f1 = c.f[1];
-  I.f2 = c.f[2];
-  I.f3 = c.f[3];
+  ConstWord* w = reinterpret_cast<ConstWord*>(p);
+  uint32_t* d = reinterpret_cast<uint32_t*>(&I);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(TailInstr) / 4); ++i) d[i] = w[i];
   return I;
 }
 
@@ -772,7 +735,7 @@ struct TailCopy {
 struct TailProgram {
   int nops;
   int ncin;
-  const TailCode* ops;   // instruction list (device memory)
+  const TailInstr* ops;  // instruction list (device memory)
   uint32_t scal_off;     // LDS offset of the scalar area
   const TailCopy* cin;
   TailCopy cout;  // solution of the tail level, LDS -> device
@@ -797,12 +760,21 @@ __device__ __forceinline__ Mat<MT> instr_mat(const TailInstr& I, char* lds) {
 
 // Runs a recorded program in one workgroup; every op is a data-parallel loop
 // over rows followed by a workgroup barrier.  Reductions are workgroup
-// reductions (no grid synchronization needed).  The next op's description is
-// loaded while the current one runs.
+// reductions (no grid synchronization needed).
 template <typename VT, typename MT>
 __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double* red, double* sb, double* sy,
                                          bool copy_constants) {
   const int tid = threadIdx.x, bd = blockDim.x;
+  {
+    // one scalar load per 64-byte line of the instruction list, many in
+    // flight, overlapping the copy-in below; the value itself is not needed
+    ConstWord* w = (ConstWord*)(P.ops);
+    const int lines = P.nops * (int)(sizeof(TailInstr) / 64);
+    uint32_t acc = 0;
+#pragma unroll 16
+    for (int l = 0; l < lines; ++l) acc ^= w[16 * l];
+    __asm__ volatile("" : : "s"(acc));
+  }
   for (int c = copy_constants ? 0 : P.ncin - 1; c < P.ncin; ++c) {
     const TailCopy cp = P.cin[c];
     const int4* __restrict__ src = static_cast<const int4*>(cp.src);
@@ -821,12 +793,9 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
   __syncthreads();
   double* scal = lds_at<double>(lds, P.scal_off);
   const CoarseView C{P.nL, lds_at<const double>(lds, P.linv_off), lds_at<const double>(lds, P.linvt_off)};
-  const ConstCode* ops = (const ConstCode*)(P.ops);
-  TailCode next;
-  if (P.nops > 0) code_fetch(ops, next);
+  const ConstInstr* ops = (const ConstInstr*)(P.ops);
   for (int o = 0; o < P.nops; ++o) {
-    const TailInstr I = code_unpack(next);
-    if (o + 1 < P.nops) code_fetch(ops + o + 1, next);
+    const TailInstr I = instr_load(ops + o);
     switch (I.type) {
       case OP_CHEB_FIRST: {
         const Mat<MT> A = instr_mat<MT>(I, lds);

@@ -1363,32 +1363,6 @@ inline size_t aux_total(const std::vector<TailOp>& ops) {
 // auxiliary operand lists.
 inline size_t header_bytes(const std::vector<TailOp>& ops) { return round16(aux_total(ops) * sizeof(int32_t)); }
 
-// The kernel's packed form of an instruction (offsets in 16-byte units).
-inline bool pack_instr(const TailInstr& I, TailCode& c) {
-  std::memset(&c, 0, sizeof(c));
-  auto u = [](uint32_t off, bool& ok) -> uint32_t {
-    if ((off & 15) || (off >> 4) > 0xFFFF) ok = false;
-    return off >> 4;
-  };
-  bool ok = I.type >= 0 && I.type < 256 && I.k >= 0 && I.k < 256 && (I.i2 & ~1) == 0 && (I.i3 & ~1) == 0;
-  c.w[0] = (uint32_t)I.type | ((uint32_t)I.k << 8) | ((uint32_t)I.i2 << 16) | ((uint32_t)I.i3 << 17);
-  c.w[1] = (uint32_t)I.n;
-  c.w[2] = (uint32_t)I.i0;
-  c.w[3] = (uint32_t)I.i1;
-  c.w[4] = u(I.a, ok) | (u(I.b, ok) << 16);
-  c.w[5] = u(I.c, ok) | (u(I.d, ok) << 16);
-  c.w[6] = u(I.off, ok) | (u(I.width, ok) << 16);
-  c.w[7] = u(I.col, ok) | (u(I.val, ok) << 16);
-  c.w[8] = u(I.D, ok) | (u(I.agg, ok) << 16);
-  c.w[9] = u(I.members, ok) | (u(I.member_off, ok) << 16);
-  c.w[10] = u(I.e, ok) | (u(I.aux, ok) << 16);
-  c.f[0] = I.f0;
-  c.f[1] = I.f1;
-  c.f[2] = I.f2;
-  c.f[3] = I.f3;
-  return ok;
-}
-
 template <typename VT, typename MT>
 int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   h->tail_level = 0;
@@ -1517,8 +1491,6 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
       while (aux.size() & 3) aux.push_back(0);
     }
   }
-  std::vector<TailCode> code(ins.size());
-  for (size_t i = 0; i < ins.size(); ++i) ok = pack_instr(ins[i], code[i]) && ok;
   const uint32_t linv = lo(h->chol_inv);
   const uint32_t linvt = lo(h->chol_invT);
   const uint32_t scal_t = lo(h->scal);
@@ -1533,12 +1505,12 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   std::vector<char> head(header_bytes(ops), 0);
   if (!aux.empty()) std::memcpy(head.data() + aux_off, aux.data(), aux.size() * sizeof(int32_t));
   const size_t blob_bytes = std::max<size_t>(head.size(), const_end);
-  const size_t code_at = round16(blob_bytes) + 256;
+  const size_t code_at = ((blob_bytes + 63) & ~size_t(63)) + 256;  // instructions on 64-byte lines
   char* d_blob = nullptr;
   void* d_cin = nullptr;
-  AMG_TRY(dalloc(h, (void**)&d_blob, code_at + code.size() * sizeof(TailCode) + 16));
+  AMG_TRY(dalloc(h, (void**)&d_blob, code_at + ins.size() * sizeof(TailInstr) + 16));
   if (!head.empty()) AMG_HIP(hipMemcpyAsync(d_blob, head.data(), head.size(), hipMemcpyHostToDevice, s));
-  AMG_HIP(hipMemcpyAsync(d_blob + code_at, code.data(), code.size() * sizeof(TailCode), hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(d_blob + code_at, ins.data(), ins.size() * sizeof(TailInstr), hipMemcpyHostToDevice, s));
   for (const auto& c : consts)
     if (c.first->bytes > 0)
       AMG_HIP(hipMemcpyAsync(d_blob + c.second, c.first->g, c.first->bytes, hipMemcpyDeviceToDevice, s));
@@ -1552,7 +1524,7 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   std::memset(&P, 0, sizeof(P));
   P.nops = (int)ops.size();
   P.ncin = (int)cin.size();
-  P.ops = reinterpret_cast<const TailCode*>(d_blob + code_at);
+  P.ops = reinterpret_cast<const TailInstr*>(d_blob + code_at);
   P.scal_off = scal_t;
   P.cin = (const TailCopy*)d_cin;
   P.cout = TailCopy{h->ws[t].sol, sol_t, (int)round16(sizeof(VT) * h->lv[t].n)};
