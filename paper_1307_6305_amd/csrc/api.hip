@@ -35,6 +35,10 @@ int32_t dalloc(amg_hier* h, void** p, size_t bytes) {
   return AMG_OK;
 }
 
+// the parent's workspace, with room for the 256-byte alignment of each of
+// its buffers (several per level)
+size_t clone_bytes_of(const amg_hier* h) { return h->ws_bytes + 256 * (32 * (size_t)h->lv.size() + 64); }
+
 int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s) {
   amg_hier* c = new amg_hier();
   c->p = h->p;
@@ -51,10 +55,8 @@ int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s) {
   c->amli_g0 = h->amli_g0;
   c->amli_g1 = h->amli_g1;
   c->parent = h;
-  // the parent's workspace, with room for the 256-byte alignment of each of
-  // its buffers (several per level); a clone that outgrows it falls back to
-  // separate allocations
-  const size_t cap = h->ws_bytes + 256 * (32 * (size_t)h->lv.size() + 64);
+  // one arena; a clone that outgrows it falls back to separate allocations
+  const size_t cap = clone_bytes_of(h);
   void* a = nullptr;
   if (hipMalloc(&a, cap) == hipSuccess) {
     c->arena = static_cast<char*>(a);

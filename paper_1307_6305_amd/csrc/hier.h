@@ -136,6 +136,8 @@ size_t noalloc_max_rows();
 int32_t solve_batch(int nb, amg_hier* const* hs, const double* const* f, double* const* u, hipStream_t s,
                     amg_info* infos);
 void drop_batches_using(const amg_hier* h);
+// Device bytes a clone of h takes (its workspace arena).
+size_t clone_bytes_of(const amg_hier* h);
 int32_t make_clone(amg_hier* h, amg_hier** out, hipStream_t s);
 void free_clone(amg_hier* c);
 

@@ -307,6 +307,67 @@ struct OffPre {
   }
 };
 
+// The tail program's matrices: 64-row slices of one width PW for the whole
+// level (a multiple of 4; short rows padded with zero weights on the row's
+// own column), entry t of row r at ((r >> 6) * PW + t) * 64 + (r & 63), so
+// that no per-slice offset or width is read.  All loads of a row's entries
+// are issued before any product is formed, and the products go to four
+// chains, entry t to chain t mod 4, added at the end as (c0 + c1) + (c2 + c3)
+// -- the tail's own fixed order, whichever code path below runs.
+template <int PW, typename AT, typename MT, typename XA>
+__device__ __forceinline__ AT rowsum_pw(const int* __restrict__ c, const MT* __restrict__ v, const XA& x) {
+  int cc[PW];
+  AT vv[PW], xx[PW];
+#pragma unroll
+  for (int t = 0; t < PW; ++t) cc[t] = c[t * 64];
+#pragma unroll
+  for (int t = 0; t < PW; ++t) vv[t] = (AT)v[t * 64];
+#pragma unroll
+  for (int t = 0; t < PW; ++t) xx[t] = (AT)x(cc[t]);
+  AT a[4] = {(AT)0, (AT)0, (AT)0, (AT)0};
+#pragma unroll
+  for (int t = 0; t < PW; ++t) a[t & 3] = fmadd(vv[t], xx[t], a[t & 3]);
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+struct OffTail {
+  int pw;
+  template <typename AT, typename MT, typename XA>
+  __device__ __forceinline__ AT sum(const Mat<MT>& A, int slot, int, const XA& x) const {
+    const int base = (slot >> 6) * pw * 64 + (slot & 63);
+    const int* __restrict__ c = A.col + base;
+    const MT* __restrict__ v = A.val + base;
+    switch (pw) {
+      case 0:
+        return (AT)0;
+      case 4:
+        return rowsum_pw<4, AT>(c, v, x);
+      case 8:
+        return rowsum_pw<8, AT>(c, v, x);
+      case 12:
+        return rowsum_pw<12, AT>(c, v, x);
+      case 16:
+        return rowsum_pw<16, AT>(c, v, x);
+      default: {  // wider levels: four entries at a time, the same chains
+        AT a[4] = {(AT)0, (AT)0, (AT)0, (AT)0};
+        for (int t = 0; t < pw; t += 4) {
+          int cc[4];
+          AT vv[4], xx[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) cc[i] = c[(t + i) * 64];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) vv[i] = (AT)v[(t + i) * 64];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) xx[i] = (AT)x(cc[i]);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = fmadd(vv[i], xx[i], a[i]);
+        }
+        return (a[0] + a[1]) + (a[2] + a[3]);
+      }
+    }
+  }
+};
+
 template <typename MT>
 __device__ __forceinline__ int row_at(const Mat<MT>& A, int slot) {
   return A.perm ? A.perm[slot] : slot;
@@ -509,15 +570,15 @@ __device__ __forceinline__ void row_prolong(const Transfer& T, int i, const VT* 
 
 // q = A p for the row in `slot`; the writing lane returns the row and sets
 // v = (p_r q_r, p_r rv_r) in FP64, the other lanes return -1.
-template <typename VT, typename MT, typename RT, bool G = true>
+template <typename VT, typename MT, typename RT, bool G = true, typename OD = OffMat<G>>
 __device__ __forceinline__ int row_spmv_dots(const Mat<MT>& A, int slot, int j, const VT* __restrict__ p, VT* q,
-                                             const RT* __restrict__ rv, double (&v)[2]) {
+                                             const RT* __restrict__ rv, double (&v)[2], const OD& od = OD()) {
   using AT = VT;
   const int r = row_at(A, slot);
   const AT pr = (AT)p[r];
   const AT d = (AT)A.D[r];
   const double rr = (double)rv[r];
-  const AT off = offdiag<AT, G>(A, slot, j, p);
+  const AT off = od.template sum<AT>(A, slot, j, XPlain<VT>{p});
   if (j) return -1;
   const AT ap = d * pr - off;
   q[r] = (VT)ap;
@@ -677,8 +738,10 @@ struct TailOp {
 };
 
 // One op as the tail interpreter reads it: every operand is a byte offset
-// into the workgroup's LDS image, with the op's matrix (plain layout) and
-// transfer map resolved when the program is laid out.  Fields by op:
+// into the workgroup's LDS image, with the op's matrix and transfer map
+// resolved when the program is laid out; an op on a level's matrix has the
+// matrix's col, val and D offsets and, in `width`, its padded width PW (the
+// uniform-width layout of OffTail; `off` is unused).  Fields by op:
 //   CHEB_FIRST  a w0, c w1, d y, f0 theta, f1 1/eta, f2 c0, f3 c1, i0 accum,
 //               i1 store, i2 fold (e = coarse correction, agg)
 //   CHEB_NEXT   a w_k, b w_k-1, c w_k+1, d y, f0 theta, f1 2/eta, f2 c, i0 store
@@ -754,8 +817,8 @@ __device__ __forceinline__ T* lds_at(char* lds, uint32_t off) {
 
 template <typename MT>
 __device__ __forceinline__ Mat<MT> instr_mat(const TailInstr& I, char* lds) {
-  return Mat<MT>{I.n, 0, 6, 0, lds_at<const int>(lds, I.off), lds_at<const int>(lds, I.width),
-                 lds_at<const int>(lds, I.col), lds_at<const MT>(lds, I.val), lds_at<const MT>(lds, I.D), nullptr};
+  return Mat<MT>{I.n, 0, 6, 0, nullptr, nullptr, lds_at<const int>(lds, I.col), lds_at<const MT>(lds, I.val),
+                 lds_at<const MT>(lds, I.D), nullptr};
 }
 
 // Runs a recorded program in one workgroup; every op is a data-parallel loop
@@ -805,7 +868,8 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* e = I.i2 ? lds_at<const VT>(lds, I.e) : nullptr;
         const int* agg = I.i2 ? lds_at<const int>(lds, I.agg) : nullptr;
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_first<VT, MT, VT, false>(A, r, 0, w0, w1, y, I.f0, I.f1, I.f2, I.f3, I.i0, I.i1, e, agg);
+          row_cheb_first<VT, MT, VT, false, OffTail>(A, r, 0, w0, w1, y, I.f0, I.f1, I.f2, I.f3, I.i0, I.i1, e, agg,
+                                                     OffTail{(int)I.width});
         break;
       }
       case OP_CHEB_NEXT: {
@@ -815,7 +879,8 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         VT* wn = lds_at<VT>(lds, I.c);
         VT* y = lds_at<VT>(lds, I.d);
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_next<VT, MT, VT, false>(A, r, 0, wk, wp, wn, y, I.f0, I.f1, I.f2, I.i0);
+          row_cheb_next<VT, MT, VT, false, false, OffTail>(A, r, 0, wk, wp, wn, y, I.f0, I.f1, I.f2, I.i0,
+                                                           OffTail{(int)I.width});
         break;
       }
       case OP_SCALE_ADD: {
@@ -833,7 +898,8 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* f = lds_at<const VT>(lds, I.a);
         const VT* x = lds_at<const VT>(lds, I.b);
         VT* sv = lds_at<VT>(lds, I.c);
-        for (int r = tid; r < A.n; r += bd) (void)row_residual<VT, MT, VT, false>(A, r, 0, f, x, sv);
+        for (int r = tid; r < A.n; r += bd)
+          (void)row_residual<VT, MT, VT, false, OffTail>(A, r, 0, f, x, sv, OffTail{(int)I.width});
         break;
       }
       case OP_RESIDUAL_P: {
@@ -843,7 +909,8 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* e = lds_at<const VT>(lds, I.e);
         const int* agg = lds_at<const int>(lds, I.agg);
         VT* sv = lds_at<VT>(lds, I.c);
-        for (int r = tid; r < A.n; r += bd) (void)row_residual_p<VT, MT, VT, false>(A, r, 0, f, x, e, agg, sv);
+        for (int r = tid; r < A.n; r += bd)
+          (void)row_residual_p<VT, MT, VT, false, OffTail>(A, r, 0, f, x, e, agg, sv, OffTail{(int)I.width});
         break;
       }
       case OP_RESTRICT: {
@@ -855,14 +922,28 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
           VT acc = 0;
           int k = moff[J];
           const int k1 = moff[J + 1];
-          for (; k + 8 <= k1; k += 8) {  // eight members' loads in flight, added in order
-            VT v[8];
+          if (k1 - k <= 16) {
+            // every member's loads at once (indices clamped to the list),
+            // added in member order: the same sums as one at a time
+            const int last = k1 - 1;
+            int m[16];
+            VT v[16];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = sv[members[k + q]];
+            for (int q = 0; q < 16; ++q) m[q] = members[min(k + q, last)];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc += v[q];
+            for (int q = 0; q < 16; ++q) v[q] = sv[m[q]];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc = k + q < k1 ? acc + v[q] : acc;
+          } else {
+            for (; k + 8 <= k1; k += 8) {  // eight members' loads in flight, added in order
+              VT v[8];
+#pragma unroll
+              for (int q = 0; q < 8; ++q) v[q] = sv[members[k + q]];
+#pragma unroll
+              for (int q = 0; q < 8; ++q) acc += v[q];
+            }
+            for (; k < k1; ++k) acc += sv[members[k]];
           }
-          for (; k < k1; ++k) acc += sv[members[k]];
           b[J] = acc;
         }
         break;
@@ -931,7 +1012,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         double v[2] = {0.0, 0.0};
         for (int r = tid; r < A.n; r += bd) {
           double w[2];
-          (void)row_spmv_dots<VT, MT, VT, false>(A, r, 0, p, q, rv, w);
+          (void)row_spmv_dots<VT, MT, VT, false, OffTail>(A, r, 0, p, q, rv, w, OffTail{(int)I.width});
           v[0] += w[0];
           v[1] += w[1];
         }

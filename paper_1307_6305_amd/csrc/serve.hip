@@ -490,7 +490,7 @@ struct Server {
             } else if (!R->own_lent) {
               own = true;  // the hierarchy's own workspace is free
             } else {
-              extra += R->h->ws_bytes;
+              extra += clone_bytes_of(R->h);  // what make_clone allocates
             }
             if (!make_room(extra, R)) {
               if (active.empty() && fresh.empty()) {  // nothing will ever free memory: give up on it

@@ -1301,26 +1301,73 @@ int32_t solve_impl(amg_hier* h, const double* f, double* u, hipStream_t s, amg_i
 // below it), place the data it touches in LDS, and upload it.  The tail level
 // is the finest level t >= 1 with at most tail_rows rows whose levels t..L fit
 // in the LDS left over by the kernel's static arrays.
+// `g` names the buffer (the device array it mirrors); a constant buffer is
+// copied in from `host` when given, else from `g`.
 struct LdsBuf {
   const void* g;
   size_t bytes;
   bool copy_in;
+  const void* host = nullptr;
 };
 
 inline size_t round16(size_t b) { return (b + 15) & ~size_t(15); }
 
+// A tail level's matrix in the uniform-width layout the tail program reads
+// (OffTail): the level's plain layout (64-row slices, rows in order) with
+// every slice padded to the widest, rounded up to a multiple of 4, by zero
+// weights on the row's own column.
+struct TailMatHost {
+  int pw = -1;
+  std::vector<int> col;
+  std::vector<char> val;
+};
+
+template <typename MT>
+int32_t tail_mat_host(const Level& lv, hipStream_t s, TailMatHost& out) {
+  const int ns = lv.plain_nslices;
+  const Mat<MT> A = plain_mat_of<MT>(lv);
+  std::vector<int> w(ns), off(ns + 1), col((size_t)lv.plain_entries);
+  std::vector<MT> val((size_t)lv.plain_entries);
+  AMG_HIP(hipMemcpyAsync(w.data(), A.width, sizeof(int) * ns, hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipMemcpyAsync(off.data(), A.off, sizeof(int) * (ns + 1), hipMemcpyDeviceToHost, s));
+  if (!col.empty()) {
+    AMG_HIP(hipMemcpyAsync(col.data(), A.col, sizeof(int) * col.size(), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(val.data(), A.val, sizeof(MT) * val.size(), hipMemcpyDeviceToHost, s));
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+  int mw = 0;
+  for (int x : w) mw = std::max(mw, x);
+  const int pw = (mw + 3) & ~3;
+  const size_t ent = (size_t)ns * pw * 64;
+  out.pw = pw;
+  out.col.assign(ent, 0);
+  out.val.assign(sizeof(MT) * ent, 0);
+  MT* pv = reinterpret_cast<MT*>(out.val.data());
+  for (int sl = 0; sl < ns; ++sl)
+    for (int p = 0; p < 64; ++p) {
+      const int r = sl * 64 + p;
+      const int self = r < lv.n ? r : 0;
+      for (int t = 0; t < pw; ++t) {
+        const size_t i = ((size_t)sl * pw + t) * 64 + p;
+        const bool real = t < w[sl];
+        out.col[i] = real ? col[(size_t)off[sl] + (size_t)t * 64 + p] : self;
+        pv[i] = real ? val[(size_t)off[sl] + (size_t)t * 64 + p] : MT(0);
+      }
+    }
+  return AMG_OK;
+}
+
 template <typename VT, typename MT>
-void tail_buffers(const amg_hier* h, int t, std::vector<LdsBuf>& bufs) {
+void tail_buffers(const amg_hier* h, int t, const std::vector<TailMatHost>& mats, std::vector<LdsBuf>& bufs) {
   const size_t vt = sizeof(VT), mt = sizeof(MT);
   const int nu = h->p.inner_steps;
   for (int l = t; l < h->L; ++l) {
     const Level& lv = h->lv[l];
     const size_t n = lv.n;
     const Mat<MT> A = plain_mat_of<MT>(lv);
-    bufs.push_back({A.off, sizeof(int) * (lv.plain_nslices + 1), true});
-    bufs.push_back({A.width, sizeof(int) * lv.plain_nslices, true});
-    bufs.push_back({A.col, sizeof(int) * lv.plain_entries, true});
-    bufs.push_back({A.val, mt * lv.plain_entries, true});
+    const TailMatHost& M = mats[l];
+    bufs.push_back({A.col, sizeof(int) * M.col.size(), true, M.col.data()});
+    bufs.push_back({A.val, M.val.size(), true, M.val.data()});
     bufs.push_back({A.D, mt * n, true});
     bufs.push_back({lv.agg, sizeof(int) * n, true});
     bufs.push_back({lv.members, sizeof(int) * n, true});
@@ -1374,10 +1421,12 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   const size_t budget = (size_t)max_lds - static_lds;
   // LDS image: [instructions][auxiliary operand lists][level data ...]
   int t = 0;
+  std::vector<TailMatHost> mats(h->L);
   for (int cand = h->L - 1; cand >= 1; --cand) {
     if (h->lv[cand].n > h->p.tail_rows || h->lv[cand].n > kTailMaxRows || !h->lv[cand].plain_off) break;
+    AMG_TRY(tail_mat_host<MT>(h->lv[cand], s, mats[cand]));
     std::vector<LdsBuf> bufs;
-    tail_buffers<VT, MT>(h, cand, bufs);
+    tail_buffers<VT, MT>(h, cand, mats, bufs);
     std::vector<TailOp> ops;
     {
       Engine<VT, MT> E{h, s, &ops};
@@ -1405,7 +1454,7 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   const uint32_t aux_off = 0;
   uint64_t off = header_bytes(ops);
   std::vector<LdsBuf> bufs;
-  tail_buffers<VT, MT>(h, t, bufs);
+  tail_buffers<VT, MT>(h, t, mats, bufs);
   // image order: the header, then every constant buffer (one contiguous
   // region, copied in from one packed device blob), then the tail level's
   // right-hand side (the only per-call input), then the work vectors
@@ -1462,8 +1511,8 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
       const Transfer T = transfer_of(h, o.level);
       switch (o.type) {
         case OP_CHEB_FIRST: case OP_CHEB_NEXT: case OP_RESIDUAL: case OP_RESIDUAL_P: case OP_SPMV_DOTS:
-          I.off = lo(A.off);
-          I.width = lo(A.width);
+          I.off = 0;
+          I.width = (uint32_t)mats[o.level].pw;
           I.col = lo(A.col);
           I.val = lo(A.val);
           I.D = lo(A.D);
@@ -1513,7 +1562,8 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   AMG_HIP(hipMemcpyAsync(d_blob + code_at, ins.data(), ins.size() * sizeof(TailInstr), hipMemcpyHostToDevice, s));
   for (const auto& c : consts)
     if (c.first->bytes > 0)
-      AMG_HIP(hipMemcpyAsync(d_blob + c.second, c.first->g, c.first->bytes, hipMemcpyDeviceToDevice, s));
+      AMG_HIP(hipMemcpyAsync(d_blob + c.second, c.first->host ? c.first->host : c.first->g, c.first->bytes,
+                             c.first->host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
   std::vector<TailCopy> cin;
   cin.push_back(TailCopy{d_blob, 0, (int)round16(blob_bytes)});
   if (rhs_bytes) cin.push_back(TailCopy{rhs_t, (uint32_t)rhs_off, (int)rhs_bytes});
