@@ -79,7 +79,8 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 
 // red[0*K + k] + red[1*K + k] + ... + red[(nw-1)*K + k], added in that
 // order: all sixteen slots are loaded at once (one LDS round trip instead of
-// nw dependent ones) and the sums past nw are discarded, not added.
+// nw dependent ones), and the adds stop at nw (nw is uniform: a scalar
+// branch per slot, no chain of selects through the unused ones).
 template <int K>
 __device__ __forceinline__ double wave_partials_sum(const double* red, int k, int nw) {
   double r[16];
@@ -87,7 +88,10 @@ __device__ __forceinline__ double wave_partials_sum(const double* red, int k, in
   for (int w = 0; w < 16; ++w) r[w] = red[w * K + k];
   double s = r[0];
 #pragma unroll
-  for (int w = 1; w < 16; ++w) s = w < nw ? s + r[w] : s;
+  for (int w = 1; w < 16; ++w) {
+    if (w >= nw) break;
+    s += r[w];
+  }
   return s;
 }
 

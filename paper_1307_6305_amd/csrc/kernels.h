@@ -750,9 +750,11 @@ struct TailOp {
 //   RESTRICT    a s, c b, n coarse rows (members, member_off)
 //   PROLONG     a e, c x (agg)
 //   COARSE      a b, c x
-//   MULTIDOT    a z, k; aux: k vector offsets, k destination slots
+//   MULTIDOT    a z, k; aux: k vector offsets, k destination slots (k = 1:
+//               also b the vector, i0 the slot)
 //   SPMV_DOTS   a p, b r, c q, i0 i1 destination slots
 //   FCG_P       a z, c p, k; aux: k vector offsets, k dot slots, k rho slots
+//               (k = 1: also b the vector, i0 the dot slot, i1 the rho slot)
 //   FCG_XR      a p, b q, c x, d r, i0 rho slot, i1 gamma slot, i2 x_init, i3 update r
 struct TailInstr {
   int type, n, k, i0;
@@ -959,6 +961,15 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         coarse_apply<VT, VT>(C, lds_at<const VT>(lds, I.a), lds_at<VT>(lds, I.c), sb, sy);
         break;
       case OP_MULTIDOT: {
+        if (I.k == 1) {  // one product: its operand and slot are in the instruction (b, i0)
+          const VT* z = lds_at<const VT>(lds, I.a);
+          const VT* q = lds_at<const VT>(lds, I.b);
+          double v[1] = {0.0};
+          for (int j = tid; j < I.n; j += bd) v[0] += (double)z[j] * (double)q[j];
+          block_sum<1>(v, red);
+          if (tid == 0) scal[I.i0] = v[0];
+          break;
+        }
         const uint32_t* vo = lds_at<const uint32_t>(lds, I.aux);
         const int* so = lds_at<const int>(lds, I.aux + 4 * I.k);
         uint32_t qo[8];
@@ -983,6 +994,18 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         break;
       }
       case OP_FCG_P: {
+        if (I.k == 1) {  // one earlier direction: operand and slots in the instruction (b, i0, i1)
+          const double beta = fcg_beta(scal, I.i0, I.i1);
+          const VT* z = lds_at<const VT>(lds, I.a);
+          const VT* po = lds_at<const VT>(lds, I.b);
+          VT* p = lds_at<VT>(lds, I.c);
+          for (int j = tid; j < I.n; j += bd) {
+            double v = (double)z[j];
+            v -= beta * (double)po[j];
+            p[j] = (VT)v;
+          }
+          break;
+        }
         const uint32_t* vo = lds_at<const uint32_t>(lds, I.aux);
         const int* sd = lds_at<const int>(lds, I.aux + 4 * I.k);
         const int* sr = lds_at<const int>(lds, I.aux + 8 * I.k);

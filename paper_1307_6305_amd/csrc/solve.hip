@@ -1531,6 +1531,11 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
       I.i0 = o.s0.s[0];
       I.i1 = o.s0.s[1];
     }
+    if (o.k == 1 && (o.type == OP_MULTIDOT || o.type == OP_FCG_P)) {
+      I.b = lo(o.w.p[0]);
+      I.i0 = o.s0.s[0];
+      I.i1 = o.type == OP_FCG_P ? o.s1.s[0] : 0;
+    }
     if (aux_words(o)) {
       I.aux = aux_off + (uint32_t)(aux.size() * sizeof(int32_t));
       for (int j = 0; j < o.k; ++j) aux.push_back((int32_t)lo(o.w.p[j]));
