@@ -831,13 +831,16 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
                                          bool copy_constants) {
   const int tid = threadIdx.x, bd = blockDim.x;
   {
-    // one scalar load per 64-byte line of the instruction list, many in
-    // flight, overlapping the copy-in below; the value itself is not needed
+    // one scalar load per 64-byte line of the instruction list, the lines
+    // dealt out over the wavefronts (the scalar cache is shared) so that each
+    // has few loads in flight, overlapping the copy-in below; the value
+    // itself is not needed
     ConstWord* w = (ConstWord*)(P.ops);
     const int lines = P.nops * (int)(sizeof(TailInstr) / 64);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwave = bd >> 6;
     uint32_t acc = 0;
 #pragma unroll 16
-    for (int l = 0; l < lines; ++l) acc ^= w[16 * l];
+    for (int l = wave; l < lines; l += nwave) acc ^= w[16 * l];
     __asm__ volatile("" : : "s"(acc));
   }
   for (int c = copy_constants ? 0 : P.ncin - 1; c < P.ncin; ++c) {
