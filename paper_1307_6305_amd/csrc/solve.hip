@@ -1419,7 +1419,7 @@ int32_t prepare_tail(amg_hier* h, hipStream_t s) {
   const size_t static_lds = sizeof(double) * (16 * 8 + 2 * 1024) + 1024;  // red, sb, sy + margin
   if ((size_t)max_lds <= static_lds) return AMG_OK;
   const size_t budget = (size_t)max_lds - static_lds;
-  // LDS image: [instructions][auxiliary operand lists][level data ...]
+  // LDS image: [auxiliary operand lists][level data ...]
   int t = 0;
   std::vector<TailMatHost> mats(h->L);
   for (int cand = h->L - 1; cand >= 1; --cand) {
