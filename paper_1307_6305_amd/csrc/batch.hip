@@ -352,34 +352,34 @@ __device__ __forceinline__ void batch_group_tile(const BatchOp* __restrict__ ops
     if (!op_runs(op.type, *op.st)) continue;
     if constexpr (TYPE == B_CHEB_NEXT) {
       if (op.i2)
-        row_cheb_next<VT, MT, double, true, false, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const double*)op.b,
+        row_cheb_next<VT, MT, double, false, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const double*)op.b,
                                                                    (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.i0, P);
       else
-        row_cheb_next<VT, MT, VT, true, false, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b,
+        row_cheb_next<VT, MT, VT, false, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b,
                                                                (VT*)op.c, (VT*)op.d, op.f0, op.f1, op.f2, op.i0, P);
     } else if constexpr (TYPE == B_CHEB_FIRST) {
       const VT* e = (const VT*)op.w.p[0];
       const int* agg = e ? op.T.agg : nullptr;
       if (op.i2)
-        row_cheb_first<VT, MT, double, true, OffPre<K, MT>>(A, slot, lane, (const double*)op.a, (VT*)op.c, (VT*)op.d,
+        row_cheb_first<VT, MT, double, OffPre<K, MT>>(A, slot, lane, (const double*)op.a, (VT*)op.c, (VT*)op.d,
                                                             op.f0, op.f1, op.f2, op.f3, op.i0, op.i1, e, agg, P);
       else
-        row_cheb_first<VT, MT, VT, true, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0,
+        row_cheb_first<VT, MT, VT, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (VT*)op.c, (VT*)op.d, op.f0,
                                                         op.f1, op.f2, op.f3, op.i0, op.i1, e, agg, P);
     } else if constexpr (TYPE == B_RESIDUAL) {
       const VT* e = (const VT*)op.w.p[0];
       if (e) {
         if (op.i2)
-          (void)row_residual_p<VT, MT, double, true, OffPre<K, MT>>(A, slot, lane, (const double*)op.a,
+          (void)row_residual_p<VT, MT, double, OffPre<K, MT>>(A, slot, lane, (const double*)op.a,
                                                                     (const VT*)op.b, e, op.T.agg, (VT*)op.c, P);
         else
-          (void)row_residual_p<VT, MT, VT, true, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b, e,
+          (void)row_residual_p<VT, MT, VT, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b, e,
                                                                 op.T.agg, (VT*)op.c, P);
       } else if (op.i2) {
-        (void)row_residual<VT, MT, double, true, OffPre<K, MT>>(A, slot, lane, (const double*)op.a, (const VT*)op.b,
+        (void)row_residual<VT, MT, double, OffPre<K, MT>>(A, slot, lane, (const double*)op.a, (const VT*)op.b,
                                                                 (VT*)op.c, P);
       } else {
-        (void)row_residual<VT, MT, VT, true, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b,
+        (void)row_residual<VT, MT, VT, OffPre<K, MT>>(A, slot, lane, (const VT*)op.a, (const VT*)op.b,
                                                             (VT*)op.c, P);
       }
     }

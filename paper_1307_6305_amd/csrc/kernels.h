@@ -202,63 +202,30 @@ __device__ __forceinline__ AT offdiag_k(const Mat<MT>& A, int slot, int j, const
   return sum;
 }
 
-// The same sum on the plain layout (one lane per row) in LDS, where the
-// one-workgroup tail program runs: entries added in order.  A wavefront's rows
-// share one slice, so the trip count is uniform.  The tail always uses the
-// plain layout, so its results do not depend on the level's layout.
+// The off-diagonal sum of the row in `slot` on the level's layout (K lanes).
 template <typename AT, typename MT, typename XA>
-__device__ __forceinline__ AT offdiag_seq(const Mat<MT>& A, int r, const XA& x) {
-  const int s = r >> 6, p = r & 63;
-  const int* __restrict__ c = A.col + A.off[s] + p;
-  const MT* __restrict__ v = A.val + A.off[s] + p;
-  const int wd = A.width[s];
-  AT acc = (AT)0;
-  int t = 0;
-  for (; t + 8 <= wd; t += 8) {  // eight entries' loads in flight, added in order
-    int cc[8];
-    AT vv[8], xx[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) cc[i] = c[(t + i) * 64];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) vv[i] = (AT)v[(t + i) * 64];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) xx[i] = (AT)x(cc[i]);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc += vv[i] * xx[i];
-  }
-  for (; t < wd; ++t) acc += (AT)v[t * 64] * (AT)x(c[t * 64]);
-  return acc;
-}
-
-// GLOBAL: device-wide kernels on the level's layout; otherwise the tail
-// program on the plain layout.
-template <typename AT, bool GLOBAL = true, typename MT, typename XA>
 __device__ __forceinline__ AT offdiag_a(const Mat<MT>& A, int slot, int j, const XA& x) {
-  if constexpr (!GLOBAL) {
-    return offdiag_seq<AT>(A, slot, x);
-  } else {
-    if (A.lk == 0) return offdiag_k<1, AT>(A, slot, j, x);
-    if (A.lk == 1) return offdiag_k<2, AT>(A, slot, j, x);
-    return offdiag_k<4, AT>(A, slot, j, x);
-  }
+  if (A.lk == 0) return offdiag_k<1, AT>(A, slot, j, x);
+  if (A.lk == 1) return offdiag_k<2, AT>(A, slot, j, x);
+  return offdiag_k<4, AT>(A, slot, j, x);
 }
 
-template <typename AT, bool GLOBAL = true, typename MT, typename XT>
+template <typename AT, typename MT, typename XT>
 __device__ __forceinline__ AT offdiag(const Mat<MT>& A, int slot, int j, const XT* __restrict__ x) {
-  return offdiag_a<AT, GLOBAL>(A, slot, j, XPlain<XT>{x});
+  return offdiag_a<AT>(A, slot, j, XPlain<XT>{x});
 }
 
 // Where a row step takes its off-diagonal sum from: the matrix in its layout
-// (OffMat), or entries a caller has already loaded for this lane (OffPre:
-// rows whose slice is at most one batch of 8 / K entries per lane wide, the
-// loads offdiag_k issues for its first and only batch, added the same way --
-// the same bits).  The batched executor loads a row's entries once and
-// applies them to every right-hand side that shares the matrix.
-template <bool G>
+// (OffMat), entries a caller has already loaded for this lane (OffPre: rows
+// whose slice is at most one batch of 8 / K entries per lane wide, the loads
+// offdiag_k issues for its first and only batch, added the same way -- the
+// same bits), or the tail program's uniform-width layout in LDS (OffTail).
+// The batched executor loads a row's entries once and applies them to every
+// right-hand side that shares the matrix.
 struct OffMat {
   template <typename AT, typename MT, typename XA>
   __device__ __forceinline__ AT sum(const Mat<MT>& A, int slot, int j, const XA& x) const {
-    return offdiag_a<AT, G>(A, slot, j, x);
+    return offdiag_a<AT>(A, slot, j, x);
   }
 };
 
@@ -380,7 +347,7 @@ __device__ __forceinline__ int row_at(const Mat<MT>& A, int slot) {
 //
 // With e and agg given (accumulating steps only), y holds x before the
 // prolongation of a coarse correction: y is read as y_r + e_{agg(r)}.
-template <typename VT, typename MT, typename RT, bool G = true, typename OD = OffMat<G>>
+template <typename VT, typename MT, typename RT, typename OD = OffMat>
 __device__ __forceinline__ void row_cheb_first(const Mat<MT>& A, int slot, int j, const RT* __restrict__ w0, VT* w1,
                                                VT* y, double theta, double inv_eta, double c0, double c1, int accum,
                                                int store, const VT* __restrict__ e = nullptr,
@@ -412,7 +379,7 @@ __device__ __forceinline__ int row_cheb_first_a(const Mat<MT>& A, int slot, int 
   const AT x0 = (AT)w0(r);
   const AT d = (AT)A.D[r];
   const AT y0 = accum ? (AT)yin(r) : (AT)0;
-  const AT off = offdiag_a<AT, true>(A, slot, j, w0);
+  const AT off = offdiag_a<AT>(A, slot, j, w0);
   if (j) return -1;
   const AT ax = d * x0 - off;
   const AT t = (ax - (AT)theta * x0) * (AT)inv_eta;
@@ -456,7 +423,7 @@ __device__ __forceinline__ void st_row(T* p, T v) {
 // NT (levels far larger than the caches): the row's own operands D_r,
 // w_{k-1,r}, y_r and its results are streamed non-temporally, so that the
 // matrix and the gathered w_k stay cached; same arithmetic.
-template <typename VT, typename MT, typename PT, bool G = true, bool NT = false, typename OD = OffMat<G>>
+template <typename VT, typename MT, typename PT, bool NT = false, typename OD = OffMat>
 __device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int slot, int j, const VT* __restrict__ wk,
                                               const PT* wprev, VT* wnext, VT* y, double theta, double two_inv_eta,
                                               double ck, int store, const OD& od = OD()) {
@@ -475,7 +442,7 @@ __device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int slot, int j,
 }
 
 // s = f - A x; returns the row in the writing lane, -1 in the others
-template <typename VT, typename MT, typename RT, bool G = true, typename OD = OffMat<G>>
+template <typename VT, typename MT, typename RT, typename OD = OffMat>
 __device__ __forceinline__ int row_residual(const Mat<MT>& A, int slot, int j, const RT* __restrict__ f,
                                             const VT* __restrict__ x, VT* s, const OD& od = OD()) {
   using AT = VT;
@@ -492,7 +459,7 @@ __device__ __forceinline__ int row_residual(const Mat<MT>& A, int slot, int j, c
 
 // s = f - A (x + P e): the residual after the prolongation of the coarse
 // correction e, without writing x + P e (the next smoothing step adds e).
-template <typename VT, typename MT, typename RT, bool G = true, typename OD = OffMat<G>>
+template <typename VT, typename MT, typename RT, typename OD = OffMat>
 __device__ __forceinline__ int row_residual_p(const Mat<MT>& A, int slot, int j, const RT* __restrict__ f,
                                               const VT* __restrict__ x, const VT* __restrict__ e,
                                               const int* __restrict__ agg, VT* s, const OD& od = OD()) {
@@ -519,7 +486,7 @@ __device__ __forceinline__ int row_residual_a(const Mat<MT>& A, int slot, int j,
   const AT xr = (AT)X(r);
   const AT d = (AT)A.D[r];
   const AT fr = (AT)f[r];
-  const AT off = offdiag_a<AT, true>(A, slot, j, X);
+  const AT off = offdiag_a<AT>(A, slot, j, X);
   if (j) return -1;
   const AT ax = d * xr - off;
   s[r] = (VT)(fr - ax);
@@ -535,7 +502,7 @@ __device__ __forceinline__ VT row_residual_value(const Mat<MT>& A, int slot, int
   const AT xr = (AT)x[r];
   const AT d = (AT)A.D[r];
   const AT fr = (AT)f[r];
-  const AT off = offdiag<AT, true>(A, slot, j, x);
+  const AT off = offdiag<AT>(A, slot, j, x);
   const AT ax = d * xr - off;
   return (VT)(fr - ax);
 }
@@ -570,7 +537,7 @@ __device__ __forceinline__ void row_prolong(const Transfer& T, int i, const VT* 
 
 // q = A p for the row in `slot`; the writing lane returns the row and sets
 // v = (p_r q_r, p_r rv_r) in FP64, the other lanes return -1.
-template <typename VT, typename MT, typename RT, bool G = true, typename OD = OffMat<G>>
+template <typename VT, typename MT, typename RT, typename OD = OffMat>
 __device__ __forceinline__ int row_spmv_dots(const Mat<MT>& A, int slot, int j, const VT* __restrict__ p, VT* q,
                                              const RT* __restrict__ rv, double (&v)[2], const OD& od = OD()) {
   using AT = VT;
@@ -596,7 +563,7 @@ __device__ __forceinline__ int row_spmv_dots_a(const Mat<MT>& A, int slot, int j
   const AT pr = (AT)P(r);
   const AT d = (AT)A.D[r];
   const double rr = (double)rv[r];
-  const AT off = offdiag_a<AT, true>(A, slot, j, P);
+  const AT off = offdiag_a<AT>(A, slot, j, P);
   if (j) return -1;
   const AT ap = d * pr - off;
   q[r] = (VT)ap;
@@ -873,7 +840,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* e = I.i2 ? lds_at<const VT>(lds, I.e) : nullptr;
         const int* agg = I.i2 ? lds_at<const int>(lds, I.agg) : nullptr;
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_first<VT, MT, VT, false, OffTail>(A, r, 0, w0, w1, y, I.f0, I.f1, I.f2, I.f3, I.i0, I.i1, e, agg,
+          row_cheb_first<VT, MT, VT, OffTail>(A, r, 0, w0, w1, y, I.f0, I.f1, I.f2, I.f3, I.i0, I.i1, e, agg,
                                                      OffTail{(int)I.width});
         break;
       }
@@ -884,7 +851,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         VT* wn = lds_at<VT>(lds, I.c);
         VT* y = lds_at<VT>(lds, I.d);
         for (int r = tid; r < A.n; r += bd)
-          row_cheb_next<VT, MT, VT, false, false, OffTail>(A, r, 0, wk, wp, wn, y, I.f0, I.f1, I.f2, I.i0,
+          row_cheb_next<VT, MT, VT, false, OffTail>(A, r, 0, wk, wp, wn, y, I.f0, I.f1, I.f2, I.i0,
                                                            OffTail{(int)I.width});
         break;
       }
@@ -904,7 +871,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const VT* x = lds_at<const VT>(lds, I.b);
         VT* sv = lds_at<VT>(lds, I.c);
         for (int r = tid; r < A.n; r += bd)
-          (void)row_residual<VT, MT, VT, false, OffTail>(A, r, 0, f, x, sv, OffTail{(int)I.width});
+          (void)row_residual<VT, MT, VT, OffTail>(A, r, 0, f, x, sv, OffTail{(int)I.width});
         break;
       }
       case OP_RESIDUAL_P: {
@@ -915,7 +882,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         const int* agg = lds_at<const int>(lds, I.agg);
         VT* sv = lds_at<VT>(lds, I.c);
         for (int r = tid; r < A.n; r += bd)
-          (void)row_residual_p<VT, MT, VT, false, OffTail>(A, r, 0, f, x, e, agg, sv, OffTail{(int)I.width});
+          (void)row_residual_p<VT, MT, VT, OffTail>(A, r, 0, f, x, e, agg, sv, OffTail{(int)I.width});
         break;
       }
       case OP_RESTRICT: {
@@ -1038,7 +1005,7 @@ __device__ __forceinline__ void run_tail(const TailProgram& P, char* lds, double
         double v[2] = {0.0, 0.0};
         for (int r = tid; r < A.n; r += bd) {
           double w[2];
-          (void)row_spmv_dots<VT, MT, VT, false, OffTail>(A, r, 0, p, q, rv, w, OffTail{(int)I.width});
+          (void)row_spmv_dots<VT, MT, VT, OffTail>(A, r, 0, p, q, rv, w, OffTail{(int)I.width});
           v[0] += w[0];
           v[1] += w[1];
         }

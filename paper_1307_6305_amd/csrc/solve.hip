@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(kMaxRowThreads) k_cheb_next(Mat<MT> A, const V
                                                               double ck) {
   const SlotLane q = slot_of(A);
   if (q.slot >= 0)
-    row_cheb_next<VT, MT, PT, true, KIND == kStepFine || KIND == kStepFineTimed>(A, q.slot, q.lane, wk, wprev, wnext, y,
+    row_cheb_next<VT, MT, PT, KIND == kStepFine || KIND == kStepFineTimed>(A, q.slot, q.lane, wk, wprev, wnext, y,
                                                                                 theta, two_inv_eta, ck, STORE);
 }
 
