@@ -56,6 +56,9 @@ CASES = {
     "delaunay11_mis2": (lambda: inputs.delaunay3d(11, seed=inputs.seed_for(6, 11)),
                         dict(degree=4, aggregation="mis", mis_distance=2)),
     "grid100x37_mis1": (lambda: inputs.grid2d(100, 37), dict(degree=3, aggregation="mis", mis_distance=1)),
+    # a path (one row of the grid): coarse levels of two neighbours per row, so
+    # the tail program's padded width is 4 (the other cases give 8 to 44)
+    "path3000_agg4_m3": (lambda: inputs.grid2d(3000, 1), dict(degree=3, agg_size=4)),
 }
 
 
