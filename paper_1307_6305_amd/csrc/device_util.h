@@ -192,14 +192,17 @@ __device__ __forceinline__ void sum_partials(const double* partials, int nparts,
 }
 
 // kn: only the first kn values are summed (the rest are written as given).
+// part: the block's partial slot (default: its block index; every slot of
+// 0..gridDim.x-1 must be written by exactly one block).
 template <int K>
-__device__ __forceinline__ void grid_sum_finish(double (&v)[K], const Red& r, int kn = K) {
+__device__ __forceinline__ void grid_sum_finish(double (&v)[K], const Red& r, int kn = K, int part = -1) {
   __shared__ double red[16 * 8];
   __shared__ bool last;
   block_sum_k<K>(v, kn, red);
   if (threadIdx.x == 0) {
+    const int b = part >= 0 ? part : (int)blockIdx.x;
 #pragma unroll
-    for (int k = 0; k < K; ++k) r.partials[blockIdx.x * K + k] = v[k];
+    for (int k = 0; k < K; ++k) r.partials[b * K + k] = v[k];
   }
   if (!r.last_block) return;
   if (threadIdx.x == 0) {

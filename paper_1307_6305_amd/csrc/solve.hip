@@ -91,6 +91,30 @@ __global__ void __launch_bounds__(kMaxRowThreads) k_cheb_next(Mat<MT> A, const V
                                                                                 theta, two_inv_eta, ck, STORE);
 }
 
+// The last Chebyshev step of a smoothing (w_{k+1} not stored) fused with the
+// inner product (y, q) of its result with a vector: the sums k_multidot forms
+// -- each tile's rows in row order (staged when the layout permutes or splits
+// rows), the tile's partial in the slot of its tile index -- so the same bits,
+// one launch fewer.
+template <typename VT, typename MT, typename PT>
+__global__ void __launch_bounds__(kMaxRowThreads) k_cheb_next_dot(Mat<MT> A, const VT* __restrict__ wk, const PT* wprev,
+                                                                  VT* y, double theta, double two_inv_eta, double ck,
+                                                                  const VT* __restrict__ q, Red red) {
+  __shared__ double stage[TPB];
+  const SlotLane sl = slot_of(A);
+  double v[1] = {0.0};
+  int r = -1;
+  if (sl.slot >= 0) {
+    row_cheb_next<VT, MT, PT>(A, sl.slot, sl.lane, wk, wprev, nullptr, y, theta, two_inv_eta, ck, 0);
+    if (sl.lane == 0) {  // as k_multidot: v += z_j q_j from zero
+      r = row_at(A, sl.slot);
+      v[0] += (double)y[r] * (double)q[r];
+    }
+  }
+  if (needs_stage(A)) tile_stage<1>(v, r >= 0 ? r - sl.tile * TPB : -1, stage);
+  grid_sum_finish<1>(v, red, 1, sl.tile);
+}
+
 // degree 0: y = [y +] c0 w0
 template <typename VT, typename RT>
 __global__ void k_scale_add(int n, const RT* __restrict__ w0, VT* y, double c0, int accum) {
@@ -479,6 +503,13 @@ struct Engine {
     int x_init;
     int s_rho, s_gam;
   };
+  // The inner product (result, q) into scal[slot], asked of a cycle so that
+  // its last smoothing step can form it (done is set when it did).
+  struct DotReq {
+    const VT* q;
+    int slot;
+    bool done;
+  };
 
   Mat<MT> A(int l) const { return mat_of<MT>(h->lv[l]); }
   static VT* wsv(void* p) { return static_cast<VT*>(p); }
@@ -597,6 +628,20 @@ struct Engine {
     return AMG_OK;
   }
 
+  // the last step of a smoothing (nothing stored but y) with (y, dot->q)
+  template <typename PT>
+  int32_t cheb_next_dot(int l, const VT* wk, const PT* wprev, VT* y, double ck, DotReq* dot) {
+    const Level& lv = h->lv[l];
+    const auto Am = A(l);
+    const Slots sl = slots1(dot->slot);
+    hipLaunchKernelGGL((k_cheb_next_dot<VT, MT, PT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev, y,
+                       lv.theta, 2.0 / lv.eta, ck, dot->q, red_for(Am.nb, sl));
+    AMG_HIP(hipGetLastError());
+    AMG_TRY(finish<1>(Am.nb, sl));
+    dot->done = true;
+    return AMG_OK;
+  }
+
   // `reps` back-to-back launches of the finest level's storing Chebyshev step
   // (w_k fixed in buffer A, w_{k-1} and w_{k+1} in buffer B, y in S) between
   // two events; values stay bounded (B alternates between two vectors).
@@ -667,7 +712,7 @@ struct Engine {
   // accumulating): y is x before the prolongation x += P fold_e.
   template <typename RT>
   int32_t smooth(int l, const RT* r, VT* y, bool accum, const VT* fold_e = nullptr, const Deferred* fold_d = nullptr,
-                 const StepUpd* upd = nullptr) {
+                 const StepUpd* upd = nullptr, DotReq* dot = nullptr) {
     const Level& lv = h->lv[l];
     const int m = h->p.degree;
     const double* c = lv.coef.data();
@@ -679,13 +724,20 @@ struct Engine {
     VT* prevbuf = nullptr;
     for (int k = 1; k < m; ++k) {
       const bool store = (k + 1 < m);
+      const bool with_dot = dot && !rec && !store;
       VT* next;
       if (k == 1) {
         next = bufB;
-        AMG_TRY(cheb_next(l, cur, r, next, y, c[k + 1], store));
+        if (with_dot)
+          AMG_TRY(cheb_next_dot(l, cur, r, y, c[k + 1], dot));
+        else
+          AMG_TRY(cheb_next(l, cur, r, next, y, c[k + 1], store));
       } else {
         next = prevbuf;
-        AMG_TRY(cheb_next(l, cur, static_cast<const VT*>(prevbuf), next, y, c[k + 1], store));
+        if (with_dot)
+          AMG_TRY(cheb_next_dot(l, cur, static_cast<const VT*>(prevbuf), y, c[k + 1], dot));
+        else
+          AMG_TRY(cheb_next(l, cur, static_cast<const VT*>(prevbuf), next, y, c[k + 1], store));
       }
       prevbuf = cur;
       cur = next;
@@ -884,7 +936,7 @@ struct Engine {
   template <typename RT>
   // upd: the first smoothing step also applies the previous inner step's
   // update (r is then the rhs2 it writes).
-  int32_t kcycle(int l, const RT* r, VT* x, const StepUpd* upd = nullptr) {
+  int32_t kcycle(int l, const RT* r, VT* x, const StepUpd* upd = nullptr, DotReq* dot = nullptr) {
     if (l == h->L) return coarse(r, x);
     VT* S = wsv(h->ws[l].S);
     VT* b = wsv(h->ws[l + 1].rhs);
@@ -912,7 +964,7 @@ struct Engine {
     // follow it: the same roundings, one pass fewer
     if (h->p.degree > 0 && (rec || h->lv[l].n < kFoldProlongRows)) {
       AMG_TRY(residual_p(l, r, x, e, S, &d));
-      AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true, e, &d));
+      AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true, e, &d, nullptr, dot));
       return AMG_OK;
     }
     AMG_TRY(prolong(l, e, x, &d));
@@ -967,10 +1019,14 @@ struct Engine {
     AMG_TRY(kcycle(l, static_cast<const VT*>(rhs), Z0));
     AMG_TRY(spmv_dots(l, Z0, Q0, rhs, slots2(base, base + 8)));
     const StepUpd u{rhs, Q0, Z0, sol, 1, base, base + 8};
-    AMG_TRY(kcycle(l, static_cast<const VT*>(rhs2), Z1, &u));
-    VecPtrs qs{};
-    qs.p[0] = W.Q[0];
-    AMG_TRY(multidot(l, n, Z1, qs, 1, slots_range(base + 16, 1), false));
+    // (Z1, Q0) from the cycle's last smoothing step when it can form it
+    DotReq dq{Q0, base + 16, false};
+    AMG_TRY(kcycle(l, static_cast<const VT*>(rhs2), Z1, &u, &dq));
+    if (!dq.done) {
+      VecPtrs qs{};
+      qs.p[0] = W.Q[0];
+      AMG_TRY(multidot(l, n, Z1, qs, 1, slots_range(base + 16, 1), false));
+    }
     const auto Am = A(l);
     const Slots pq = slots2(base + 1, base + 9);
     hipLaunchKernelGGL((k_spmv_dots_dir<VT, MT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, Z1, Z0, P1, Q1, rhs2,
