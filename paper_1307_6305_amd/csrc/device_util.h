@@ -191,6 +191,36 @@ __device__ __forceinline__ void sum_partials(const double* partials, int nparts,
   block_sum_k<K>(acc, kn, red);
 }
 
+// Sums a producer left as per-block partials (a grid too large to finish in
+// the kernel), finished at the start of the kernel that consumes them instead
+// of in a launch of their own: every block forms the sums k_finish_sum would
+// (sum_partials, the same order), block 0 also stores them into scal for later
+// kernels, and every thread gets them in vals.  nparts = 0: nothing pending.
+struct PendingSum {
+  const double* partials;
+  int nparts;
+  int kn;
+  Slots slots;
+};
+
+template <int K>
+__device__ __forceinline__ void finish_pending(const PendingSum& ps, double* scal, double (&vals)[K]) {
+  __shared__ double red[16 * 8];
+  __shared__ double out[K];
+  double acc[K];
+  sum_partials<K>(ps.partials, ps.nparts, acc, red, ps.kn);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      out[k] = acc[k];
+      if (blockIdx.x == 0 && k < ps.kn) scal[ps.slots.s[k]] = acc[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) vals[k] = out[k];
+}
+
 // kn: only the first kn values are summed (the rest are written as given).
 // part: the block's partial slot (default: its block index; every slot of
 // 0..gridDim.x-1 must be written by exactly one block).

@@ -596,14 +596,16 @@ __device__ __forceinline__ bool needs_stage(const Mat<MT>& A) {
   return A.perm != nullptr || A.lk != 0;
 }
 
+__device__ __forceinline__ double fcg_alpha_of(double rho, double gam) {
+  return (rho > 0.0 && isfinite(rho)) ? gam / rho : 0.0;
+}
 __device__ __forceinline__ double fcg_alpha(const double* scal, int s_rho, int s_gam) {
-  const double rho = scal[s_rho];
-  return (rho > 0.0 && isfinite(rho)) ? scal[s_gam] / rho : 0.0;
+  return fcg_alpha_of(scal[s_rho], scal[s_gam]);
 }
 
+__device__ __forceinline__ double fcg_beta_of(double dot, double rho) { return rho > 0.0 ? dot / rho : 0.0; }
 __device__ __forceinline__ double fcg_beta(const double* scal, int s_dot, int s_rho) {
-  const double rho = scal[s_rho];
-  return rho > 0.0 ? scal[s_dot] / rho : 0.0;
+  return fcg_beta_of(scal[s_dot], scal[s_rho]);
 }
 
 // Coarsest solve x = L^-T (L^-1 b) with the inverted factor: two triangular

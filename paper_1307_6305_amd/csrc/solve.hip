@@ -335,8 +335,16 @@ __global__ void __launch_bounds__(kMaxRowThreads) k_cheb_first_upd(Mat<MT> A, co
                                                                    const VT* __restrict__ p, VT* sol, int x_init,
                                                                    VT* w1, VT* y, double theta, double inv_eta,
                                                                    double c0, double c1, int store,
-                                                                   const double* scal, int s_rho, int s_gam) {
-  const double alpha = fcg_alpha(scal, s_rho, s_gam);
+                                                                   double* scal, int s_rho, int s_gam,
+                                                                   PendingSum pend) {
+  double alpha;
+  if (pend.nparts > 0) {  // rho and gamma still partials: finished here (slots s_rho, s_gam)
+    double pv[2];
+    finish_pending<2>(pend, scal, pv);
+    alpha = fcg_alpha_of(pv[0], pv[1]);
+  } else {
+    alpha = fcg_alpha(scal, s_rho, s_gam);
+  }
   const SlotLane sl = slot_of(A);
   if (sl.slot < 0) return;
   VT w0v;
@@ -354,10 +362,17 @@ __global__ void __launch_bounds__(kMaxRowThreads) k_cheb_first_upd(Mat<MT> A, co
 template <typename VT, typename MT>
 __global__ void __launch_bounds__(kMaxRowThreads) k_spmv_dots_dir(Mat<MT> A, const VT* __restrict__ z,
                                                                   const VT* __restrict__ z0, VT* pout, VT* q,
-                                                                  const VT* __restrict__ rv, const double* scal,
-                                                                  int s_dot, int s_rho, Red red) {
+                                                                  const VT* __restrict__ rv, double* scal,
+                                                                  int s_dot, int s_rho, Red red, PendingSum pend) {
   __shared__ double stage[2 * TPB];
-  const double beta = fcg_beta(scal, s_dot, s_rho);
+  double beta;
+  if (pend.nparts > 0) {  // the dot still partials: finished here (slot s_dot)
+    double pv[1];
+    finish_pending<1>(pend, scal, pv);
+    beta = fcg_beta_of(pv[0], scal[s_rho]);
+  } else {
+    beta = fcg_beta(scal, s_dot, s_rho);
+  }
   const SlotLane sl = slot_of(A);
   double v[2] = {0.0, 0.0};
   int r = -1;
@@ -502,13 +517,16 @@ struct Engine {
     VT* sol;
     int x_init;
     int s_rho, s_gam;
+    PendingSum pend;  // rho and gamma left as partials (nparts 0: in scal)
   };
   // The inner product (result, q) into scal[slot], asked of a cycle so that
-  // its last smoothing step can form it (done is set when it did).
+  // its last smoothing step can form it (done is set when it did; pend holds
+  // its partials when their finish is left to the next kernel).
   struct DotReq {
     const VT* q;
     int slot;
     bool done;
+    PendingSum pend;
   };
 
   Mat<MT> A(int l) const { return mat_of<MT>(h->lv[l]); }
@@ -527,6 +545,14 @@ struct Engine {
   Red red_for(int blocks, Slots slots) const {
     return Red{pa(), co(), sc(), slots, blocks <= h->last_block_max ? 1 : 0};
   }
+  // A reduction of `blocks` blocks (K values each) whose finish the next
+  // kernel takes over: too many blocks to finish in the kernel, and its
+  // partials fit the upper half of the partials buffer (the lower half stays
+  // for the consumer's own reduction).
+  bool defer_finish(int blocks, int K) const {
+    return !rec && blocks > h->last_block_max && (size_t)blocks * K <= (size_t)h->max_blocks * 4;
+  }
+  double* pa_deferred() const { return pa() + (size_t)h->max_blocks * 4; }
   // host: publish (the sum, scal[pub]) to the pinned host mirror as well
   template <int K>
   int32_t finish(int blocks, Slots slots, double* host = nullptr, int pub = 0, int kn = K) {
@@ -555,7 +581,7 @@ struct Engine {
         const auto Am = A(l);
         hipLaunchKernelGGL((k_cheb_first_upd<VT, MT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, upd->rhs, upd->q,
                            const_cast<VT*>(w0), upd->p, upd->sol, upd->x_init, w1, y, lv.theta, 1.0 / lv.eta, c0, c1,
-                           (int)store, (const double*)sc(), upd->s_rho, upd->s_gam);
+                           (int)store, sc(), upd->s_rho, upd->s_gam, upd->pend);
         AMG_HIP(hipGetLastError());
         return AMG_OK;
       }
@@ -634,10 +660,16 @@ struct Engine {
     const Level& lv = h->lv[l];
     const auto Am = A(l);
     const Slots sl = slots1(dot->slot);
+    const bool defer = defer_finish(Am.nb, 1);
+    const Red rd = defer ? Red{pa_deferred(), co(), sc(), sl, 0} : red_for(Am.nb, sl);
     hipLaunchKernelGGL((k_cheb_next_dot<VT, MT, PT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk, wprev, y,
-                       lv.theta, 2.0 / lv.eta, ck, dot->q, red_for(Am.nb, sl));
+                       lv.theta, 2.0 / lv.eta, ck, dot->q, rd);
     AMG_HIP(hipGetLastError());
-    AMG_TRY(finish<1>(Am.nb, sl));
+    if (defer) {
+      dot->pend = PendingSum{pa_deferred(), Am.nb, 1, sl};
+    } else {
+      AMG_TRY(finish<1>(Am.nb, sl));
+    }
     dot->done = true;
     return AMG_OK;
   }
@@ -1017,20 +1049,30 @@ struct Engine {
     VT* P1 = wsv(W.P1);
     const int base = lbase(l);
     AMG_TRY(kcycle(l, static_cast<const VT*>(rhs), Z0));
-    AMG_TRY(spmv_dots(l, Z0, Q0, rhs, slots2(base, base + 8)));
-    const StepUpd u{rhs, Q0, Z0, sol, 1, base, base + 8};
+    const auto Am = A(l);
+    // step 0's (p, q) and (p, r): on a grid too large to finish them in the
+    // kernel, the next cycle's first kernel (the only reader) finishes them
+    StepUpd u{rhs, Q0, Z0, sol, 1, base, base + 8};
+    const Slots pr0 = slots2(base, base + 8);
+    if (defer_finish(Am.nb, 2)) {
+      hipLaunchKernelGGL((k_spmv_dots<VT, MT, VT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, Z0, Q0, rhs,
+                         Red{pa_deferred(), co(), sc(), pr0, 0});
+      AMG_HIP(hipGetLastError());
+      u.pend = PendingSum{pa_deferred(), Am.nb, 2, pr0};
+    } else {
+      AMG_TRY(spmv_dots(l, Z0, Q0, rhs, pr0));
+    }
     // (Z1, Q0) from the cycle's last smoothing step when it can form it
-    DotReq dq{Q0, base + 16, false};
+    DotReq dq{Q0, base + 16, false, PendingSum{}};
     AMG_TRY(kcycle(l, static_cast<const VT*>(rhs2), Z1, &u, &dq));
     if (!dq.done) {
       VecPtrs qs{};
       qs.p[0] = W.Q[0];
       AMG_TRY(multidot(l, n, Z1, qs, 1, slots_range(base + 16, 1), false));
     }
-    const auto Am = A(l);
     const Slots pq = slots2(base + 1, base + 9);
     hipLaunchKernelGGL((k_spmv_dots_dir<VT, MT>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, Z1, Z0, P1, Q1, rhs2,
-                       (const double*)sc(), base + 16, base, red_for(Am.nb, pq));
+                       sc(), base + 16, base, red_for(Am.nb, pq), dq.pend);
     AMG_HIP(hipGetLastError());
     AMG_TRY(finish<2>(Am.nb, pq));
     out->on = true;
