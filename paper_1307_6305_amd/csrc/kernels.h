@@ -426,7 +426,7 @@ __device__ __forceinline__ void st_row(T* p, T v) {
 template <typename VT, typename MT, typename PT, bool NT = false, typename OD = OffMat>
 __device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int slot, int j, const VT* __restrict__ wk,
                                               const PT* wprev, VT* wnext, VT* y, double theta, double two_inv_eta,
-                                              double ck, int store, const OD& od = OD()) {
+                                              double ck, int store, const OD& od = OD(), VT* y_out = nullptr) {
   using AT = VT;
   const int r = row_at(A, slot);
   const AT xk = (AT)wk[r];
@@ -438,7 +438,9 @@ __device__ __forceinline__ void row_cheb_next(const Mat<MT>& A, int slot, int j,
   const AT ax = d * xk - off;
   const AT t = (ax - (AT)theta * xk) * (AT)two_inv_eta - wp;
   if (store) st_row<NT>(wnext + r, (VT)t);
-  st_row<NT>(y + r, (VT)(y0 + (AT)ck * t));
+  const VT yv = (VT)(y0 + (AT)ck * t);
+  st_row<NT>(y + r, yv);
+  if (y_out) *y_out = yv;  // the stored value, for a caller that goes on with it
 }
 
 // s = f - A x; returns the row in the writing lane, -1 in the others

@@ -105,14 +105,45 @@ __global__ void __launch_bounds__(kMaxRowThreads) k_cheb_next_dot(Mat<MT> A, con
   double v[1] = {0.0};
   int r = -1;
   if (sl.slot >= 0) {
-    row_cheb_next<VT, MT, PT>(A, sl.slot, sl.lane, wk, wprev, nullptr, y, theta, two_inv_eta, ck, 0);
+    VT yv;
+    row_cheb_next<VT, MT, PT>(A, sl.slot, sl.lane, wk, wprev, nullptr, y, theta, two_inv_eta, ck, 0, OffMat(), &yv);
     if (sl.lane == 0) {  // as k_multidot: v += z_j q_j from zero
       r = row_at(A, sl.slot);
-      v[0] += (double)y[r] * (double)q[r];
+      v[0] += (double)yv * (double)q[r];
     }
   }
   if (needs_stage(A)) tile_stage<1>(v, r >= 0 ? r - sl.tile * TPB : -1, stage);
   grid_sum_finish<1>(v, red, 1, sl.tile);
+}
+
+// The same with the outer iteration's window of products (y, q_i), i < k
+// (q_i FP64), on any level (the finest: its row operands streamed, KIND): the
+// sums of k_multidot<VT, double>.
+template <typename VT, typename MT, typename PT, int KIND>
+__global__ void __launch_bounds__(kMaxRowThreads) k_cheb_next_mdot(Mat<MT> A, const VT* __restrict__ wk,
+                                                                   const PT* wprev, VT* y, double theta,
+                                                                   double two_inv_eta, double ck, VecPtrs qs, int k,
+                                                                   Red red) {
+  __shared__ double stage[8 * TPB];
+  const SlotLane sl = slot_of(A);
+  double v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = 0.0;
+  int r = -1;
+  if (sl.slot >= 0) {
+    VT yv;
+    row_cheb_next<VT, MT, PT, KIND == kStepFine || KIND == kStepFineTimed>(A, sl.slot, sl.lane, wk, wprev, nullptr, y,
+                                                                          theta, two_inv_eta, ck, 0, OffMat(), &yv);
+    if (sl.lane == 0) {
+      r = row_at(A, sl.slot);
+      const double zj = (double)yv;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < k) v[i] += zj * static_cast<const double*>(qs.p[i])[r];
+    }
+  }
+  if (needs_stage(A)) tile_stage<8>(v, r >= 0 ? r - sl.tile * TPB : -1, stage);
+  grid_sum_finish<8>(v, red, k, sl.tile);
 }
 
 // degree 0: y = [y +] c0 w0
@@ -528,6 +559,14 @@ struct Engine {
     bool done;
     PendingSum pend;
   };
+  // The outer iteration's window of products (result, q_i), i < k (q_i FP64),
+  // into slots, asked of the finest level's cycle in the same way.
+  struct MDotReq {
+    VecPtrs qs;
+    int k;
+    Slots slots;
+    bool done;
+  };
 
   Mat<MT> A(int l) const { return mat_of<MT>(h->lv[l]); }
   static VT* wsv(void* p) { return static_cast<VT*>(p); }
@@ -674,6 +713,25 @@ struct Engine {
     return AMG_OK;
   }
 
+  // the last step of a smoothing with the window products (y, q_i)
+  template <typename PT>
+  int32_t cheb_next_mdot(int l, const VT* wk, const PT* wprev, VT* y, double ck, MDotReq* md) {
+    const Level& lv = h->lv[l];
+    const auto Am = A(l);
+    const double ti = 2.0 / lv.eta;
+    const Red rd = red_for(Am.nb, md->slots);
+    if (l == 0 && lv.n >= kStreamRows)
+      hipLaunchKernelGGL((k_cheb_next_mdot<VT, MT, PT, kStepFine>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk,
+                         wprev, y, lv.theta, ti, ck, md->qs, md->k, rd);
+    else
+      hipLaunchKernelGGL((k_cheb_next_mdot<VT, MT, PT, kStepCoarse>), dim3(Am.nb), dim3(TPB << Am.lk), 0, s, Am, wk,
+                         wprev, y, lv.theta, ti, ck, md->qs, md->k, rd);
+    AMG_HIP(hipGetLastError());
+    AMG_TRY(finish<8>(Am.nb, md->slots, nullptr, 0, md->k));
+    md->done = true;
+    return AMG_OK;
+  }
+
   // `reps` back-to-back launches of the finest level's storing Chebyshev step
   // (w_k fixed in buffer A, w_{k-1} and w_{k+1} in buffer B, y in S) between
   // two events; values stay bounded (B alternates between two vectors).
@@ -744,7 +802,7 @@ struct Engine {
   // accumulating): y is x before the prolongation x += P fold_e.
   template <typename RT>
   int32_t smooth(int l, const RT* r, VT* y, bool accum, const VT* fold_e = nullptr, const Deferred* fold_d = nullptr,
-                 const StepUpd* upd = nullptr, DotReq* dot = nullptr) {
+                 const StepUpd* upd = nullptr, DotReq* dot = nullptr, MDotReq* mdot = nullptr) {
     const Level& lv = h->lv[l];
     const int m = h->p.degree;
     const double* c = lv.coef.data();
@@ -757,17 +815,22 @@ struct Engine {
     for (int k = 1; k < m; ++k) {
       const bool store = (k + 1 < m);
       const bool with_dot = dot && !rec && !store;
+      const bool with_mdot = mdot && !rec && !store;
       VT* next;
       if (k == 1) {
         next = bufB;
         if (with_dot)
           AMG_TRY(cheb_next_dot(l, cur, r, y, c[k + 1], dot));
+        else if (with_mdot)
+          AMG_TRY(cheb_next_mdot(l, cur, r, y, c[k + 1], mdot));
         else
           AMG_TRY(cheb_next(l, cur, r, next, y, c[k + 1], store));
       } else {
         next = prevbuf;
         if (with_dot)
           AMG_TRY(cheb_next_dot(l, cur, static_cast<const VT*>(prevbuf), y, c[k + 1], dot));
+        else if (with_mdot)
+          AMG_TRY(cheb_next_mdot(l, cur, static_cast<const VT*>(prevbuf), y, c[k + 1], mdot));
         else
           AMG_TRY(cheb_next(l, cur, static_cast<const VT*>(prevbuf), next, y, c[k + 1], store));
       }
@@ -968,7 +1031,8 @@ struct Engine {
   template <typename RT>
   // upd: the first smoothing step also applies the previous inner step's
   // update (r is then the rhs2 it writes).
-  int32_t kcycle(int l, const RT* r, VT* x, const StepUpd* upd = nullptr, DotReq* dot = nullptr) {
+  int32_t kcycle(int l, const RT* r, VT* x, const StepUpd* upd = nullptr, DotReq* dot = nullptr,
+                 MDotReq* mdot = nullptr) {
     if (l == h->L) return coarse(r, x);
     VT* S = wsv(h->ws[l].S);
     VT* b = wsv(h->ws[l + 1].rhs);
@@ -996,12 +1060,12 @@ struct Engine {
     // follow it: the same roundings, one pass fewer
     if (h->p.degree > 0 && (rec || h->lv[l].n < kFoldProlongRows)) {
       AMG_TRY(residual_p(l, r, x, e, S, &d));
-      AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true, e, &d, nullptr, dot));
+      AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true, e, &d, nullptr, dot, mdot));
       return AMG_OK;
     }
     AMG_TRY(prolong(l, e, x, &d));
     AMG_TRY(residual(l, r, x, S));
-    AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true));
+    AMG_TRY(smooth(l, static_cast<const VT*>(S), x, true, nullptr, nullptr, nullptr, dot, mdot));
     return AMG_OK;
   }
 
@@ -1125,13 +1189,16 @@ struct Engine {
     const int nb = nblk(n);
     const auto A64 = mat_of<double>(h->lv[0]);
     VT* z = wsv(h->z);
-    AMG_TRY(kcycle(0, static_cast<const double*>(h->r), z));
     VecPtrs qs{}, ps{};
     for (int i = 0; i < j; ++i) {
       qs.p[i] = h->Qo[i];
       ps.p[i] = h->P[i];
     }
-    if (j > 0) AMG_TRY(multidot(0, n, z, qs, j, slots_range(S_DOTS, j), true));
+    // the window products (z, q_i) from the cycle's last smoothing step when
+    // it can form them
+    MDotReq md{qs, j, slots_range(S_DOTS, j), false};
+    AMG_TRY(kcycle(0, static_cast<const double*>(h->r), z, nullptr, nullptr, h->p.fuse && j > 0 ? &md : nullptr));
+    if (j > 0 && !md.done) AMG_TRY(multidot(0, n, z, qs, j, slots_range(S_DOTS, j), true));
     hipLaunchKernelGGL((k_fcg_p<double, VT>), dim3(nb), dim3(TPB), 0, s, n, h->P[j], z, ps, j, sc(),
                        slots_range(S_DOTS, j), slots_range(S_RHOW, j));
     const Slots pq = slots2(S_RHOW + j, S_GAM);
