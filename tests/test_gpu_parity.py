@@ -211,6 +211,25 @@ def test_single_level_hierarchy(amg):
     assert info["iters"] == 1 and info["rel_res_true"] <= 1e-12
 
 
+def test_one_vertex(amg):
+    """The smallest problem, n = 1 with no edges: A = [d] is its own coarsest
+    level, the preconditioner is the exact solve, and one iteration gives
+    u = f / d, in FP64 and in mixed precision (same as the oracle)."""
+    rp = np.array([0, 0], dtype=np.int32)
+    col = np.zeros(0, dtype=np.int32)
+    w = np.zeros(0)
+    d = np.array([2.5])
+    res = oracle.fcg(oracle.build_hierarchy(1, rp, col, w, d, oracle.Params(degree=3)), np.array([5.0]))
+    assert res.iters == 1 and res.x[0] == pytest.approx(2.0, rel=1e-15)
+    for precision in ("fp64", "mixed"):
+        h = amg.amg_setup(1, rp, col, w, d, amg.amg_params_default(degree=3, precision=precision))
+        assert amg.amg_describe(h)["levels"] == 1
+        u = torch.zeros(1, dtype=torch.float64, device="cuda")
+        info = amg.amg_solve(h, torch.tensor([5.0], dtype=torch.float64, device="cuda"), u)
+        assert info["status"] == 0 and info["iters"] == res.iters
+        assert float(u[0]) == pytest.approx(2.0, rel=1e-15)
+
+
 def test_stagnating_coarsening_uses_block_cholesky(amg):
     """A star graph coarsens by one pair per pass: stagnation stops the
     hierarchy and the coarsest level (> 64 rows) is solved by the workgroup
