@@ -4,8 +4,8 @@ q_m is the polynomial of degree m of best uniform approximation to 1/x on
 [lambda0, lambda1] (eq. (1x-1-min)), with lambda1 = ||A||_inf (an upper bound on
 rho(A)) and, in the experiments of Section 4, lambda0 = lambda1 / 10.
 
-The paper defers the construction ("the three-term recurrence used in its
-construction") to its reference on polynomial smoothers.  Reading taken here:
+The paper leaves how the coefficients are built (by a recurrence) to its
+reference on polynomial smoothers.  Reading taken here:
 Chebyshev's classical solution.  With theta = (lambda1+lambda0)/2,
 eta = (lambda1-lambda0)/2, t = (x - theta)/eta and a = theta/eta = (k+1)/(k-1)
 (k = lambda1/lambda0), 1/x = (1/eta) / (t + a), and with

@@ -8,9 +8,9 @@ infrastructure only).
 * Symmetrized preconditioner B = R_bar + (I-RA) P A_H^+ P^T (I-AR),
   R_bar = 2R - RAR.
 * Weak approximation constant c_p = max_l 1/lambda_l over the aggregates, with
-  lambda_l the smallest positive eigenvalue of the graph Laplacian of the
-  subgraph G_l (eq. (wap)); singleton aggregates contribute nothing (v - Qv
-  vanishes on them).
+  lambda_l the second eigenvalue (the first nonzero one, G_l being connected)
+  of the Laplacian of the aggregate's induced subgraph G_l (eq. (wap));
+  singleton aggregates contribute nothing (v - Qv vanishes on them).
 """
 from __future__ import annotations
 
